@@ -1,0 +1,245 @@
+"""Plain FP64 CPU oracle of one Henon Monte Carlo step (test infrastructure).
+
+Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark
+may import this package.  It wraps ``liboracle.so`` (plain C, built from
+``cmc_oracle.c`` by ``oracle/build.py``) and shares no code with the HIP
+library.  Method: arXiv:1206.5878, Sec. 2.1 (serial step) and Sec. 3.2 (bins).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+P_INIT_POS, P_INIT_SPEED, P_INIT_MASS = 0x10, 0x11, 0x12
+P_RELAX, P_ORBIT, P_SIGN, P_ENSEMBLE = 0x20, 0x30, 0x31, 0x40
+
+ST_NONFINITE, ST_TRIAL_CAP, ST_BOUND = 1, 2, 4
+ST_ESCAPER, ST_DT_DEGEN, ST_NUMERIC = 8, 16, 32
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_up = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_vp = C.c_void_p
+
+
+class OrbitStats(C.Structure):
+    _fields_ = [("n_esc", C.c_int64), ("trials", C.c_int64), ("violations", C.c_int64),
+                ("capped", C.c_int64), ("e_esc", C.c_double), ("status", C.c_uint32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("step", C.c_uint32), ("gamma", C.c_double),
+                ("target", C.c_double), ("dt_fixed", C.c_double), ("trial_cap", C.c_int32),
+                ("bound_factor", C.c_double)]
+
+
+class StepOut(C.Structure):
+    _fields_ = [("dt", C.c_double), ("n_after", C.c_int64), ("orbit", OrbitStats),
+                ("status", C.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(_LIB_PATH)
+        L.ora_philox_many.argtypes = [C.c_int64, C.c_uint64, _up, _up]
+        L.ora_u01.argtypes = [C.c_uint32, C.c_uint32]
+        L.ora_u01.restype = C.c_double
+        L.ora_u01f.argtypes = [C.c_uint32]
+        L.ora_u01f.restype = C.c_float
+        L.ora_plummer.argtypes = [C.c_int64, C.c_uint64, C.c_int, _dp, _dp, _dp, _dp, _up]
+        L.ora_sort_perm.argtypes = [C.c_int64, _dp, _ip]
+        L.ora_potential.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp]
+        L.ora_phi_at.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, C.c_double]
+        L.ora_phi_at.restype = C.c_double
+        L.ora_pair_terms.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _up, C.c_uint64,
+                                     C.c_uint32, C.c_double, _dp, _dp, _dp]
+        L.ora_pair_terms.restype = C.c_int64
+        L.ora_mean_sin2.argtypes = [C.c_int64, _dp, _dp, C.c_double]
+        L.ora_mean_sin2.restype = C.c_double
+        L.ora_solve_dt.argtypes = [C.c_int64, _dp, _dp, C.c_double, C.POINTER(C.c_uint32)]
+        L.ora_solve_dt.restype = C.c_double
+        L.ora_relax.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _up, C.c_uint64, C.c_uint32,
+                                C.c_double, C.c_double]
+        L.ora_orbit.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _up, C.c_uint64,
+                                C.c_uint32, C.c_int32, C.c_double, _dp,
+                                _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                C.POINTER(OrbitStats)]
+        L.ora_step.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _up, _dp, _dp,
+                               C.POINTER(Params), C.POINTER(StepOut)]
+        L.ora_diagnostics.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        _lib = L
+    return _lib
+
+
+def _f64(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def _u32(x):
+    return np.ascontiguousarray(x, dtype=np.uint32)
+
+
+# ---------------------------------------------------------------- random numbers
+def philox(key: int, ctr: np.ndarray) -> np.ndarray:
+    """Philox4x32-10 blocks for counters ``ctr`` (shape (n, 4), uint32)."""
+    ctr = _u32(ctr).reshape(-1, 4)
+    out = np.empty_like(ctr)
+    lib().ora_philox_many(ctr.shape[0], key, ctr.reshape(-1), out.reshape(-1))
+    return out
+
+
+def u01(hi, lo) -> float:
+    return lib().ora_u01(int(hi), int(lo))
+
+
+def u01f(hi) -> float:
+    return lib().ora_u01f(int(hi))
+
+
+# ---------------------------------------------------------------- state helpers
+class State:
+    """Sorted SoA star state (host, FP64)."""
+
+    def __init__(self, r, vr, vt, m, id_):
+        self.r = _f64(r).copy()
+        self.vr = _f64(vr).copy()
+        self.vt = _f64(vt).copy()
+        self.m = _f64(m).copy()
+        self.id = _u32(id_).copy()
+
+    @property
+    def n(self) -> int:
+        return self.r.shape[0]
+
+    def copy(self) -> "State":
+        return State(self.r, self.vr, self.vt, self.m, self.id)
+
+
+def plummer_unsorted(n: int, seed: int, mass_spectrum: int = 0):
+    r = np.empty(n); vr = np.empty(n); vt = np.empty(n); m = np.empty(n)
+    id_ = np.empty(n, dtype=np.uint32)
+    lib().ora_plummer(n, seed, mass_spectrum, r, vr, vt, m, id_)
+    return r, vr, vt, m, id_
+
+
+def sort_perm(key: np.ndarray) -> np.ndarray:
+    key = _f64(key)
+    perm = np.empty(key.shape[0], dtype=np.int64)
+    lib().ora_sort_perm(key.shape[0], key, perm)
+    return perm
+
+
+def plummer(n: int, seed: int, mass_spectrum: int = 0) -> State:
+    """Initial Plummer model sorted by radius (ties by id)."""
+    r, vr, vt, m, id_ = plummer_unsorted(n, seed, mass_spectrum)
+    p = sort_perm(r)
+    return State(r[p], vr[p], vt[p], m[p], id_[p])
+
+
+def potential(r, m):
+    """(phi, mcum, ssuf): Phi_k, inclusive mass prefix M_k, exclusive suffix
+    S_k of m/r, with Phi_k = -(M_k / r_k + S_k)."""
+    r = _f64(r); m = _f64(m)
+    phi = np.empty_like(r); mcum = np.empty_like(r); ssuf = np.empty_like(r)
+    lib().ora_potential(r.shape[0], r, m, phi, mcum, ssuf)
+    return phi, mcum, ssuf
+
+
+def phi_at(r, table, x: float) -> float:
+    phi, mcum, ssuf = table
+    return lib().ora_phi_at(r.shape[0], _f64(r), _f64(phi), _f64(mcum), _f64(ssuf),
+                            float(x))
+
+
+def pair_terms(st: State, seed: int, step: int, gamma: float):
+    np_ = st.n // 2
+    w = np.empty(max(np_, 1)); tp = np.empty(max(np_, 1)); nb = np.empty(max(np_, 1))
+    lib().ora_pair_terms(st.n, st.r, st.m, st.vr, st.vt, st.id, seed, step, gamma, w, tp, nb)
+    return w[:np_], tp[:np_], nb[:np_]
+
+
+def mean_sin2(w, tp, dt: float) -> float:
+    return lib().ora_mean_sin2(len(w), _f64(w), _f64(tp), float(dt))
+
+
+def solve_dt(w, tp, target: float):
+    """(dt, status) with mean sin^2(beta/2) = target."""
+    if len(w) == 0:
+        return 0.0, ST_DT_DEGEN
+    status = C.c_uint32(0)
+    dt = lib().ora_solve_dt(len(w), _f64(w), _f64(tp), target, C.byref(status))
+    return dt, status.value
+
+
+def timestep(st: State, seed: int, step: int, gamma: float, target: float):
+    w, tp, _ = pair_terms(st, seed, step, gamma)
+    return solve_dt(w, tp, target)
+
+
+def relax(st: State, seed: int, step: int, gamma: float, dt: float) -> State:
+    out = st.copy()
+    lib().ora_relax(out.n, out.r, out.m, out.vr, out.vt, out.id, seed, step, gamma, dt)
+    return out
+
+
+def orbit(st: State, table, seed: int, step: int, trial_cap: int = 10000,
+          bound_factor: float = 1.2, details: bool = False):
+    """New orbits for a sorted state with table (phi, mcum, ssuf) from
+    ``potential``.  Returns (r_new, vr_new, vt_new, stats[, details dict])."""
+    phi, mcum, ssuf = table
+    n = st.n
+    vr = st.vr.copy(); vt = st.vt.copy()
+    r_new = np.empty(max(n, 1))
+    st_ = OrbitStats()
+    d = {}
+    keys = ("E", "J", "kmin", "kmax", "rmin", "rmax", "trials", "flags")
+    ptrs = [None] * len(keys)
+    if details:
+        d = dict(E=np.empty(n), J=np.empty(n), kmin=np.empty(n, np.int64),
+                 kmax=np.empty(n, np.int64), rmin=np.empty(n), rmax=np.empty(n),
+                 trials=np.empty(n, np.int32), flags=np.empty(n, np.uint32))
+        ptrs = [d[k].ctypes.data for k in keys]
+    lib().ora_orbit(n, st.r, _f64(phi), _f64(mcum), _f64(ssuf), st.m, vr, vt, st.id, seed, step,
+                    trial_cap, bound_factor, r_new, *ptrs, C.byref(st_))
+    stats = {k: getattr(st_, k) for k, _ in OrbitStats._fields_}
+    if details:
+        return r_new[:n], vr, vt, stats, d
+    return r_new[:n], vr, vt, stats
+
+
+def step(st: State, seed: int, step_idx: int, gamma: float, target: float = 0.03,
+         dt_fixed: float = 0.0, trial_cap: int = 10000, bound_factor: float = 1.2):
+    """One whole step on a copy of ``st``.  Returns (new_state, info dict)."""
+    s = st.copy()
+    phi = np.empty(max(s.n, 1)); mcum = np.empty(max(s.n, 1))
+    p = Params(seed, step_idx, gamma, target, dt_fixed, trial_cap, bound_factor)
+    o = StepOut()
+    lib().ora_step(s.n, s.r, s.vr, s.vt, s.m, s.id, phi, mcum, C.byref(p), C.byref(o))
+    k = o.n_after
+    new = State(s.r[:k], s.vr[:k], s.vt[:k], s.m[:k], s.id[:k])
+    info = dict(dt=o.dt, n_after=k, status=o.status,
+                orbit={f: getattr(o.orbit, f) for f, _ in OrbitStats._fields_},
+                phi=phi[:st.n], mcum=mcum[:st.n])
+    return new, info
+
+
+def diagnostics(st: State, phi=None, mcum=None) -> dict:
+    if phi is None:
+        phi, mcum, _ = potential(st.r, st.m)
+    out = np.empty(9)
+    lib().ora_diagnostics(st.n, st.r, st.vr, st.vt, st.m, _f64(phi), _f64(mcum), out)
+    return dict(T=out[0], W=out[1], E=out[2], virial=out[3], M=out[4],
+                r01=out[5], r10=out[6], r50=out[7], r90=out[8])
