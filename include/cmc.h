@@ -1,0 +1,187 @@
+/*
+ * cmc.h -- C ABI of libcmc.so: one Henon Monte Carlo step of a spherical star
+ * cluster on an AMD Instinct MI355X (gfx950), written in HIP.
+ *
+ * The method is the one of Pattabiraman et al., "A Parallel Monte Carlo Code
+ * for Simulating Collisional N-body Systems" (arXiv:1206.5878), Sec. 2.1: with
+ * the stars sorted by radius, (1) compute the potential, (2) fix the shared
+ * timestep, (3) relax neighbouring pairs by a representative two-body
+ * encounter, (5) draw a new orbit and radius for every star, (6) sort by
+ * radius.  Units: G = 1, total mass 1 (Henon units).  Stars are 0-based.
+ *
+ * Conventions for every call:
+ *  - All pointers inside cmc_state, and every pointer named *_dev, are DEVICE
+ *    memory owned by the caller.  The library never allocates, frees or
+ *    synchronises; each call only enqueues kernels on `stream` (a hipStream_t,
+ *    NULL = the default stream) and returns.
+ *  - The active star count lives on the device (cmc_scalars.n), so a sequence
+ *    of calls never needs a host round trip.  `cap` bounds it.
+ *  - Return value: CMC_OK, or a negative CMC_E* code when the arguments fail
+ *    the host-side checks (nothing is enqueued then) or a launch fails.
+ *  - Problems found on the device set sticky CMC_ST_* bits in
+ *    cmc_scalars.status; the caller reads them after synchronising.
+ *  - Calls on different states may run concurrently on different streams;
+ *    calls on one state must be ordered (one stream).
+ *  - No C++ exception crosses this boundary.
+ */
+#ifndef CMC_H
+#define CMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CMC_ABI_VERSION 1
+
+/* ---- return codes --------------------------------------------------------- */
+#define CMC_OK 0
+#define CMC_EINVAL (-1)     /* null pointer, cap out of range, bad argument    */
+#define CMC_EWORKSPACE (-2) /* work_bytes < cmc_workspace_bytes(cap)            */
+#define CMC_EHIP (-3)       /* a kernel launch failed (hipGetLastError)         */
+#define CMC_ERANGE (-4)     /* n > cap                                          */
+
+/* ---- sticky device status bits (cmc_scalars.status) ----------------------- */
+#define CMC_ST_NONFINITE 0x01u /* a non-finite radius or velocity was produced  */
+#define CMC_ST_TRIAL_CAP 0x02u /* a star used trial_cap rejection trials         */
+#define CMC_ST_BOUND 0x04u     /* a trial exceeded the rejection bound F         */
+#define CMC_ST_ESCAPER 0x08u   /* a star had E >= 0 and was removed              */
+#define CMC_ST_DT_DEGEN 0x10u  /* no positive dt reaches the target; dt = 0     */
+#define CMC_ST_NUMERIC 0x20u   /* degenerate orbit: infinite rejection bound     */
+#define CMC_ST_DT_NOCONV 0x40u /* the dt solve ran out of iterations            */
+
+/* ---- arithmetic of a call --------------------------------------------------- */
+#define CMC_FP64 0  /* every step in double precision                          */
+#define CMC_MIXED 1 /* fp32 pair kicks and rejection trials; compensated fp32
+                       potential scan with an fp64 carry; fp64 turning points  */
+
+/* Device-resident scalars of one cluster (128 bytes, caller-owned). */
+typedef struct cmc_scalars {
+  int64_t n;          /* active star count (set by cmc_init_plummer / cmc_sort) */
+  double dt;          /* timestep: solved by cmc_timestep, read by cmc_relax    */
+  uint32_t status;    /* sticky CMC_ST_* bits                                   */
+  uint32_t dt_iters;  /* Newton iterations the last dt solve used               */
+  int64_t n_esc;      /* escapers found by the last orbit pass                  */
+  int64_t trials;     /* rejection trials of the last orbit pass                */
+  int64_t violations; /* trials with g(s) > F in the last orbit pass            */
+  int64_t capped;     /* stars that hit trial_cap in the last orbit pass        */
+  double e_esc;       /* sum of m E over the last orbit pass's escapers         */
+  double mass_norm;   /* total raw mass drawn by cmc_init_plummer               */
+  int64_t reserved[7];
+} cmc_scalars;
+
+/* One cluster.  Every array has `cap` entries of device memory.
+ *  r, vr, vt, m, id : the stars, sorted by r on entry to cmc_potential,
+ *                     cmc_timestep, cmc_relax and cmc_orbit (SoA).
+ *  m                : double, or float when m_f32 != 0.
+ *  id               : persistent star id; it names the star's random streams.
+ *  phi, mcum, ssuf  : the potential table written by cmc_potential:
+ *                     mcum[k] = sum_{i<=k} m_i, ssuf[k] = sum_{i>k} m_i/r_i,
+ *                     phi[k] = -(mcum[k]/r[k] + ssuf[k]).
+ *  r_new            : new radius from cmc_orbit, +inf for an escaper; the key
+ *                     that cmc_sort orders by.
+ *  sc               : device scalars (see cmc_scalars).
+ *  work, work_bytes : scratch of at least cmc_workspace_bytes(cap) bytes,
+ *                     256-byte aligned, zero-filled by the caller once before
+ *                     the first call (the library returns its internal
+ *                     counters to zero at the end of every call); no other
+ *                     contents are preserved between calls. */
+typedef struct cmc_state {
+  int64_t cap;
+  double *r, *vr, *vt;
+  void *m;
+  int32_t m_f32;
+  int32_t reserved0;
+  uint32_t *id;
+  double *phi, *mcum, *ssuf;
+  double *r_new;
+  cmc_scalars *sc;
+  void *work;
+  size_t work_bytes;
+} cmc_state;
+
+/* Parameters of one step. */
+typedef struct cmc_params {
+  uint64_t seed;       /* Philox key                                              */
+  uint32_t step;       /* step index: Philox counter word 1                       */
+  int32_t precision;   /* CMC_FP64 or CMC_MIXED                                   */
+  double gamma;        /* Coulomb logarithm ln(gamma N), N = active stars         */
+  double target;       /* mean sin^2(beta/2) over pairs that fixes dt (0.03)      */
+  double bound_factor; /* rejection bound F = bound_factor * max endpoint g (1.2) */
+  int32_t trial_cap;   /* rejection trials per star before giving up (10000)      */
+  int32_t dt_iters;    /* Newton iterations enqueued for dt; 0 = default (24)     */
+} cmc_params;
+
+/* Bytes of scratch a state of capacity `cap` needs. */
+size_t cmc_workspace_bytes(int64_t cap);
+
+/* Initial Plummer model (Sec. 2.1 opening paragraph: sample (m, r, vr, vt),
+ * keep |r|, vr, vt, start sorted).  Star i < n draws from Philox key `seed`,
+ * counter (i, 0, purpose, trial): r = (X1^(-2/3) - 1)^(-1/2); speed by
+ * rejection on q^2 (1-q^2)^(7/2); isotropic direction; Henon-unit scaling
+ * r * 3pi/16, v * sqrt(16/(3pi)).  mass_spectrum 0: m = 1/n; 1: broken power
+ * law dN/dm ~ m^-1.3 on [0.1,0.5], m^-2.3 on [0.5,100], rescaled to sum 1.
+ * Writes r, vr, vt, m, id sorted by radius (ties by id) and sc->n = n, clears
+ * the other scalars.  CMC_ERANGE if n > cap. */
+int cmc_init_plummer(cmc_state *s, int64_t n, uint64_t seed, int32_t mass_spectrum,
+                     void *stream);
+
+/* Sort (Sec. 2.1 step 6): order the stars by r_new ascending (key = bit
+ * pattern of r_new + 0.0, so +inf and NaN go last), equal keys in their
+ * present order; write r = r_new, vr, vt, m, id permuted accordingly and drop
+ * the stars whose key is not finite (escapers) by lowering sc->n. */
+int cmc_sort(cmc_state *s, void *stream);
+
+/* Potential (Sec. 2.1 step 1): for r_k <= r < r_{k+1},
+ * Phi(r) = -(1/r) sum_{i<=k} m_i - sum_{i>k} m_i/r_i.  Writes mcum, ssuf, phi
+ * for the sc->n sorted stars.  precision: CMC_FP64 or CMC_MIXED. */
+int cmc_potential(cmc_state *s, int32_t precision, void *stream);
+
+/* Shared timestep (Sec. 2.1 step 2 and Sec. 3.2 bins, as fixed for this
+ * method): pairs (2j, 2j+1); local density from the pair's 20-star bin;
+ * t_p = (pi/32) w^3 / (ln(gamma N) n_b (m1+m2)^2); beta_p = min(pi,
+ * (pi/2) sqrt(dt/t_p)); solve mean over pairs with w > 0 of sin^2(beta_p/2)
+ * = p->target for dt (Newton on ln dt, started from sc->dt when > 0).
+ * Writes sc->dt, sc->dt_iters; CMC_ST_DT_DEGEN / CMC_ST_DT_NOCONV bits. */
+int cmc_timestep(cmc_state *s, const cmc_params *p, void *stream);
+
+/* Two-body relaxation (Sec. 2.1 step 3(i)): rotate each pair's relative
+ * velocity by beta_p (with dt = sc->dt) about a random azimuth in the
+ * centre-of-mass frame; pair momentum and kinetic energy are conserved.
+ * Updates vr, vt in place.  An odd last star is left alone. */
+int cmc_relax(cmc_state *s, const cmc_params *p, void *stream);
+
+/* New orbits (Sec. 2.1 step 5): E = phi_i + (vr^2+vt^2)/2, J = r_i vt_i;
+ * bracket rmin and rmax between table radii by bisection on
+ * Q(r) = 2E - 2Phi(r) - J^2/r^2, solve inside the bracket, then draw the new
+ * radius with probability proportional to dr/|v_r| by rejection in
+ * r = r_c + r_a sin s (trial j of star i uses Philox counter
+ * (id_i, step, 0x30, j)).  Writes r_new (+inf when E >= 0) and the new vr,
+ * vt in place; counters in sc.  Needs the table of cmc_potential. */
+int cmc_orbit(cmc_state *s, const cmc_params *p, void *stream);
+
+/* One whole step: potential -> timestep -> relax -> orbit -> sort. */
+int cmc_step(cmc_state *s, const cmc_params *p, void *stream);
+
+/* Diagnostics of the sorted state and its table (needs cmc_potential):
+ * out_dev[0..8] = T, W = sum m phi / 2, E = T + W, 2T/|W|, M, and the radii
+ * holding 1%, 10%, 50%, 90% of the mass. */
+int cmc_diagnostics(const cmc_state *s, double *out_dev, void *stream);
+
+/* Raw Philox4x32-10 blocks: out_dev[4i..4i+3] = Philox(key, ctr_dev[4i..4i+3])
+ * for i < n.  The generator every random draw above goes through. */
+int cmc_philox(uint64_t key, const uint32_t *ctr_dev, uint32_t *out_dev, int64_t n,
+               void *stream);
+
+/* Text for a CMC_E* code. */
+const char *cmc_strerror(int code);
+
+/* CMC_ABI_VERSION of the loaded library. */
+int cmc_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

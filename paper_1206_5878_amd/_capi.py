@@ -1,0 +1,83 @@
+"""ctypes declarations of libcmc.so (include/cmc.h), argument marshalling only.
+
+Every computation runs in the HIP library; this module only mirrors the C
+structs and loads the shared object.  It raises when the library is missing:
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcmc.so")
+
+CMC_OK, CMC_EINVAL, CMC_EWORKSPACE, CMC_EHIP, CMC_ERANGE = 0, -1, -2, -3, -4
+CMC_FP64, CMC_MIXED = 0, 1
+ST_NONFINITE, ST_TRIAL_CAP, ST_BOUND, ST_ESCAPER = 0x01, 0x02, 0x04, 0x08
+ST_DT_DEGEN, ST_NUMERIC, ST_DT_NOCONV = 0x10, 0x20, 0x40
+
+EXPORTS = ("cmc_workspace_bytes", "cmc_init_plummer", "cmc_sort", "cmc_potential",
+           "cmc_timestep", "cmc_relax", "cmc_orbit", "cmc_step", "cmc_diagnostics",
+           "cmc_philox", "cmc_strerror", "cmc_abi_version")
+
+
+class cmc_scalars(C.Structure):
+    _fields_ = [("n", C.c_int64), ("dt", C.c_double), ("status", C.c_uint32),
+                ("dt_iters", C.c_uint32), ("n_esc", C.c_int64), ("trials", C.c_int64),
+                ("violations", C.c_int64), ("capped", C.c_int64), ("e_esc", C.c_double),
+                ("mass_norm", C.c_double), ("reserved", C.c_int64 * 7)]
+
+
+class cmc_state(C.Structure):
+    _fields_ = [("cap", C.c_int64), ("r", C.c_void_p), ("vr", C.c_void_p),
+                ("vt", C.c_void_p), ("m", C.c_void_p), ("m_f32", C.c_int32),
+                ("reserved0", C.c_int32), ("id", C.c_void_p), ("phi", C.c_void_p),
+                ("mcum", C.c_void_p), ("ssuf", C.c_void_p), ("r_new", C.c_void_p),
+                ("sc", C.c_void_p), ("work", C.c_void_p), ("work_bytes", C.c_size_t)]
+
+
+class cmc_params(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("step", C.c_uint32), ("precision", C.c_int32),
+                ("gamma", C.c_double), ("target", C.c_double), ("bound_factor", C.c_double),
+                ("trial_cap", C.c_int32), ("dt_iters", C.c_int32)]
+
+
+assert C.sizeof(cmc_scalars) == 128
+
+_lib = None
+
+
+class CmcError(RuntimeError):
+    pass
+
+
+def lib() -> C.CDLL:
+    """The loaded libcmc.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise CmcError(f"{LIB_PATH} is missing: build it with "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        sp, vp = C.POINTER(cmc_state), C.c_void_p
+        pp = C.POINTER(cmc_params)
+        L.cmc_workspace_bytes.argtypes = [C.c_int64]
+        L.cmc_workspace_bytes.restype = C.c_size_t
+        L.cmc_init_plummer.argtypes = [sp, C.c_int64, C.c_uint64, C.c_int32, vp]
+        L.cmc_sort.argtypes = [sp, vp]
+        L.cmc_potential.argtypes = [sp, C.c_int32, vp]
+        for f in ("cmc_timestep", "cmc_relax", "cmc_orbit", "cmc_step"):
+            getattr(L, f).argtypes = [sp, pp, vp]
+        L.cmc_diagnostics.argtypes = [sp, vp, vp]
+        L.cmc_philox.argtypes = [C.c_uint64, vp, vp, C.c_int64, vp]
+        L.cmc_strerror.argtypes = [C.c_int]
+        L.cmc_strerror.restype = C.c_char_p
+        L.cmc_abi_version.restype = C.c_int  # every other call returns int too
+        _lib = L
+    return _lib
+
+
+def check(rc: int, what: str) -> None:
+    if rc != CMC_OK:
+        raise CmcError(f"{what}: {lib().cmc_strerror(rc).decode()} (code {rc})")

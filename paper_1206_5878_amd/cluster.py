@@ -1,0 +1,166 @@
+"""Torch-backed cluster state and thin wrappers named after the C ABI calls.
+
+PyTorch supplies device memory (one tensor per SoA array, a zero-filled
+workspace) and the current HIP stream; every step of the method runs in
+libcmc.so.  Method: arXiv:1206.5878, Sec. 2.1.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _capi as A
+
+
+@dataclass
+class Params:
+    """Mirror of cmc_params with the workload defaults."""
+    seed: int = 1
+    step: int = 0
+    precision: int = A.CMC_FP64
+    gamma: float = 0.11
+    target: float = 0.03
+    bound_factor: float = 1.2
+    trial_cap: int = 10000
+    dt_iters: int = 0
+
+    def c(self) -> A.cmc_params:
+        return A.cmc_params(self.seed, self.step, self.precision, self.gamma, self.target,
+                            self.bound_factor, self.trial_cap, self.dt_iters)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Cluster:
+    """Device arrays of one cluster of capacity ``cap`` (see cmc_state)."""
+
+    def __init__(self, cap: int, m_f32: bool = False, device: str = "cuda"):
+        if cap <= 0:
+            raise ValueError("cap must be positive")
+        L = A.lib()
+        dev = torch.device(device)
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.cap = int(cap)
+        self.m_f32 = bool(m_f32)
+        self.r = torch.zeros(cap, **f64)
+        self.vr = torch.zeros(cap, **f64)
+        self.vt = torch.zeros(cap, **f64)
+        self.m = torch.zeros(cap, dtype=torch.float32 if m_f32 else torch.float64, device=dev)
+        self.id = torch.zeros(cap, dtype=torch.int32, device=dev)  # uint32 bits
+        self.phi = torch.zeros(cap, **f64)
+        self.mcum = torch.zeros(cap, **f64)
+        self.ssuf = torch.zeros(cap, **f64)
+        self.r_new = torch.zeros(cap, **f64)
+        self.sc = torch.zeros(16, dtype=torch.int64, device=dev)
+        nbytes = int(L.cmc_workspace_bytes(cap))
+        if nbytes == 0:
+            raise A.CmcError("capacity out of range")
+        self.work = torch.zeros(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = self.work.data_ptr()
+        off = (-base) % 256
+        self._c = A.cmc_state(cap, self.r.data_ptr(), self.vr.data_ptr(), self.vt.data_ptr(),
+                              self.m.data_ptr(), 1 if m_f32 else 0, 0, self.id.data_ptr(),
+                              self.phi.data_ptr(), self.mcum.data_ptr(), self.ssuf.data_ptr(),
+                              self.r_new.data_ptr(), self.sc.data_ptr(), base + off, nbytes)
+
+    # ------------------------------------------------------------ host views
+    def scalars(self) -> dict:
+        raw = self.sc.cpu().numpy().tobytes()
+        s = A.cmc_scalars.from_buffer_copy(raw)
+        return {f: getattr(s, f) for f, _ in A.cmc_scalars._fields_ if f != "reserved"}
+
+    @property
+    def n(self) -> int:
+        return int(self.sc[0].item())
+
+    def set_scalar(self, name: str, value) -> None:
+        s = A.cmc_scalars.from_buffer_copy(self.sc.cpu().numpy().tobytes())
+        setattr(s, name, value)
+        buf = np.frombuffer(bytes(s), dtype=np.int64).copy()
+        self.sc.copy_(torch.from_numpy(buf))
+
+    def load(self, r, vr, vt, m, id_) -> None:
+        """Upload a host state (first len(r) entries) and set n."""
+        n = len(r)
+        if n > self.cap:
+            raise A.CmcError("n > cap")
+        dev = self.r.device
+        self.r[:n] = torch.as_tensor(np.asarray(r, np.float64), device=dev)
+        self.vr[:n] = torch.as_tensor(np.asarray(vr, np.float64), device=dev)
+        self.vt[:n] = torch.as_tensor(np.asarray(vt, np.float64), device=dev)
+        mt = np.float32 if self.m_f32 else np.float64
+        self.m[:n] = torch.as_tensor(np.asarray(m, mt), device=dev)
+        self.id[:n] = torch.as_tensor(np.asarray(id_, np.uint32).view(np.int32), device=dev)
+        self.set_scalar("n", n)
+
+    def host(self, n: int | None = None) -> dict:
+        """Copy the first n (default: active) entries of every array to numpy."""
+        n = self.n if n is None else n
+        out = {k: getattr(self, k)[:n].cpu().numpy() for k in
+               ("r", "vr", "vt", "phi", "mcum", "ssuf", "r_new")}
+        out["m"] = self.m[:n].cpu().numpy().astype(np.float64)
+        out["id"] = self.id[:n].cpu().numpy().view(np.uint32)
+        return out
+
+    @property
+    def c(self):
+        return C.byref(self._c)
+
+
+# ---------------------------------------------------------------- ABI calls
+def cmc_init_plummer(cl: Cluster, n: int, seed: int, mass_spectrum: int = 0, stream=None):
+    A.check(A.lib().cmc_init_plummer(cl.c, n, seed, mass_spectrum, _stream(stream)),
+            "cmc_init_plummer")
+
+
+def cmc_sort(cl: Cluster, stream=None):
+    A.check(A.lib().cmc_sort(cl.c, _stream(stream)), "cmc_sort")
+
+
+def cmc_potential(cl: Cluster, precision: int = A.CMC_FP64, stream=None):
+    A.check(A.lib().cmc_potential(cl.c, precision, _stream(stream)), "cmc_potential")
+
+
+def cmc_timestep(cl: Cluster, p: Params, stream=None):
+    pc = p.c()
+    A.check(A.lib().cmc_timestep(cl.c, C.byref(pc), _stream(stream)), "cmc_timestep")
+
+
+def cmc_relax(cl: Cluster, p: Params, stream=None):
+    pc = p.c()
+    A.check(A.lib().cmc_relax(cl.c, C.byref(pc), _stream(stream)), "cmc_relax")
+
+
+def cmc_orbit(cl: Cluster, p: Params, stream=None):
+    pc = p.c()
+    A.check(A.lib().cmc_orbit(cl.c, C.byref(pc), _stream(stream)), "cmc_orbit")
+
+
+def cmc_step(cl: Cluster, p: Params, stream=None):
+    pc = p.c()
+    A.check(A.lib().cmc_step(cl.c, C.byref(pc), _stream(stream)), "cmc_step")
+
+
+def cmc_diagnostics(cl: Cluster, stream=None) -> dict:
+    out = torch.zeros(9, dtype=torch.float64, device=cl.r.device)
+    A.check(A.lib().cmc_diagnostics(cl.c, C.c_void_p(out.data_ptr()), _stream(stream)),
+            "cmc_diagnostics")
+    v = out.cpu().numpy()
+    return dict(T=v[0], W=v[1], E=v[2], virial=v[3], M=v[4], r01=v[5], r10=v[6], r50=v[7],
+                r90=v[8])
+
+
+def cmc_philox(key: int, ctr: np.ndarray, device: str = "cuda", stream=None) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    n = c.shape[0]
+    dc = torch.as_tensor(c.view(np.int32), device=device)
+    do = torch.zeros_like(dc)
+    A.check(A.lib().cmc_philox(key, C.c_void_p(dc.data_ptr()), C.c_void_p(do.data_ptr()), n,
+                               _stream(stream)), "cmc_philox")
+    return do.cpu().numpy().view(np.uint32)

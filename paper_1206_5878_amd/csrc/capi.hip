@@ -1,0 +1,146 @@
+// capi.hip -- the extern "C" entry points of libcmc.so (declared in
+// include/cmc.h): host-side argument checks, workspace carving, and the
+// launch sequence of each step of arXiv:1206.5878 Sec. 2.1.  Nothing here
+// allocates, frees or synchronises.
+#include "cmc_internal.hpp"
+
+using cmc::Workspace;
+
+static_assert(sizeof(cmc_scalars) == 128, "cmc_scalars is 128 bytes in the ABI");
+
+namespace {
+
+constexpr int64_t kMaxCap = (int64_t(1) << 32) - 1;  // ids and sort values are 32-bit
+
+int check_state(const cmc_state *s, Workspace *w) {
+  if (!s || s->cap <= 0 || s->cap > kMaxCap) return CMC_EINVAL;
+  if (!s->r || !s->vr || !s->vt || !s->m || !s->id || !s->phi || !s->mcum || !s->ssuf ||
+      !s->r_new || !s->sc || !s->work)
+    return CMC_EINVAL;
+  if (reinterpret_cast<uintptr_t>(s->work) % 256 != 0) return CMC_EINVAL;
+  *w = cmc::layout(s->cap, s->work);
+  if (s->work_bytes < w->bytes) return CMC_EWORKSPACE;
+  return CMC_OK;
+}
+
+int check_params(const cmc_params *p) {
+  if (!p) return CMC_EINVAL;
+  if (p->precision != CMC_FP64 && p->precision != CMC_MIXED) return CMC_EINVAL;
+  if (!(p->gamma > 0.0) || !(p->target > 0.0 && p->target < 1.0)) return CMC_EINVAL;
+  if (p->bound_factor < 0.0 || p->trial_cap < 0 || p->dt_iters < 0) return CMC_EINVAL;
+  return CMC_OK;
+}
+
+int status_of(hipError_t e) { return e == hipSuccess ? CMC_OK : CMC_EHIP; }
+
+hipStream_t as_stream(void *stream) { return static_cast<hipStream_t>(stream); }
+
+}  // namespace
+
+extern "C" {
+
+int cmc_abi_version(void) { return CMC_ABI_VERSION; }
+
+size_t cmc_workspace_bytes(int64_t cap) {
+  if (cap <= 0 || cap > kMaxCap) return 0;
+  return cmc::layout(cap, nullptr).bytes;
+}
+
+const char *cmc_strerror(int code) {
+  switch (code) {
+    case CMC_OK:
+      return "ok";
+    case CMC_EINVAL:
+      return "invalid argument (null pointer, capacity out of range, bad parameter)";
+    case CMC_EWORKSPACE:
+      return "workspace smaller than cmc_workspace_bytes(cap)";
+    case CMC_EHIP:
+      return "HIP kernel launch failed";
+    case CMC_ERANGE:
+      return "star count larger than the state capacity";
+    default:
+      return "unknown cmc error code";
+  }
+}
+
+int cmc_init_plummer(cmc_state *s, int64_t n, uint64_t seed, int32_t mass_spectrum,
+                     void *stream) {
+  Workspace w;
+  int rc = check_state(s, &w);
+  if (rc) return rc;
+  if (n < 0) return CMC_EINVAL;
+  if (n > s->cap) return CMC_ERANGE;
+  if (mass_spectrum != 0 && mass_spectrum != 1) return CMC_EINVAL;
+  return status_of(cmc::launch_init_plummer(*s, w, n, seed, mass_spectrum, as_stream(stream)));
+}
+
+int cmc_sort(cmc_state *s, void *stream) {
+  Workspace w;
+  int rc = check_state(s, &w);
+  if (rc) return rc;
+  hipError_t e = cmc::launch_stage_from_state(*s, w, as_stream(stream));
+  if (e != hipSuccess) return CMC_EHIP;
+  return status_of(cmc::launch_sort_stage(*s, w, false, as_stream(stream)));
+}
+
+int cmc_potential(cmc_state *s, int32_t precision, void *stream) {
+  Workspace w;
+  int rc = check_state(s, &w);
+  if (rc) return rc;
+  if (precision != CMC_FP64 && precision != CMC_MIXED) return CMC_EINVAL;
+  return status_of(cmc::launch_potential(*s, w, precision, as_stream(stream)));
+}
+
+int cmc_timestep(cmc_state *s, const cmc_params *p, void *stream) {
+  Workspace w;
+  int rc = check_state(s, &w);
+  if (rc) return rc;
+  if ((rc = check_params(p))) return rc;
+  return status_of(cmc::launch_timestep(*s, w, *p, as_stream(stream)));
+}
+
+int cmc_relax(cmc_state *s, const cmc_params *p, void *stream) {
+  Workspace w;
+  int rc = check_state(s, &w);
+  if (rc) return rc;
+  if ((rc = check_params(p))) return rc;
+  return status_of(cmc::launch_relax(*s, w, *p, as_stream(stream)));
+}
+
+int cmc_orbit(cmc_state *s, const cmc_params *p, void *stream) {
+  Workspace w;
+  int rc = check_state(s, &w);
+  if (rc) return rc;
+  if ((rc = check_params(p))) return rc;
+  return status_of(cmc::launch_orbit(*s, w, *p, false, as_stream(stream)));
+}
+
+int cmc_step(cmc_state *s, const cmc_params *p, void *stream) {
+  Workspace w;
+  int rc = check_state(s, &w);
+  if (rc) return rc;
+  if ((rc = check_params(p))) return rc;
+  hipStream_t st = as_stream(stream);
+  hipError_t e = cmc::launch_potential(*s, w, p->precision, st);
+  if (e == hipSuccess) e = cmc::launch_timestep(*s, w, *p, st);
+  if (e == hipSuccess) e = cmc::launch_relax(*s, w, *p, st);
+  if (e == hipSuccess) e = cmc::launch_orbit(*s, w, *p, true, st);
+  if (e == hipSuccess) e = cmc::launch_sort_stage(*s, w, false, st);
+  return status_of(e);
+}
+
+int cmc_diagnostics(const cmc_state *s, double *out_dev, void *stream) {
+  Workspace w;
+  int rc = check_state(s, &w);
+  if (rc) return rc;
+  if (!out_dev) return CMC_EINVAL;
+  return status_of(cmc::launch_diagnostics(*s, w, out_dev, as_stream(stream)));
+}
+
+int cmc_philox(uint64_t key, const uint32_t *ctr_dev, uint32_t *out_dev, int64_t n,
+               void *stream) {
+  if (n < 0 || (n > 0 && (!ctr_dev || !out_dev))) return CMC_EINVAL;
+  return status_of(cmc::launch_philox(key, ctr_dev, out_dev, n, as_stream(stream)));
+}
+
+}  // extern "C"

@@ -1,0 +1,251 @@
+// cmc_internal.hpp -- device helpers and workspace layout shared by the HIP
+// translation units of libcmc.so.  gfx950: 64-lane wavefronts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/cmc.h"
+
+namespace cmc {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kInf = __builtin_inf();
+
+// Philox counter word 2: what a draw is for.
+enum : uint32_t {
+  kInitPos = 0x10,
+  kInitSpeed = 0x11,
+  kInitMass = 0x12,
+  kRelax = 0x20,
+  kOrbit = 0x30,
+  kSign = 0x31,
+  kEnsemble = 0x40,
+};
+
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): per round, two 32x32
+// products of counter words 0 and 2 with fixed multipliers; the new words are
+// (hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0); the key advances by two Weyl
+// increments between rounds.
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                     uint64_t key) {
+  uint32_t k0 = static_cast<uint32_t>(key), k1 = static_cast<uint32_t>(key >> 32);
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return U4{c0, c1, c2, c3};
+}
+
+// Open-interval uniforms: (2x+1) 2^-53 from the top 52 bits of hi:lo, and
+// (2x+1) 2^-24 from the top 23 bits of hi.  Both exact; they differ < 2^-23.
+__device__ __forceinline__ double u01(uint32_t hi, uint32_t lo) {
+  const uint64_t x = ((static_cast<uint64_t>(hi) << 32) | lo) >> 12;
+  return static_cast<double>(2 * x + 1) * 0x1.0p-53;
+}
+__device__ __forceinline__ float u01f(uint32_t hi) {
+  return static_cast<float>(2 * (hi >> 9) + 1) * 0x1.0p-24f;
+}
+
+// ---------------------------------------------------------------- reductions
+// Deterministic: fixed butterfly inside a wave, fixed order across waves.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the block, valid in thread 0.  `sh` holds NT/64 entries.
+template <int NT, typename T>
+__device__ __forceinline__ T block_sum(T v, T *sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  T t = T(0);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) t += sh[i];
+  }
+  __syncthreads();
+  return t;
+}
+
+// Inclusive prefix within the wave (lane order).
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const T u = __shfl_up(v, o, 64);
+    if (l >= o) v += u;
+  }
+  return v;
+}
+
+// Inclusive suffix within the wave (sum over lanes >= this lane).
+template <typename T>
+__device__ __forceinline__ T wave_incl_suffix(T v) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const T u = __shfl_down(v, o, 64);
+    if (l + o < 64) v += u;
+  }
+  return v;
+}
+
+// Exclusive prefix over the block (thread order); *total gets the block sum.
+template <int NT, typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T *sh, T *total) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const T inc = wave_incl_scan(v);
+  T exc = __shfl_up(inc, 1, 64);
+  if (l == 0) exc = T(0);
+  if (l == 63) sh[w] = inc;
+  __syncthreads();
+  T base = T(0), tot = T(0);
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) {
+    if (i < w) base += sh[i];
+    tot += sh[i];
+  }
+  __syncthreads();
+  if (total) *total = tot;
+  return base + exc;
+}
+
+// Exclusive suffix over the block: sum over threads with a larger index.
+template <int NT, typename T>
+__device__ __forceinline__ T block_excl_suffix(T v, T *sh, T *total) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const T inc = wave_incl_suffix(v);
+  T exc = __shfl_down(inc, 1, 64);
+  if (l == 63) exc = T(0);
+  if (l == 0) sh[w] = inc;
+  __syncthreads();
+  T base = T(0), tot = T(0);
+#pragma unroll
+  for (int i = NT / 64 - 1; i >= 0; --i) {
+    if (i > w) base += sh[i];
+    tot += sh[i];
+  }
+  __syncthreads();
+  if (total) *total = tot;
+  return base + exc;
+}
+
+template <typename MT>
+__device__ __forceinline__ double load_mass(const MT *m, int64_t k) {
+  return static_cast<double>(m[k]);
+}
+
+__device__ __forceinline__ void set_status(cmc_scalars *sc, uint32_t bits) {
+  if (bits) atomicOr(&sc->status, bits);
+}
+
+// ---------------------------------------------------------------- staging
+// One star as it leaves the orbit pass and enters the sort's final gather.
+struct alignas(8) StageRec {
+  double r, vr, vt, m;
+  uint32_t id, pad;
+};
+
+// ---------------------------------------------------------------- workspace
+constexpr int kSortTile = 4096;  // keys per radix tile (256 threads x 16)
+constexpr int kPotTile = 2048;   // stars per potential tile (256 x 8)
+constexpr int kBlock = 256;
+
+struct Workspace {
+  StageRec *stage;          // [cap]
+  uint64_t *keys[2];        // [cap]
+  uint32_t *vals[2];        // [cap]
+  uint32_t *tile_hist;      // [256 * sort_tiles]
+  uint32_t *tile_off;       // [256 * sort_tiles]
+  uint32_t *hist_all;       // [8 * 256]
+  uint32_t *pass_info;      // [64]: skip mask, parity ...
+  double *pot_tsum;         // [2 * pot_tiles]
+  double *pot_carry;        // [2 * pot_tiles]
+  double *pair_tp;          // [cap/2 + 1]
+  double *pair_part;        // [4 * pair_blocks]
+  double *dt_state;         // [32]
+  uint32_t *dt_ticket;      // [16]
+  double *red_part;         // [8 * star_blocks]  generic per-block partials
+  uint32_t *red_ticket;     // [16]
+  int64_t sort_tiles, pot_tiles, pair_blocks, star_blocks;
+  size_t bytes;
+};
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+inline Workspace layout(int64_t cap, void *base) {
+  Workspace w{};
+  char *p = static_cast<char *>(base);
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char * {
+    off = (off + 255) & ~size_t(255);
+    char *q = p ? p + off : nullptr;
+    off += bytes;
+    return q;
+  };
+  const int64_t c = cap > 0 ? cap : 1;
+  w.sort_tiles = cdiv(c, kSortTile);
+  w.pot_tiles = cdiv(c, kPotTile);
+  w.pair_blocks = cdiv(c / 2 + 1, kBlock);
+  w.star_blocks = cdiv(c, kBlock);
+  w.stage = reinterpret_cast<StageRec *>(take(sizeof(StageRec) * c));
+  w.keys[0] = reinterpret_cast<uint64_t *>(take(8 * c));
+  w.keys[1] = reinterpret_cast<uint64_t *>(take(8 * c));
+  w.vals[0] = reinterpret_cast<uint32_t *>(take(4 * c));
+  w.vals[1] = reinterpret_cast<uint32_t *>(take(4 * c));
+  w.tile_hist = reinterpret_cast<uint32_t *>(take(4 * 256 * w.sort_tiles));
+  w.tile_off = reinterpret_cast<uint32_t *>(take(4 * 256 * w.sort_tiles));
+  w.hist_all = reinterpret_cast<uint32_t *>(take(4 * 8 * 256));
+  w.pass_info = reinterpret_cast<uint32_t *>(take(4 * 64));
+  w.pot_tsum = reinterpret_cast<double *>(take(8 * 2 * w.pot_tiles));
+  w.pot_carry = reinterpret_cast<double *>(take(8 * 2 * w.pot_tiles));
+  w.pair_tp = reinterpret_cast<double *>(take(8 * (c / 2 + 1)));
+  w.pair_part = reinterpret_cast<double *>(take(8 * 4 * w.pair_blocks));
+  w.dt_state = reinterpret_cast<double *>(take(8 * 32));
+  w.dt_ticket = reinterpret_cast<uint32_t *>(take(4 * 16));
+  w.red_part = reinterpret_cast<double *>(take(8 * 8 * w.star_blocks));
+  w.red_ticket = reinterpret_cast<uint32_t *>(take(4 * 16));
+  w.bytes = (off + 255) & ~size_t(255);
+  return w;
+}
+
+// ---------------------------------------------------------------- launchers
+// Defined in the translation units; each returns hipGetLastError().
+hipError_t launch_potential(const cmc_state &s, const Workspace &w, int precision,
+                            hipStream_t st);
+hipError_t launch_timestep(const cmc_state &s, const Workspace &w, const cmc_params &p,
+                           hipStream_t st);
+hipError_t launch_relax(const cmc_state &s, const Workspace &w, const cmc_params &p,
+                        hipStream_t st);
+hipError_t launch_orbit(const cmc_state &s, const Workspace &w, const cmc_params &p,
+                        bool to_stage, hipStream_t st);
+hipError_t launch_stage_from_state(const cmc_state &s, const Workspace &w, hipStream_t st);
+hipError_t launch_sort_stage(const cmc_state &s, const Workspace &w, bool normalise_mass,
+                             hipStream_t st);
+hipError_t launch_init_plummer(const cmc_state &s, const Workspace &w, int64_t n,
+                               uint64_t seed, int mass_spectrum, hipStream_t st);
+hipError_t launch_diagnostics(const cmc_state &s, const Workspace &w, double *out,
+                              hipStream_t st);
+hipError_t launch_philox(uint64_t key, const uint32_t *ctr, uint32_t *out, int64_t n,
+                         hipStream_t st);
+
+}  // namespace cmc

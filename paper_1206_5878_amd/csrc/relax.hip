@@ -1,0 +1,348 @@
+// relax.hip -- shared timestep and two-body relaxation (arXiv:1206.5878,
+// Sec. 2.1 steps 2-3, Sec. 3.2 bins).  Neighbour pairs (2p, 2p+1); local
+// number density from the pair's 20-star radial bin; representative-encounter
+// time t_p = (pi/32) w^3 / (lnL n_b (m1+m2)^2); deflection
+// beta = min(pi, (pi/2) sqrt(dt/t_p)).  dt solves mean_p sin^2(beta_p/2) =
+// target by safeguarded Newton on x = ln dt, one grid-wide evaluation per
+// launch, finished by the last block to arrive.  One thread per pair.
+#include "cmc_internal.hpp"
+
+namespace cmc {
+namespace {
+
+constexpr int NT = kBlock;
+
+struct PairGeo {
+  double v1x, v1y, v2x, v2y, v2z, wx, wy, wz, wm, tp, u2, ma, mb;
+};
+
+template <typename MT>
+__device__ __forceinline__ PairGeo pair_geometry(int64_t p, int64_t n,
+                                                 const double *__restrict__ r,
+                                                 const MT *__restrict__ m,
+                                                 const double *__restrict__ vr,
+                                                 const double *__restrict__ vt,
+                                                 const uint32_t *__restrict__ id,
+                                                 uint64_t seed, uint32_t step, double lnL) {
+  PairGeo g;
+  int64_t nbins = n / 20;
+  if (nbins < 1) nbins = 1;
+  const int64_t a = 2 * p, b = a + 1;
+  int64_t bin = a / 20;
+  if (bin > nbins - 1) bin = nbins - 1;
+  const int64_t lo = 20 * bin;
+  const int64_t hi = (bin == nbins - 1) ? n - 1 : 20 * bin + 19;
+  const double rl = r[lo], rh = r[hi];
+  const double vol = (4.0 * kPi / 3.0) * (rh - rl) * (rh * rh + rh * rl + rl * rl);
+  const double nb = vol > 0.0 ? static_cast<double>(hi - lo) / vol : kInf;
+
+  const U4 w = philox(id[a], step, kRelax, 0u, seed);
+  const double u1 = u01(w.y, w.x);
+  g.u2 = u01(w.w, w.z);
+  const double psi = 2.0 * kPi * u1;
+  const double cp = cos(psi), sp = sin(psi);
+  g.v1x = vr[a];
+  g.v1y = vt[a];
+  g.v2x = vr[b];
+  g.v2y = vt[b] * cp;
+  g.v2z = vt[b] * sp;
+  g.wx = g.v1x - g.v2x;
+  g.wy = g.v1y - g.v2y;
+  g.wz = 0.0 - g.v2z;
+  g.wm = sqrt(g.wx * g.wx + g.wy * g.wy + g.wz * g.wz);
+  g.ma = load_mass(m, a);
+  g.mb = load_mass(m, b);
+  const double ms = g.ma + g.mb;
+  if (ms == 0.0 || lnL == 0.0)
+    g.tp = kInf;
+  else if (isinf(nb))
+    g.tp = 0.0;
+  else
+    g.tp = (kPi / 32.0) * (g.wm * g.wm * g.wm) / (lnL * nb * (ms * ms));
+  return g;
+}
+
+__device__ __forceinline__ double coulomb_log(double gamma, int64_t n) {
+  const double l = log(gamma * static_cast<double>(n));
+  return l > 0.0 ? l : 0.0;
+}
+
+__device__ __forceinline__ double beta_of(double tp, double dt) {
+  if (!(dt > 0.0) || isinf(tp)) return 0.0;
+  if (tp == 0.0) return kPi;
+  const double b = 0.5 * kPi * sqrt(dt / tp);
+  return b < kPi ? b : kPi;
+}
+
+// Loads of values written by other blocks of the same launch, past L1.
+__device__ __forceinline__ double ld_coherent(const double *p) {
+  const uint64_t u = __hip_atomic_load(reinterpret_cast<const uint64_t *>(p),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __builtin_bit_cast(double, u);
+}
+
+// ---------------------------------------------------------------- timestep
+// dt_state slots
+enum { kX = 0, kLo, kHi, kDone, kIt, kCnt, kZero, kInfN, kLogSum };
+
+template <typename MT>
+__global__ __launch_bounds__(NT) void k_pair_tp(const double *__restrict__ r,
+                                                const MT *__restrict__ m,
+                                                const double *__restrict__ vr,
+                                                const double *__restrict__ vt,
+                                                const uint32_t *__restrict__ id,
+                                                const cmc_scalars *__restrict__ sc,
+                                                double *__restrict__ tp_out,
+                                                double *__restrict__ part, uint64_t seed,
+                                                uint32_t step, double gamma) {
+  __shared__ double sh[NT / 64];
+  const int64_t n = sc->n;
+  const int64_t np = n / 2;
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  double cnt = 0.0, nz = 0.0, ni = 0.0, ls = 0.0;
+  if (p < np) {
+    const PairGeo g = pair_geometry(p, n, r, m, vr, vt, id, seed, step, coulomb_log(gamma, n));
+    if (g.wm > 0.0) {
+      tp_out[p] = g.tp;
+      cnt = 1.0;
+      if (g.tp == 0.0)
+        nz = 1.0;
+      else if (isinf(g.tp))
+        ni = 1.0;
+      else
+        ls = log(g.tp);
+    } else {
+      tp_out[p] = -1.0;  // no relative motion: not counted
+    }
+  }
+  cnt = block_sum<NT>(cnt, sh);
+  nz = block_sum<NT>(nz, sh);
+  ni = block_sum<NT>(ni, sh);
+  ls = block_sum<NT>(ls, sh);
+  if (threadIdx.x == 0) {
+    part[4 * blockIdx.x + 0] = cnt;
+    part[4 * blockIdx.x + 1] = nz;
+    part[4 * blockIdx.x + 2] = ni;
+    part[4 * blockIdx.x + 3] = ls;
+  }
+}
+
+constexpr int IT = 1024;
+
+// Reduce the pair counts, detect the degenerate cases, pick the start point.
+__global__ __launch_bounds__(IT) void k_dt_init(const double *__restrict__ part,
+                                                int64_t nblocks, double *__restrict__ st,
+                                                uint32_t *__restrict__ ticket,
+                                                cmc_scalars *__restrict__ sc, double target) {
+  __shared__ double sh[IT / 64];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t b = threadIdx.x; b < nblocks; b += IT)
+    for (int q = 0; q < 4; ++q) v[q] += part[4 * b + q];
+  for (int q = 0; q < 4; ++q) v[q] = block_sum<IT>(v[q], sh);
+  if (threadIdx.x == 0) {
+    const double cnt = v[0], nz = v[1], ni = v[2], ls = v[3];
+    ticket[0] = 0u;
+    st[kCnt] = cnt;
+    st[kZero] = nz;
+    st[kInfN] = ni;
+    st[kIt] = 0.0;
+    st[kLo] = -kInf;
+    st[kHi] = kInf;
+    if (cnt == 0.0 || nz / cnt >= target || (cnt - ni) / cnt <= target) {
+      st[kDone] = 1.0;
+      st[kX] = -kInf;
+      sc->dt = 0.0;
+      sc->dt_iters = 0u;
+      atomicOr(&sc->status, CMC_ST_DT_DEGEN);
+      return;
+    }
+    double x;
+    if (sc->dt > 0.0) {
+      x = log(sc->dt);
+    } else {
+      // small angles: mean sin^2(beta/2) ~ (pi^2/16) dt <1/t_p>; use the
+      // geometric mean of the finite t_p for <1/t_p>^-1
+      const double nf = cnt - nz - ni;
+      x = log(16.0 * target / (kPi * kPi)) + (nf > 0.0 ? ls / nf : 0.0);
+    }
+    st[kX] = x;
+    st[kDone] = 0.0;
+  }
+}
+
+// One Newton evaluation of F(x) = mean sin^2(beta/2) and dF/dx over all pairs;
+// the last block to finish updates x.
+__global__ __launch_bounds__(NT) void k_dt_iter(const double *__restrict__ tp,
+                                                const cmc_scalars *__restrict__ scr,
+                                                cmc_scalars *__restrict__ sc,
+                                                double *__restrict__ part,
+                                                double *__restrict__ st,
+                                                uint32_t *__restrict__ ticket, double target,
+                                                int32_t last_iter) {
+  __shared__ double sh[NT / 64];
+  __shared__ uint32_t is_last;
+  if (st[kDone] != 0.0) return;
+  const int64_t np = scr->n / 2;
+  const double x = st[kX];
+  const double dt = exp(x);
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  double h = 0.0, d = 0.0;
+  if (p < np) {
+    const double t = tp[p];
+    if (t >= 0.0) {
+      const double b = beta_of(t, dt);
+      const double s = sin(0.5 * b);
+      h = s * s;
+      if (b < kPi) d = 0.25 * b * sin(b);
+    }
+  }
+  h = block_sum<NT>(h, sh);
+  d = block_sum<NT>(d, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x + 0] = h;
+    part[2 * blockIdx.x + 1] = d;
+    __threadfence();
+    const uint32_t tk = atomicAdd(ticket, 1u);
+    is_last = (tk == gridDim.x - 1) ? 1u : 0u;
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  double H = 0.0, D = 0.0;
+  for (int64_t b = threadIdx.x; b < gridDim.x; b += NT) {
+    H += ld_coherent(part + 2 * b);
+    D += ld_coherent(part + 2 * b + 1);
+  }
+  H = block_sum<NT>(H, sh);
+  D = block_sum<NT>(D, sh);
+  if (threadIdx.x != 0) return;
+  ticket[0] = 0u;
+  const double cnt = st[kCnt];
+  const double F = H / cnt, Fp = D / cnt;
+  double lo = st[kLo], hi = st[kHi];
+  if (F < target)
+    lo = x;
+  else
+    hi = x;
+  bool conv = (F == target);
+  double xn = x;
+  if (!conv) {
+    // Newton on G(x) = ln F - ln target, dG/dx = F'/F
+    xn = (F > 0.0 && Fp > 0.0) ? x - log(F / target) * F / Fp : __builtin_nan("");
+    const bool closed = isfinite(lo) && isfinite(hi);
+    if (!(xn > lo && xn < hi) || (!closed && fabs(xn - x) > 16.0)) {
+      if (closed)
+        xn = 0.5 * (lo + hi);
+      else
+        xn = (F < target) ? x + 8.0 : x - 8.0;
+    }
+    if (fabs(xn - x) <= 1e-14 * fmax(1.0, fabs(x))) conv = true;
+    if (closed && hi - lo <= 1e-15 * fmax(1.0, fabs(x))) conv = true;
+  }
+  const double it = st[kIt] + 1.0;
+  st[kIt] = it;
+  st[kLo] = lo;
+  st[kHi] = hi;
+  st[kX] = xn;
+  st[kDone] = conv ? 1.0 : 0.0;
+  sc->dt = exp(xn);
+  sc->dt_iters = static_cast<uint32_t>(it);
+  if (!conv && last_iter) atomicOr(&sc->status, CMC_ST_DT_NOCONV);
+}
+
+// ---------------------------------------------------------------- kicks
+template <typename MT>
+__global__ __launch_bounds__(NT) void k_relax(const double *__restrict__ r,
+                                              const MT *__restrict__ m,
+                                              double *__restrict__ vr,
+                                              double *__restrict__ vt,
+                                              const uint32_t *__restrict__ id,
+                                              const cmc_scalars *__restrict__ sc,
+                                              uint64_t seed, uint32_t step, double gamma) {
+  const int64_t n = sc->n;
+  const int64_t np = n / 2;
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  if (p >= np) return;
+  const double dt = sc->dt;
+  const PairGeo g = pair_geometry(p, n, r, m, vr, vt, id, seed, step, coulomb_log(gamma, n));
+  const double beta = beta_of(g.tp, dt);
+  if (!(g.wm > 0.0) || beta == 0.0) return;
+  const int64_t a = 2 * p, b = a + 1;
+
+  const double e1x = g.wx / g.wm, e1y = g.wy / g.wm, e1z = g.wz / g.wm;
+  const double ax = fabs(g.wx), ay = fabs(g.wy), az = fabs(g.wz);
+  double cx, cy, cz;  // e1 x (axis of the smallest |w| component)
+  if (ax <= ay && ax <= az) {
+    cx = 0.0;
+    cy = e1z;
+    cz = -e1y;
+  } else if (ay <= az) {
+    cx = -e1z;
+    cy = 0.0;
+    cz = e1x;
+  } else {
+    cx = e1y;
+    cy = -e1x;
+    cz = 0.0;
+  }
+  const double cn = sqrt(cx * cx + cy * cy + cz * cz);
+  const double e2x = cx / cn, e2y = cy / cn, e2z = cz / cn;
+  const double e3x = e1y * e2z - e1z * e2y;
+  const double e3y = e1z * e2x - e1x * e2z;
+  const double e3z = e1x * e2y - e1y * e2x;
+  const double psi2 = 2.0 * kPi * g.u2;
+  const double cb = cos(beta), sb = sin(beta), c2 = cos(psi2), s2 = sin(psi2);
+  const double wnx = g.wm * (cb * e1x + sb * (c2 * e2x + s2 * e3x));
+  const double wny = g.wm * (cb * e1y + sb * (c2 * e2y + s2 * e3y));
+  const double wnz = g.wm * (cb * e1z + sb * (c2 * e2z + s2 * e3z));
+  const double ms = g.ma + g.mb;
+  const double fa = g.ma / ms, fb = g.mb / ms;
+  const double cmx = fa * g.v1x + fb * g.v2x;
+  const double cmy = fa * g.v1y + fb * g.v2y;
+  const double cmz = fa * 0.0 + fb * g.v2z;
+  const double n1x = cmx + fb * wnx, n1y = cmy + fb * wny, n1z = cmz + fb * wnz;
+  const double n2x = cmx - fa * wnx, n2y = cmy - fa * wny, n2z = cmz - fa * wnz;
+  vr[a] = n1x;
+  vt[a] = hypot(n1y, n1z);
+  vr[b] = n2x;
+  vt[b] = hypot(n2y, n2z);
+}
+
+template <typename MT>
+hipError_t run_timestep(const cmc_state &s, const Workspace &w, const cmc_params &p,
+                        hipStream_t st) {
+  const MT *m = static_cast<const MT *>(s.m);
+  const unsigned pb = static_cast<unsigned>(w.pair_blocks);
+  k_pair_tp<MT><<<pb, NT, 0, st>>>(s.r, m, s.vr, s.vt, s.id, s.sc, w.pair_tp, w.pair_part,
+                                   p.seed, p.step, p.gamma);
+  k_dt_init<<<1, IT, 0, st>>>(w.pair_part, w.pair_blocks, w.dt_state, w.dt_ticket, s.sc,
+                              p.target);
+  const int iters = p.dt_iters > 0 ? p.dt_iters : 24;
+  for (int i = 0; i < iters; ++i)
+    k_dt_iter<<<pb, NT, 0, st>>>(w.pair_tp, s.sc, s.sc, w.red_part, w.dt_state, w.dt_ticket,
+                                 p.target, i == iters - 1 ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <typename MT>
+hipError_t run_relax(const cmc_state &s, const Workspace &w, const cmc_params &p,
+                     hipStream_t st) {
+  const MT *m = static_cast<const MT *>(s.m);
+  k_relax<MT><<<static_cast<unsigned>(w.pair_blocks), NT, 0, st>>>(
+      s.r, m, s.vr, s.vt, s.id, s.sc, p.seed, p.step, p.gamma);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_timestep(const cmc_state &s, const Workspace &w, const cmc_params &p,
+                           hipStream_t st) {
+  return s.m_f32 ? run_timestep<float>(s, w, p, st) : run_timestep<double>(s, w, p, st);
+}
+
+hipError_t launch_relax(const cmc_state &s, const Workspace &w, const cmc_params &p,
+                        hipStream_t st) {
+  return s.m_f32 ? run_relax<float>(s, w, p, st) : run_relax<double>(s, w, p, st);
+}
+
+}  // namespace cmc

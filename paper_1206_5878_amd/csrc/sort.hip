@@ -1,0 +1,304 @@
+// sort.hip -- radial sort (arXiv:1206.5878, Sec. 2.1 step 6), replacing the
+// paper's Quicksort / sample sort by a stable LSD radix sort on gfx950.
+//
+// Key of a star: the bit pattern of r_new + 0.0 as an unsigned integer, which
+// orders non-negative radii (and +inf) numerically.  Keys are compressed to
+// key - min_key over the finite keys, non-finite keys (escapers) map to
+// range + 1, so only ceil(bits(range + 1) / 8) digit passes run.  Each pass:
+// per-tile digit histograms in LDS, a per-digit scan over tiles, and a
+// scatter in which every wavefront ranks its keys with 8 ballots per slot
+// (stable: tile order = wave, slot, lane = input order).  Values are the
+// star's index in the staged records; a final gather writes the SoA arrays.
+#include "cmc_internal.hpp"
+
+namespace cmc {
+namespace {
+
+constexpr int NT = kBlock;           // 4 waves
+constexpr int SLOTS = kSortTile / NT;  // 16 keys per thread
+constexpr uint64_t kInfKey = 0x7FF0000000000000ull;
+
+// pass_info as uint64 slots
+enum { kNTotal = 0, kNKept, kPasses, kMinKey, kMaxKey, kNonFin, kEscKey };
+
+__device__ __forceinline__ uint64_t radius_key(double x) {
+  return __builtin_bit_cast(uint64_t, x + 0.0);
+}
+
+__global__ void k_sort_prep(const cmc_scalars *__restrict__ sc, uint64_t *__restrict__ pi) {
+  pi[kNTotal] = static_cast<uint64_t>(sc->n);
+  pi[kMinKey] = ~0ull;
+  pi[kMaxKey] = 0ull;
+  pi[kNonFin] = 0ull;
+}
+
+__global__ __launch_bounds__(NT) void k_stage_from_state(
+    const double *__restrict__ r_new, const double *__restrict__ vr,
+    const double *__restrict__ vt, const void *__restrict__ m, int32_t m_f32,
+    const uint32_t *__restrict__ id, const cmc_scalars *__restrict__ sc,
+    StageRec *__restrict__ stage, uint64_t *__restrict__ keys) {
+  const int64_t n = sc->n;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  if (i >= n) return;
+  StageRec rec;
+  rec.r = r_new[i];
+  rec.vr = vr[i];
+  rec.vt = vt[i];
+  rec.m = m_f32 ? static_cast<double>(static_cast<const float *>(m)[i])
+                : static_cast<const double *>(m)[i];
+  rec.id = id[i];
+  rec.pad = 0u;
+  stage[i] = rec;
+  keys[i] = radius_key(rec.r);
+}
+
+__global__ __launch_bounds__(NT) void k_key_range(const uint64_t *__restrict__ keys,
+                                                  uint64_t *__restrict__ pi) {
+  __shared__ uint64_t smin[NT / 64], smax[NT / 64];
+  __shared__ uint32_t snf[NT / 64];
+  const int64_t n = static_cast<int64_t>(pi[kNTotal]);
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kSortTile;
+  uint64_t lo = ~0ull, hi = 0ull;
+  uint32_t nf = 0;
+  for (int j = 0; j < SLOTS; ++j) {
+    const int64_t k = base + j * NT + threadIdx.x;
+    if (k < n) {
+      const uint64_t x = keys[k];
+      if (x < kInfKey) {
+        lo = x < lo ? x : lo;
+        hi = x > hi ? x : hi;
+      } else {
+        ++nf;
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t a = __shfl_xor(lo, o, 64), b = __shfl_xor(hi, o, 64);
+    lo = a < lo ? a : lo;
+    hi = b > hi ? b : hi;
+    nf += __shfl_xor(nf, o, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    smin[w] = lo;
+    smax[w] = hi;
+    snf[w] = nf;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < NT / 64; ++q) {
+      lo = smin[q] < lo ? smin[q] : lo;
+      hi = smax[q] > hi ? smax[q] : hi;
+      nf += snf[q];
+    }
+    if (lo != ~0ull) atomicMin(reinterpret_cast<unsigned long long *>(pi + kMinKey), lo);
+    if (hi != 0ull) atomicMax(reinterpret_cast<unsigned long long *>(pi + kMaxKey), hi);
+    if (nf) atomicAdd(reinterpret_cast<unsigned long long *>(pi + kNonFin), nf);
+  }
+}
+
+__global__ void k_plan(uint64_t *__restrict__ pi, cmc_scalars *__restrict__ sc) {
+  const uint64_t n = pi[kNTotal], nf = pi[kNonFin];
+  const uint64_t kept = n - nf;
+  const uint64_t lo = pi[kMinKey], hi = pi[kMaxKey];
+  const uint64_t range = kept ? hi - lo : 0ull;
+  const uint64_t esc = range + 1ull;
+  const uint64_t top = nf ? esc : range;
+  int bits = 0;
+  while (bits < 64 && (top >> bits) != 0ull) ++bits;
+  pi[kPasses] = (n <= 1) ? 0ull : static_cast<uint64_t>((bits + 7) / 8);
+  pi[kNKept] = kept;
+  pi[kEscKey] = esc;
+  if (!kept) pi[kMinKey] = 0ull;
+  sc->n = static_cast<int64_t>(kept);
+}
+
+// key of item k for pass 0 (compression applied) or a later pass
+__device__ __forceinline__ uint64_t pass_key(const uint64_t *__restrict__ in, int64_t k,
+                                             bool first, uint64_t kmin, uint64_t esc) {
+  const uint64_t x = in[k];
+  if (!first) return x;
+  return x < kInfKey ? x - kmin : esc;
+}
+
+__global__ __launch_bounds__(NT) void k_upsweep(const uint64_t *keys0, const uint64_t *keys1,
+                                                const uint64_t *__restrict__ pi, int pass,
+                                                uint32_t *__restrict__ tile_hist,
+                                                int64_t tiles) {
+  __shared__ uint32_t hist[256];
+  if (static_cast<uint64_t>(pass) >= pi[kPasses]) return;
+  const int64_t n = static_cast<int64_t>(pi[kNTotal]);
+  const uint64_t *in = (pass & 1) ? keys1 : keys0;
+  const uint64_t kmin = pi[kMinKey], esc = pi[kEscKey];
+  const int shift = 8 * pass;
+  hist[threadIdx.x] = 0u;
+  __syncthreads();
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kSortTile;
+  for (int j = 0; j < SLOTS; ++j) {
+    const int64_t k = base + j * NT + threadIdx.x;
+    if (k < n) {
+      const uint32_t d = static_cast<uint32_t>(pass_key(in, k, pass == 0, kmin, esc) >> shift) & 255u;
+      atomicAdd(&hist[d], 1u);
+    }
+  }
+  __syncthreads();
+  tile_hist[static_cast<int64_t>(threadIdx.x) * tiles + blockIdx.x] = hist[threadIdx.x];
+}
+
+// Block d: exclusive scan of digit d's counts over tiles; total in digit_tot[d].
+__global__ __launch_bounds__(NT) void k_scan_digits(const uint32_t *__restrict__ tile_hist,
+                                                    const uint64_t *__restrict__ pi, int pass,
+                                                    uint32_t *__restrict__ tile_off,
+                                                    uint32_t *__restrict__ digit_tot,
+                                                    int64_t tiles) {
+  __shared__ uint32_t sh[NT / 64];
+  if (static_cast<uint64_t>(pass) >= pi[kPasses]) return;
+  const int64_t d = blockIdx.x;
+  const uint32_t *h = tile_hist + d * tiles;
+  uint32_t *o = tile_off + d * tiles;
+  uint32_t carry = 0u;
+  for (int64_t t0 = 0; t0 < tiles; t0 += NT) {
+    const int64_t t = t0 + threadIdx.x;
+    const uint32_t v = t < tiles ? h[t] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<NT>(v, sh, &tot);
+    if (t < tiles) o[t] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) digit_tot[d] = carry;
+}
+
+// The in and out buffers of a pass are the two halves of one ping-pong pair,
+// so they carry no restrict qualifier.
+__global__ __launch_bounds__(NT) void k_downsweep(
+    const uint64_t *keys0, const uint64_t *keys1, const uint32_t *vals0, const uint32_t *vals1,
+    uint64_t *okeys0, uint64_t *okeys1, uint32_t *ovals0, uint32_t *ovals1,
+    const uint64_t *__restrict__ pi, int pass,
+    const uint32_t *__restrict__ tile_off, const uint32_t *__restrict__ digit_tot,
+    int64_t tiles) {
+  __shared__ uint32_t cnt[NT / 64][256];
+  __shared__ uint32_t gbase[NT / 64][256];
+  __shared__ uint32_t sh[NT / 64];
+  const uint64_t passes = pi[kPasses];
+  if (static_cast<uint64_t>(pass) >= passes) return;
+  const int64_t n = static_cast<int64_t>(pi[kNTotal]);
+  const uint64_t *in = (pass & 1) ? keys1 : keys0;
+  const uint32_t *vin = (pass & 1) ? vals1 : vals0;
+  uint64_t *out = (pass & 1) ? okeys0 : okeys1;
+  uint32_t *vout = (pass & 1) ? ovals0 : ovals1;
+  const bool first = pass == 0, last = static_cast<uint64_t>(pass) + 1 == passes;
+  const uint64_t kmin = pi[kMinKey], esc = pi[kEscKey];
+  const int shift = 8 * pass;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+  for (int q = 0; q < NT / 64; ++q) cnt[q][threadIdx.x] = 0u;
+  __syncthreads();
+
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kSortTile + w * (SLOTS * 64);
+  uint64_t key[SLOTS];
+  uint32_t val[SLOTS], rank[SLOTS];
+  uint32_t dig[SLOTS];
+#pragma unroll
+  for (int j = 0; j < SLOTS; ++j) {
+    const int64_t k = base + j * 64 + lane;
+    const bool ok = k < n;
+    key[j] = ok ? pass_key(in, k, first, kmin, esc) : 0ull;
+    val[j] = ok ? (first ? static_cast<uint32_t>(k) : vin[k]) : 0u;
+    const uint32_t d = static_cast<uint32_t>(key[j] >> shift) & 255u;
+    dig[j] = ok ? d : 256u;
+    // peers: valid lanes of this slot with the same digit
+    uint64_t peers = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t bal = __ballot((d >> b) & 1u);
+      peers &= ((d >> b) & 1u) ? bal : ~bal;
+    }
+    uint32_t before = 0u;
+    if (ok) before = cnt[w][d];
+    const uint32_t rk = static_cast<uint32_t>(__popcll(peers & lt));
+    rank[j] = before + rk;
+    __builtin_amdgcn_wave_barrier();
+    if (ok && (peers & lt) == 0ull) cnt[w][d] = before + static_cast<uint32_t>(__popcll(peers));
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  // digit bases: global digit offset + this tile's offset + earlier waves
+  {
+    const uint32_t d = threadIdx.x;
+    const uint32_t dbase = block_excl_scan<NT>(digit_tot[d], sh, static_cast<uint32_t *>(nullptr));
+    uint32_t acc = dbase + tile_off[static_cast<int64_t>(d) * tiles + blockIdx.x];
+    for (int q = 0; q < NT / 64; ++q) {
+      gbase[q][d] = acc;
+      acc += cnt[q][d];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < SLOTS; ++j) {
+    if (dig[j] < 256u) {
+      const uint32_t dst = gbase[w][dig[j]] + rank[j];
+      if (!last) out[dst] = key[j];
+      vout[dst] = val[j];
+    }
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_gather(const StageRec *__restrict__ stage,
+                                               const uint32_t *__restrict__ vals0,
+                                               const uint32_t *__restrict__ vals1,
+                                               const uint64_t *__restrict__ pi,
+                                               const cmc_scalars *__restrict__ sc,
+                                               int normalise, double *__restrict__ r,
+                                               double *__restrict__ vr,
+                                               double *__restrict__ vt, void *__restrict__ m,
+                                               int32_t m_f32, uint32_t *__restrict__ id) {
+  const int64_t kept = static_cast<int64_t>(pi[kNKept]);
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  if (p >= kept) return;
+  const uint32_t *vals = (pi[kPasses] & 1ull) ? vals1 : vals0;
+  const uint32_t src = pi[kPasses] ? vals[p] : static_cast<uint32_t>(p);
+  const StageRec rec = stage[src];
+  r[p] = rec.r;
+  vr[p] = rec.vr;
+  vt[p] = rec.vt;
+  const double mm = normalise ? rec.m / sc->mass_norm : rec.m;
+  if (m_f32)
+    static_cast<float *>(m)[p] = static_cast<float>(mm);
+  else
+    static_cast<double *>(m)[p] = mm;
+  id[p] = rec.id;
+}
+
+}  // namespace
+
+hipError_t launch_stage_from_state(const cmc_state &s, const Workspace &w, hipStream_t st) {
+  k_stage_from_state<<<static_cast<unsigned>(w.star_blocks), NT, 0, st>>>(
+      s.r_new, s.vr, s.vt, s.m, s.m_f32, s.id, s.sc, w.stage, w.keys[0]);
+  return hipGetLastError();
+}
+
+// Sort the staged records by keys[0] (n = sc->n on entry) into the state.
+hipError_t launch_sort_stage(const cmc_state &s, const Workspace &w, bool normalise_mass,
+                             hipStream_t st) {
+  uint64_t *pi = reinterpret_cast<uint64_t *>(w.pass_info);
+  const unsigned tiles = static_cast<unsigned>(w.sort_tiles);
+  k_sort_prep<<<1, 1, 0, st>>>(s.sc, pi);
+  k_key_range<<<tiles, NT, 0, st>>>(w.keys[0], pi);
+  k_plan<<<1, 1, 0, st>>>(pi, s.sc);
+  for (int pass = 0; pass < 8; ++pass) {
+    k_upsweep<<<tiles, NT, 0, st>>>(w.keys[0], w.keys[1], pi, pass, w.tile_hist, w.sort_tiles);
+    k_scan_digits<<<256, NT, 0, st>>>(w.tile_hist, pi, pass, w.tile_off, w.hist_all,
+                                      w.sort_tiles);
+    k_downsweep<<<tiles, NT, 0, st>>>(w.keys[0], w.keys[1], w.vals[0], w.vals[1], w.keys[0],
+                                      w.keys[1], w.vals[0], w.vals[1], pi, pass, w.tile_off,
+                                      w.hist_all, w.sort_tiles);
+  }
+  k_gather<<<static_cast<unsigned>(w.star_blocks), NT, 0, st>>>(
+      w.stage, w.vals[0], w.vals[1], pi, s.sc, normalise_mass ? 1 : 0, s.r, s.vr, s.vt, s.m,
+      s.m_f32, s.id);
+  return hipGetLastError();
+}
+
+}  // namespace cmc

@@ -1,0 +1,68 @@
+"""The C-ABI library loads on the CPU and exports every call include/cmc.h
+declares; the host-side argument checks reject bad input without a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    text = open(os.path.join(ROOT, "include", "cmc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cmc_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_call():
+    from paper_1206_5878_amd import _capi as A
+    L = A.lib()
+    names = declared()
+    assert "cmc_step" in names and len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(A.EXPORTS) == set(names)
+    assert L.cmc_abi_version() == 1
+
+
+def test_host_side_checks_without_gpu():
+    from paper_1206_5878_amd import _capi as A
+    L = A.lib()
+    assert L.cmc_workspace_bytes(0) == 0
+    assert L.cmc_workspace_bytes(1000) > 1000 * 64
+    assert L.cmc_workspace_bytes(2**32) == 0
+    s = A.cmc_state()  # all null pointers
+    s.cap = 100
+    p = A.cmc_params(1, 0, A.CMC_FP64, 0.11, 0.03, 1.2, 10000, 0)
+    assert L.cmc_step(C.byref(s), C.byref(p), None) == A.CMC_EINVAL
+    assert L.cmc_sort(C.byref(s), None) == A.CMC_EINVAL
+    assert L.cmc_potential(C.byref(s), 0, None) == A.CMC_EINVAL
+    assert L.cmc_init_plummer(None, 10, 1, 0, None) == A.CMC_EINVAL
+    assert L.cmc_philox(1, None, None, 5, None) == A.CMC_EINVAL
+    assert L.cmc_philox(1, None, None, 0, None) == A.CMC_OK
+    # a fake, aligned, too-small workspace is caught before anything runs
+    fake = 1 << 20
+    s = A.cmc_state(100, fake, fake, fake, fake, 0, 0, fake, fake, fake, fake, fake, fake,
+                    fake, 10)
+    assert L.cmc_sort(C.byref(s), None) == A.CMC_EWORKSPACE
+    s.work_bytes = L.cmc_workspace_bytes(100)
+    s.work = fake + 8  # misaligned
+    assert L.cmc_sort(C.byref(s), None) == A.CMC_EINVAL
+    s.work = fake
+    bad = A.cmc_params(1, 0, 7, 0.11, 0.03, 1.2, 10000, 0)
+    assert L.cmc_step(C.byref(s), C.byref(bad), None) == A.CMC_EINVAL
+    bad = A.cmc_params(1, 0, 0, 0.11, 1.5, 1.2, 10000, 0)
+    assert L.cmc_timestep(C.byref(s), C.byref(bad), None) == A.CMC_EINVAL
+    assert L.cmc_init_plummer(C.byref(s), 101, 1, 0, None) == A.CMC_ERANGE
+    assert L.cmc_init_plummer(C.byref(s), 10, 1, 3, None) == A.CMC_EINVAL
+    assert b"workspace" in L.cmc_strerror(A.CMC_EWORKSPACE)
+
+
+def test_product_does_not_import_oracle():
+    pkg = os.path.join(ROOT, "paper_1206_5878_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in text.replace("the oracle", ""), f

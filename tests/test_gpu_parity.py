@@ -1,0 +1,280 @@
+"""GPU parity: every C-ABI call against the FP64 oracle on the same seeded
+inputs, element by element.  Bit-exact for integer work (Philox words, the
+sort permutation, ids); for doubles |gpu - oracle| <= TOL * max(|oracle|, s)
+with s the natural scale of the quantity (see each test)."""
+import numpy as np
+import pytest
+
+import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def cmc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    import paper_1206_5878_amd as P
+    P.lib()
+    return P
+
+
+def rel(a, b, scale=0.0):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    den = np.maximum(np.abs(b), scale)
+    den = np.where(den > 0, den, 1.0)
+    return np.max(np.abs(a - b) / den) if a.size else 0.0
+
+
+def upload(cmc, st, cap=None, m_f32=False):
+    cl = cmc.Cluster(cap or max(st.n, 1), m_f32=m_f32)
+    cl.load(st.r, st.vr, st.vt, st.m, st.id)
+    return cl
+
+
+def gstate(ora, n, seed, **kw):
+    return ora.State(*inputs.generic_state(n, seed, **kw))
+
+
+# ---------------------------------------------------------------- Philox
+def test_philox_words_bitexact(cmc, ora):
+    g = np.random.default_rng(1)
+    ctr = g.integers(0, 2**32, size=(300_000, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:1000, 1:] = 0  # small counters as used by the method
+    for key in (0, 1, 2**64 - 1, 12345678901234567):
+        assert np.array_equal(cmc.cmc_philox(key, ctr), ora.philox(key, ctr))
+
+
+# ---------------------------------------------------------------- init
+@pytest.mark.parametrize("n,seed,ms", [(10_000, 1, 0), (10_007, 3, 1), (1, 2, 0), (2, 5, 1),
+                                       (4097, 9, 0)])
+def test_init_plummer(cmc, ora, n, seed, ms):
+    cl = cmc.Cluster(n + 13)
+    cmc.cmc_init_plummer(cl, n, seed, ms)
+    h = cl.host()
+    ref = ora.plummer(n, seed, ms)
+    assert cl.n == n
+    assert np.array_equal(h["id"], ref.id)
+    assert rel(h["r"], ref.r) < TOL
+    vs = np.hypot(ref.vr, ref.vt)
+    assert rel(h["vr"], ref.vr, vs.max()) < TOL
+    assert rel(h["vt"], ref.vt, vs.max()) < TOL
+    assert rel(h["m"], ref.m) < TOL
+    assert cl.scalars()["status"] == 0
+
+
+def test_init_plummer_f32_masses(cmc, ora):
+    n = 20_000
+    cl = cmc.Cluster(n, m_f32=True)
+    cmc.cmc_init_plummer(cl, n, 4, 1)
+    h = cl.host()
+    ref = ora.plummer(n, 4, 1)
+    assert np.array_equal(h["id"], ref.id)
+    assert np.array_equal(h["m"].astype(np.float32), ref.m.astype(np.float32))
+
+
+# ---------------------------------------------------------------- sort
+@pytest.mark.parametrize("n,seed,ties,ninf", [(1, 1, 0, 0), (2, 2, 1, 0), (4095, 3, 50, 3),
+                                              (4096, 4, 0, 0), (4097, 5, 400, 7),
+                                              (100_003, 6, 5000, 40), (20_000, 7, 0, 20_000)])
+def test_sort_permutation_bitexact(cmc, ora, n, seed, ties, ninf):
+    key = inputs.random_keys(n, seed, ties=ties, n_inf=ninf)
+    g = np.random.default_rng(seed)
+    st = ora.State(np.sort(g.random(n)), g.normal(size=n), np.abs(g.normal(size=n)),
+                   g.random(n), np.arange(n, dtype=np.uint32))
+    cl = upload(cmc, st, cap=n + 5)
+    import torch
+    cl.r_new[:n] = torch.as_tensor(key, device="cuda")
+    cmc.cmc_sort(cl)
+    perm = ora.sort_perm(key)
+    kept = int(np.sum(np.isfinite(key)))
+    assert cl.n == kept
+    h = cl.host()
+    assert np.array_equal(h["id"], perm[:kept].astype(np.uint32))
+    assert np.array_equal(h["r"], key[perm[:kept]])
+    assert np.array_equal(h["vr"], st.vr[perm[:kept]])
+    assert np.array_equal(h["m"], st.m[perm[:kept]])
+
+
+def test_sort_all_equal_keys(cmc, ora):
+    n = 9000
+    st = gstate(ora, n, 3)
+    cl = upload(cmc, st)
+    import torch
+    cl.r_new[:n] = 0.75
+    cmc.cmc_sort(cl)
+    assert np.array_equal(cl.host()["id"], st.id)
+
+
+# ---------------------------------------------------------------- potential
+@pytest.mark.parametrize("n,seed,kw", [(1, 1, {}), (2, 2, {}), (3, 3, {"massless": 0.5}),
+                                       (2047, 4, {}), (2048, 5, {"ties": 100}),
+                                       (2049, 6, {"massless": 0.1}), (100_003, 7, {"ties": 999})])
+def test_potential(cmc, ora, n, seed, kw):
+    st = gstate(ora, n, seed, **kw)
+    cl = upload(cmc, st, cap=n + 100)
+    cmc.cmc_potential(cl)
+    h = cl.host()
+    phi, mcum, ssuf = ora.potential(st.r, st.m)
+    assert rel(h["phi"], phi) < TOL
+    assert rel(h["mcum"], mcum, 1e-300) < TOL
+    assert rel(h["ssuf"], ssuf, np.abs(phi).max() * 1e-3) < TOL
+
+
+def test_potential_plummer_f32_masses(cmc, ora):
+    st = ora.plummer(50_000, 2, 1)
+    st.m = st.m.astype(np.float32).astype(np.float64)
+    cl = upload(cmc, st, m_f32=True)
+    cmc.cmc_potential(cl)
+    phi, mcum, _ = ora.potential(st.r, st.m)
+    assert rel(cl.host()["phi"], phi) < TOL
+
+
+# ---------------------------------------------------------------- timestep
+@pytest.mark.parametrize("n,seed,gamma", [(10_000, 1, 0.11), (10_001, 2, 0.01),
+                                          (100_000, 3, 0.11), (41, 4, 0.11)])
+def test_timestep(cmc, ora, n, seed, gamma):
+    st = ora.plummer(n, seed)
+    cl = upload(cmc, st)
+    p = cmc.Params(seed=7, step=3, gamma=gamma)
+    cmc.cmc_timestep(cl, p)
+    s = cl.scalars()
+    dt, status = ora.timestep(st, 7, 3, gamma, 0.03)
+    assert status == 0 and s["status"] == 0, s
+    assert rel(s["dt"], dt) < TOL
+    assert 0 < s["dt_iters"] <= 24
+    # warm start from the previous dt converges in few iterations
+    cl.set_scalar("dt", dt * 1.01)
+    cmc.cmc_timestep(cl, p)
+    s2 = cl.scalars()
+    assert rel(s2["dt"], dt) < TOL and s2["dt_iters"] <= 6
+
+
+def test_timestep_degenerate(cmc, ora):
+    # one pair; all radii equal (zero-volume bins); no relative motion
+    for r, vr, vt in ((np.array([1.0]), np.array([0.1]), np.array([0.1])),
+                      (np.full(40, 1.0), np.linspace(-1, 1, 40), np.full(40, 0.3)),
+                      (np.linspace(1, 2, 40), np.full(40, 0.2), np.full(40, 0.3))):
+        n = len(r)
+        st = ora.State(r, vr, vt, np.full(n, 1.0 / n), np.arange(n, dtype=np.uint32))
+        cl = upload(cmc, st)
+        cmc.cmc_timestep(cl, cmc.Params())
+        s = cl.scalars()
+        dt, status = ora.timestep(st, 1, 0, 0.11, 0.03)
+        assert s["dt"] == dt == 0.0
+        assert s["status"] & cmc.ST_DT_DEGEN and status & ora.ST_DT_DEGEN
+
+
+# ---------------------------------------------------------------- relax
+@pytest.mark.parametrize("n,seed,kw", [(2, 1, {}), (3, 2, {}), (1001, 3, {"jzero": 0.1}),
+                                       (100_000, 4, {"massless": 0.01}),
+                                       (40_001, 5, {"ties": 400})])
+def test_relax(cmc, ora, n, seed, kw):
+    st = gstate(ora, n, seed, **kw)
+    w, tp, nb = ora.pair_terms(st, 11, 2, 0.11)
+    dt, _ = ora.solve_dt(w, tp, 0.03)
+    dt = dt if dt > 0 else 1e-3
+    cl = upload(cmc, st)
+    cl.set_scalar("dt", dt)
+    cmc.cmc_relax(cl, cmc.Params(seed=11, step=2))
+    h = cl.host()
+    ref = ora.relax(st, 11, 2, 0.11, dt)
+    # scale: the pair's speed
+    sp = np.hypot(st.vr, st.vt)
+    pair = np.maximum(sp[0::2][: n // 2], sp[1::2][: n // 2]) if n > 1 else np.zeros(0)
+    scale = np.zeros(n)
+    scale[: 2 * (n // 2)] = np.repeat(pair, 2)
+    if n % 2:
+        scale[-1] = sp[-1]
+    for k in ("vr", "vt"):
+        d = np.abs(h[k] - getattr(ref, k)) / np.maximum(np.maximum(np.abs(getattr(ref, k)), scale), 1e-300)
+        assert d.max() < TOL, (k, d.argmax())
+
+
+# ---------------------------------------------------------------- orbit
+def _orbit_case(cmc, ora, st, seed=5, step=1):
+    tab = ora.potential(st.r, st.m)
+    cl = upload(cmc, st)
+    import torch
+    n = st.n
+    for k, v in zip(("phi", "mcum", "ssuf"), tab):
+        getattr(cl, k)[:n] = torch.as_tensor(v, device="cuda")
+    cmc.cmc_orbit(cl, cmc.Params(seed=seed, step=step))
+    h = cl.host(n)
+    s = cl.scalars()
+    rn, vrn, vtn, so, d = ora.orbit(st, tab, seed, step, details=True)
+    return h, s, (rn, vrn, vtn, so, d), tab
+
+
+@pytest.mark.parametrize("n,seed", [(1, 1), (2, 2), (7, 3), (10_000, 4), (100_000, 5)])
+def test_orbit_plummer(cmc, ora, n, seed):
+    st = ora.plummer(n, seed)
+    if n > 10:
+        st.vr[n // 3] = 3.0  # an escaper
+    h, s, (rn, vrn, vtn, so, d), tab = _orbit_case(cmc, ora, st)
+    fin = np.isfinite(rn)
+    assert np.array_equal(np.isfinite(h["r_new"]), fin)
+    assert rel(h["r_new"][fin], rn[fin]) < TOL
+    # v_r is sqrt(Q): compare Q on its own scale
+    E, J = d["E"][fin], d["J"][fin]
+    qscale = 2 * np.abs(E) + 2 * np.abs(tab[0][fin]) + (J / np.maximum(rn[fin], 1e-300)) ** 2
+    assert np.max(np.abs(h["vr"][fin] ** 2 - vrn[fin] ** 2) / qscale) < TOL
+    assert np.array_equal(np.sign(h["vr"][fin]), np.sign(vrn[fin]))
+    assert rel(h["vt"][fin], vtn[fin], np.abs(vtn).max() * 1e-6) < TOL
+    assert s["n_esc"] == so["n_esc"] and s["trials"] == so["trials"]
+    assert s["violations"] == so["violations"] and s["capped"] == so["capped"]
+    assert rel(s["e_esc"], so["e_esc"], 1e-300) < 1e-10
+    assert (s["status"] & ~cmc.ST_ESCAPER & ~cmc.ST_BOUND) == 0
+
+
+@pytest.mark.parametrize("E,J", [(-0.5, 0.9), (-0.5, 0.0), (-0.2, 0.3)])
+def test_orbit_kepler(cmc, ora, E, J):
+    st = ora.State(*inputs.kepler_probes(30_000, E, J, 3))
+    h, s, (rn, vrn, vtn, so, d), tab = _orbit_case(cmc, ora, st)
+    assert rel(h["r_new"], rn) < TOL
+    assert s["trials"] == so["trials"] and s["violations"] == so["violations"]
+
+
+def test_orbit_generic_edge_cases(cmc, ora):
+    st = gstate(ora, 20_001, 8, ties=300, massless=0.05, jzero=0.05)
+    h, s, (rn, vrn, vtn, so, d), tab = _orbit_case(cmc, ora, st, seed=9, step=4)
+    fin = np.isfinite(rn)
+    assert np.array_equal(np.isfinite(h["r_new"]), fin)
+    assert rel(h["r_new"][fin], rn[fin]) < TOL
+    assert s["n_esc"] == so["n_esc"] and s["trials"] == so["trials"]
+
+
+# ---------------------------------------------------------------- whole step
+@pytest.mark.parametrize("n,gamma,ms,steps", [(10_000, 0.11, 0, 10), (4_001, 0.01, 1, 4)])
+def test_step_lockstep(cmc, ora, n, gamma, ms, steps):
+    """Each step starts both sides from the same (oracle) state."""
+    st = ora.plummer(n, 1, ms)
+    cl = cmc.Cluster(n)
+    for k in range(steps):
+        cl.load(st.r, st.vr, st.vt, st.m, st.id)
+        cl.set_scalar("dt", 0.0)
+        cmc.cmc_step(cl, cmc.Params(seed=1, step=k, gamma=gamma))
+        s = cl.scalars()
+        h = cl.host()
+        new, info = ora.step(st, 1, k, gamma)
+        assert rel(s["dt"], info["dt"]) < TOL
+        assert s["n"] == new.n
+        assert np.array_equal(h["id"], new.id), k
+        assert rel(h["r"], new.r) < TOL
+        vs = np.hypot(new.vr, new.vt).max()
+        assert rel(h["vt"], new.vt, vs * 1e-6) < TOL
+        assert np.max(np.abs(h["vr"] ** 2 - new.vr ** 2)) < TOL * 4 * vs**2
+        st = new
+
+
+def test_diagnostics(cmc, ora):
+    st = ora.plummer(30_000, 2)
+    cl = upload(cmc, st)
+    cmc.cmc_potential(cl)
+    d = cmc.cmc_diagnostics(cl)
+    ref = ora.diagnostics(st)
+    for k in ("T", "W", "E", "virial", "M", "r01", "r10", "r50", "r90"):
+        assert rel(d[k], ref[k]) < TOL, k
