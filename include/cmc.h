@@ -165,6 +165,11 @@ int cmc_orbit(cmc_state *s, const cmc_params *p, void *stream);
 /* One whole step: potential -> timestep -> relax -> orbit -> sort. */
 int cmc_step(cmc_state *s, const cmc_params *p, void *stream);
 
+/* cmc_step that also records events[0] on `stream` before the step and
+ * events[1..5] after its potential, timestep, relax, orbit and sort phases,
+ * for per-phase timing.  events: 6 hipEvent_t created by the caller. */
+int cmc_step_timed(cmc_state *s, const cmc_params *p, void *const *events, void *stream);
+
 /* Diagnostics of the sorted state and its table (needs cmc_potential):
  * out_dev[0..8] = T, W = sum m phi / 2, E = T + W, 2T/|W|, M, and the radii
  * holding 1%, 10%, 50%, 90% of the mass. */

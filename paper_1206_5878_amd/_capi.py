@@ -18,8 +18,8 @@ ST_NONFINITE, ST_TRIAL_CAP, ST_BOUND, ST_ESCAPER = 0x01, 0x02, 0x04, 0x08
 ST_DT_DEGEN, ST_NUMERIC, ST_DT_NOCONV = 0x10, 0x20, 0x40
 
 EXPORTS = ("cmc_workspace_bytes", "cmc_init_plummer", "cmc_sort", "cmc_potential",
-           "cmc_timestep", "cmc_relax", "cmc_orbit", "cmc_step", "cmc_diagnostics",
-           "cmc_philox", "cmc_strerror", "cmc_abi_version")
+           "cmc_timestep", "cmc_relax", "cmc_orbit", "cmc_step", "cmc_step_timed",
+           "cmc_diagnostics", "cmc_philox", "cmc_strerror", "cmc_abi_version")
 
 
 class cmc_scalars(C.Structure):
@@ -69,6 +69,7 @@ def lib() -> C.CDLL:
         L.cmc_potential.argtypes = [sp, C.c_int32, vp]
         for f in ("cmc_timestep", "cmc_relax", "cmc_orbit", "cmc_step"):
             getattr(L, f).argtypes = [sp, pp, vp]
+        L.cmc_step_timed.argtypes = [sp, pp, C.POINTER(C.c_void_p), vp]
         L.cmc_diagnostics.argtypes = [sp, vp, vp]
         L.cmc_philox.argtypes = [C.c_uint64, vp, vp, C.c_int64, vp]
         L.cmc_strerror.argtypes = [C.c_int]

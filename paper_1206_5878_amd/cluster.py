@@ -164,3 +164,11 @@ def cmc_philox(key: int, ctr: np.ndarray, device: str = "cuda", stream=None) -> 
     A.check(A.lib().cmc_philox(key, C.c_void_p(dc.data_ptr()), C.c_void_p(do.data_ptr()), n,
                                _stream(stream)), "cmc_philox")
     return do.cpu().numpy().view(np.uint32)
+
+
+def cmc_step_timed(cl: Cluster, p: Params, events, stream=None):
+    """cmc_step recording the six HIP events ``events`` (raw hipEvent_t
+    handles, see hipevents.EventSet) around its five phases."""
+    pc = p.c()
+    arr = (C.c_void_p * 6)(*events)
+    A.check(A.lib().cmc_step_timed(cl.c, C.byref(pc), arr, _stream(stream)), "cmc_step_timed")

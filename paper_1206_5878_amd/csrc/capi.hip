@@ -115,18 +115,38 @@ int cmc_orbit(cmc_state *s, const cmc_params *p, void *stream) {
   return status_of(cmc::launch_orbit(*s, w, *p, false, as_stream(stream)));
 }
 
-int cmc_step(cmc_state *s, const cmc_params *p, void *stream) {
+// The step's five phases; events (if given) are recorded between them.
+static int run_step(cmc_state *s, const cmc_params *p, void *const *events, hipStream_t st) {
   Workspace w;
   int rc = check_state(s, &w);
   if (rc) return rc;
   if ((rc = check_params(p))) return rc;
-  hipStream_t st = as_stream(stream);
-  hipError_t e = cmc::launch_potential(*s, w, p->precision, st);
+  auto mark = [&](int i) -> hipError_t {
+    return events ? hipEventRecord(static_cast<hipEvent_t>(events[i]), st) : hipSuccess;
+  };
+  hipError_t e = mark(0);
+  if (e == hipSuccess) e = cmc::launch_potential(*s, w, p->precision, st);
+  if (e == hipSuccess) e = mark(1);
   if (e == hipSuccess) e = cmc::launch_timestep(*s, w, *p, st);
+  if (e == hipSuccess) e = mark(2);
   if (e == hipSuccess) e = cmc::launch_relax(*s, w, *p, st);
+  if (e == hipSuccess) e = mark(3);
   if (e == hipSuccess) e = cmc::launch_orbit(*s, w, *p, true, st);
+  if (e == hipSuccess) e = mark(4);
   if (e == hipSuccess) e = cmc::launch_sort_stage(*s, w, false, st);
+  if (e == hipSuccess) e = mark(5);
   return status_of(e);
+}
+
+int cmc_step(cmc_state *s, const cmc_params *p, void *stream) {
+  return run_step(s, p, nullptr, as_stream(stream));
+}
+
+int cmc_step_timed(cmc_state *s, const cmc_params *p, void *const *events, void *stream) {
+  if (!events) return CMC_EINVAL;
+  for (int i = 0; i < 6; ++i)
+    if (!events[i]) return CMC_EINVAL;
+  return run_step(s, p, events, as_stream(stream));
 }
 
 int cmc_diagnostics(const cmc_state *s, double *out_dev, void *stream) {

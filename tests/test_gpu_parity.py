@@ -157,7 +157,7 @@ def test_timestep_degenerate(cmc, ora):
     # one pair; all radii equal (zero-volume bins); no relative motion
     for r, vr, vt in ((np.array([1.0]), np.array([0.1]), np.array([0.1])),
                       (np.full(40, 1.0), np.linspace(-1, 1, 40), np.full(40, 0.3)),
-                      (np.linspace(1, 2, 40), np.full(40, 0.2), np.full(40, 0.3))):
+                      (np.linspace(1, 2, 40), np.full(40, 0.2), np.zeros(40))):
         n = len(r)
         st = ora.State(r, vr, vt, np.full(n, 1.0 / n), np.arange(n, dtype=np.uint32))
         cl = upload(cmc, st)
