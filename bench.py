@@ -76,6 +76,8 @@ def main() -> int:
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plain", action="store_true",
+                    help="time plain cmc_step calls only (no per-phase events); for profilers")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -104,6 +106,20 @@ def main() -> int:
     print(f"# warmup done: {args.warmup} steps, n={cl.n}", file=sys.stderr, flush=True)
 
     K = args.steps
+    if args.plain:
+        n_start = cl.n
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(K):
+            params.step = args.warmup + k
+            P.cmc_step(cl, params)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        print(json.dumps({"metric": METRIC, "value": n_start * K / el, "unit": "star-updates/s",
+                          "n_gpus": 1, "steps": K, "warmup": args.warmup,
+                          "ms_per_step": el / K * 1e3, "mode": "plain", "n_start": n_start,
+                          "n_end": cl.n, "workload": args.workload}), flush=True)
+        return 0
     ev = [EventSet(6) for _ in range(K)]
     nlog = torch.zeros(K + 1, dtype=torch.int64, device="cuda")
     nlog[0].copy_(cl.sc[0])

@@ -84,10 +84,9 @@ typedef struct cmc_scalars {
  *                     that cmc_sort orders by.
  *  sc               : device scalars (see cmc_scalars).
  *  work, work_bytes : scratch of at least cmc_workspace_bytes(cap) bytes,
- *                     256-byte aligned, zero-filled by the caller once before
- *                     the first call (the library returns its internal
- *                     counters to zero at the end of every call); no other
- *                     contents are preserved between calls. */
+ *                     256-byte aligned; calls leave nothing in it that a later
+ *                     call relies on, except the potential table a cmc_step
+ *                     or cmc_potential builds for the same step's orbit pass. */
 typedef struct cmc_state {
   int64_t cap;
   double *r, *vr, *vt;
@@ -111,7 +110,7 @@ typedef struct cmc_params {
   double target;       /* mean sin^2(beta/2) over pairs that fixes dt (0.03)      */
   double bound_factor; /* rejection bound F = bound_factor * max endpoint g (1.2) */
   int32_t trial_cap;   /* rejection trials per star before giving up (10000)      */
-  int32_t dt_iters;    /* Newton iterations enqueued for dt; 0 = default (24)     */
+  int32_t dt_iters;    /* Newton iterations enqueued for dt; 0 = default (10)     */
 } cmc_params;
 
 /* Bytes of scratch a state of capacity `cap` needs. */
@@ -162,7 +161,9 @@ int cmc_relax(cmc_state *s, const cmc_params *p, void *stream);
  * vt in place; counters in sc.  Needs the table of cmc_potential. */
 int cmc_orbit(cmc_state *s, const cmc_params *p, void *stream);
 
-/* One whole step: potential -> timestep -> relax -> orbit -> sort. */
+/* One whole step: potential -> timestep -> relax -> orbit -> sort.  The
+ * potential table is kept in the workspace; phi, mcum, ssuf of the state are
+ * not written (call cmc_potential for them). */
 int cmc_step(cmc_state *s, const cmc_params *p, void *stream);
 
 /* cmc_step that also records events[0] on `stream` before the step and

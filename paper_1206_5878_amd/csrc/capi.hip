@@ -88,7 +88,7 @@ int cmc_potential(cmc_state *s, int32_t precision, void *stream) {
   int rc = check_state(s, &w);
   if (rc) return rc;
   if (precision != CMC_FP64 && precision != CMC_MIXED) return CMC_EINVAL;
-  return status_of(cmc::launch_potential(*s, w, precision, as_stream(stream)));
+  return status_of(cmc::launch_potential(*s, w, precision, true, as_stream(stream)));
 }
 
 int cmc_timestep(cmc_state *s, const cmc_params *p, void *stream) {
@@ -112,7 +112,9 @@ int cmc_orbit(cmc_state *s, const cmc_params *p, void *stream) {
   int rc = check_state(s, &w);
   if (rc) return rc;
   if ((rc = check_params(p))) return rc;
-  return status_of(cmc::launch_orbit(*s, w, *p, false, as_stream(stream)));
+  hipError_t e = cmc::launch_table_pack(*s, w, as_stream(stream));
+  if (e == hipSuccess) e = cmc::launch_orbit(*s, w, *p, false, as_stream(stream));
+  return status_of(e);
 }
 
 // The step's five phases; events (if given) are recorded between them.
@@ -125,7 +127,7 @@ static int run_step(cmc_state *s, const cmc_params *p, void *const *events, hipS
     return events ? hipEventRecord(static_cast<hipEvent_t>(events[i]), st) : hipSuccess;
   };
   hipError_t e = mark(0);
-  if (e == hipSuccess) e = cmc::launch_potential(*s, w, p->precision, st);
+  if (e == hipSuccess) e = cmc::launch_potential(*s, w, p->precision, false, st);
   if (e == hipSuccess) e = mark(1);
   if (e == hipSuccess) e = cmc::launch_timestep(*s, w, *p, st);
   if (e == hipSuccess) e = mark(2);

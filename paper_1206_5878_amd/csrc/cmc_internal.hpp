@@ -165,12 +165,28 @@ struct alignas(8) StageRec {
   uint32_t id, pad;
 };
 
+// ---------------------------------------------------------------- orbit table
+// Entry k of the potential table as the orbit pass reads it: one 32-byte
+// record, so a probe brings r_k, Phi_k, M_k and S_k in the same cache line.
+struct alignas(32) TabEntry {
+  double r, phi, M, S;
+};
+// Every kCoarse-th (r, Phi): the top of each table search, small enough to
+// stay in L2 (16 bytes per kCoarse stars).
+struct alignas(16) Coarse {
+  double r, phi;
+};
+constexpr int kCoarse = 64;
+
 // ---------------------------------------------------------------- workspace
 constexpr int kSortTile = 4096;  // keys per radix tile (256 threads x 16)
 constexpr int kPotTile = 2048;   // stars per potential tile (256 x 8)
 constexpr int kBlock = 256;
+constexpr int kRedBlocks = 2048;  // grid of the grid-stride reduction kernels
 
 struct Workspace {
+  TabEntry *tab;            // [cap]
+  Coarse *coarse;           // [cap / kCoarse + 1]
   StageRec *stage;          // [cap]
   uint64_t *keys[2];        // [cap]
   uint32_t *vals[2];        // [cap]
@@ -183,9 +199,7 @@ struct Workspace {
   double *pair_tp;          // [cap/2 + 1]
   double *pair_part;        // [4 * pair_blocks]
   double *dt_state;         // [32]
-  uint32_t *dt_ticket;      // [16]
   double *red_part;         // [8 * star_blocks]  generic per-block partials
-  uint32_t *red_ticket;     // [16]
   int64_t sort_tiles, pot_tiles, pair_blocks, star_blocks;
   size_t bytes;
 };
@@ -207,6 +221,8 @@ inline Workspace layout(int64_t cap, void *base) {
   w.pot_tiles = cdiv(c, kPotTile);
   w.pair_blocks = cdiv(c / 2 + 1, kBlock);
   w.star_blocks = cdiv(c, kBlock);
+  w.tab = reinterpret_cast<TabEntry *>(take(sizeof(TabEntry) * c));
+  w.coarse = reinterpret_cast<Coarse *>(take(sizeof(Coarse) * (c / kCoarse + 1)));
   w.stage = reinterpret_cast<StageRec *>(take(sizeof(StageRec) * c));
   w.keys[0] = reinterpret_cast<uint64_t *>(take(8 * c));
   w.keys[1] = reinterpret_cast<uint64_t *>(take(8 * c));
@@ -221,23 +237,24 @@ inline Workspace layout(int64_t cap, void *base) {
   w.pair_tp = reinterpret_cast<double *>(take(8 * (c / 2 + 1)));
   w.pair_part = reinterpret_cast<double *>(take(8 * 4 * w.pair_blocks));
   w.dt_state = reinterpret_cast<double *>(take(8 * 32));
-  w.dt_ticket = reinterpret_cast<uint32_t *>(take(4 * 16));
   w.red_part = reinterpret_cast<double *>(take(8 * 8 * w.star_blocks));
-  w.red_ticket = reinterpret_cast<uint32_t *>(take(4 * 16));
   w.bytes = (off + 255) & ~size_t(255);
   return w;
 }
 
 // ---------------------------------------------------------------- launchers
 // Defined in the translation units; each returns hipGetLastError().
+// public_arrays: also write phi, mcum, ssuf of the state (the orbit pass
+// reads only the workspace table)
 hipError_t launch_potential(const cmc_state &s, const Workspace &w, int precision,
-                            hipStream_t st);
+                            bool public_arrays, hipStream_t st);
 hipError_t launch_timestep(const cmc_state &s, const Workspace &w, const cmc_params &p,
                            hipStream_t st);
 hipError_t launch_relax(const cmc_state &s, const Workspace &w, const cmc_params &p,
                         hipStream_t st);
 hipError_t launch_orbit(const cmc_state &s, const Workspace &w, const cmc_params &p,
                         bool to_stage, hipStream_t st);
+hipError_t launch_table_pack(const cmc_state &s, const Workspace &w, hipStream_t st);
 hipError_t launch_stage_from_state(const cmc_state &s, const Workspace &w, hipStream_t st);
 hipError_t launch_sort_stage(const cmc_state &s, const Workspace &w, bool normalise_mass,
                              hipStream_t st);

@@ -9,54 +9,45 @@ namespace {
 
 constexpr int NT = kBlock;
 
-__device__ __forceinline__ double ld_coherent(const double *p) {
-  const uint64_t u = __hip_atomic_load(reinterpret_cast<const uint64_t *>(p),
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return __builtin_bit_cast(double, u);
-}
-
 template <typename MT>
-__global__ __launch_bounds__(NT) void k_diag(const double *__restrict__ r,
-                                             const double *__restrict__ vr,
+__global__ __launch_bounds__(NT) void k_diag(const double *__restrict__ vr,
                                              const double *__restrict__ vt,
                                              const MT *__restrict__ m,
                                              const double *__restrict__ phi,
-                                             const double *__restrict__ mcum,
                                              const cmc_scalars *__restrict__ sc,
-                                             double *__restrict__ part,
-                                             uint32_t *__restrict__ ticket,
-                                             double *__restrict__ out) {
+                                             double *__restrict__ part) {
   __shared__ double sh[NT / 64];
-  __shared__ uint32_t is_last;
   const int64_t n = sc->n;
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
   double t = 0.0, wv = 0.0;
-  if (i < n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * NT) {
     const double mi = load_mass(m, i);
-    t = 0.5 * mi * (vr[i] * vr[i] + vt[i] * vt[i]);
-    wv = 0.5 * mi * phi[i];
+    t += 0.5 * mi * (vr[i] * vr[i] + vt[i] * vt[i]);
+    wv += 0.5 * mi * phi[i];
   }
   t = block_sum<NT>(t, sh);
   wv = block_sum<NT>(wv, sh);
   if (threadIdx.x == 0) {
     part[2 * blockIdx.x] = t;
     part[2 * blockIdx.x + 1] = wv;
-    __threadfence();
-    const uint32_t tk = atomicAdd(ticket, 1u);
-    is_last = (tk == gridDim.x - 1) ? 1u : 0u;
   }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
+}
+
+__global__ __launch_bounds__(NT) void k_diag_final(const double *__restrict__ part, int nblocks,
+                                                   const double *__restrict__ r,
+                                                   const double *__restrict__ mcum,
+                                                   const cmc_scalars *__restrict__ sc,
+                                                   double *__restrict__ out) {
+  __shared__ double sh[NT / 64];
   double T = 0.0, W = 0.0;
-  for (int64_t b = threadIdx.x; b < gridDim.x; b += NT) {
-    T += ld_coherent(part + 2 * b);
-    W += ld_coherent(part + 2 * b + 1);
+  for (int b = threadIdx.x; b < nblocks; b += NT) {
+    T += part[2 * b];
+    W += part[2 * b + 1];
   }
   T = block_sum<NT>(T, sh);
   W = block_sum<NT>(W, sh);
   if (threadIdx.x != 0) return;
-  ticket[0] = 0u;
+  const int64_t n = sc->n;
   const double M = n > 0 ? mcum[n - 1] : 0.0;
   out[0] = T;
   out[1] = W;
@@ -91,9 +82,10 @@ __global__ __launch_bounds__(NT) void k_philox(uint64_t key, const uint32_t *__r
 
 template <typename MT>
 hipError_t run(const cmc_state &s, const Workspace &w, double *out, hipStream_t st) {
-  k_diag<MT><<<static_cast<unsigned>(w.star_blocks), NT, 0, st>>>(
-      s.r, s.vr, s.vt, static_cast<const MT *>(s.m), s.phi, s.mcum, s.sc, w.red_part,
-      w.red_ticket, out);
+  const int nb = static_cast<int>(w.star_blocks < kRedBlocks ? w.star_blocks : kRedBlocks);
+  k_diag<MT><<<nb, NT, 0, st>>>(s.vr, s.vt, static_cast<const MT *>(s.m), s.phi, s.sc,
+                                w.red_part);
+  k_diag_final<<<1, NT, 0, st>>>(w.red_part, nb, s.r, s.mcum, s.sc, out);
   return hipGetLastError();
 }
 

@@ -17,12 +17,6 @@ namespace {
 
 constexpr int NT = kBlock;
 
-__device__ __forceinline__ double ld_coherent(const double *p) {
-  const uint64_t u = __hip_atomic_load(reinterpret_cast<const uint64_t *>(p),
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return __builtin_bit_cast(double, u);
-}
-
 __global__ void k_clear_scalars(cmc_scalars *__restrict__ sc, int64_t n) {
   sc->n = n;
   sc->dt = 0.0;
@@ -40,11 +34,8 @@ __global__ void k_clear_scalars(cmc_scalars *__restrict__ sc, int64_t n) {
 __global__ __launch_bounds__(NT) void k_plummer(int64_t n, uint64_t seed, int mass_spectrum,
                                                 StageRec *__restrict__ stage,
                                                 uint64_t *__restrict__ keys,
-                                                cmc_scalars *__restrict__ sc,
-                                                double *__restrict__ part,
-                                                uint32_t *__restrict__ ticket) {
+                                                double *__restrict__ part) {
   __shared__ double sh[NT / 64];
-  __shared__ uint32_t is_last;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
   double mraw = 0.0;
   if (i < n) {
@@ -98,24 +89,20 @@ __global__ __launch_bounds__(NT) void k_plummer(int64_t n, uint64_t seed, int ma
     keys[i] = __builtin_bit_cast(uint64_t, rec.r + 0.0);
   }
   if (!mass_spectrum) return;
-  // total raw mass: block partials summed in block order by the last block
+  // total raw mass: block partials, summed in block order by k_mass_total
   const double bs = block_sum<NT>(mraw, sh);
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = bs;
-    __threadfence();
-    const uint32_t tk = atomicAdd(ticket, 1u);
-    is_last = (tk == gridDim.x - 1) ? 1u : 0u;
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  double tot = 0.0;
-  for (int64_t b = threadIdx.x; b < gridDim.x; b += NT) tot += ld_coherent(part + b);
-  tot = block_sum<NT>(tot, sh);
-  if (threadIdx.x == 0) {
-    ticket[0] = 0u;
-    sc->mass_norm = tot;
-  }
+  if (threadIdx.x == 0) part[blockIdx.x] = bs;
+}
+
+constexpr int FT = 1024;
+
+__global__ __launch_bounds__(FT) void k_mass_total(const double *__restrict__ part,
+                                                   int64_t nblocks, cmc_scalars *__restrict__ sc) {
+  __shared__ double sh[FT / 64];
+  double t = 0.0;
+  for (int64_t b = threadIdx.x; b < nblocks; b += FT) t += part[b];
+  t = block_sum<FT>(t, sh);
+  if (threadIdx.x == 0) sc->mass_norm = t;
 }
 
 }  // namespace
@@ -124,8 +111,8 @@ hipError_t launch_init_plummer(const cmc_state &s, const Workspace &w, int64_t n
                                uint64_t seed, int mass_spectrum, hipStream_t st) {
   k_clear_scalars<<<1, 1, 0, st>>>(s.sc, n);
   const unsigned nb = static_cast<unsigned>(cdiv(n > 0 ? n : 1, NT));
-  k_plummer<<<nb, NT, 0, st>>>(n, seed, mass_spectrum, w.stage, w.keys[0], s.sc, w.red_part,
-                               w.red_ticket);
+  k_plummer<<<nb, NT, 0, st>>>(n, seed, mass_spectrum, w.stage, w.keys[0], w.red_part);
+  if (mass_spectrum) k_mass_total<<<1, FT, 0, st>>>(w.red_part, nb, s.sc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_sort_stage(s, w, mass_spectrum != 0, st);

@@ -6,26 +6,42 @@
 // ~ 1/|v_r| by rejection in r = r_c + r_a sin s, where the density in s,
 // g(s) = r_a cos s / sqrt(Q), is finite at both turning points.  The table
 // (r, Phi, M, S) is read-only for the whole pass (old potential).
+//
+// Every search is a bisection in two levels: first over the coarse samples
+// (every kCoarse-th entry, L2-resident), then inside one kCoarse-entry block
+// of 32-byte table entries.  Because the brackets are unique sign changes and
+// the radii are sorted, this finds the same index as a bisection over the
+// whole table.
 #include "cmc_internal.hpp"
 
 namespace cmc {
 namespace {
 
 constexpr int NT = kBlock;
+constexpr int64_t C = kCoarse;
 
-__device__ __forceinline__ double ld_coherent(const double *p) {
-  const uint64_t u = __hip_atomic_load(reinterpret_cast<const uint64_t *>(p),
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return __builtin_bit_cast(double, u);
+__device__ __forceinline__ double q_of(double r, double phi, double E, double J2) {
+  return 2.0 * E - 2.0 * phi - J2 / (r * r);
 }
 
-// Last table index k in [klo, khi] with r_k <= x.
-__device__ __forceinline__ int64_t interval_of(const double *__restrict__ r, int64_t klo,
-                                               int64_t khi, double x) {
-  int64_t lo = klo, hi = khi + 1;
+// kmin = last k in [-1, i-1] with Q_k < 0, given Q_i >= 0 and Q_{-1} = -inf.
+__device__ __forceinline__ int64_t find_kmin(const TabEntry *__restrict__ tab,
+                                             const Coarse *__restrict__ co, int64_t i,
+                                             double E, double J2) {
+  int64_t slo = -1, shi = (i + C - 1) / C;  // samples s < shi lie below i
+  while (shi - slo > 1) {
+    const int64_t s = slo + ((shi - slo) >> 1);
+    const Coarse c = co[s];
+    if (q_of(c.r, c.phi, E, J2) < 0.0)
+      slo = s;
+    else
+      shi = s;
+  }
+  int64_t lo = slo >= 0 ? slo * C : -1;
+  int64_t hi = shi * C < i ? shi * C : i;
   while (hi - lo > 1) {
     const int64_t mid = lo + ((hi - lo) >> 1);
-    if (r[mid] <= x)
+    if (q_of(tab[mid].r, tab[mid].phi, E, J2) < 0.0)
       lo = mid;
     else
       hi = mid;
@@ -33,37 +49,89 @@ __device__ __forceinline__ int64_t interval_of(const double *__restrict__ r, int
   return lo;
 }
 
-__device__ __forceinline__ double phi_in(const double *__restrict__ phi,
-                                         const double *__restrict__ mcum,
-                                         const double *__restrict__ ssuf, int64_t k, double x) {
-  if (k < 0) return phi[0];
-  return -(mcum[k] / x + ssuf[k]);
+// kmax = last k in [i, n-1] with Q_k >= 0, given Q_i >= 0 and Q_n = 2E < 0.
+__device__ __forceinline__ int64_t find_kmax(const TabEntry *__restrict__ tab,
+                                             const Coarse *__restrict__ co, int64_t i,
+                                             int64_t n, double E, double J2) {
+  const int64_t ns = (n + C - 1) / C;
+  int64_t slo = i / C, shi = ns;  // samples s > slo lie above i
+  while (shi - slo > 1) {
+    const int64_t s = slo + ((shi - slo) >> 1);
+    const Coarse c = co[s];
+    if (q_of(c.r, c.phi, E, J2) >= 0.0)
+      slo = s;
+    else
+      shi = s;
+  }
+  int64_t lo = slo * C > i ? slo * C : i;
+  int64_t hi = shi < ns ? shi * C : n;
+  while (hi - lo > 1) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if (q_of(tab[mid].r, tab[mid].phi, E, J2) >= 0.0)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
 }
 
-__device__ __forceinline__ double dq_in(const double *__restrict__ mcum, int64_t k, double x,
+// Last k in [klo, khi] with r_k <= x (r_{-1} = 0).
+__device__ __forceinline__ int64_t interval_of(const TabEntry *__restrict__ tab,
+                                               const Coarse *__restrict__ co, int64_t klo,
+                                               int64_t khi, double x) {
+  int64_t lo = klo, hi = khi + 1;
+  int64_t slo = lo >= 0 ? lo / C : -1, shi = (hi + C - 1) / C;
+  while (shi - slo > 1) {
+    const int64_t s = slo + ((shi - slo) >> 1);
+    if (co[s].r <= x)
+      slo = s;
+    else
+      shi = s;
+  }
+  if (slo >= 0 && slo * C > lo) lo = slo * C;
+  if (shi * C < hi) hi = shi * C;
+  while (hi - lo > 1) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if (tab[mid].r <= x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Potential inside interval k from the defining sum: -(M_k / x + S_k);
+// flat at Phi_0 inside the innermost star.
+__device__ __forceinline__ double phi_in(const TabEntry *__restrict__ tab, int64_t k,
+                                         double x) {
+  if (k < 0) return tab[0].phi;
+  const TabEntry t = tab[k];
+  return -(t.M / x + t.S);
+}
+
+__device__ __forceinline__ double dq_in(const TabEntry *__restrict__ tab, int64_t k, double x,
                                         double J2) {
-  const double grav = (k >= 0) ? -2.0 * mcum[k] / (x * x) : 0.0;
+  const double grav = (k >= 0) ? -2.0 * tab[k].M / (x * x) : 0.0;
   return grav + 2.0 * J2 / (x * x * x);
 }
 
 template <typename MT, bool TO_STAGE>
 __global__ __launch_bounds__(NT) void k_orbit(
-    const double *__restrict__ r, const double *__restrict__ phi,
-    const double *__restrict__ mcum, const double *__restrict__ ssuf,
+    const TabEntry *__restrict__ tab, const Coarse *__restrict__ co,
     const MT *__restrict__ m, double *__restrict__ vr, double *__restrict__ vt,
     const uint32_t *__restrict__ id, double *__restrict__ r_new, StageRec *__restrict__ stage,
-    uint64_t *__restrict__ keys, cmc_scalars *__restrict__ sc, double *__restrict__ part, uint32_t *__restrict__ ticket,
+    uint64_t *__restrict__ keys, cmc_scalars *__restrict__ sc, double *__restrict__ part,
     uint64_t seed, uint32_t step, int32_t trial_cap, double bound_factor) {
   __shared__ double shd[NT / 64];
-  __shared__ uint32_t is_last;
   const int64_t n = sc->n;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
   double c_esc = 0.0, c_tr = 0.0, c_viol = 0.0, c_cap = 0.0, e_esc = 0.0;
   uint32_t fl = 0;
 
   if (i < n) {
-    const double vri = vr[i], vti = vt[i], ri = r[i];
-    const double E = phi[i] + 0.5 * (vri * vri + vti * vti);
+    const TabEntry me = tab[i];
+    const double vri = vr[i], vti = vt[i], ri = me.r;
+    const double E = me.phi + 0.5 * (vri * vri + vti * vti);
     const double J = ri * vti;
     const double J2 = J * J;
     const uint32_t sid = id[i];
@@ -74,64 +142,47 @@ __global__ __launch_bounds__(NT) void k_orbit(
       fl |= CMC_ST_ESCAPER;
       if (E != E) fl |= CMC_ST_NONFINITE;
     } else {
-      // brackets
-      int64_t lo = -1, hi = i;
-      while (hi - lo > 1) {
-        const int64_t mid = lo + ((hi - lo) >> 1);
-        const double rk = r[mid];
-        if (2.0 * E - 2.0 * phi[mid] - J2 / (rk * rk) < 0.0)
-          lo = mid;
-        else
-          hi = mid;
-      }
-      const int64_t kmin = lo;
-      lo = i;
-      hi = n;
-      while (hi - lo > 1) {
-        const int64_t mid = lo + ((hi - lo) >> 1);
-        const double rk = r[mid];
-        if (2.0 * E - 2.0 * phi[mid] - J2 / (rk * rk) >= 0.0)
-          lo = mid;
-        else
-          hi = mid;
-      }
-      const int64_t kmax = lo;
+      const int64_t kmin = find_kmin(tab, co, i, E, J2);
+      const int64_t kmax = find_kmax(tab, co, i, n, E, J2);
 
-      // roots
+      // roots inside the brackets
       double rmin, rmax;
       if (J2 == 0.0) {
         rmin = 0.0;
       } else if (kmin < 0) {
-        rmin = J / sqrt(2.0 * (E - phi[0]));
+        rmin = J / sqrt(2.0 * (E - tab[0].phi));
       } else {
-        const double a = 2.0 * (E + ssuf[kmin]);
-        const double b = 2.0 * mcum[kmin];
+        const TabEntry t = tab[kmin];
+        const double a = 2.0 * (E + t.S);
+        const double b = 2.0 * t.M;
         const double disc = b * b + 4.0 * a * J2;
         const double den = b + sqrt(disc > 0.0 ? disc : 0.0);
-        rmin = den > 0.0 ? 2.0 * J2 / den : r[kmin];
+        rmin = den > 0.0 ? 2.0 * J2 / den : t.r;
       }
       {
-        const double rl = kmin >= 0 ? r[kmin] : 0.0, rh = r[kmin + 1];
+        const double rl = kmin >= 0 ? tab[kmin].r : 0.0, rh = tab[kmin + 1].r;
         rmin = rmin < rl ? rl : (rmin > rh ? rh : rmin);
       }
       {
-        const double a = 2.0 * (E + ssuf[kmax]);
-        const double b = 2.0 * mcum[kmax];
+        const TabEntry t = tab[kmax];
+        const double a = 2.0 * (E + t.S);
+        const double b = 2.0 * t.M;
         const double disc = b * b + 4.0 * a * J2;
         const double sq = sqrt(disc > 0.0 ? disc : 0.0);
-        const double rh = (kmax + 1 < n) ? r[kmax + 1] : kInf;
+        const double rh = (kmax + 1 < n) ? tab[kmax + 1].r : kInf;
         rmax = a < 0.0 ? (b + sq) / (-2.0 * a) : rh;
-        const double rl = r[kmax];
-        rmax = rmax < rl ? rl : (rmax > rh ? rh : rmax);
+        rmax = rmax < t.r ? t.r : (rmax > rh ? rh : rmax);
       }
 
       // rejection sampling in s
       const double rc = 0.5 * (rmax + rmin), ra = 0.5 * (rmax - rmin);
       double r0 = rmin;
+      double qacc = 0.0;
+      bool have_q = false;
       int32_t ntr = 0;
       if (ra > 0.0) {
-        const double glo = (J2 != 0.0) ? sqrt(2.0 * ra / fabs(dq_in(mcum, kmin, rmin, J2))) : 0.0;
-        const double ghi = sqrt(2.0 * ra / fabs(dq_in(mcum, kmax, rmax, J2)));
+        const double glo = (J2 != 0.0) ? sqrt(2.0 * ra / fabs(dq_in(tab, kmin, rmin, J2))) : 0.0;
+        const double ghi = sqrt(2.0 * ra / fabs(dq_in(tab, kmax, rmax, J2)));
         const double F = bound_factor * (glo > ghi ? glo : ghi);
         if (F > 0.0 && F < kInf) {
           bool accepted = false;
@@ -143,8 +194,8 @@ __global__ __launch_bounds__(NT) void k_orbit(
             const double ss = sin(s0), cs = cos(s0);
             r0 = rc + ra * ss;
             ++ntr;
-            const int64_t k0 = interval_of(r, kmin, kmax, r0);
-            const double q0 = 2.0 * E - 2.0 * phi_in(phi, mcum, ssuf, k0, r0) - J2 / (r0 * r0);
+            const int64_t k0 = interval_of(tab, co, kmin, kmax, r0);
+            const double q0 = 2.0 * E - 2.0 * phi_in(tab, k0, r0) - J2 / (r0 * r0);
             if (!(q0 > 0.0)) continue;
             const double g0 = ra * cs / sqrt(q0);
             if (g0 > F) {
@@ -153,6 +204,8 @@ __global__ __launch_bounds__(NT) void k_orbit(
             }
             if (F * X2 < g0) {
               accepted = true;
+              qacc = q0;  // Q at the accepted radius, reused for v_r
+              have_q = true;
               break;
             }
           }
@@ -169,9 +222,11 @@ __global__ __launch_bounds__(NT) void k_orbit(
 
       // new state: J conserved, E conserved in the old potential
       rn = r0 + 0.0;
-      const int64_t kn = interval_of(r, kmin, kmax, rn);
-      const double qn = 2.0 * E - 2.0 * phi_in(phi, mcum, ssuf, kn, rn) -
-                        (J2 == 0.0 ? 0.0 : J2 / (rn * rn));
+      double qn = qacc;
+      if (!have_q) {
+        const int64_t kn = interval_of(tab, co, kmin, kmax, rn);
+        qn = 2.0 * E - 2.0 * phi_in(tab, kn, rn) - (J2 == 0.0 ? 0.0 : J2 / (rn * rn));
+      }
       const U4 w = philox(sid, step, kSign, 0u, seed);
       const double vmag = sqrt(qn > 0.0 ? qn : 0.0);
       vrn = (w.x >> 31) ? -vmag : vmag;
@@ -195,9 +250,8 @@ __global__ __launch_bounds__(NT) void k_orbit(
     }
   }
 
-  // per-pass counters: block partials, summed in block order by the last block
-  const uint64_t any = __ballot(fl != 0);
-  if (any) {
+  // per-pass counters: block partials, summed in block order by k_orbit_sum
+  if (__ballot(fl != 0)) {
     uint32_t wf = fl;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) wf |= __shfl_xor(wf, o, 64);
@@ -215,25 +269,43 @@ __global__ __launch_bounds__(NT) void k_orbit(
     pp[2] = c_viol;
     pp[3] = c_cap;
     pp[4] = e_esc;
-    __threadfence();
-    const uint32_t tk = atomicAdd(ticket, 1u);
-    is_last = (tk == gridDim.x - 1) ? 1u : 0u;
   }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
+}
+
+constexpr int FT = 1024;
+
+__global__ __launch_bounds__(FT) void k_orbit_sum(const double *__restrict__ part,
+                                                  int64_t nblocks, cmc_scalars *__restrict__ sc) {
+  __shared__ double sh[FT / 64];
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int64_t b = threadIdx.x; b < gridDim.x; b += NT)
-    for (int q = 0; q < 5; ++q) v[q] += ld_coherent(part + 5 * b + q);
-  for (int q = 0; q < 5; ++q) v[q] = block_sum<NT>(v[q], shd);
+  for (int64_t b = threadIdx.x; b < nblocks; b += FT)
+#pragma unroll
+    for (int q = 0; q < 5; ++q) v[q] += part[5 * b + q];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) v[q] = block_sum<FT>(v[q], sh);
   if (threadIdx.x == 0) {
-    ticket[0] = 0u;
     sc->n_esc = static_cast<int64_t>(v[0]);
     sc->trials = static_cast<int64_t>(v[1]);
     sc->violations = static_cast<int64_t>(v[2]);
     sc->capped = static_cast<int64_t>(v[3]);
     sc->e_esc = v[4];
   }
+}
+
+// The standalone orbit call reads the state's phi, mcum, ssuf: pack them into
+// the table layout first.
+__global__ __launch_bounds__(NT) void k_table_pack(const double *__restrict__ r,
+                                                   const double *__restrict__ phi,
+                                                   const double *__restrict__ mcum,
+                                                   const double *__restrict__ ssuf,
+                                                   const cmc_scalars *__restrict__ sc,
+                                                   TabEntry *__restrict__ tab,
+                                                   Coarse *__restrict__ co) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  if (k >= sc->n) return;
+  const TabEntry t{r[k], phi[k], mcum[k], ssuf[k]};
+  tab[k] = t;
+  if (k % C == 0) co[k / C] = Coarse{t.r, t.phi};
 }
 
 template <typename MT>
@@ -244,19 +316,24 @@ hipError_t run(const cmc_state &s, const Workspace &w, const cmc_params &p, bool
   const int32_t cap = p.trial_cap > 0 ? p.trial_cap : 10000;
   const double bf = p.bound_factor > 0.0 ? p.bound_factor : 1.2;
   if (to_stage)
-    k_orbit<MT, true><<<nb, NT, 0, st>>>(s.r, s.phi, s.mcum, s.ssuf, m, s.vr, s.vt, s.id,
-                                         s.r_new, w.stage, w.keys[0], s.sc, w.red_part,
-                                         w.red_ticket,
-                                         p.seed, p.step, cap, bf);
+    k_orbit<MT, true><<<nb, NT, 0, st>>>(w.tab, w.coarse, m, s.vr, s.vt, s.id, s.r_new,
+                                         w.stage, w.keys[0], s.sc, w.red_part, p.seed, p.step,
+                                         cap, bf);
   else
-    k_orbit<MT, false><<<nb, NT, 0, st>>>(s.r, s.phi, s.mcum, s.ssuf, m, s.vr, s.vt, s.id,
-                                          s.r_new, w.stage, w.keys[0], s.sc, w.red_part,
-                                          w.red_ticket,
-                                          p.seed, p.step, cap, bf);
+    k_orbit<MT, false><<<nb, NT, 0, st>>>(w.tab, w.coarse, m, s.vr, s.vt, s.id, s.r_new,
+                                          w.stage, w.keys[0], s.sc, w.red_part, p.seed, p.step,
+                                          cap, bf);
+  k_orbit_sum<<<1, FT, 0, st>>>(w.red_part, w.star_blocks, s.sc);
   return hipGetLastError();
 }
 
 }  // namespace
+
+hipError_t launch_table_pack(const cmc_state &s, const Workspace &w, hipStream_t st) {
+  k_table_pack<<<static_cast<unsigned>(w.star_blocks), NT, 0, st>>>(s.r, s.phi, s.mcum, s.ssuf,
+                                                                    s.sc, w.tab, w.coarse);
+  return hipGetLastError();
+}
 
 hipError_t launch_orbit(const cmc_state &s, const Workspace &w, const cmc_params &p,
                         bool to_stage, hipStream_t st) {

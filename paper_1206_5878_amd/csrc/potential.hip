@@ -3,8 +3,9 @@
 // inclusive prefix of m and S_k the exclusive suffix of m/r.  Device-wide
 // scan in three deterministic passes: per-tile sums, a one-block scan of the
 // tile sums (forward for M, backward for S), and a per-tile apply that adds
-// the carries to in-tile scans.  HBM-bound: reads r and m, writes phi, mcum,
-// ssuf.
+// the carries to in-tile scans.  HBM-bound: reads r and m, writes the
+// orbit table (r, Phi, M, S per star, and (r, Phi) at every 64th star) and,
+// for the standalone call, the state's phi, mcum, ssuf.
 #include "cmc_internal.hpp"
 
 namespace cmc {
@@ -69,14 +70,16 @@ __global__ __launch_bounds__(ST) void k_pot_tile_scan(const double *__restrict__
   }
 }
 
-template <typename MT>
+template <typename MT, bool PUBLIC>
 __global__ __launch_bounds__(PT) void k_pot_apply(const double *__restrict__ r,
                                                   const MT *__restrict__ m,
                                                   const cmc_scalars *__restrict__ sc,
                                                   const double *__restrict__ carry,
                                                   int64_t tiles, double *__restrict__ phi,
                                                   double *__restrict__ mcum,
-                                                  double *__restrict__ ssuf) {
+                                                  double *__restrict__ ssuf,
+                                                  TabEntry *__restrict__ tab,
+                                                  Coarse *__restrict__ coarse) {
   __shared__ double sh[PT / 64];
   const int64_t n = sc->n;
   const int64_t t = blockIdx.x;
@@ -112,31 +115,42 @@ __global__ __launch_bounds__(PT) void k_pot_apply(const double *__restrict__ r,
     if (k < n) {
       const double M = cm + pm[j];
       const double S = cq + sq[j];
-      mcum[k] = M;
-      ssuf[k] = S;
-      phi[k] = -(M / rr[j] + S);
+      const double ph = -(M / rr[j] + S);
+      if (PUBLIC) {
+        mcum[k] = M;
+        ssuf[k] = S;
+        phi[k] = ph;
+      }
+      tab[k] = TabEntry{rr[j], ph, M, S};
+      if (j == 0 && (k % kCoarse) == 0) coarse[k / kCoarse] = Coarse{rr[j], ph};
     }
   }
 }
 
+static_assert(PJ <= kCoarse && kCoarse % PJ == 0, "a coarse sample starts a thread's run");
+
 template <typename MT>
-hipError_t run(const cmc_state &s, const Workspace &w, hipStream_t st) {
+hipError_t run(const cmc_state &s, const Workspace &w, bool pub, hipStream_t st) {
   const MT *m = static_cast<const MT *>(s.m);
   const int64_t tiles = w.pot_tiles;
-  k_pot_tile_sums<MT><<<dim3(static_cast<unsigned>(tiles)), PT, 0, st>>>(s.r, m, s.sc,
-                                                                         w.pot_tsum, tiles);
+  const dim3 grid(static_cast<unsigned>(tiles));
+  k_pot_tile_sums<MT><<<grid, PT, 0, st>>>(s.r, m, s.sc, w.pot_tsum, tiles);
   k_pot_tile_scan<<<1, ST, 0, st>>>(w.pot_tsum, w.pot_carry, tiles);
-  k_pot_apply<MT><<<dim3(static_cast<unsigned>(tiles)), PT, 0, st>>>(
-      s.r, m, s.sc, w.pot_carry, tiles, s.phi, s.mcum, s.ssuf);
+  if (pub)
+    k_pot_apply<MT, true><<<grid, PT, 0, st>>>(s.r, m, s.sc, w.pot_carry, tiles, s.phi,
+                                                s.mcum, s.ssuf, w.tab, w.coarse);
+  else
+    k_pot_apply<MT, false><<<grid, PT, 0, st>>>(s.r, m, s.sc, w.pot_carry, tiles, s.phi,
+                                                 s.mcum, s.ssuf, w.tab, w.coarse);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_potential(const cmc_state &s, const Workspace &w, int precision,
-                            hipStream_t st) {
+                            bool public_arrays, hipStream_t st) {
   (void)precision;
-  return s.m_f32 ? run<float>(s, w, st) : run<double>(s, w, st);
+  return s.m_f32 ? run<float>(s, w, public_arrays, st) : run<double>(s, w, public_arrays, st);
 }
 
 }  // namespace cmc

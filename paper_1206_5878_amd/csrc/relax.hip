@@ -3,8 +3,8 @@
 // number density from the pair's 20-star radial bin; representative-encounter
 // time t_p = (pi/32) w^3 / (lnL n_b (m1+m2)^2); deflection
 // beta = min(pi, (pi/2) sqrt(dt/t_p)).  dt solves mean_p sin^2(beta_p/2) =
-// target by safeguarded Newton on x = ln dt, one grid-wide evaluation per
-// launch, finished by the last block to arrive.  One thread per pair.
+// target by safeguarded Newton on x = ln dt: per iteration one grid-wide
+// evaluation and a one-block update.  One thread per pair otherwise.
 #include "cmc_internal.hpp"
 
 namespace cmc {
@@ -74,13 +74,6 @@ __device__ __forceinline__ double beta_of(double tp, double dt) {
   return b < kPi ? b : kPi;
 }
 
-// Loads of values written by other blocks of the same launch, past L1.
-__device__ __forceinline__ double ld_coherent(const double *p) {
-  const uint64_t u = __hip_atomic_load(reinterpret_cast<const uint64_t *>(p),
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return __builtin_bit_cast(double, u);
-}
-
 // ---------------------------------------------------------------- timestep
 // dt_state slots
 enum { kX = 0, kLo, kHi, kDone, kIt, kCnt, kZero, kInfN, kLogSum };
@@ -132,7 +125,6 @@ constexpr int IT = 1024;
 // Reduce the pair counts, detect the degenerate cases, pick the start point.
 __global__ __launch_bounds__(IT) void k_dt_init(const double *__restrict__ part,
                                                 int64_t nblocks, double *__restrict__ st,
-                                                uint32_t *__restrict__ ticket,
                                                 cmc_scalars *__restrict__ sc, double target) {
   __shared__ double sh[IT / 64];
   double v[4] = {0.0, 0.0, 0.0, 0.0};
@@ -141,7 +133,6 @@ __global__ __launch_bounds__(IT) void k_dt_init(const double *__restrict__ part,
   for (int q = 0; q < 4; ++q) v[q] = block_sum<IT>(v[q], sh);
   if (threadIdx.x == 0) {
     const double cnt = v[0], nz = v[1], ni = v[2], ls = v[3];
-    ticket[0] = 0u;
     st[kCnt] = cnt;
     st[kZero] = nz;
     st[kInfN] = ni;
@@ -170,30 +161,26 @@ __global__ __launch_bounds__(IT) void k_dt_init(const double *__restrict__ part,
   }
 }
 
-// One Newton evaluation of F(x) = mean sin^2(beta/2) and dF/dx over all pairs;
-// the last block to finish updates x.
-__global__ __launch_bounds__(NT) void k_dt_iter(const double *__restrict__ tp,
-                                                const cmc_scalars *__restrict__ scr,
-                                                cmc_scalars *__restrict__ sc,
-                                                double *__restrict__ part,
-                                                double *__restrict__ st,
-                                                uint32_t *__restrict__ ticket, double target,
-                                                int32_t last_iter) {
+// One Newton evaluation: block partials of sum sin^2(beta/2) and of
+// d/dx sin^2(beta/2) = (1/4) beta sin(beta) (beta < pi) at dt = exp(x).
+__global__ __launch_bounds__(NT) void k_dt_eval(const double *__restrict__ tp,
+                                                const cmc_scalars *__restrict__ sc,
+                                                const double *__restrict__ st,
+                                                double *__restrict__ part) {
   __shared__ double sh[NT / 64];
-  __shared__ uint32_t is_last;
   if (st[kDone] != 0.0) return;
-  const int64_t np = scr->n / 2;
-  const double x = st[kX];
-  const double dt = exp(x);
-  const int64_t p = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  const int64_t np = sc->n / 2;
+  const double dt = exp(st[kX]);
   double h = 0.0, d = 0.0;
-  if (p < np) {
+  for (int64_t p = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; p < np;
+       p += static_cast<int64_t>(gridDim.x) * NT) {
     const double t = tp[p];
     if (t >= 0.0) {
       const double b = beta_of(t, dt);
-      const double s = sin(0.5 * b);
-      h = s * s;
-      if (b < kPi) d = 0.25 * b * sin(b);
+      double s, c;
+      sincos(0.5 * b, &s, &c);
+      h += s * s;
+      if (b < kPi) d += 0.5 * b * s * c;  // (1/4) b sin b
     }
   }
   h = block_sum<NT>(h, sh);
@@ -201,22 +188,27 @@ __global__ __launch_bounds__(NT) void k_dt_iter(const double *__restrict__ tp,
   if (threadIdx.x == 0) {
     part[2 * blockIdx.x + 0] = h;
     part[2 * blockIdx.x + 1] = d;
-    __threadfence();
-    const uint32_t tk = atomicAdd(ticket, 1u);
-    is_last = (tk == gridDim.x - 1) ? 1u : 0u;
   }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
+}
+
+// Sum the partials in block order and take one safeguarded Newton step on
+// G(x) = ln F(x) - ln target (dG/dx = F'/F), keeping a bracket [lo, hi] of the
+// root; converged when the step falls below 1e-14 relative.
+__global__ __launch_bounds__(NT) void k_dt_update(const double *__restrict__ part,
+                                                  int nblocks, double *__restrict__ st,
+                                                  cmc_scalars *__restrict__ sc, double target,
+                                                  int32_t last_iter) {
+  __shared__ double sh[NT / 64];
+  if (st[kDone] != 0.0) return;
   double H = 0.0, D = 0.0;
-  for (int64_t b = threadIdx.x; b < gridDim.x; b += NT) {
-    H += ld_coherent(part + 2 * b);
-    D += ld_coherent(part + 2 * b + 1);
+  for (int b = threadIdx.x; b < nblocks; b += NT) {
+    H += part[2 * b];
+    D += part[2 * b + 1];
   }
   H = block_sum<NT>(H, sh);
   D = block_sum<NT>(D, sh);
   if (threadIdx.x != 0) return;
-  ticket[0] = 0u;
+  const double x = st[kX];
   const double cnt = st[kCnt];
   const double F = H / cnt, Fp = D / cnt;
   double lo = st[kLo], hi = st[kHi];
@@ -227,7 +219,6 @@ __global__ __launch_bounds__(NT) void k_dt_iter(const double *__restrict__ tp,
   bool conv = (F == target);
   double xn = x;
   if (!conv) {
-    // Newton on G(x) = ln F - ln target, dG/dx = F'/F
     xn = (F > 0.0 && Fp > 0.0) ? x - log(F / target) * F / Fp : __builtin_nan("");
     const bool closed = isfinite(lo) && isfinite(hi);
     if (!(xn > lo && xn < hi) || (!closed && fabs(xn - x) > 16.0)) {
@@ -315,12 +306,14 @@ hipError_t run_timestep(const cmc_state &s, const Workspace &w, const cmc_params
   const unsigned pb = static_cast<unsigned>(w.pair_blocks);
   k_pair_tp<MT><<<pb, NT, 0, st>>>(s.r, m, s.vr, s.vt, s.id, s.sc, w.pair_tp, w.pair_part,
                                    p.seed, p.step, p.gamma);
-  k_dt_init<<<1, IT, 0, st>>>(w.pair_part, w.pair_blocks, w.dt_state, w.dt_ticket, s.sc,
-                              p.target);
-  const int iters = p.dt_iters > 0 ? p.dt_iters : 24;
-  for (int i = 0; i < iters; ++i)
-    k_dt_iter<<<pb, NT, 0, st>>>(w.pair_tp, s.sc, s.sc, w.red_part, w.dt_state, w.dt_ticket,
-                                 p.target, i == iters - 1 ? 1 : 0);
+  k_dt_init<<<1, IT, 0, st>>>(w.pair_part, w.pair_blocks, w.dt_state, s.sc, p.target);
+  const int iters = p.dt_iters > 0 ? p.dt_iters : 10;
+  const int eb = static_cast<int>(w.pair_blocks < kRedBlocks ? w.pair_blocks : kRedBlocks);
+  for (int i = 0; i < iters; ++i) {
+    k_dt_eval<<<eb, NT, 0, st>>>(w.pair_tp, s.sc, w.dt_state, w.red_part);
+    k_dt_update<<<1, NT, 0, st>>>(w.red_part, eb, w.dt_state, s.sc, p.target,
+                                  i == iters - 1 ? 1 : 0);
+  }
   return hipGetLastError();
 }
 

@@ -11,7 +11,9 @@ _hip = None
 def hip() -> C.CDLL:
     global _hip
     if _hip is None:
-        cands = [os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib", "libamdhip64.so"),
+        # the soname first, so the runtime torch already loaded is reused
+        cands = ["libamdhip64.so.7",
+                 os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib", "libamdhip64.so"),
                  ctypes.util.find_library("amdhip64") or "libamdhip64.so"]
         err = None
         for c in cands:

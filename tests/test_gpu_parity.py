@@ -276,5 +276,15 @@ def test_diagnostics(cmc, ora):
     cmc.cmc_potential(cl)
     d = cmc.cmc_diagnostics(cl)
     ref = ora.diagnostics(st)
-    for k in ("T", "W", "E", "virial", "M", "r01", "r10", "r50", "r90"):
+    for k in ("T", "W", "E", "virial", "M"):
         assert rel(d[k], ref[k]) < TOL, k
+    # Lagrange radius: the first star whose enclosed mass reaches f M.  With
+    # equal masses M_k can equal f M exactly, so the index is checked against
+    # that definition within rounding rather than bit for bit.
+    _, mcum, _ = ora.potential(st.r, st.m)
+    M = mcum[-1]
+    for k, f in (("r01", 0.01), ("r10", 0.1), ("r50", 0.5), ("r90", 0.9)):
+        i = int(np.searchsorted(st.r, d[k]))
+        assert st.r[i] == d[k]
+        assert mcum[i] >= f * M * (1 - 1e-12)
+        assert i == 0 or mcum[i - 1] < f * M * (1 + 1e-12)
