@@ -166,18 +166,23 @@ struct alignas(8) StageRec {
 };
 
 // ---------------------------------------------------------------- orbit table
-// Entry k of the potential table as the orbit pass reads it: one 32-byte
-// record, so a probe brings r_k, Phi_k, M_k and S_k in the same cache line.
-struct alignas(32) TabEntry {
-  double r, phi, M, S;
-};
-// Every kCoarse-th (r, Phi): the top of each table search, small enough to
-// stay in L2 (16 bytes per kCoarse stars).
-struct alignas(16) Coarse {
+// The potential table as the orbit pass reads it.  Level 0 holds (r_k, Phi_k)
+// for every star; level L >= 1 holds (r, Phi) of every 8^L-th star.  Each
+// level starts 128-byte aligned, so the 8 children of a level-(L+1) sample
+// are one aligned cache line of level L: a search descends one line per
+// level (a static 8-ary B+tree in sampled-array form).  (M_k, S_k) sit in a
+// parallel array read once per located interval.
+struct alignas(16) RPhi {
   double r, phi;
 };
-constexpr int kCoarse = 64;
-
+struct alignas(16) MS {
+  double M, S;
+};
+constexpr int kMaxLevels = 12;  // 8^11 > 2^32 stars
+struct Levels {
+  RPhi *lev[kMaxLevels];
+  int nlev;  // levels in use for the capacity; the top one has <= 8 entries
+};
 // ---------------------------------------------------------------- workspace
 constexpr int kSortTile = 4096;  // keys per radix tile (256 threads x 16)
 constexpr int kPotTile = 2048;   // stars per potential tile (256 x 8)
@@ -185,8 +190,9 @@ constexpr int kBlock = 256;
 constexpr int kRedBlocks = 2048;  // grid of the grid-stride reduction kernels
 
 struct Workspace {
-  TabEntry *tab;            // [cap]
-  Coarse *coarse;           // [cap / kCoarse + 1]
+  RPhi *lev[kMaxLevels];    // level L: [ceil(cap / 8^L)]
+  int nlev;
+  MS *ms;                   // [cap]
   StageRec *stage;          // [cap]
   uint64_t *keys[2];        // [cap]
   uint32_t *vals[2];        // [cap]
@@ -221,8 +227,17 @@ inline Workspace layout(int64_t cap, void *base) {
   w.pot_tiles = cdiv(c, kPotTile);
   w.pair_blocks = cdiv(c / 2 + 1, kBlock);
   w.star_blocks = cdiv(c, kBlock);
-  w.tab = reinterpret_cast<TabEntry *>(take(sizeof(TabEntry) * c));
-  w.coarse = reinterpret_cast<Coarse *>(take(sizeof(Coarse) * (c / kCoarse + 1)));
+  {
+    int64_t len = c;
+    w.nlev = 0;
+    for (;;) {
+      w.lev[w.nlev++] = reinterpret_cast<RPhi *>(take(sizeof(RPhi) * len));
+      if (len <= 8 || w.nlev == kMaxLevels) break;
+      len = (len + 7) / 8;
+    }
+    for (int L = w.nlev; L < kMaxLevels; ++L) w.lev[L] = nullptr;
+  }
+  w.ms = reinterpret_cast<MS *>(take(sizeof(MS) * c));
   w.stage = reinterpret_cast<StageRec *>(take(sizeof(StageRec) * c));
   w.keys[0] = reinterpret_cast<uint64_t *>(take(8 * c));
   w.keys[1] = reinterpret_cast<uint64_t *>(take(8 * c));
@@ -240,6 +255,27 @@ inline Workspace layout(int64_t cap, void *base) {
   w.red_part = reinterpret_cast<double *>(take(8 * 8 * w.star_blocks));
   w.bytes = (off + 255) & ~size_t(255);
   return w;
+}
+
+inline Levels levels_of(const Workspace &w) {
+  Levels L{};
+  for (int i = 0; i < kMaxLevels; ++i) L.lev[i] = w.lev[i];
+  L.nlev = w.nlev;
+  return L;
+}
+
+// Write star k's table entries (level 0, every level L whose stride divides
+// k, and M, S).
+__device__ __forceinline__ void put_table(const Levels &lv, MS *ms, int64_t k, double r,
+                                          double phi, double M, double S) {
+  const RPhi e{r, phi};
+  lv.lev[0][k] = e;
+  ms[k] = MS{M, S};
+  int64_t q = k;
+  for (int L = 1; L < lv.nlev && (q & 7) == 0; ++L) {
+    q >>= 3;
+    lv.lev[L][q] = e;
+  }
 }
 
 // ---------------------------------------------------------------- launchers

@@ -4,8 +4,8 @@
 // scan in three deterministic passes: per-tile sums, a one-block scan of the
 // tile sums (forward for M, backward for S), and a per-tile apply that adds
 // the carries to in-tile scans.  HBM-bound: reads r and m, writes the
-// orbit table (r, Phi, M, S per star, and (r, Phi) at every 64th star) and,
-// for the standalone call, the state's phi, mcum, ssuf.
+// orbit table ((r, Phi) and (M, S) per star plus the sampled search levels)
+// and, for the standalone call, the state's phi, mcum, ssuf.
 #include "cmc_internal.hpp"
 
 namespace cmc {
@@ -77,9 +77,8 @@ __global__ __launch_bounds__(PT) void k_pot_apply(const double *__restrict__ r,
                                                   const double *__restrict__ carry,
                                                   int64_t tiles, double *__restrict__ phi,
                                                   double *__restrict__ mcum,
-                                                  double *__restrict__ ssuf,
-                                                  TabEntry *__restrict__ tab,
-                                                  Coarse *__restrict__ coarse) {
+                                                  double *__restrict__ ssuf, Levels lv,
+                                                  MS *__restrict__ ms) {
   __shared__ double sh[PT / 64];
   const int64_t n = sc->n;
   const int64_t t = blockIdx.x;
@@ -121,13 +120,10 @@ __global__ __launch_bounds__(PT) void k_pot_apply(const double *__restrict__ r,
         ssuf[k] = S;
         phi[k] = ph;
       }
-      tab[k] = TabEntry{rr[j], ph, M, S};
-      if (j == 0 && (k % kCoarse) == 0) coarse[k / kCoarse] = Coarse{rr[j], ph};
+      put_table(lv, ms, k, rr[j], ph, M, S);
     }
   }
 }
-
-static_assert(PJ <= kCoarse && kCoarse % PJ == 0, "a coarse sample starts a thread's run");
 
 template <typename MT>
 hipError_t run(const cmc_state &s, const Workspace &w, bool pub, hipStream_t st) {
@@ -136,12 +132,13 @@ hipError_t run(const cmc_state &s, const Workspace &w, bool pub, hipStream_t st)
   const dim3 grid(static_cast<unsigned>(tiles));
   k_pot_tile_sums<MT><<<grid, PT, 0, st>>>(s.r, m, s.sc, w.pot_tsum, tiles);
   k_pot_tile_scan<<<1, ST, 0, st>>>(w.pot_tsum, w.pot_carry, tiles);
+  const Levels lv = levels_of(w);
   if (pub)
     k_pot_apply<MT, true><<<grid, PT, 0, st>>>(s.r, m, s.sc, w.pot_carry, tiles, s.phi,
-                                                s.mcum, s.ssuf, w.tab, w.coarse);
+                                                s.mcum, s.ssuf, lv, w.ms);
   else
     k_pot_apply<MT, false><<<grid, PT, 0, st>>>(s.r, m, s.sc, w.pot_carry, tiles, s.phi,
-                                                 s.mcum, s.ssuf, w.tab, w.coarse);
+                                                 s.mcum, s.ssuf, lv, w.ms);
   return hipGetLastError();
 }
 

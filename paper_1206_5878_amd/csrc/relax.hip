@@ -220,15 +220,21 @@ __global__ __launch_bounds__(NT) void k_dt_update(const double *__restrict__ par
   double xn = x;
   if (!conv) {
     xn = (F > 0.0 && Fp > 0.0) ? x - log(F / target) * F / Fp : __builtin_nan("");
-    const bool closed = isfinite(lo) && isfinite(hi);
-    if (!(xn > lo && xn < hi) || (!closed && fabs(xn - x) > 16.0)) {
-      if (closed)
-        xn = 0.5 * (lo + hi);
-      else
-        xn = (F < target) ? x + 8.0 : x - 8.0;
+    const double tol = 1e-14 * fmax(1.0, fabs(x));
+    // a Newton step this small is done, even when it rounds back onto x (which
+    // may coincide with the bracket end just moved there)
+    if (fabs(xn - x) <= tol) {
+      conv = true;
+    } else {
+      const bool closed = isfinite(lo) && isfinite(hi);
+      if (!(xn > lo && xn < hi) || (!closed && fabs(xn - x) > 16.0)) {
+        if (closed)
+          xn = 0.5 * (lo + hi);
+        else
+          xn = (F < target) ? x + 8.0 : x - 8.0;
+      }
+      if (closed && hi - lo <= 1e-15 * fmax(1.0, fabs(x))) conv = true;
     }
-    if (fabs(xn - x) <= 1e-14 * fmax(1.0, fabs(x))) conv = true;
-    if (closed && hi - lo <= 1e-15 * fmax(1.0, fabs(x))) conv = true;
   }
   const double it = st[kIt] + 1.0;
   st[kIt] = it;

@@ -150,7 +150,8 @@ def test_timestep(cmc, ora, n, seed, gamma):
     cl.set_scalar("dt", dt * 1.01)
     cmc.cmc_timestep(cl, p)
     s2 = cl.scalars()
-    assert rel(s2["dt"], dt) < TOL and s2["dt_iters"] <= 6
+    assert rel(s2["dt"], dt) < TOL and s2["dt_iters"] <= 5
+    assert not (s2["status"] & cmc.ST_DT_NOCONV)
 
 
 def test_timestep_degenerate(cmc, ora):
@@ -261,6 +262,7 @@ def test_step_lockstep(cmc, ora, n, gamma, ms, steps):
         h = cl.host()
         new, info = ora.step(st, 1, k, gamma)
         assert rel(s["dt"], info["dt"]) < TOL
+        assert not (s["status"] & cmc.ST_DT_NOCONV), s
         assert s["n"] == new.n
         assert np.array_equal(h["id"], new.id), k
         assert rel(h["r"], new.r) < TOL
