@@ -10,7 +10,7 @@ static_assert(sizeof(cmc_scalars) == 128, "cmc_scalars is 128 bytes in the ABI")
 
 namespace {
 
-constexpr int64_t kMaxCap = (int64_t(1) << 32) - 1;  // ids and sort values are 32-bit
+constexpr int64_t kMaxCap = (int64_t(1) << 31) - 1;  // table indices are 32-bit signed
 
 int check_state(const cmc_state *s, Workspace *w) {
   if (!s || s->cap <= 0 || s->cap > kMaxCap) return CMC_EINVAL;

@@ -178,6 +178,11 @@ struct alignas(16) RPhi {
 struct alignas(16) MS {
   double M, S;
 };
+// Orbit of one star between the bracket and trial kernels (F < 0: done).
+struct alignas(16) OrbitRec {
+  double E, J, rmin, rmax, F;
+  int32_t kmin, kmax;
+};
 constexpr int kMaxLevels = 12;  // 8^11 > 2^32 stars
 struct Levels {
   RPhi *lev[kMaxLevels];
@@ -193,6 +198,7 @@ struct Workspace {
   RPhi *lev[kMaxLevels];    // level L: [ceil(cap / 8^L)]
   int nlev;
   MS *ms;                   // [cap]
+  OrbitRec *orec;           // [cap]
   StageRec *stage;          // [cap]
   uint64_t *keys[2];        // [cap]
   uint32_t *vals[2];        // [cap]
@@ -238,6 +244,7 @@ inline Workspace layout(int64_t cap, void *base) {
     for (int L = w.nlev; L < kMaxLevels; ++L) w.lev[L] = nullptr;
   }
   w.ms = reinterpret_cast<MS *>(take(sizeof(MS) * c));
+  w.orec = reinterpret_cast<OrbitRec *>(take(sizeof(OrbitRec) * c));
   w.stage = reinterpret_cast<StageRec *>(take(sizeof(StageRec) * c));
   w.keys[0] = reinterpret_cast<uint64_t *>(take(8 * c));
   w.keys[1] = reinterpret_cast<uint64_t *>(take(8 * c));

@@ -1,5 +1,5 @@
-// orbit.hip -- new orbits (arXiv:1206.5878, Sec. 2.1 step 5).  One thread per
-// star: E = Phi_i + v^2/2 and J = r_i vt_i; the turning points are bracketed
+// orbit.hip -- new orbits (arXiv:1206.5878, Sec. 2.1 step 5).  Per star:
+// E = Phi_i + v^2/2 and J = r_i vt_i; the turning points are bracketed
 // between table radii by the sign of Q_k = 2E - 2Phi_k - J^2/r_k^2 (negative,
 // positive, negative over k), solved in the bracket from
 // r^2 Q = 2(E + S_k) r^2 + 2 M_k r - J^2; the new radius is drawn with density
@@ -7,19 +7,27 @@
 // g(s) = r_a cos s / sqrt(Q), is finite at both turning points.  The table
 // is read-only for the whole pass (old potential).
 //
-// Searches.  Each of the three lookups -- the lower bracket, the upper
-// bracket, the interval of a trial radius -- is "the last index k where a
-// predicate monotone in k holds".  It descends the sampled levels of the
-// table (level L = every 8^L-th (r, Phi)): at every level it loads the 8
-// children of the current sample, one aligned cache line, and counts how many
-// satisfy the predicate.  The brackets and intervals are unique, so this
-// finds the index a bisection over the whole table finds.
+// Two kernels.  k_orbit_bracket: one thread per star, brackets, roots and the
+// rejection bound F, written as a 48-byte orbit record (escapers and
+// degenerate orbits are finished there).  k_orbit_trials: each wavefront owns
+// a chunk of stars and every lane draws trials for one star at a time,
+// taking the chunk's next star as soon as its own is accepted, so the loop
+// does not wait for the unluckiest lane of the wavefront.
+//
+// Searches.  The lower bracket, the upper bracket and the interval of a trial
+// radius are each "the last index k where a predicate monotone in k holds".
+// They descend the sampled levels of the table (level L = every 8^L-th
+// (r, Phi)): per level, the 8 children of the current sample are one aligned
+// cache line; the count of children that satisfy the predicate is the next
+// sample.  Brackets and intervals are unique, so this finds the index a
+// bisection over the whole table finds.
 #include "cmc_internal.hpp"
 
 namespace cmc {
 namespace {
 
 constexpr int NT = kBlock;
+constexpr int kChunk = 512;  // stars per wavefront in the trial kernel
 
 // Q_k < 0 as (2E - 2Phi_k) r_k^2 < J^2 (r_k > 0): no division in the descent.
 struct QNeg {
@@ -37,44 +45,35 @@ struct QNonNeg {
     return k <= upto || (twoE - 2.0 * e.phi) * (e.r * e.r) >= J2;
   }
 };
-// k <= klo, or k <= khi and r_k <= x.
+// r_k <= x.
 struct RBelow {
   double x;
-  int64_t klo, khi;
-  __device__ bool operator()(int64_t k, const RPhi &e) const {
-    return k <= klo || (k <= khi && e.r <= x);
-  }
+  __device__ bool operator()(int64_t, const RPhi &e) const { return e.r <= x; }
 };
 
 // Last k in [0, n-1] with pred(k) true (-1 if none); pred must be monotone
-// (true ... true false ... false).
+// (true ... true false ... false).  Levels are unrolled so each level's base
+// pointer is a kernel-argument register.
 template <class Pred>
 __device__ __forceinline__ int64_t last_true(const Levels &lv, int64_t n, const Pred &pred) {
-  int L = lv.nlev - 1;
-  int64_t stride = int64_t(1) << (3 * L);
-  int64_t s = -1;
-  {
-    const int64_t cnt = (n + stride - 1) / stride;  // <= 8
-    int c = 0;
+  if (!pred(0, lv.lev[0][0])) return -1;
+  int64_t s = 0;  // sample 0 of a virtual level above the top: index 0
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (q < cnt && pred(q * stride, lv.lev[L][q])) c = q + 1;
-    s = c - 1;
-  }
-  if (s < 0) return -1;
-  for (--L; L >= 0; --L) {
-    stride >>= 3;
-    const int64_t cnt = (n + stride - 1) / stride;
-    const int64_t base = s * 8;  // child 0 is sample s itself: known true
-    const RPhi *blk = lv.lev[L] + base;
-    int c = 0;
-    RPhi e[7];
+  for (int L = kMaxLevels - 1; L >= 0; --L) {
+    if (L < lv.nlev) {
+      const int64_t stride = int64_t(1) << (3 * L);
+      const int64_t cnt = (n + stride - 1) / stride;
+      const int64_t base = s * 8;  // child 0 is the current sample: known true
+      const RPhi *blk = lv.lev[L] + base;
+      RPhi e[7];
 #pragma unroll
-    for (int q = 0; q < 7; ++q) e[q] = (base + 1 + q < cnt) ? blk[1 + q] : RPhi{0.0, 0.0};
+      for (int q = 0; q < 7; ++q) e[q] = (base + 1 + q < cnt) ? blk[1 + q] : RPhi{0.0, 0.0};
+      int c = 0;
 #pragma unroll
-    for (int q = 0; q < 7; ++q)
-      if (base + 1 + q < cnt && pred((base + 1 + q) * stride, e[q])) c = q + 1;
-    s = base + c;
+      for (int q = 0; q < 7; ++q)
+        if (base + 1 + q < cnt && pred((base + 1 + q) * stride, e[q])) c = q + 1;
+      s = base + c;
+    }
   }
   return s;
 }
@@ -94,17 +93,71 @@ __device__ __forceinline__ double dq_in(const MS *__restrict__ ms, int64_t k, do
   return grav + 2.0 * J2 / (x * x * x);
 }
 
+// Interval of x for the potential: the last k with r_k <= x, kept inside the
+// orbit's brackets [kmin, kmax].
+__device__ __forceinline__ int64_t interval_in(const Levels &lv, int64_t n, double x,
+                                               int64_t kmin, int64_t kmax) {
+  int64_t k = last_true(lv, n, RBelow{x});
+  return k < kmin ? kmin : (k > kmax ? kmax : k);
+}
+
+// Star outputs: staged record + sort key, or the state arrays in place.
+template <bool TO_STAGE>
+__device__ __forceinline__ void emit(int64_t i, double rn, double vrn, double vtn, double mi,
+                                     uint32_t sid, double *__restrict__ r_new,
+                                     double *__restrict__ vr, double *__restrict__ vt,
+                                     StageRec *__restrict__ stage, uint64_t *__restrict__ keys) {
+  if (TO_STAGE) {
+    StageRec rec;
+    rec.r = rn;
+    rec.vr = vrn;
+    rec.vt = vtn;
+    rec.m = mi;
+    rec.id = sid;
+    rec.pad = 0u;
+    stage[i] = rec;
+    keys[i] = __builtin_bit_cast(uint64_t, rn + 0.0);
+  } else {
+    r_new[i] = rn;
+    vr[i] = vrn;
+    vt[i] = vtn;
+  }
+}
+
+// New velocity from Q at the new radius: J conserved, E conserved in the old
+// potential, random sign of v_r.
+__device__ __forceinline__ void finish(double rn, double qn, double J, double J2, uint32_t sid,
+                                       uint32_t step, uint64_t seed, double &vrn, double &vtn,
+                                       uint32_t &fl) {
+  const U4 w = philox(sid, step, kSign, 0u, seed);
+  const double vmag = sqrt(qn > 0.0 ? qn : 0.0);
+  vrn = (w.x >> 31) ? -vmag : vmag;
+  vtn = (J2 == 0.0) ? 0.0 : J / rn;
+  if (!isfinite(rn) || !isfinite(vrn) || !isfinite(vtn)) fl |= CMC_ST_NONFINITE;
+}
+
+__device__ __forceinline__ void or_status(cmc_scalars *sc, uint32_t fl) {
+  if (__ballot(fl != 0)) {
+    uint32_t wf = fl;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wf |= __shfl_xor(wf, o, 64);
+    if ((threadIdx.x & 63) == 0 && wf) atomicOr(&sc->status, wf);
+  }
+}
+
 template <typename MT, bool TO_STAGE>
-__global__ __launch_bounds__(NT) void k_orbit(
-    Levels lv, const MS *__restrict__ ms, const MT *__restrict__ m, double *__restrict__ vr,
-    double *__restrict__ vt, const uint32_t *__restrict__ id, double *__restrict__ r_new,
-    StageRec *__restrict__ stage, uint64_t *__restrict__ keys, cmc_scalars *__restrict__ sc,
-    double *__restrict__ part, uint64_t seed, uint32_t step, int32_t trial_cap,
-    double bound_factor) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6)))
+void k_orbit_bracket(Levels lv, const MS *__restrict__ ms, const MT *__restrict__ m,
+                     double *__restrict__ vr, double *__restrict__ vt,
+                     const uint32_t *__restrict__ id, double *__restrict__ r_new,
+                     StageRec *__restrict__ stage, uint64_t *__restrict__ keys,
+                     OrbitRec *__restrict__ orec, cmc_scalars *__restrict__ sc,
+                     double *__restrict__ part, uint64_t seed, uint32_t step,
+                     double bound_factor) {
   __shared__ double shd[NT / 64];
   const int64_t n = sc->n;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
-  double c_esc = 0.0, c_tr = 0.0, c_viol = 0.0, c_cap = 0.0, e_esc = 0.0;
+  double c_esc = 0.0, e_esc = 0.0;
   uint32_t fl = 0;
   const RPhi *tab = lv.lev[0];
 
@@ -114,18 +167,16 @@ __global__ __launch_bounds__(NT) void k_orbit(
     const double E = me.phi + 0.5 * (vri * vri + vti * vti);
     const double J = ri * vti;
     const double J2 = J * J;
-    const uint32_t sid = id[i];
-    double rn = kInf, vrn = vri, vtn = vti;
-    if (!(E < 0.0)) {
+    OrbitRec rec{E, J, 0.0, 0.0, -1.0, 0, 0};
+    if (!(E < 0.0)) {  // unbound: leaves the cluster
       c_esc = 1.0;
       e_esc = load_mass(m, i) * E;
       fl |= CMC_ST_ESCAPER;
       if (E != E) fl |= CMC_ST_NONFINITE;
+      emit<TO_STAGE>(i, kInf, vri, vti, load_mass(m, i), id[i], r_new, vr, vt, stage, keys);
     } else {
       const int64_t kmin = last_true(lv, n, QNeg{2.0 * E, J2, i});
       const int64_t kmax = last_true(lv, n, QNonNeg{2.0 * E, J2, i});
-
-      // roots inside the brackets
       double rmin, rmax;
       if (J2 == 0.0) {
         rmin = 0.0;
@@ -154,114 +205,170 @@ __global__ __launch_bounds__(NT) void k_orbit(
         rmax = a < 0.0 ? (b + sq) / (-2.0 * a) : rh;
         rmax = rmax < rl ? rl : (rmax > rh ? rh : rmax);
       }
-
-      // rejection sampling in s
       const double rc = 0.5 * (rmax + rmin), ra = 0.5 * (rmax - rmin);
-      double r0 = rmin;
-      double qacc = 0.0;
-      bool have_q = false;
-      int32_t ntr = 0;
+      double F = -1.0;
+      double rdone = rmin;  // radius of an orbit finished without trials
       if (ra > 0.0) {
         const double glo = (J2 != 0.0) ? sqrt(2.0 * ra / fabs(dq_in(ms, kmin, rmin, J2))) : 0.0;
         const double ghi = sqrt(2.0 * ra / fabs(dq_in(ms, kmax, rmax, J2)));
-        const double F = bound_factor * (glo > ghi ? glo : ghi);
-        if (F > 0.0 && F < kInf) {
-          bool accepted = false;
-          for (int32_t j = 0; j < trial_cap; ++j) {
-            const U4 w = philox(sid, step, kOrbit, static_cast<uint32_t>(j), seed);
-            const double X = u01(w.y, w.x);
-            const double X2 = u01(w.w, w.z);
-            const double s0 = kPi * (X - 0.5);
-            const double ss = sin(s0), cs = cos(s0);
-            r0 = rc + ra * ss;
-            ++ntr;
-            const int64_t k0 = last_true(lv, n, RBelow{r0, kmin, kmax});
-            const double q0 = 2.0 * E - 2.0 * phi_in(lv, ms, k0, r0) - J2 / (r0 * r0);
-            if (!(q0 > 0.0)) continue;
-            const double g0 = ra * cs / sqrt(q0);
-            if (g0 > F) {
-              c_viol += 1.0;
-              fl |= CMC_ST_BOUND;
-            }
-            if (F * X2 < g0) {
-              accepted = true;
-              qacc = q0;  // Q at the accepted radius, reused for v_r
-              have_q = true;
-              break;
-            }
-          }
-          if (!accepted) {
-            c_cap = 1.0;
-            fl |= CMC_ST_TRIAL_CAP;
-          }
-        } else {
-          r0 = rc;
+        F = bound_factor * (glo > ghi ? glo : ghi);
+        if (!(F > 0.0 && F < kInf)) {
+          F = -1.0;
+          rdone = rc;
           fl |= CMC_ST_NUMERIC;
         }
       }
-      c_tr = static_cast<double>(ntr);
+      if (F > 0.0) {
+        rec.rmin = rmin;
+        rec.rmax = rmax;
+        rec.F = F;
+        rec.kmin = static_cast<int32_t>(kmin);
+        rec.kmax = static_cast<int32_t>(kmax);
+      } else {
+        const double rn = rdone + 0.0;
+        const int64_t kn = interval_in(lv, n, rn, kmin, kmax);
+        const double qn = 2.0 * E - 2.0 * phi_in(lv, ms, kn, rn) -
+                          (J2 == 0.0 ? 0.0 : J2 / (rn * rn));
+        double vrn, vtn;
+        finish(rn, qn, J, J2, id[i], step, seed, vrn, vtn, fl);
+        emit<TO_STAGE>(i, rn, vrn, vtn, load_mass(m, i), id[i], r_new, vr, vt, stage, keys);
+      }
+    }
+    orec[i] = rec;
+  }
+  or_status(sc, fl);
+  c_esc = block_sum<NT>(c_esc, shd);
+  e_esc = block_sum<NT>(e_esc, shd);
+  if (threadIdx.x == 0) {
+    part[2 * static_cast<int64_t>(blockIdx.x)] = c_esc;
+    part[2 * static_cast<int64_t>(blockIdx.x) + 1] = e_esc;
+  }
+}
 
-      // new state: J conserved, E conserved in the old potential
-      rn = r0 + 0.0;
-      double qn = qacc;
-      if (!have_q) {
-        const int64_t kn = last_true(lv, n, RBelow{rn, kmin, kmax});
+template <typename MT, bool TO_STAGE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6)))
+void k_orbit_trials(Levels lv, const MS *__restrict__ ms, const MT *__restrict__ m,
+                    double *__restrict__ vr, double *__restrict__ vt,
+                    const uint32_t *__restrict__ id, double *__restrict__ r_new,
+                    StageRec *__restrict__ stage, uint64_t *__restrict__ keys,
+                    const OrbitRec *__restrict__ orec, cmc_scalars *__restrict__ sc,
+                    double *__restrict__ part, uint64_t seed, uint32_t step,
+                    int32_t trial_cap) {
+  __shared__ double shd[NT / 64];
+  const int64_t n = sc->n;
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t wave = static_cast<int64_t>(blockIdx.x) * (NT / 64) + (threadIdx.x >> 6);
+  const int64_t c_end0 = (wave + 1) * kChunk;
+  const int64_t c_end = c_end0 < n ? c_end0 : n;
+  int64_t cursor = wave * kChunk;  // wave-uniform
+  double c_tr = 0.0, c_viol = 0.0, c_cap = 0.0;
+  uint32_t fl = 0;
+
+  // lane state: current star and its orbit
+  bool busy = false;
+  int64_t i = 0;
+  double E = 0.0, J = 0.0, J2 = 0.0, rc = 0.0, ra = 0.0, F = 0.0;
+  int64_t kmin = 0, kmax = 0;
+  uint32_t sid = 0;
+  int32_t j = 0;
+  double r0 = 0.0;
+
+  for (;;) {
+    // idle lanes take the chunk's next stars that still need trials
+    for (;;) {
+      const uint64_t need = __ballot(!busy);
+      if (need == 0ull || cursor >= c_end) break;
+      const int64_t mine = cursor + __popcll(need & lt);
+      cursor += __popcll(need);
+      if (!busy && mine < c_end) {
+        const OrbitRec o = orec[mine];
+        if (o.F > 0.0) {
+          busy = true;
+          i = mine;
+          E = o.E;
+          J = o.J;
+          J2 = J * J;
+          rc = 0.5 * (o.rmax + o.rmin);
+          ra = 0.5 * (o.rmax - o.rmin);
+          F = o.F;
+          kmin = o.kmin;
+          kmax = o.kmax;
+          sid = id[mine];
+          j = 0;
+        }
+      }
+    }
+    if (__ballot(busy) == 0ull) break;
+    if (busy) {
+      // one rejection trial
+      const U4 w = philox(sid, step, kOrbit, static_cast<uint32_t>(j), seed);
+      const double X = u01(w.y, w.x);
+      const double X2 = u01(w.w, w.z);
+      const double s0 = kPi * (X - 0.5);
+      double ss, cs;
+      sincos(s0, &ss, &cs);
+      r0 = rc + ra * ss;
+      ++j;
+      c_tr += 1.0;
+      const int64_t k0 = interval_in(lv, n, r0, kmin, kmax);
+      const double q0 = 2.0 * E - 2.0 * phi_in(lv, ms, k0, r0) - J2 / (r0 * r0);
+      bool done = false;
+      double qn = 0.0;
+      if (q0 > 0.0) {
+        const double g0 = ra * cs / sqrt(q0);
+        if (g0 > F) {
+          c_viol += 1.0;
+          fl |= CMC_ST_BOUND;
+        }
+        if (F * X2 < g0) {
+          done = true;
+          qn = q0;
+        }
+      }
+      if (!done && j >= trial_cap) {  // give up: keep the last trial radius
+        done = true;
+        c_cap += 1.0;
+        fl |= CMC_ST_TRIAL_CAP;
+        const double rn = r0 + 0.0;
+        const int64_t kn = interval_in(lv, n, rn, kmin, kmax);
         qn = 2.0 * E - 2.0 * phi_in(lv, ms, kn, rn) - (J2 == 0.0 ? 0.0 : J2 / (rn * rn));
       }
-      const U4 w = philox(sid, step, kSign, 0u, seed);
-      const double vmag = sqrt(qn > 0.0 ? qn : 0.0);
-      vrn = (w.x >> 31) ? -vmag : vmag;
-      vtn = (J2 == 0.0) ? 0.0 : J / rn;
-      if (!isfinite(rn) || !isfinite(vrn) || !isfinite(vtn)) fl |= CMC_ST_NONFINITE;
-    }
-    if (TO_STAGE) {
-      StageRec rec;
-      rec.r = rn;
-      rec.vr = vrn;
-      rec.vt = vtn;
-      rec.m = load_mass(m, i);
-      rec.id = sid;
-      rec.pad = 0u;
-      stage[i] = rec;
-      keys[i] = __builtin_bit_cast(uint64_t, rn + 0.0);
-    } else {
-      r_new[i] = rn;
-      vr[i] = vrn;
-      vt[i] = vtn;
+      if (done) {
+        const double rn = r0 + 0.0;
+        double vrn, vtn;
+        finish(rn, qn, J, J2, sid, step, seed, vrn, vtn, fl);
+        emit<TO_STAGE>(i, rn, vrn, vtn, load_mass(m, i), sid, r_new, vr, vt, stage, keys);
+        busy = false;
+      }
     }
   }
-
-  // per-pass counters: block partials, summed in block order by k_orbit_sum
-  if (__ballot(fl != 0)) {
-    uint32_t wf = fl;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) wf |= __shfl_xor(wf, o, 64);
-    if ((threadIdx.x & 63) == 0 && wf) atomicOr(&sc->status, wf);
-  }
-  c_esc = block_sum<NT>(c_esc, shd);
+  or_status(sc, fl);
   c_tr = block_sum<NT>(c_tr, shd);
   c_viol = block_sum<NT>(c_viol, shd);
   c_cap = block_sum<NT>(c_cap, shd);
-  e_esc = block_sum<NT>(e_esc, shd);
   if (threadIdx.x == 0) {
-    double *pp = part + 5 * static_cast<int64_t>(blockIdx.x);
-    pp[0] = c_esc;
-    pp[1] = c_tr;
-    pp[2] = c_viol;
-    pp[3] = c_cap;
-    pp[4] = e_esc;
+    double *pp = part + 3 * static_cast<int64_t>(blockIdx.x);
+    pp[0] = c_tr;
+    pp[1] = c_viol;
+    pp[2] = c_cap;
   }
 }
 
 constexpr int FT = 1024;
 
-__global__ __launch_bounds__(FT) void k_orbit_sum(const double *__restrict__ part,
-                                                  int64_t nblocks, cmc_scalars *__restrict__ sc) {
+__global__ __launch_bounds__(FT) void k_orbit_sum(const double *__restrict__ pa, int64_t na,
+                                                  const double *__restrict__ pb, int64_t nb,
+                                                  cmc_scalars *__restrict__ sc) {
   __shared__ double sh[FT / 64];
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int64_t b = threadIdx.x; b < nblocks; b += FT)
+  for (int64_t b = threadIdx.x; b < na; b += FT) {
+    v[0] += pa[2 * b];
+    v[4] += pa[2 * b + 1];
+  }
+  for (int64_t b = threadIdx.x; b < nb; b += FT)
 #pragma unroll
-    for (int q = 0; q < 5; ++q) v[q] += part[5 * b + q];
+    for (int q = 0; q < 3; ++q) v[1 + q] += pb[3 * b + q];
 #pragma unroll
   for (int q = 0; q < 5; ++q) v[q] = block_sum<FT>(v[q], sh);
   if (threadIdx.x == 0) {
@@ -286,25 +393,34 @@ __global__ __launch_bounds__(NT) void k_table_pack(const double *__restrict__ r,
   put_table(lv, ms, k, r[k], phi[k], mcum[k], ssuf[k]);
 }
 
-template <typename MT>
-hipError_t run(const cmc_state &s, const Workspace &w, const cmc_params &p, bool to_stage,
-               hipStream_t st) {
+template <typename MT, bool TO_STAGE>
+hipError_t run2(const cmc_state &s, const Workspace &w, const cmc_params &p, hipStream_t st) {
   const MT *m = static_cast<const MT *>(s.m);
-  const unsigned nb = static_cast<unsigned>(w.star_blocks);
   const int32_t cap = p.trial_cap > 0 ? p.trial_cap : 10000;
   const double bf = p.bound_factor > 0.0 ? p.bound_factor : 1.2;
   const Levels lv = levels_of(w);
-  if (to_stage)
-    k_orbit<MT, true><<<nb, NT, 0, st>>>(lv, w.ms, m, s.vr, s.vt, s.id, s.r_new, w.stage,
-                                         w.keys[0], s.sc, w.red_part, p.seed, p.step, cap, bf);
-  else
-    k_orbit<MT, false><<<nb, NT, 0, st>>>(lv, w.ms, m, s.vr, s.vt, s.id, s.r_new, w.stage,
-                                          w.keys[0], s.sc, w.red_part, p.seed, p.step, cap, bf);
-  k_orbit_sum<<<1, FT, 0, st>>>(w.red_part, w.star_blocks, s.sc);
+  const unsigned nba = static_cast<unsigned>(w.star_blocks);
+  const int64_t nbb = cdiv(s.cap, int64_t(kChunk) * (NT / 64));
+  double *pa = w.red_part, *pb = w.red_part + 2 * w.star_blocks;
+  k_orbit_bracket<MT, TO_STAGE><<<nba, NT, 0, st>>>(lv, w.ms, m, s.vr, s.vt, s.id, s.r_new,
+                                                    w.stage, w.keys[0], w.orec, s.sc, pa,
+                                                    p.seed, p.step, bf);
+  k_orbit_trials<MT, TO_STAGE><<<static_cast<unsigned>(nbb), NT, 0, st>>>(
+      lv, w.ms, m, s.vr, s.vt, s.id, s.r_new, w.stage, w.keys[0], w.orec, s.sc, pb, p.seed,
+      p.step, cap);
+  k_orbit_sum<<<1, FT, 0, st>>>(pa, w.star_blocks, pb, nbb, s.sc);
   return hipGetLastError();
 }
 
+template <typename MT>
+hipError_t run(const cmc_state &s, const Workspace &w, const cmc_params &p, bool to_stage,
+               hipStream_t st) {
+  return to_stage ? run2<MT, true>(s, w, p, st) : run2<MT, false>(s, w, p, st);
+}
+
 }  // namespace
+
+static_assert(sizeof(OrbitRec) == 48, "orbit record layout");
 
 hipError_t launch_table_pack(const cmc_state &s, const Workspace &w, hipStream_t st) {
   k_table_pack<<<static_cast<unsigned>(w.star_blocks), NT, 0, st>>>(s.r, s.phi, s.mcum, s.ssuf,
