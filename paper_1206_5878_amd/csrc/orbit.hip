@@ -27,7 +27,8 @@ namespace cmc {
 namespace {
 
 constexpr int NT = kBlock;
-constexpr int kChunk = 512;  // stars per wavefront in the trial kernel
+constexpr int kChunk = 128;     // stars per wavefront in the trial kernel
+constexpr int kGroupBatch = 4;  // group searches whose loads are in flight together
 
 // Q_k < 0 as (2E - 2Phi_k) r_k^2 < J^2 (r_k > 0): no division in the descent.
 struct QNeg {
@@ -101,6 +102,82 @@ __device__ __forceinline__ int64_t interval_in(const Levels &lv, int64_t n, doub
   return k < kmin ? kmin : (k > kmax ? kmax : k);
 }
 
+// ---------------------------------------------------------------- group search
+// The same search, cooperative: lanes form groups of 8 (group g = lanes
+// 8g..8g+7), and each group runs the searches of its 8 lanes together.  Per
+// level, lane q of the group loads child q of each of the 8 current samples,
+// so every node is one coalesced 128-byte load instead of 7 loads per lane,
+// and a ballot counts the children that satisfy the predicate.  Predicate
+// parameters travel through LDS.  Every lane of the wavefront must call it.
+struct GParams {
+  double a, b;  // QNeg/QNonNeg: 2E, J^2; RBelow: x
+  int32_t c;    // QNeg: below; QNonNeg: upto
+  int32_t on;   // lane has a search
+};
+struct GQNeg {
+  __device__ static bool eval(const GParams &p, int64_t k, const RPhi &e) {
+    return k < p.c && (p.a - 2.0 * e.phi) * (e.r * e.r) < p.b;
+  }
+};
+struct GQNonNeg {
+  __device__ static bool eval(const GParams &p, int64_t k, const RPhi &e) {
+    return k <= p.c || (p.a - 2.0 * e.phi) * (e.r * e.r) >= p.b;
+  }
+};
+struct GRBelow {
+  __device__ static bool eval(const GParams &p, int64_t, const RPhi &e) { return e.r <= p.a; }
+};
+
+template <class Pred>
+__device__ __forceinline__ int64_t group_last_true(const Levels &lv, int64_t n, const GParams &mine,
+                                                   GParams *wave_prm) {
+  const int lane = threadIdx.x & 63, g = lane >> 3, q = lane & 7;
+  wave_prm[lane] = mine;
+  __builtin_amdgcn_wave_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  const RPhi root = lv.lev[0][0];
+  int32_t s[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const GParams p = wave_prm[(g << 3) + t];
+    s[t] = (p.on && Pred::eval(p, 0, root)) ? 0 : -1;
+  }
+#pragma unroll
+  for (int L = kMaxLevels - 1; L >= 0; --L) {
+    if (L < lv.nlev) {
+      const int64_t stride = int64_t(1) << (3 * L);
+      const int64_t cnt = (n + stride - 1) / stride;
+      const RPhi *lev = lv.lev[L];
+#pragma unroll
+      for (int h = 0; h < 8; h += kGroupBatch) {  // batches bound the live registers
+        RPhi e[kGroupBatch];
+#pragma unroll
+        for (int u = 0; u < kGroupBatch; ++u) {
+          const int64_t child = static_cast<int64_t>(s[h + u]) * 8 + q;
+          e[u] = (s[h + u] >= 0 && child < cnt) ? lev[child] : RPhi{0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < kGroupBatch; ++u) {
+          const int t = h + u;
+          const GParams p = wave_prm[(g << 3) + t];
+          const int64_t child = static_cast<int64_t>(s[t]) * 8 + q;
+          const bool ok = s[t] >= 0 && child < cnt && Pred::eval(p, child * stride, e[u]);
+          const uint64_t m = __ballot(ok);
+          const int c = __popcll((m >> (g << 3)) & 0xFFull);
+          if (s[t] >= 0) s[t] = s[t] * 8 + c - 1;
+        }
+      }
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  int32_t r = s[0];
+#pragma unroll
+  for (int t = 1; t < 8; ++t)
+    if (q == t) r = s[t];
+  return r;
+}
+
 // Star outputs: staged record + sort key, or the state arrays in place.
 template <bool TO_STAGE>
 __device__ __forceinline__ void emit(int64_t i, double rn, double vrn, double vtn, double mi,
@@ -146,7 +223,7 @@ __device__ __forceinline__ void or_status(cmc_scalars *sc, uint32_t fl) {
 }
 
 template <typename MT, bool TO_STAGE>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6)))
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5)))
 void k_orbit_bracket(Levels lv, const MS *__restrict__ ms, const MT *__restrict__ m,
                      double *__restrict__ vr, double *__restrict__ vt,
                      const uint32_t *__restrict__ id, double *__restrict__ r_new,
@@ -155,18 +232,30 @@ void k_orbit_bracket(Levels lv, const MS *__restrict__ ms, const MT *__restrict_
                      double *__restrict__ part, uint64_t seed, uint32_t step,
                      double bound_factor) {
   __shared__ double shd[NT / 64];
+  __shared__ GParams prm[NT];
   const int64_t n = sc->n;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
   double c_esc = 0.0, e_esc = 0.0;
   uint32_t fl = 0;
   const RPhi *tab = lv.lev[0];
+  GParams *wprm = prm + (threadIdx.x & ~63);
 
+  // brackets of every bound star, searched by groups of 8 lanes
+  double E = 0.0, J = 0.0, J2 = 0.0, vri = 0.0, vti = 0.0;
   if (i < n) {
     const RPhi me = tab[i];
-    const double vri = vr[i], vti = vt[i], ri = me.r;
-    const double E = me.phi + 0.5 * (vri * vri + vti * vti);
-    const double J = ri * vti;
-    const double J2 = J * J;
+    vri = vr[i];
+    vti = vt[i];
+    E = me.phi + 0.5 * (vri * vri + vti * vti);
+    J = me.r * vti;
+    J2 = J * J;
+  }
+  const bool bound = i < n && E < 0.0;
+  const int32_t ii = static_cast<int32_t>(i);
+  const int64_t kmin_g = group_last_true<GQNeg>(lv, n, GParams{2.0 * E, J2, ii, bound}, wprm);
+  const int64_t kmax_g = group_last_true<GQNonNeg>(lv, n, GParams{2.0 * E, J2, ii, bound}, wprm);
+
+  if (i < n) {
     OrbitRec rec{E, J, 0.0, 0.0, -1.0, 0, 0};
     if (!(E < 0.0)) {  // unbound: leaves the cluster
       c_esc = 1.0;
@@ -175,8 +264,7 @@ void k_orbit_bracket(Levels lv, const MS *__restrict__ ms, const MT *__restrict_
       if (E != E) fl |= CMC_ST_NONFINITE;
       emit<TO_STAGE>(i, kInf, vri, vti, load_mass(m, i), id[i], r_new, vr, vt, stage, keys);
     } else {
-      const int64_t kmin = last_true(lv, n, QNeg{2.0 * E, J2, i});
-      const int64_t kmax = last_true(lv, n, QNonNeg{2.0 * E, J2, i});
+      const int64_t kmin = kmin_g, kmax = kmax_g;
       double rmin, rmax;
       if (J2 == 0.0) {
         rmin = 0.0;
@@ -246,7 +334,7 @@ void k_orbit_bracket(Levels lv, const MS *__restrict__ ms, const MT *__restrict_
 }
 
 template <typename MT, bool TO_STAGE>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6)))
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5)))
 void k_orbit_trials(Levels lv, const MS *__restrict__ ms, const MT *__restrict__ m,
                     double *__restrict__ vr, double *__restrict__ vt,
                     const uint32_t *__restrict__ id, double *__restrict__ r_new,
@@ -255,6 +343,8 @@ void k_orbit_trials(Levels lv, const MS *__restrict__ ms, const MT *__restrict__
                     double *__restrict__ part, uint64_t seed, uint32_t step,
                     int32_t trial_cap) {
   __shared__ double shd[NT / 64];
+  __shared__ GParams prm[NT];
+  GParams *wprm = prm + (threadIdx.x & ~63);
   const int64_t n = sc->n;
   const int lane = threadIdx.x & 63;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -262,7 +352,7 @@ void k_orbit_trials(Levels lv, const MS *__restrict__ ms, const MT *__restrict__
   const int64_t c_end0 = (wave + 1) * kChunk;
   const int64_t c_end = c_end0 < n ? c_end0 : n;
   int64_t cursor = wave * kChunk;  // wave-uniform
-  double c_tr = 0.0, c_viol = 0.0, c_cap = 0.0;
+  uint32_t c_tr = 0, c_viol = 0, c_cap = 0;
   uint32_t fl = 0;
 
   // lane state: current star and its orbit
@@ -300,25 +390,29 @@ void k_orbit_trials(Levels lv, const MS *__restrict__ ms, const MT *__restrict__
       }
     }
     if (__ballot(busy) == 0ull) break;
+    // one rejection trial per busy lane; the interval search runs in groups
+    double X2 = 0.0, cs = 0.0;
     if (busy) {
-      // one rejection trial
       const U4 w = philox(sid, step, kOrbit, static_cast<uint32_t>(j), seed);
       const double X = u01(w.y, w.x);
-      const double X2 = u01(w.w, w.z);
+      X2 = u01(w.w, w.z);
       const double s0 = kPi * (X - 0.5);
-      double ss, cs;
+      double ss;
       sincos(s0, &ss, &cs);
       r0 = rc + ra * ss;
       ++j;
-      c_tr += 1.0;
-      const int64_t k0 = interval_in(lv, n, r0, kmin, kmax);
+      ++c_tr;
+    }
+    const int64_t kg = group_last_true<GRBelow>(lv, n, GParams{r0, 0.0, 0, busy}, wprm);
+    if (busy) {
+      const int64_t k0 = kg < kmin ? kmin : (kg > kmax ? kmax : kg);
       const double q0 = 2.0 * E - 2.0 * phi_in(lv, ms, k0, r0) - J2 / (r0 * r0);
       bool done = false;
       double qn = 0.0;
       if (q0 > 0.0) {
         const double g0 = ra * cs / sqrt(q0);
         if (g0 > F) {
-          c_viol += 1.0;
+          ++c_viol;
           fl |= CMC_ST_BOUND;
         }
         if (F * X2 < g0) {
@@ -328,7 +422,7 @@ void k_orbit_trials(Levels lv, const MS *__restrict__ ms, const MT *__restrict__
       }
       if (!done && j >= trial_cap) {  // give up: keep the last trial radius
         done = true;
-        c_cap += 1.0;
+        ++c_cap;
         fl |= CMC_ST_TRIAL_CAP;
         const double rn = r0 + 0.0;
         const int64_t kn = interval_in(lv, n, rn, kmin, kmax);
@@ -344,14 +438,14 @@ void k_orbit_trials(Levels lv, const MS *__restrict__ ms, const MT *__restrict__
     }
   }
   or_status(sc, fl);
-  c_tr = block_sum<NT>(c_tr, shd);
-  c_viol = block_sum<NT>(c_viol, shd);
-  c_cap = block_sum<NT>(c_cap, shd);
+  const double t_tr = block_sum<NT>(static_cast<double>(c_tr), shd);
+  const double t_viol = block_sum<NT>(static_cast<double>(c_viol), shd);
+  const double t_cap = block_sum<NT>(static_cast<double>(c_cap), shd);
   if (threadIdx.x == 0) {
     double *pp = part + 3 * static_cast<int64_t>(blockIdx.x);
-    pp[0] = c_tr;
-    pp[1] = c_viol;
-    pp[2] = c_cap;
+    pp[0] = t_tr;
+    pp[1] = t_viol;
+    pp[2] = t_cap;
   }
 }
 
