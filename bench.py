@@ -78,6 +78,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain", action="store_true",
                     help="time plain cmc_step calls only (no per-phase events); for profilers")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB, --steps times "
+                         "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -92,6 +95,19 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    if args.copy_mib:
+        nb = args.copy_mib << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        print(json.dumps({"mode": "copy", "bytes_per_copy": nb, "copies": args.steps,
+                          "GBs_read_plus_write": 2 * nb * args.steps / el / 1e9}), flush=True)
+        return 0
     wl = WORKLOADS[args.workload]
     prec = P.CMC_FP64 if args.precision == "fp64" else P.CMC_MIXED
     n0 = wl["n"]
