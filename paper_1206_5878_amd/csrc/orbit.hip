@@ -7,6 +7,9 @@
 // g(s) = r_a cos s / sqrt(Q), is finite at both turning points.  The table
 // is read-only for the whole pass (old potential).
 //
+// The mixed form draws the trial angle and takes the accept test in FP32;
+// brackets, roots, the table and Q stay in FP64.
+//
 // Two kernels.  k_orbit_bracket: one thread per star, brackets, roots and the
 // rejection bound F, written as a 48-byte orbit record (escapers and
 // degenerate orbits are finished there).  k_orbit_trials: each wavefront owns
@@ -333,7 +336,7 @@ void k_orbit_bracket(Levels lv, const MS *__restrict__ ms, const MT *__restrict_
   }
 }
 
-template <typename MT, bool TO_STAGE>
+template <typename MT, bool TO_STAGE, bool MIXED>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5)))
 void k_orbit_trials(Levels lv, const MS *__restrict__ ms, const MT *__restrict__ m,
                     double *__restrict__ vr, double *__restrict__ vt,
@@ -394,11 +397,20 @@ void k_orbit_trials(Levels lv, const MS *__restrict__ ms, const MT *__restrict__
     double X2 = 0.0, cs = 0.0;
     if (busy) {
       const U4 w = philox(sid, step, kOrbit, static_cast<uint32_t>(j), seed);
-      const double X = u01(w.y, w.x);
-      X2 = u01(w.w, w.z);
-      const double s0 = kPi * (X - 0.5);
       double ss;
-      sincos(s0, &ss, &cs);
+      if (MIXED) {  // trial angle and acceptance in FP32
+        const float s0 = static_cast<float>(kPi) * (u01f(w.y) - 0.5f);
+        float ssf, csf;
+        sincosf(s0, &ssf, &csf);
+        ss = ssf;
+        cs = csf;
+        X2 = u01f(w.w);
+      } else {
+        const double X = u01(w.y, w.x);
+        X2 = u01(w.w, w.z);
+        const double s0 = kPi * (X - 0.5);
+        sincos(s0, &ss, &cs);
+      }
       r0 = rc + ra * ss;
       ++j;
       ++c_tr;
@@ -410,12 +422,22 @@ void k_orbit_trials(Levels lv, const MS *__restrict__ ms, const MT *__restrict__
       bool done = false;
       double qn = 0.0;
       if (q0 > 0.0) {
-        const double g0 = ra * cs / sqrt(q0);
-        if (g0 > F) {
+        bool over, acc;
+        if (MIXED) {
+          const float g0 = static_cast<float>(ra * cs) / sqrtf(static_cast<float>(q0));
+          const float Ff = static_cast<float>(F);
+          over = g0 > Ff;
+          acc = Ff * static_cast<float>(X2) < g0;
+        } else {
+          const double g0 = ra * cs / sqrt(q0);
+          over = g0 > F;
+          acc = F * X2 < g0;
+        }
+        if (over) {
           ++c_viol;
           fl |= CMC_ST_BOUND;
         }
-        if (F * X2 < g0) {
+        if (acc) {
           done = true;
           qn = q0;
         }
@@ -489,6 +511,7 @@ __global__ __launch_bounds__(NT) void k_table_pack(const double *__restrict__ r,
 
 template <typename MT, bool TO_STAGE>
 hipError_t run2(const cmc_state &s, const Workspace &w, const cmc_params &p, hipStream_t st) {
+  const bool mixed = p.precision == CMC_MIXED;
   const MT *m = static_cast<const MT *>(s.m);
   const int32_t cap = p.trial_cap > 0 ? p.trial_cap : 10000;
   const double bf = p.bound_factor > 0.0 ? p.bound_factor : 1.2;
@@ -499,9 +522,14 @@ hipError_t run2(const cmc_state &s, const Workspace &w, const cmc_params &p, hip
   k_orbit_bracket<MT, TO_STAGE><<<nba, NT, 0, st>>>(lv, w.ms, m, s.vr, s.vt, s.id, s.r_new,
                                                     w.stage, w.keys[0], w.orec, s.sc, pa,
                                                     p.seed, p.step, bf);
-  k_orbit_trials<MT, TO_STAGE><<<static_cast<unsigned>(nbb), NT, 0, st>>>(
-      lv, w.ms, m, s.vr, s.vt, s.id, s.r_new, w.stage, w.keys[0], w.orec, s.sc, pb, p.seed,
-      p.step, cap);
+  if (mixed)
+    k_orbit_trials<MT, TO_STAGE, true><<<static_cast<unsigned>(nbb), NT, 0, st>>>(
+        lv, w.ms, m, s.vr, s.vt, s.id, s.r_new, w.stage, w.keys[0], w.orec, s.sc, pb, p.seed,
+        p.step, cap);
+  else
+    k_orbit_trials<MT, TO_STAGE, false><<<static_cast<unsigned>(nbb), NT, 0, st>>>(
+        lv, w.ms, m, s.vr, s.vt, s.id, s.r_new, w.stage, w.keys[0], w.orec, s.sc, pb, p.seed,
+        p.step, cap);
   k_orbit_sum<<<1, FT, 0, st>>>(pa, w.star_blocks, pb, nbb, s.sc);
   return hipGetLastError();
 }

@@ -3,7 +3,9 @@
 // inclusive prefix of m and S_k the exclusive suffix of m/r.  Device-wide
 // scan in three deterministic passes: per-tile sums, a one-block scan of the
 // tile sums (forward for M, backward for S), and a per-tile apply that adds
-// the carries to in-tile scans.  HBM-bound: reads r and m, writes the
+// the carries to in-tile scans.  The mixed form sums each thread's run of 8
+// stars in compensated FP32 and keeps the block scans and carries in FP64.
+// HBM-bound: reads r and m, writes the
 // orbit table ((r, Phi) and (M, S) per star plus the sampled search levels)
 // and, for the standalone call, the state's phi, mcum, ssuf.
 #include "cmc_internal.hpp"
@@ -14,7 +16,41 @@ namespace {
 constexpr int PT = kBlock;
 constexpr int PJ = kPotTile / kBlock;  // 8 consecutive stars per thread
 
-template <typename MT>
+// Error-free float addition (Knuth's two-sum): s + e == a + b exactly.
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Running sum of a thread's run: FP64, or compensated FP32 (sum + error term,
+// read out in FP64) for the mixed form.
+template <bool MIXED>
+struct Acc {
+  double d = 0.0;
+  float s = 0.0f, e = 0.0f;
+  __device__ __forceinline__ void add(double x) {
+    if (MIXED) {
+      float t, err;
+      two_sum(s, static_cast<float>(x), t, err);
+      s = t;
+      e += err;
+    } else {
+      d += x;
+    }
+  }
+  __device__ __forceinline__ double value() const {
+    return MIXED ? static_cast<double>(s) + static_cast<double>(e) : d;
+  }
+};
+
+// m / r: FP64, or FP32 for the mixed form.
+template <bool MIXED>
+__device__ __forceinline__ double m_over_r(double m, double r) {
+  return MIXED ? static_cast<double>(static_cast<float>(m) / static_cast<float>(r)) : m / r;
+}
+
+template <typename MT, bool MIXED>
 __global__ __launch_bounds__(PT) void k_pot_tile_sums(const double *__restrict__ r,
                                                       const MT *__restrict__ m,
                                                       const cmc_scalars *__restrict__ sc,
@@ -24,18 +60,18 @@ __global__ __launch_bounds__(PT) void k_pot_tile_sums(const double *__restrict__
   const int64_t n = sc->n;
   const int64_t t = blockIdx.x;
   const int64_t base = t * kPotTile + static_cast<int64_t>(threadIdx.x) * PJ;
-  double sm = 0.0, sq = 0.0;
+  Acc<MIXED> sm, sq;
 #pragma unroll
   for (int j = 0; j < PJ; ++j) {
     const int64_t k = base + j;
     if (k < n) {
       const double mk = load_mass(m, k);
-      sm += mk;
-      sq += mk / r[k];
+      sm.add(mk);
+      sq.add(m_over_r<MIXED>(mk, r[k]));
     }
   }
-  const double tm = block_sum<PT>(sm, sh);
-  const double tq = block_sum<PT>(sq, sh);
+  const double tm = block_sum<PT>(sm.value(), sh);
+  const double tq = block_sum<PT>(sq.value(), sh);
   if (threadIdx.x == 0) {
     tsum[t] = tm;
     tsum[tiles + t] = tq;
@@ -70,7 +106,7 @@ __global__ __launch_bounds__(ST) void k_pot_tile_scan(const double *__restrict__
   }
 }
 
-template <typename MT, bool PUBLIC>
+template <typename MT, bool PUBLIC, bool MIXED>
 __global__ __launch_bounds__(PT) void k_pot_apply(const double *__restrict__ r,
                                                   const MT *__restrict__ m,
                                                   const cmc_scalars *__restrict__ sc,
@@ -84,26 +120,26 @@ __global__ __launch_bounds__(PT) void k_pot_apply(const double *__restrict__ r,
   const int64_t t = blockIdx.x;
   const int64_t base = t * kPotTile + static_cast<int64_t>(threadIdx.x) * PJ;
   double rr[PJ], pm[PJ], sq[PJ];
-  double acc = 0.0;
+  Acc<MIXED> am;
 #pragma unroll
   for (int j = 0; j < PJ; ++j) {
     const int64_t k = base + j;
     const bool ok = k < n;
     rr[j] = ok ? r[k] : 1.0;
     const double mk = ok ? load_mass(m, k) : 0.0;
-    acc += mk;
-    pm[j] = acc;  // inclusive prefix inside the thread
-    sq[j] = mk / rr[j];
+    am.add(mk);
+    pm[j] = am.value();  // inclusive prefix inside the thread
+    sq[j] = m_over_r<MIXED>(mk, rr[j]);
   }
-  const double tm = acc;
-  acc = 0.0;
+  const double tm = am.value();
+  Acc<MIXED> aq;
 #pragma unroll
   for (int j = PJ - 1; j >= 0; --j) {  // exclusive suffix inside the thread
     const double q = sq[j];
-    sq[j] = acc;
-    acc += q;
+    sq[j] = aq.value();
+    aq.add(q);
   }
-  const double tq = acc;
+  const double tq = aq.value();
   const double em = block_excl_scan<PT>(tm, sh, static_cast<double *>(nullptr));
   const double eq = block_excl_suffix<PT>(tq, sh, static_cast<double *>(nullptr));
   const double cm = carry[t] + em;
@@ -125,29 +161,35 @@ __global__ __launch_bounds__(PT) void k_pot_apply(const double *__restrict__ r,
   }
 }
 
-template <typename MT>
+template <typename MT, bool MIXED>
 hipError_t run(const cmc_state &s, const Workspace &w, bool pub, hipStream_t st) {
   const MT *m = static_cast<const MT *>(s.m);
   const int64_t tiles = w.pot_tiles;
   const dim3 grid(static_cast<unsigned>(tiles));
-  k_pot_tile_sums<MT><<<grid, PT, 0, st>>>(s.r, m, s.sc, w.pot_tsum, tiles);
+  k_pot_tile_sums<MT, MIXED><<<grid, PT, 0, st>>>(s.r, m, s.sc, w.pot_tsum, tiles);
   k_pot_tile_scan<<<1, ST, 0, st>>>(w.pot_tsum, w.pot_carry, tiles);
   const Levels lv = levels_of(w);
   if (pub)
-    k_pot_apply<MT, true><<<grid, PT, 0, st>>>(s.r, m, s.sc, w.pot_carry, tiles, s.phi,
-                                                s.mcum, s.ssuf, lv, w.ms);
+    k_pot_apply<MT, true, MIXED><<<grid, PT, 0, st>>>(s.r, m, s.sc, w.pot_carry, tiles, s.phi,
+                                                       s.mcum, s.ssuf, lv, w.ms);
   else
-    k_pot_apply<MT, false><<<grid, PT, 0, st>>>(s.r, m, s.sc, w.pot_carry, tiles, s.phi,
-                                                 s.mcum, s.ssuf, lv, w.ms);
+    k_pot_apply<MT, false, MIXED><<<grid, PT, 0, st>>>(s.r, m, s.sc, w.pot_carry, tiles, s.phi,
+                                                        s.mcum, s.ssuf, lv, w.ms);
   return hipGetLastError();
+}
+
+template <typename MT>
+hipError_t run_p(const cmc_state &s, const Workspace &w, int precision, bool pub,
+                 hipStream_t st) {
+  return precision == CMC_MIXED ? run<MT, true>(s, w, pub, st) : run<MT, false>(s, w, pub, st);
 }
 
 }  // namespace
 
 hipError_t launch_potential(const cmc_state &s, const Workspace &w, int precision,
                             bool public_arrays, hipStream_t st) {
-  (void)precision;
-  return s.m_f32 ? run<float>(s, w, public_arrays, st) : run<double>(s, w, public_arrays, st);
+  return s.m_f32 ? run_p<float>(s, w, precision, public_arrays, st)
+                 : run_p<double>(s, w, precision, public_arrays, st);
 }
 
 }  // namespace cmc

@@ -4,7 +4,9 @@
 // time t_p = (pi/32) w^3 / (lnL n_b (m1+m2)^2); deflection
 // beta = min(pi, (pi/2) sqrt(dt/t_p)).  dt solves mean_p sin^2(beta_p/2) =
 // target by safeguarded Newton on x = ln dt: per iteration one grid-wide
-// evaluation and a one-block update.  One thread per pair otherwise.
+// evaluation and a one-block update.  One thread per pair otherwise.  The
+// mixed form computes the pair terms and the kick in FP32 and keeps the
+// centre-of-mass velocity, the sums and the Newton solve in FP64.
 #include "cmc_internal.hpp"
 
 namespace cmc {
@@ -16,7 +18,7 @@ struct PairGeo {
   double v1x, v1y, v2x, v2y, v2z, wx, wy, wz, wm, tp, u2, ma, mb;
 };
 
-template <typename MT>
+template <typename MT, bool MIXED>
 __device__ __forceinline__ PairGeo pair_geometry(int64_t p, int64_t n,
                                                  const double *__restrict__ r,
                                                  const MT *__restrict__ m,
@@ -37,22 +39,50 @@ __device__ __forceinline__ PairGeo pair_geometry(int64_t p, int64_t n,
   const double nb = vol > 0.0 ? static_cast<double>(hi - lo) / vol : kInf;
 
   const U4 w = philox(id[a], step, kRelax, 0u, seed);
+  g.v1x = vr[a];
+  g.v1y = vt[a];
+  g.v2x = vr[b];
+  g.ma = load_mass(m, a);
+  g.mb = load_mass(m, b);
+  const double ms = g.ma + g.mb;
+  if (MIXED) {
+    // pair terms in FP32 (psi from the 23-bit uniform)
+    g.u2 = static_cast<double>(u01f(w.w));
+    float sp, cp;
+    sincosf(2.0f * static_cast<float>(kPi) * u01f(w.y), &sp, &cp);
+    const float vtb = static_cast<float>(vt[b]);
+    const float v2y = vtb * cp, v2z = vtb * sp;
+    const float wx = static_cast<float>(g.v1x - g.v2x);
+    const float wy = static_cast<float>(g.v1y) - v2y;
+    const float wz = -v2z;
+    const float wm = sqrtf(wx * wx + wy * wy + wz * wz);
+    g.v2y = v2y;
+    g.v2z = v2z;
+    g.wx = wx;
+    g.wy = wy;
+    g.wz = wz;
+    g.wm = wm;
+    if (ms == 0.0 || lnL == 0.0)
+      g.tp = kInf;
+    else if (isinf(nb))
+      g.tp = 0.0;
+    else {
+      const float msf = static_cast<float>(ms);
+      g.tp = static_cast<double>((static_cast<float>(kPi) / 32.0f) * (wm * wm * wm) /
+                                 (static_cast<float>(lnL) * static_cast<float>(nb) * (msf * msf)));
+    }
+    return g;
+  }
   const double u1 = u01(w.y, w.x);
   g.u2 = u01(w.w, w.z);
   const double psi = 2.0 * kPi * u1;
   const double cp = cos(psi), sp = sin(psi);
-  g.v1x = vr[a];
-  g.v1y = vt[a];
-  g.v2x = vr[b];
   g.v2y = vt[b] * cp;
   g.v2z = vt[b] * sp;
   g.wx = g.v1x - g.v2x;
   g.wy = g.v1y - g.v2y;
   g.wz = 0.0 - g.v2z;
   g.wm = sqrt(g.wx * g.wx + g.wy * g.wy + g.wz * g.wz);
-  g.ma = load_mass(m, a);
-  g.mb = load_mass(m, b);
-  const double ms = g.ma + g.mb;
   if (ms == 0.0 || lnL == 0.0)
     g.tp = kInf;
   else if (isinf(nb))
@@ -78,7 +108,7 @@ __device__ __forceinline__ double beta_of(double tp, double dt) {
 // dt_state slots
 enum { kX = 0, kLo, kHi, kDone, kIt, kCnt, kZero, kInfN, kLogSum };
 
-template <typename MT>
+template <typename MT, bool MIXED>
 __global__ __launch_bounds__(NT) void k_pair_tp(const double *__restrict__ r,
                                                 const MT *__restrict__ m,
                                                 const double *__restrict__ vr,
@@ -94,7 +124,8 @@ __global__ __launch_bounds__(NT) void k_pair_tp(const double *__restrict__ r,
   const int64_t p = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
   double cnt = 0.0, nz = 0.0, ni = 0.0, ls = 0.0;
   if (p < np) {
-    const PairGeo g = pair_geometry(p, n, r, m, vr, vt, id, seed, step, coulomb_log(gamma, n));
+    const PairGeo g =
+        pair_geometry<MT, MIXED>(p, n, r, m, vr, vt, id, seed, step, coulomb_log(gamma, n));
     if (g.wm > 0.0) {
       tp_out[p] = g.tp;
       cnt = 1.0;
@@ -163,6 +194,7 @@ __global__ __launch_bounds__(IT) void k_dt_init(const double *__restrict__ part,
 
 // One Newton evaluation: block partials of sum sin^2(beta/2) and of
 // d/dx sin^2(beta/2) = (1/4) beta sin(beta) (beta < pi) at dt = exp(x).
+template <bool MIXED>
 __global__ __launch_bounds__(NT) void k_dt_eval(const double *__restrict__ tp,
                                                 const cmc_scalars *__restrict__ sc,
                                                 const double *__restrict__ st,
@@ -177,10 +209,18 @@ __global__ __launch_bounds__(NT) void k_dt_eval(const double *__restrict__ tp,
     const double t = tp[p];
     if (t >= 0.0) {
       const double b = beta_of(t, dt);
-      double s, c;
-      sincos(0.5 * b, &s, &c);
-      h += s * s;
-      if (b < kPi) d += 0.5 * b * s * c;  // (1/4) b sin b
+      if (MIXED) {  // per-pair terms in FP32, sums in FP64
+        const float bf = static_cast<float>(b);
+        float sf, cf;
+        sincosf(0.5f * bf, &sf, &cf);
+        h += static_cast<double>(sf * sf);
+        if (b < kPi) d += static_cast<double>(0.5f * bf * sf * cf);
+      } else {
+        double s, c;
+        sincos(0.5 * b, &s, &c);
+        h += s * s;
+        if (b < kPi) d += 0.5 * b * s * c;  // (1/4) b sin b
+      }
     }
   }
   h = block_sum<NT>(h, sh);
@@ -248,7 +288,7 @@ __global__ __launch_bounds__(NT) void k_dt_update(const double *__restrict__ par
 }
 
 // ---------------------------------------------------------------- kicks
-template <typename MT>
+template <typename MT, bool MIXED>
 __global__ __launch_bounds__(NT) void k_relax(const double *__restrict__ r,
                                               const MT *__restrict__ m,
                                               double *__restrict__ vr,
@@ -261,10 +301,56 @@ __global__ __launch_bounds__(NT) void k_relax(const double *__restrict__ r,
   const int64_t p = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
   if (p >= np) return;
   const double dt = sc->dt;
-  const PairGeo g = pair_geometry(p, n, r, m, vr, vt, id, seed, step, coulomb_log(gamma, n));
+  const PairGeo g =
+      pair_geometry<MT, MIXED>(p, n, r, m, vr, vt, id, seed, step, coulomb_log(gamma, n));
   const double beta = beta_of(g.tp, dt);
   if (!(g.wm > 0.0) || beta == 0.0) return;
   const int64_t a = 2 * p, b = a + 1;
+  if (MIXED) {
+    // the kick in FP32, the centre of mass and the new velocities in FP64
+    const float wm = static_cast<float>(g.wm);
+    const float wx = static_cast<float>(g.wx), wy = static_cast<float>(g.wy),
+                wz = static_cast<float>(g.wz);
+    const float e1x = wx / wm, e1y = wy / wm, e1z = wz / wm;
+    const float ax = fabsf(wx), ay = fabsf(wy), az = fabsf(wz);
+    float cx, cy, cz;
+    if (ax <= ay && ax <= az) {
+      cx = 0.0f;
+      cy = e1z;
+      cz = -e1y;
+    } else if (ay <= az) {
+      cx = -e1z;
+      cy = 0.0f;
+      cz = e1x;
+    } else {
+      cx = e1y;
+      cy = -e1x;
+      cz = 0.0f;
+    }
+    const float cn = sqrtf(cx * cx + cy * cy + cz * cz);
+    const float e2x = cx / cn, e2y = cy / cn, e2z = cz / cn;
+    const float e3x = e1y * e2z - e1z * e2y;
+    const float e3y = e1z * e2x - e1x * e2z;
+    const float e3z = e1x * e2y - e1y * e2x;
+    float sb, cb, s2, c2;
+    sincosf(static_cast<float>(beta), &sb, &cb);
+    sincosf(2.0f * static_cast<float>(kPi) * static_cast<float>(g.u2), &s2, &c2);
+    const float wnx = wm * (cb * e1x + sb * (c2 * e2x + s2 * e3x));
+    const float wny = wm * (cb * e1y + sb * (c2 * e2y + s2 * e3y));
+    const float wnz = wm * (cb * e1z + sb * (c2 * e2z + s2 * e3z));
+    const double ms = g.ma + g.mb;
+    const double fa = g.ma / ms, fb = g.mb / ms;
+    const double cmx = fa * g.v1x + fb * g.v2x;
+    const double cmy = fa * g.v1y + fb * g.v2y;
+    const double cmz = fb * g.v2z;
+    const double n1x = cmx + fb * wnx, n1y = cmy + fb * wny, n1z = cmz + fb * wnz;
+    const double n2x = cmx - fa * wnx, n2y = cmy - fa * wny, n2z = cmz - fa * wnz;
+    vr[a] = n1x;
+    vt[a] = hypot(n1y, n1z);
+    vr[b] = n2x;
+    vt[b] = hypot(n2y, n2z);
+    return;
+  }
 
   const double e1x = g.wx / g.wm, e1y = g.wy / g.wm, e1z = g.wz / g.wm;
   const double ax = fabs(g.wx), ay = fabs(g.wy), az = fabs(g.wz);
@@ -305,43 +391,57 @@ __global__ __launch_bounds__(NT) void k_relax(const double *__restrict__ r,
   vt[b] = hypot(n2y, n2z);
 }
 
-template <typename MT>
+template <typename MT, bool MIXED>
 hipError_t run_timestep(const cmc_state &s, const Workspace &w, const cmc_params &p,
                         hipStream_t st) {
   const MT *m = static_cast<const MT *>(s.m);
   const unsigned pb = static_cast<unsigned>(w.pair_blocks);
-  k_pair_tp<MT><<<pb, NT, 0, st>>>(s.r, m, s.vr, s.vt, s.id, s.sc, w.pair_tp, w.pair_part,
-                                   p.seed, p.step, p.gamma);
+  k_pair_tp<MT, MIXED><<<pb, NT, 0, st>>>(s.r, m, s.vr, s.vt, s.id, s.sc, w.pair_tp,
+                                          w.pair_part, p.seed, p.step, p.gamma);
   k_dt_init<<<1, IT, 0, st>>>(w.pair_part, w.pair_blocks, w.dt_state, s.sc, p.target);
   const int iters = p.dt_iters > 0 ? p.dt_iters : 10;
   const int eb = static_cast<int>(w.pair_blocks < kRedBlocks ? w.pair_blocks : kRedBlocks);
   for (int i = 0; i < iters; ++i) {
-    k_dt_eval<<<eb, NT, 0, st>>>(w.pair_tp, s.sc, w.dt_state, w.red_part);
+    k_dt_eval<MIXED><<<eb, NT, 0, st>>>(w.pair_tp, s.sc, w.dt_state, w.red_part);
     k_dt_update<<<1, NT, 0, st>>>(w.red_part, eb, w.dt_state, s.sc, p.target,
                                   i == iters - 1 ? 1 : 0);
   }
   return hipGetLastError();
 }
 
-template <typename MT>
+template <typename MT, bool MIXED>
 hipError_t run_relax(const cmc_state &s, const Workspace &w, const cmc_params &p,
                      hipStream_t st) {
   const MT *m = static_cast<const MT *>(s.m);
-  k_relax<MT><<<static_cast<unsigned>(w.pair_blocks), NT, 0, st>>>(
+  k_relax<MT, MIXED><<<static_cast<unsigned>(w.pair_blocks), NT, 0, st>>>(
       s.r, m, s.vr, s.vt, s.id, s.sc, p.seed, p.step, p.gamma);
   return hipGetLastError();
+}
+
+template <typename MT>
+hipError_t timestep_p(const cmc_state &s, const Workspace &w, const cmc_params &p,
+                      hipStream_t st) {
+  return p.precision == CMC_MIXED ? run_timestep<MT, true>(s, w, p, st)
+                                  : run_timestep<MT, false>(s, w, p, st);
+}
+
+template <typename MT>
+hipError_t relax_p(const cmc_state &s, const Workspace &w, const cmc_params &p,
+                   hipStream_t st) {
+  return p.precision == CMC_MIXED ? run_relax<MT, true>(s, w, p, st)
+                                  : run_relax<MT, false>(s, w, p, st);
 }
 
 }  // namespace
 
 hipError_t launch_timestep(const cmc_state &s, const Workspace &w, const cmc_params &p,
                            hipStream_t st) {
-  return s.m_f32 ? run_timestep<float>(s, w, p, st) : run_timestep<double>(s, w, p, st);
+  return s.m_f32 ? timestep_p<float>(s, w, p, st) : timestep_p<double>(s, w, p, st);
 }
 
 hipError_t launch_relax(const cmc_state &s, const Workspace &w, const cmc_params &p,
                         hipStream_t st) {
-  return s.m_f32 ? run_relax<float>(s, w, p, st) : run_relax<double>(s, w, p, st);
+  return s.m_f32 ? relax_p<float>(s, w, p, st) : relax_p<double>(s, w, p, st);
 }
 
 }  // namespace cmc
