@@ -460,11 +460,15 @@ void ora_relax(int64_t n, const double *r, const double *m, double *vr, double *
  * The bound is F = bound_factor * max(g(-pi/2), g(pi/2)).  The table (r, Phi,
  * M) is frozen for the whole pass: the orbit is drawn in the old potential. */
 
-/* Q at table index k; sentinels k = -1 (r = 0) and k = n (r = inf). */
+/* Q at table index k; sentinels k = -1 (r = 0) and k = n (r = inf).  A star
+ * sitting exactly at r = 0 takes the limit r -> 0 of Q(r): -inf when J != 0
+ * (the J^2/r^2 term dominates, also against Phi = -inf from the star's own
+ * m/r), else 2E - 2 Phi_k. */
 static double q_at(int64_t n, const double *r, const double *phi, int64_t k, double E,
                    double J2) {
   if (k < 0) return -INFINITY;
   if (k >= n) return 2.0 * E;
+  if (r[k] == 0.0) return (J2 > 0.0) ? -INFINITY : 2.0 * E - 2.0 * phi[k];
   return 2.0 * E - 2.0 * phi[k] - J2 / (r[k] * r[k]);
 }
 

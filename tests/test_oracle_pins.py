@@ -374,6 +374,30 @@ def test_radial_orbit_j_zero(ora):
     assert stats.kstest(cdf, "uniform").pvalue > 1e-3
 
 
+def test_orbit_star_at_centre_is_the_limit(ora):
+    """A star exactly at r = 0 (its own m/r makes Phi_0 = -inf) gives every
+    other star the orbit it gets when that star sits at a radius so small
+    that J^2/r^2 overflows: Q at r -> 0 is the limit of Q(r)."""
+    rng = np.random.default_rng(4)
+    n = 3001
+    r = np.sort(np.concatenate([[0.0], rng.lognormal(0, 1, n - 1)]))
+    v = 0.5 * rng.standard_normal((n, 2))
+    m = np.full(n, 1.0 / n)
+    ids = np.arange(n, dtype=np.uint32)
+    out = []
+    for r0 in (0.0, 1e-300):
+        rr = r.copy()
+        rr[0] = r0
+        st = ora.State(rr, v[:, 0].copy(), np.abs(v[:, 1]), m, ids)
+        tab = ora.potential(st.r, st.m)
+        out.append(ora.orbit(st, tab, 3, 2, details=True))
+    assert np.isneginf(ora.potential(r, m)[0][0])
+    (a, _, _, _, da), (b, _, _, _, db) = out
+    assert np.array_equal(a[1:], b[1:])
+    assert np.array_equal(da["kmin"][1:], db["kmin"][1:])
+    assert np.sum(da["kmin"][1:] >= 0) > 0.5 * n
+
+
 def test_orbit_brackets_on_plummer(ora):
     st = ora.plummer(20_000, 3)
     tab = ora.potential(st.r, st.m)
