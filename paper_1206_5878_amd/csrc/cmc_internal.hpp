@@ -188,6 +188,53 @@ struct Levels {
   RPhi *lev[kMaxLevels];
   int nlev;  // levels in use for the capacity; the top one has <= 8 entries
 };
+// ---------------------------------------------------------------- radial index
+// Buckets over the sorted radii.  The bucket of a radius x >= r_0 is
+// (bits(x) - bits(r_0)) >> shift: the IEEE pattern of a non-negative double
+// is monotone in its value and close to linear in log x, so buckets are
+// roughly equal steps in log r.  start[b] is the first star whose bucket is
+// >= b (start[nb] = n), so the stars with r_k <= x all lie below start[b+1]
+// and all stars below start[b] have r_k < x.  shift makes the populated range
+// fit nb = 2^lg_nb buckets.
+struct RIndexCtl {
+  uint64_t lo, hi;  // bits of r_0 and r_(n-1)
+  uint32_t shift, n;
+};
+struct RIndex {
+  const double *r;         // the sorted radii
+  const uint32_t *start;   // [nb + 1]
+  const RIndexCtl *ctl;
+};
+
+__device__ __forceinline__ uint64_t rbits(double x) { return __builtin_bit_cast(uint64_t, x + 0.0); }
+
+// Last k with r_k <= x (-1 if none; n - 1 for x >= r_(n-1)).  c is *ix.ctl,
+// loaded once by the caller.
+__device__ __forceinline__ int64_t rindex_last_le(const RIndex &ix, const RIndexCtl &c,
+                                                  double x) {
+  const uint64_t kx = rbits(x);  // ordered like x for x >= 0
+  if (kx < c.lo) return -1;
+  if (kx >= c.hi) return static_cast<int64_t>(c.n) - 1;
+  const uint64_t b = (kx - c.lo) >> c.shift;
+  int64_t lo = ix.start[b], hi = ix.start[b + 1];
+  // r_k <= x for k < lo, r_k > x for k >= hi: the answer is the last k in
+  // [lo - 1, hi - 1] with r_k <= x; halve long ranges, then scan
+  while (hi - lo > 16) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if (ix.r[mid] <= x) lo = mid + 1; else hi = mid;
+  }
+  for (;;) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = (lo + q < hi) ? ix.r[lo + q] : kInf;
+    int c2 = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) c2 += (v[q] <= x) ? 1 : 0;
+    lo += c2;
+    if (c2 < 8 || lo >= hi) return lo - 1;
+  }
+}
+
 // ---------------------------------------------------------------- workspace
 constexpr int kSortTile = 4096;  // keys per radix tile (256 threads x 16)
 constexpr int kPotTile = 2048;   // stars per potential tile (256 x 8)
@@ -212,6 +259,11 @@ struct Workspace {
   double *pair_part;        // [4 * pair_blocks]
   double *dt_state;         // [32]
   double *red_part;         // [8 * star_blocks]  generic per-block partials
+  uint32_t *rx_start;       // [rx_nb + 1] radial index buckets
+  uint32_t *rx_tile;        // [cdiv(rx_nb + 1, 4096)] prefix-maximum tiles
+  RIndexCtl *rx_ctl;        // [1]
+  int64_t rx_nb;
+  int rx_lg_nb;
   int64_t sort_tiles, pot_tiles, pair_blocks, star_blocks;
   size_t bytes;
 };
@@ -260,6 +312,12 @@ inline Workspace layout(int64_t cap, void *base) {
   w.pair_part = reinterpret_cast<double *>(take(8 * 4 * w.pair_blocks));
   w.dt_state = reinterpret_cast<double *>(take(8 * 32));
   w.red_part = reinterpret_cast<double *>(take(8 * 8 * w.star_blocks));
+  w.rx_lg_nb = 0;
+  while ((int64_t(1) << w.rx_lg_nb) < (c + 1) / 2) ++w.rx_lg_nb;
+  w.rx_nb = int64_t(1) << w.rx_lg_nb;
+  w.rx_start = reinterpret_cast<uint32_t *>(take(4 * (w.rx_nb + 1)));
+  w.rx_tile = reinterpret_cast<uint32_t *>(take(4 * cdiv(w.rx_nb + 1, 4096)));
+  w.rx_ctl = reinterpret_cast<RIndexCtl *>(take(sizeof(RIndexCtl)));
   w.bytes = (off + 255) & ~size_t(255);
   return w;
 }
@@ -298,6 +356,11 @@ hipError_t launch_relax(const cmc_state &s, const Workspace &w, const cmc_params
 hipError_t launch_orbit(const cmc_state &s, const Workspace &w, const cmc_params &p,
                         bool to_stage, hipStream_t st);
 hipError_t launch_table_pack(const cmc_state &s, const Workspace &w, hipStream_t st);
+// radial index over the sorted radii s.r[0, sc->n)
+hipError_t launch_rindex(const cmc_state &s, const Workspace &w, hipStream_t st);
+inline RIndex rindex_of(const cmc_state &s, const Workspace &w) {
+  return RIndex{s.r, w.rx_start, w.rx_ctl};
+}
 hipError_t launch_stage_from_state(const cmc_state &s, const Workspace &w, hipStream_t st);
 hipError_t launch_sort_stage(const cmc_state &s, const Workspace &w, bool normalise_mass,
                              hipStream_t st);

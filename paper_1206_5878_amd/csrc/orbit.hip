@@ -10,35 +10,56 @@
 // The mixed form draws the trial angle and takes the accept test in FP32;
 // brackets, roots, the table and Q stay in FP64.
 //
-// Two kernels.  k_orbit_bracket: one thread per star, brackets, roots and the
-// rejection bound F, written as a 48-byte orbit record (escapers and
-// degenerate orbits are finished there).  k_orbit_trials: each wavefront owns
-// a chunk of stars and every lane draws trials for one star at a time,
-// taking the chunk's next star as soon as its own is accepted, so the loop
-// does not wait for the unluckiest lane of the wavefront.
+// Two kernels.  k_orbit_bracket: brackets, roots and the rejection bound F
+// of every star, written as a 48-byte orbit record (escapers and degenerate
+// orbits are finished there); its blocks stay resident and loop over tiles
+// of stars.  k_orbit_trials: each wavefront owns a chunk of stars and every
+// lane draws trials for one star at a time, taking the chunk's next star as
+// soon as its own is accepted, so the loop does not wait for the unluckiest
+// lane of the wavefront.
 //
-// Searches.  The lower bracket, the upper bracket and the interval of a trial
-// radius are each "the last index k where a predicate monotone in k holds".
-// They descend the sampled levels of the table (level L = every 8^L-th
-// (r, Phi)): per level, the 8 children of the current sample are one aligned
-// cache line; the count of children that satisfy the predicate is the next
-// sample.  Brackets and intervals are unique, so this finds the index a
-// bisection over the whole table finds.
+// Searches.  The lower and the upper bracket are each "the last index k
+// where a predicate monotone in k holds".  They descend the sampled levels of
+// the table (level L = every 8^L-th (r, Phi)): per level, the 8 children of
+// the current sample are one aligned cache line, and the count of children
+// that satisfy the predicate is the next sample.  The top levels (a few
+// thousand entries) sit in LDS and each lane descends them alone; below
+// them, lanes work in groups of 8 so that every node is one coalesced load.
+// Brackets are unique, so this finds the index a bisection over the whole
+// table finds.  The interval of a trial radius comes from the radial bucket
+// index (rindex.hip).
+#include <algorithm>
+
 #include "cmc_internal.hpp"
 
 namespace cmc {
 namespace {
 
 constexpr int NT = kBlock;
+constexpr int BT = 512;         // threads per block of the bracket kernel
+constexpr int kBracketGrid = 1024;  // its blocks (each loops over tiles)
 constexpr int kChunk = 128;     // stars per wavefront in the trial kernel
-constexpr int kGroupBatch = 4;  // group searches whose loads are in flight together
+constexpr int kGroupBatch = 8;  // group searches whose loads are in flight together
+static_assert(16 % kGroupBatch == 0, "batches split the 16 searches of a group");
 
-// Q_k < 0 as (2E - 2Phi_k) r_k^2 < J^2 (r_k > 0): no division in the descent.
+// Sign of Q_k = 2E - 2Phi_k - J^2/r_k^2 without the division:
+// (2E - 2Phi_k) r_k^2 against J^2.  A star at r_k = 0 takes the limit r -> 0:
+// Q = -inf when J != 0 (the J^2/r^2 term wins, even against Phi_k = -inf),
+// else 2E - 2Phi_k.
+__device__ __forceinline__ bool q_neg(double twoE, double J2, const RPhi &e) {
+  if (e.r == 0.0) return J2 > 0.0 || twoE - 2.0 * e.phi < 0.0;
+  return (twoE - 2.0 * e.phi) * (e.r * e.r) < J2;
+}
+__device__ __forceinline__ bool q_nonneg(double twoE, double J2, const RPhi &e) {
+  if (e.r == 0.0) return J2 == 0.0 && twoE - 2.0 * e.phi >= 0.0;
+  return (twoE - 2.0 * e.phi) * (e.r * e.r) >= J2;
+}
+// Q_k < 0 and k < below.
 struct QNeg {
   double twoE, J2;
-  int64_t below;  // only indices < below can hold
+  int64_t below;
   __device__ bool operator()(int64_t k, const RPhi &e) const {
-    return k < below && (twoE - 2.0 * e.phi) * (e.r * e.r) < J2;
+    return k < below && q_neg(twoE, J2, e);
   }
 };
 // Q_k >= 0 or k <= upto.
@@ -46,41 +67,9 @@ struct QNonNeg {
   double twoE, J2;
   int64_t upto;
   __device__ bool operator()(int64_t k, const RPhi &e) const {
-    return k <= upto || (twoE - 2.0 * e.phi) * (e.r * e.r) >= J2;
+    return k <= upto || q_nonneg(twoE, J2, e);
   }
 };
-// r_k <= x.
-struct RBelow {
-  double x;
-  __device__ bool operator()(int64_t, const RPhi &e) const { return e.r <= x; }
-};
-
-// Last k in [0, n-1] with pred(k) true (-1 if none); pred must be monotone
-// (true ... true false ... false).  Levels are unrolled so each level's base
-// pointer is a kernel-argument register.
-template <class Pred>
-__device__ __forceinline__ int64_t last_true(const Levels &lv, int64_t n, const Pred &pred) {
-  if (!pred(0, lv.lev[0][0])) return -1;
-  int64_t s = 0;  // sample 0 of a virtual level above the top: index 0
-#pragma unroll
-  for (int L = kMaxLevels - 1; L >= 0; --L) {
-    if (L < lv.nlev) {
-      const int64_t stride = int64_t(1) << (3 * L);
-      const int64_t cnt = (n + stride - 1) / stride;
-      const int64_t base = s * 8;  // child 0 is the current sample: known true
-      const RPhi *blk = lv.lev[L] + base;
-      RPhi e[7];
-#pragma unroll
-      for (int q = 0; q < 7; ++q) e[q] = (base + 1 + q < cnt) ? blk[1 + q] : RPhi{0.0, 0.0};
-      int c = 0;
-#pragma unroll
-      for (int q = 0; q < 7; ++q)
-        if (base + 1 + q < cnt && pred((base + 1 + q) * stride, e[q])) c = q + 1;
-      s = base + c;
-    }
-  }
-  return s;
-}
 
 // Potential inside interval k from the defining sum: -(M_k / x + S_k); flat
 // at Phi_0 inside the innermost star.
@@ -99,9 +88,9 @@ __device__ __forceinline__ double dq_in(const MS *__restrict__ ms, int64_t k, do
 
 // Interval of x for the potential: the last k with r_k <= x, kept inside the
 // orbit's brackets [kmin, kmax].
-__device__ __forceinline__ int64_t interval_in(const Levels &lv, int64_t n, double x,
+__device__ __forceinline__ int64_t interval_in(const RIndex &ix, const RIndexCtl &c, double x,
                                                int64_t kmin, int64_t kmax) {
-  int64_t k = last_true(lv, n, RBelow{x});
+  const int64_t k = rindex_last_le(ix, c, x);
   return k < kmin ? kmin : (k > kmax ? kmax : k);
 }
 
@@ -113,72 +102,119 @@ __device__ __forceinline__ int64_t interval_in(const Levels &lv, int64_t n, doub
 // and a ballot counts the children that satisfy the predicate.  Predicate
 // parameters travel through LDS.  Every lane of the wavefront must call it.
 struct GParams {
-  double a, b;  // QNeg/QNonNeg: 2E, J^2; RBelow: x
+  double a, b;  // QNeg/QNonNeg: 2E, J^2
   int32_t c;    // QNeg: below; QNonNeg: upto
-  int32_t on;   // lane has a search
+  int32_t s0;   // sample reached at level ltop (-1: no index holds)
 };
 struct GQNeg {
   __device__ static bool eval(const GParams &p, int64_t k, const RPhi &e) {
-    return k < p.c && (p.a - 2.0 * e.phi) * (e.r * e.r) < p.b;
+    return k < p.c && q_neg(p.a, p.b, e);
   }
 };
 struct GQNonNeg {
   __device__ static bool eval(const GParams &p, int64_t k, const RPhi &e) {
-    return k <= p.c || (p.a - 2.0 * e.phi) * (e.r * e.r) >= p.b;
+    return k <= p.c || q_nonneg(p.a, p.b, e);
   }
 };
-struct GRBelow {
-  __device__ static bool eval(const GParams &p, int64_t, const RPhi &e) { return e.r <= p.a; }
-};
 
-template <class Pred>
-__device__ __forceinline__ int64_t group_last_true(const Levels &lv, int64_t n, const GParams &mine,
-                                                   GParams *wave_prm) {
+// Descent of the levels below ltop for two searches per lane (predicates PA
+// and PB, e.g. the lower and the upper bracket).  Each lane brings the
+// samples its own searches reached at level ltop (see top_descend; -1: no
+// index holds).  All 16 searches of a group have their loads in flight
+// together, so a level costs one memory round trip.
+template <class PA, class PB>
+__device__ __forceinline__ void group_descend2(const Levels &lv, int ltop, int64_t n,
+                                               const GParams &ma, const GParams &mb,
+                                               GParams *prm_a, GParams *prm_b, int64_t &ka,
+                                               int64_t &kb) {
   const int lane = threadIdx.x & 63, g = lane >> 3, q = lane & 7;
-  wave_prm[lane] = mine;
+  prm_a[lane] = ma;
+  prm_b[lane] = mb;
   __builtin_amdgcn_wave_barrier();
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  const RPhi root = lv.lev[0][0];
-  int32_t s[8];
+  int32_t s[16];
 #pragma unroll
   for (int t = 0; t < 8; ++t) {
-    const GParams p = wave_prm[(g << 3) + t];
-    s[t] = (p.on && Pred::eval(p, 0, root)) ? 0 : -1;
+    s[t] = prm_a[(g << 3) + t].s0;
+    s[8 + t] = prm_b[(g << 3) + t].s0;
   }
 #pragma unroll
   for (int L = kMaxLevels - 1; L >= 0; --L) {
-    if (L < lv.nlev) {
+    if (L < ltop) {
+      // re-read the parameters from LDS at every level rather than keep
+      // 16 sets of them live in registers
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
       const int64_t stride = int64_t(1) << (3 * L);
       const int64_t cnt = (n + stride - 1) / stride;
       const RPhi *lev = lv.lev[L];
 #pragma unroll
-      for (int h = 0; h < 8; h += kGroupBatch) {  // batches bound the live registers
+      for (int h = 0; h < 16; h += kGroupBatch) {
         RPhi e[kGroupBatch];
 #pragma unroll
-        for (int u = 0; u < kGroupBatch; ++u) {
-          const int64_t child = static_cast<int64_t>(s[h + u]) * 8 + q;
-          e[u] = (s[h + u] >= 0 && child < cnt) ? lev[child] : RPhi{0.0, 0.0};
+        for (int v = 0; v < kGroupBatch; ++v) {
+          const int u = h + v;
+          const int64_t child = static_cast<int64_t>(s[u]) * 8 + q;
+          e[v] = (s[u] >= 0 && child < cnt) ? lev[child] : RPhi{0.0, 0.0};
         }
 #pragma unroll
-        for (int u = 0; u < kGroupBatch; ++u) {
-          const int t = h + u;
-          const GParams p = wave_prm[(g << 3) + t];
-          const int64_t child = static_cast<int64_t>(s[t]) * 8 + q;
-          const bool ok = s[t] >= 0 && child < cnt && Pred::eval(p, child * stride, e[u]);
+        for (int v = 0; v < kGroupBatch; ++v) {
+          const int u = h + v;
+          const GParams p = (u < 8) ? prm_a[(g << 3) + u] : prm_b[(g << 3) + u - 8];
+          const int64_t child = static_cast<int64_t>(s[u]) * 8 + q;
+          const bool in = s[u] >= 0 && child < cnt;
+          const bool ok = in && ((u < 8) ? PA::eval(p, child * stride, e[v])
+                                         : PB::eval(p, child * stride, e[v]));
           const uint64_t m = __ballot(ok);
           const int c = __popcll((m >> (g << 3)) & 0xFFull);
-          if (s[t] >= 0) s[t] = s[t] * 8 + c - 1;
+          if (s[u] >= 0) s[u] = s[u] * 8 + c - 1;
         }
       }
     }
   }
   __builtin_amdgcn_wave_barrier();
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  int32_t r = s[0];
+  int32_t ra = s[0], rb = s[8];
 #pragma unroll
-  for (int t = 1; t < 8; ++t)
-    if (q == t) r = s[t];
-  return r;
+  for (int t = 1; t < 8; ++t) {
+    if (q == t) {
+      ra = s[t];
+      rb = s[8 + t];
+    }
+  }
+  ka = ra;
+  kb = rb;
+}
+
+// ---------------------------------------------------------------- LDS top
+// The levels [ltop, nlev) -- a few thousand entries -- are copied into LDS by
+// every block of the bracket kernel; each lane descends them on its own.
+struct TopLevels {
+  int32_t off[kMaxLevels];  // LDS entry offset of level L, for L >= ltop
+  int32_t len[kMaxLevels];  // entries of level L at the capacity
+  int32_t ltop, entries;
+};
+constexpr int kTopBytes = 48 * 1024;
+
+template <class Pred>
+__device__ __forceinline__ int32_t top_descend(const RPhi *top, const TopLevels &tl, int nlev,
+                                               int64_t n, const Pred &pred) {
+  if (!pred(0, top[tl.off[nlev - 1]])) return -1;
+  int64_t s = 0;
+#pragma unroll
+  for (int L = kMaxLevels - 1; L >= 0; --L) {
+    if (L < nlev && L >= tl.ltop) {
+      const int64_t stride = int64_t(1) << (3 * L);
+      const int64_t cnt = (n + stride - 1) / stride;
+      const int64_t base = s * 8;
+      const RPhi *blk = top + tl.off[L] + base;
+      int c = 0;
+#pragma unroll
+      for (int q = 1; q < 8; ++q)
+        if (base + q < cnt && pred((base + q) * stride, blk[q])) c = q;
+      s = base + c;
+    }
+  }
+  return static_cast<int32_t>(s);
 }
 
 // Star outputs: staged record + sort key, or the state arrays in place.
@@ -226,110 +262,125 @@ __device__ __forceinline__ void or_status(cmc_scalars *sc, uint32_t fl) {
 }
 
 template <typename MT, bool TO_STAGE>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5)))
-void k_orbit_bracket(Levels lv, const MS *__restrict__ ms, const MT *__restrict__ m,
-                     double *__restrict__ vr, double *__restrict__ vt,
-                     const uint32_t *__restrict__ id, double *__restrict__ r_new,
-                     StageRec *__restrict__ stage, uint64_t *__restrict__ keys,
-                     OrbitRec *__restrict__ orec, cmc_scalars *__restrict__ sc,
-                     double *__restrict__ part, uint64_t seed, uint32_t step,
-                     double bound_factor) {
-  __shared__ double shd[NT / 64];
-  __shared__ GParams prm[NT];
-  const int64_t n = sc->n;
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
-  double c_esc = 0.0, e_esc = 0.0;
-  uint32_t fl = 0;
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4)))
+void k_orbit_bracket(Levels lv, TopLevels tl, RIndex ix, const MS *__restrict__ ms,
+                     const MT *__restrict__ m, double *__restrict__ vr,
+                     double *__restrict__ vt, const uint32_t *__restrict__ id,
+                     double *__restrict__ r_new, StageRec *__restrict__ stage,
+                     uint64_t *__restrict__ keys, OrbitRec *__restrict__ orec,
+                     cmc_scalars *__restrict__ sc, double *__restrict__ part, uint64_t seed,
+                     uint32_t step, double bound_factor) {
+  extern __shared__ RPhi top[];
+  __shared__ double shd[BT / 64];
+  __shared__ GParams prm[2 * BT];
+  const RIndexCtl ictl = *ix.ctl;
+  const int64_t n = ictl.n;
   const RPhi *tab = lv.lev[0];
   GParams *wprm = prm + (threadIdx.x & ~63);
+  for (int L = tl.ltop; L < lv.nlev; ++L)
+    for (int e = threadIdx.x; e < tl.len[L]; e += BT) top[tl.off[L] + e] = lv.lev[L][e];
+  __syncthreads();
 
-  // brackets of every bound star, searched by groups of 8 lanes
-  double E = 0.0, J = 0.0, J2 = 0.0, vri = 0.0, vti = 0.0;
-  if (i < n) {
-    const RPhi me = tab[i];
-    vri = vr[i];
-    vti = vt[i];
-    E = me.phi + 0.5 * (vri * vri + vti * vti);
-    J = me.r * vti;
-    J2 = J * J;
-  }
-  const bool bound = i < n && E < 0.0;
-  const int32_t ii = static_cast<int32_t>(i);
-  const int64_t kmin_g = group_last_true<GQNeg>(lv, n, GParams{2.0 * E, J2, ii, bound}, wprm);
-  const int64_t kmax_g = group_last_true<GQNonNeg>(lv, n, GParams{2.0 * E, J2, ii, bound}, wprm);
+  double c_esc = 0.0, e_esc = 0.0;
+  uint32_t fl = 0;
+  const int64_t tiles = (n + BT - 1) / BT;
+  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {  // block-uniform
+    const int64_t i = tile * BT + threadIdx.x;
+    double E = 0.0, J = 0.0, J2 = 0.0, vri = 0.0, vti = 0.0;
+    if (i < n) {
+      const RPhi me = tab[i];
+      vri = vr[i];
+      vti = vt[i];
+      E = me.phi + 0.5 * (vri * vri + vti * vti);
+      J = me.r * vti;
+      J2 = J * J;
+    }
+    const bool bound = i < n && E < 0.0;
+    const int32_t ii = static_cast<int32_t>(i);
+    // brackets: the LDS levels per lane, the rest by groups of 8 lanes
+    int32_t t0 = -1, t1 = -1;
+    if (bound) {
+      t0 = top_descend(top, tl, lv.nlev, n, QNeg{2.0 * E, J2, ii});
+      t1 = top_descend(top, tl, lv.nlev, n, QNonNeg{2.0 * E, J2, ii});
+    }
+    int64_t kmin_g, kmax_g;
+    group_descend2<GQNeg, GQNonNeg>(lv, tl.ltop, n, GParams{2.0 * E, J2, ii, t0},
+                                    GParams{2.0 * E, J2, ii, t1}, wprm, wprm + BT, kmin_g,
+                                    kmax_g);
 
-  if (i < n) {
-    OrbitRec rec{E, J, 0.0, 0.0, -1.0, 0, 0};
-    if (!(E < 0.0)) {  // unbound: leaves the cluster
-      c_esc = 1.0;
-      e_esc = load_mass(m, i) * E;
-      fl |= CMC_ST_ESCAPER;
-      if (E != E) fl |= CMC_ST_NONFINITE;
-      emit<TO_STAGE>(i, kInf, vri, vti, load_mass(m, i), id[i], r_new, vr, vt, stage, keys);
-    } else {
-      const int64_t kmin = kmin_g, kmax = kmax_g;
-      double rmin, rmax;
-      if (J2 == 0.0) {
-        rmin = 0.0;
-      } else if (kmin < 0) {
-        rmin = J / sqrt(2.0 * (E - tab[0].phi));
+    if (i < n) {
+      OrbitRec rec{E, J, 0.0, 0.0, -1.0, 0, 0};
+      if (!(E < 0.0)) {  // unbound: leaves the cluster
+        c_esc = 1.0;
+        e_esc = load_mass(m, i) * E;
+        fl |= CMC_ST_ESCAPER;
+        if (E != E) fl |= CMC_ST_NONFINITE;
+        emit<TO_STAGE>(i, kInf, vri, vti, load_mass(m, i), id[i], r_new, vr, vt, stage, keys);
       } else {
-        const MS t = ms[kmin];
-        const double a = 2.0 * (E + t.S);
-        const double b = 2.0 * t.M;
-        const double disc = b * b + 4.0 * a * J2;
-        const double den = b + sqrt(disc > 0.0 ? disc : 0.0);
-        rmin = den > 0.0 ? 2.0 * J2 / den : tab[kmin].r;
-      }
-      {
-        const double rl = kmin >= 0 ? tab[kmin].r : 0.0, rh = tab[kmin + 1].r;
-        rmin = rmin < rl ? rl : (rmin > rh ? rh : rmin);
-      }
-      {
-        const MS t = ms[kmax];
-        const double a = 2.0 * (E + t.S);
-        const double b = 2.0 * t.M;
-        const double disc = b * b + 4.0 * a * J2;
-        const double sq = sqrt(disc > 0.0 ? disc : 0.0);
-        const double rl = tab[kmax].r;
-        const double rh = (kmax + 1 < n) ? tab[kmax + 1].r : kInf;
-        rmax = a < 0.0 ? (b + sq) / (-2.0 * a) : rh;
-        rmax = rmax < rl ? rl : (rmax > rh ? rh : rmax);
-      }
-      const double rc = 0.5 * (rmax + rmin), ra = 0.5 * (rmax - rmin);
-      double F = -1.0;
-      double rdone = rmin;  // radius of an orbit finished without trials
-      if (ra > 0.0) {
-        const double glo = (J2 != 0.0) ? sqrt(2.0 * ra / fabs(dq_in(ms, kmin, rmin, J2))) : 0.0;
-        const double ghi = sqrt(2.0 * ra / fabs(dq_in(ms, kmax, rmax, J2)));
-        F = bound_factor * (glo > ghi ? glo : ghi);
-        if (!(F > 0.0 && F < kInf)) {
-          F = -1.0;
-          rdone = rc;
-          fl |= CMC_ST_NUMERIC;
+        const int64_t kmin = kmin_g, kmax = kmax_g;
+        double rmin, rmax;
+        if (J2 == 0.0) {
+          rmin = 0.0;
+        } else if (kmin < 0) {
+          rmin = J / sqrt(2.0 * (E - tab[0].phi));
+        } else {
+          const MS t = ms[kmin];
+          const double a = 2.0 * (E + t.S);
+          const double b = 2.0 * t.M;
+          const double disc = b * b + 4.0 * a * J2;
+          const double den = b + sqrt(disc > 0.0 ? disc : 0.0);
+          rmin = den > 0.0 ? 2.0 * J2 / den : tab[kmin].r;
+        }
+        {
+          const double rl = kmin >= 0 ? tab[kmin].r : 0.0, rh = tab[kmin + 1].r;
+          rmin = rmin < rl ? rl : (rmin > rh ? rh : rmin);
+        }
+        {
+          const MS t = ms[kmax];
+          const double a = 2.0 * (E + t.S);
+          const double b = 2.0 * t.M;
+          const double disc = b * b + 4.0 * a * J2;
+          const double sq = sqrt(disc > 0.0 ? disc : 0.0);
+          const double rl = tab[kmax].r;
+          const double rh = (kmax + 1 < n) ? tab[kmax + 1].r : kInf;
+          rmax = a < 0.0 ? (b + sq) / (-2.0 * a) : rh;
+          rmax = rmax < rl ? rl : (rmax > rh ? rh : rmax);
+        }
+        const double rc = 0.5 * (rmax + rmin), ra = 0.5 * (rmax - rmin);
+        double F = -1.0;
+        double rdone = rmin;  // radius of an orbit finished without trials
+        if (ra > 0.0) {
+          const double glo = (J2 != 0.0) ? sqrt(2.0 * ra / fabs(dq_in(ms, kmin, rmin, J2))) : 0.0;
+          const double ghi = sqrt(2.0 * ra / fabs(dq_in(ms, kmax, rmax, J2)));
+          F = bound_factor * (glo > ghi ? glo : ghi);
+          if (!(F > 0.0 && F < kInf)) {
+            F = -1.0;
+            rdone = rc;
+            fl |= CMC_ST_NUMERIC;
+          }
+        }
+        if (F > 0.0) {
+          rec.rmin = rmin;
+          rec.rmax = rmax;
+          rec.F = F;
+          rec.kmin = static_cast<int32_t>(kmin);
+          rec.kmax = static_cast<int32_t>(kmax);
+        } else {
+          const double rn = rdone + 0.0;
+          const int64_t kn = interval_in(ix, ictl, rn, kmin, kmax);
+          const double qn = 2.0 * E - 2.0 * phi_in(lv, ms, kn, rn) -
+                            (J2 == 0.0 ? 0.0 : J2 / (rn * rn));
+          double vrn, vtn;
+          finish(rn, qn, J, J2, id[i], step, seed, vrn, vtn, fl);
+          emit<TO_STAGE>(i, rn, vrn, vtn, load_mass(m, i), id[i], r_new, vr, vt, stage, keys);
         }
       }
-      if (F > 0.0) {
-        rec.rmin = rmin;
-        rec.rmax = rmax;
-        rec.F = F;
-        rec.kmin = static_cast<int32_t>(kmin);
-        rec.kmax = static_cast<int32_t>(kmax);
-      } else {
-        const double rn = rdone + 0.0;
-        const int64_t kn = interval_in(lv, n, rn, kmin, kmax);
-        const double qn = 2.0 * E - 2.0 * phi_in(lv, ms, kn, rn) -
-                          (J2 == 0.0 ? 0.0 : J2 / (rn * rn));
-        double vrn, vtn;
-        finish(rn, qn, J, J2, id[i], step, seed, vrn, vtn, fl);
-        emit<TO_STAGE>(i, rn, vrn, vtn, load_mass(m, i), id[i], r_new, vr, vt, stage, keys);
-      }
+      orec[i] = rec;
     }
-    orec[i] = rec;
   }
   or_status(sc, fl);
-  c_esc = block_sum<NT>(c_esc, shd);
-  e_esc = block_sum<NT>(e_esc, shd);
+  c_esc = block_sum<BT>(c_esc, shd);
+  e_esc = block_sum<BT>(e_esc, shd);
   if (threadIdx.x == 0) {
     part[2 * static_cast<int64_t>(blockIdx.x)] = c_esc;
     part[2 * static_cast<int64_t>(blockIdx.x) + 1] = e_esc;
@@ -338,7 +389,7 @@ void k_orbit_bracket(Levels lv, const MS *__restrict__ ms, const MT *__restrict_
 
 template <typename MT, bool TO_STAGE, bool MIXED>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5)))
-void k_orbit_trials(Levels lv, const MS *__restrict__ ms, const MT *__restrict__ m,
+void k_orbit_trials(Levels lv, RIndex ix, const MS *__restrict__ ms, const MT *__restrict__ m,
                     double *__restrict__ vr, double *__restrict__ vt,
                     const uint32_t *__restrict__ id, double *__restrict__ r_new,
                     StageRec *__restrict__ stage, uint64_t *__restrict__ keys,
@@ -346,9 +397,8 @@ void k_orbit_trials(Levels lv, const MS *__restrict__ ms, const MT *__restrict__
                     double *__restrict__ part, uint64_t seed, uint32_t step,
                     int32_t trial_cap) {
   __shared__ double shd[NT / 64];
-  __shared__ GParams prm[NT];
-  GParams *wprm = prm + (threadIdx.x & ~63);
-  const int64_t n = sc->n;
+  const RIndexCtl ictl = *ix.ctl;
+  const int64_t n = ictl.n;
   const int lane = threadIdx.x & 63;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t wave = static_cast<int64_t>(blockIdx.x) * (NT / 64) + (threadIdx.x >> 6);
@@ -397,26 +447,35 @@ void k_orbit_trials(Levels lv, const MS *__restrict__ ms, const MT *__restrict__
     double X2 = 0.0, cs = 0.0;
     if (busy) {
       const U4 w = philox(sid, step, kOrbit, static_cast<uint32_t>(j), seed);
-      double ss;
-      if (MIXED) {  // trial angle and acceptance in FP32
-        const float s0 = static_cast<float>(kPi) * (u01f(w.y) - 0.5f);
-        float ssf, csf;
-        sincosf(s0, &ssf, &csf);
-        ss = ssf;
-        cs = csf;
+      if (MIXED) {
+        // Trial angle and acceptance in FP32.  With s = pi (X - 1/2), the
+        // offset of r from the nearer turning point is r_a (1 - |sin s|) =
+        // 2 r_a sin^2(pi X' / 2), X' = min(X, 1 - X) (exact in FP32), and
+        // cos s = sin(pi X'): both keep full relative precision near the
+        // turning points, where rc + ra sin s in FP32 would round the offset
+        // to a multiple of 2^-24 r_a.
+        const float X = u01f(w.y);
+        const bool upper = X > 0.5f;
+        const float Xl = upper ? 1.0f - X : X;
+        float hs, hc;
+        sincosf(static_cast<float>(0.5 * kPi) * Xl, &hs, &hc);
+        const double off = 2.0 * ra * static_cast<double>(hs * hs);
+        r0 = upper ? (rc + ra) - off : (rc - ra) + off;
+        cs = 2.0f * hs * hc;
         X2 = u01f(w.w);
       } else {
         const double X = u01(w.y, w.x);
         X2 = u01(w.w, w.z);
         const double s0 = kPi * (X - 0.5);
+        double ss;
         sincos(s0, &ss, &cs);
+        r0 = rc + ra * ss;
       }
-      r0 = rc + ra * ss;
       ++j;
       ++c_tr;
     }
-    const int64_t kg = group_last_true<GRBelow>(lv, n, GParams{r0, 0.0, 0, busy}, wprm);
     if (busy) {
+      const int64_t kg = rindex_last_le(ix, ictl, r0);
       const int64_t k0 = kg < kmin ? kmin : (kg > kmax ? kmax : kg);
       const double q0 = 2.0 * E - 2.0 * phi_in(lv, ms, k0, r0) - J2 / (r0 * r0);
       bool done = false;
@@ -447,7 +506,7 @@ void k_orbit_trials(Levels lv, const MS *__restrict__ ms, const MT *__restrict__
         ++c_cap;
         fl |= CMC_ST_TRIAL_CAP;
         const double rn = r0 + 0.0;
-        const int64_t kn = interval_in(lv, n, rn, kmin, kmax);
+        const int64_t kn = interval_in(ix, ictl, rn, kmin, kmax);
         qn = 2.0 * E - 2.0 * phi_in(lv, ms, kn, rn) - (J2 == 0.0 ? 0.0 : J2 / (rn * rn));
       }
       if (done) {
@@ -509,6 +568,24 @@ __global__ __launch_bounds__(NT) void k_table_pack(const double *__restrict__ r,
   put_table(lv, ms, k, r[k], phi[k], mcum[k], ssuf[k]);
 }
 
+// Levels from the top down while they fit kTopBytes of LDS.
+TopLevels top_levels(const Workspace &w, int64_t cap) {
+  TopLevels tl{};
+  int64_t tot = 0;
+  tl.ltop = w.nlev;
+  for (int L = w.nlev - 1; L >= 0; --L) {
+    const int64_t stride = int64_t(1) << (3 * L);
+    const int64_t len = (cap + stride - 1) / stride;
+    if ((tot + len) * static_cast<int64_t>(sizeof(RPhi)) > kTopBytes) break;
+    tl.off[L] = static_cast<int32_t>(tot);
+    tl.len[L] = static_cast<int32_t>(len);
+    tot += len;
+    tl.ltop = L;
+  }
+  tl.entries = static_cast<int32_t>(tot);
+  return tl;
+}
+
 template <typename MT, bool TO_STAGE>
 hipError_t run2(const cmc_state &s, const Workspace &w, const cmc_params &p, hipStream_t st) {
   const bool mixed = p.precision == CMC_MIXED;
@@ -516,21 +593,26 @@ hipError_t run2(const cmc_state &s, const Workspace &w, const cmc_params &p, hip
   const int32_t cap = p.trial_cap > 0 ? p.trial_cap : 10000;
   const double bf = p.bound_factor > 0.0 ? p.bound_factor : 1.2;
   const Levels lv = levels_of(w);
-  const unsigned nba = static_cast<unsigned>(w.star_blocks);
+  const TopLevels tl = top_levels(w, s.cap > 0 ? s.cap : 1);
+  const int64_t nga = std::min<int64_t>(cdiv(s.cap > 0 ? s.cap : 1, BT), kBracketGrid);
   const int64_t nbb = cdiv(s.cap, int64_t(kChunk) * (NT / 64));
   double *pa = w.red_part, *pb = w.red_part + 2 * w.star_blocks;
-  k_orbit_bracket<MT, TO_STAGE><<<nba, NT, 0, st>>>(lv, w.ms, m, s.vr, s.vt, s.id, s.r_new,
-                                                    w.stage, w.keys[0], w.orec, s.sc, pa,
-                                                    p.seed, p.step, bf);
+  const RIndex ix = rindex_of(s, w);
+  hipError_t e = launch_rindex(s, w, st);
+  if (e != hipSuccess) return e;
+  k_orbit_bracket<MT, TO_STAGE>
+      <<<static_cast<unsigned>(nga), BT, sizeof(RPhi) * tl.entries, st>>>(
+          lv, tl, ix, w.ms, m, s.vr, s.vt, s.id, s.r_new, w.stage, w.keys[0], w.orec, s.sc, pa,
+          p.seed, p.step, bf);
   if (mixed)
     k_orbit_trials<MT, TO_STAGE, true><<<static_cast<unsigned>(nbb), NT, 0, st>>>(
-        lv, w.ms, m, s.vr, s.vt, s.id, s.r_new, w.stage, w.keys[0], w.orec, s.sc, pb, p.seed,
+        lv, ix, w.ms, m, s.vr, s.vt, s.id, s.r_new, w.stage, w.keys[0], w.orec, s.sc, pb, p.seed,
         p.step, cap);
   else
     k_orbit_trials<MT, TO_STAGE, false><<<static_cast<unsigned>(nbb), NT, 0, st>>>(
-        lv, w.ms, m, s.vr, s.vt, s.id, s.r_new, w.stage, w.keys[0], w.orec, s.sc, pb, p.seed,
+        lv, ix, w.ms, m, s.vr, s.vt, s.id, s.r_new, w.stage, w.keys[0], w.orec, s.sc, pb, p.seed,
         p.step, cap);
-  k_orbit_sum<<<1, FT, 0, st>>>(pa, w.star_blocks, pb, nbb, s.sc);
+  k_orbit_sum<<<1, FT, 0, st>>>(pa, nga, pb, nbb, s.sc);
   return hipGetLastError();
 }
 

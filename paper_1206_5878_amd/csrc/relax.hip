@@ -237,7 +237,7 @@ __global__ __launch_bounds__(NT) void k_dt_eval(const double *__restrict__ tp,
 __global__ __launch_bounds__(NT) void k_dt_update(const double *__restrict__ part,
                                                   int nblocks, double *__restrict__ st,
                                                   cmc_scalars *__restrict__ sc, double target,
-                                                  int32_t last_iter) {
+                                                  double xtol, int32_t last_iter) {
   __shared__ double sh[NT / 64];
   if (st[kDone] != 0.0) return;
   double H = 0.0, D = 0.0;
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(NT) void k_dt_update(const double *__restrict__ par
   double xn = x;
   if (!conv) {
     xn = (F > 0.0 && Fp > 0.0) ? x - log(F / target) * F / Fp : __builtin_nan("");
-    const double tol = 1e-14 * fmax(1.0, fabs(x));
+    const double tol = xtol * fmax(1.0, fabs(x));
     // a Newton step this small is done, even when it rounds back onto x (which
     // may coincide with the bracket end just moved there)
     if (fabs(xn - x) <= tol) {
@@ -396,6 +396,9 @@ hipError_t run_timestep(const cmc_state &s, const Workspace &w, const cmc_params
                         hipStream_t st) {
   const MT *m = static_cast<const MT *>(s.m);
   const unsigned pb = static_cast<unsigned>(w.pair_blocks);
+  // Newton stops once its step in ln dt is below what the terms resolve:
+  // FP64 terms to ~1e-16, FP32 terms (mixed) to ~1e-7 each
+  const double kXTol = MIXED ? 1e-7 : 1e-14;
   k_pair_tp<MT, MIXED><<<pb, NT, 0, st>>>(s.r, m, s.vr, s.vt, s.id, s.sc, w.pair_tp,
                                           w.pair_part, p.seed, p.step, p.gamma);
   k_dt_init<<<1, IT, 0, st>>>(w.pair_part, w.pair_blocks, w.dt_state, s.sc, p.target);
@@ -403,7 +406,7 @@ hipError_t run_timestep(const cmc_state &s, const Workspace &w, const cmc_params
   const int eb = static_cast<int>(w.pair_blocks < kRedBlocks ? w.pair_blocks : kRedBlocks);
   for (int i = 0; i < iters; ++i) {
     k_dt_eval<MIXED><<<eb, NT, 0, st>>>(w.pair_tp, s.sc, w.dt_state, w.red_part);
-    k_dt_update<<<1, NT, 0, st>>>(w.red_part, eb, w.dt_state, s.sc, p.target,
+    k_dt_update<<<1, NT, 0, st>>>(w.red_part, eb, w.dt_state, s.sc, p.target, kXTol,
                                   i == iters - 1 ? 1 : 0);
   }
   return hipGetLastError();

@@ -9,6 +9,8 @@
 // scatter in which every wavefront ranks its keys with 8 ballots per slot
 // (stable: tile order = wave, slot, lane = input order).  Values are the
 // star's index in the staged records; a final gather writes the SoA arrays.
+#include <algorithm>
+
 #include "cmc_internal.hpp"
 
 namespace cmc {
@@ -16,6 +18,8 @@ namespace {
 
 constexpr int NT = kBlock;           // 4 waves
 constexpr int SLOTS = kSortTile / NT;  // 16 keys per thread
+constexpr int DT = 512;                 // threads of the downsweep
+constexpr int DSLOTS = kSortTile / DT;  // its keys per thread
 constexpr uint64_t kInfKey = 0x7FF0000000000000ull;
 
 // pass_info as uint64 slots
@@ -52,24 +56,24 @@ __global__ __launch_bounds__(NT) void k_stage_from_state(
   keys[i] = radius_key(rec.r);
 }
 
+// Per-block min and max of the finite keys and count of non-finite ones;
+// k_plan combines the blocks' partials (no contended atomics).
 __global__ __launch_bounds__(NT) void k_key_range(const uint64_t *__restrict__ keys,
-                                                  uint64_t *__restrict__ pi) {
+                                                  const uint64_t *__restrict__ pi,
+                                                  uint64_t *__restrict__ part) {
   __shared__ uint64_t smin[NT / 64], smax[NT / 64];
   __shared__ uint32_t snf[NT / 64];
   const int64_t n = static_cast<int64_t>(pi[kNTotal]);
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kSortTile;
   uint64_t lo = ~0ull, hi = 0ull;
   uint32_t nf = 0;
-  for (int j = 0; j < SLOTS; ++j) {
-    const int64_t k = base + j * NT + threadIdx.x;
-    if (k < n) {
-      const uint64_t x = keys[k];
-      if (x < kInfKey) {
-        lo = x < lo ? x : lo;
-        hi = x > hi ? x : hi;
-      } else {
-        ++nf;
-      }
+  for (int64_t k = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; k < n;
+       k += static_cast<int64_t>(gridDim.x) * NT) {
+    const uint64_t x = keys[k];
+    if (x < kInfKey) {
+      lo = x < lo ? x : lo;
+      hi = x > hi ? x : hi;
+    } else {
+      ++nf;
     }
   }
 #pragma unroll
@@ -92,16 +96,44 @@ __global__ __launch_bounds__(NT) void k_key_range(const uint64_t *__restrict__ k
       hi = smax[q] > hi ? smax[q] : hi;
       nf += snf[q];
     }
-    if (lo != ~0ull) atomicMin(reinterpret_cast<unsigned long long *>(pi + kMinKey), lo);
-    if (hi != 0ull) atomicMax(reinterpret_cast<unsigned long long *>(pi + kMaxKey), hi);
-    if (nf) atomicAdd(reinterpret_cast<unsigned long long *>(pi + kNonFin), nf);
+    part[3 * blockIdx.x] = lo;
+    part[3 * blockIdx.x + 1] = hi;
+    part[3 * blockIdx.x + 2] = nf;
   }
 }
 
-__global__ void k_plan(uint64_t *__restrict__ pi, cmc_scalars *__restrict__ sc) {
-  const uint64_t n = pi[kNTotal], nf = pi[kNonFin];
+__global__ __launch_bounds__(NT) void k_plan(const uint64_t *__restrict__ part, int nparts,
+                                             uint64_t *__restrict__ pi,
+                                             cmc_scalars *__restrict__ sc) {
+  __shared__ uint64_t smin[NT / 64], smax[NT / 64], snf[NT / 64];
+  uint64_t lo = ~0ull, hi = 0ull, nfin = 0ull;
+  for (int b = threadIdx.x; b < nparts; b += NT) {
+    lo = part[3 * b] < lo ? part[3 * b] : lo;
+    hi = part[3 * b + 1] > hi ? part[3 * b + 1] : hi;
+    nfin += part[3 * b + 2];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t a = __shfl_xor(lo, o, 64), b = __shfl_xor(hi, o, 64);
+    lo = a < lo ? a : lo;
+    hi = b > hi ? b : hi;
+    nfin += __shfl_xor(nfin, o, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    smin[w] = lo;
+    smax[w] = hi;
+    snf[w] = nfin;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int q = 1; q < NT / 64; ++q) {
+    lo = smin[q] < lo ? smin[q] : lo;
+    hi = smax[q] > hi ? smax[q] : hi;
+    nfin += snf[q];
+  }
+  const uint64_t n = pi[kNTotal], nf = nfin;
   const uint64_t kept = n - nf;
-  const uint64_t lo = pi[kMinKey], hi = pi[kMaxKey];
   const uint64_t range = kept ? hi - lo : 0ull;
   const uint64_t esc = range + 1ull;
   const uint64_t top = nf ? esc : range;
@@ -110,7 +142,9 @@ __global__ void k_plan(uint64_t *__restrict__ pi, cmc_scalars *__restrict__ sc) 
   pi[kPasses] = (n <= 1) ? 0ull : static_cast<uint64_t>((bits + 7) / 8);
   pi[kNKept] = kept;
   pi[kEscKey] = esc;
-  if (!kept) pi[kMinKey] = 0ull;
+  pi[kMinKey] = kept ? lo : 0ull;
+  pi[kMaxKey] = hi;
+  pi[kNonFin] = nf;
   sc->n = static_cast<int64_t>(kept);
 }
 
@@ -170,16 +204,20 @@ __global__ __launch_bounds__(NT) void k_scan_digits(const uint32_t *__restrict__
 }
 
 // The in and out buffers of a pass are the two halves of one ping-pong pair,
-// so they carry no restrict qualifier.
-__global__ __launch_bounds__(NT) void k_downsweep(
+// so they carry no restrict qualifier.  Keys are ranked in registers, placed
+// in digit order in LDS, then written out in LDS order, so consecutive
+// lanes write consecutive addresses of one digit's run.
+__global__ __launch_bounds__(DT) void k_downsweep(
     const uint64_t *keys0, const uint64_t *keys1, const uint32_t *vals0, const uint32_t *vals1,
     uint64_t *okeys0, uint64_t *okeys1, uint32_t *ovals0, uint32_t *ovals1,
     const uint64_t *__restrict__ pi, int pass,
     const uint32_t *__restrict__ tile_off, const uint32_t *__restrict__ digit_tot,
     int64_t tiles) {
-  __shared__ uint32_t cnt[NT / 64][256];
-  __shared__ uint32_t gbase[NT / 64][256];
-  __shared__ uint32_t sh[NT / 64];
+  __shared__ uint32_t cnt[DT / 64][256];
+  __shared__ uint32_t gdelta[256];
+  __shared__ uint32_t sh[DT / 64];
+  __shared__ uint64_t lkey[kSortTile];
+  __shared__ uint32_t lval[kSortTile];
   const uint64_t passes = pi[kPasses];
   if (static_cast<uint64_t>(pass) >= passes) return;
   const int64_t n = static_cast<int64_t>(pi[kNTotal]);
@@ -192,20 +230,27 @@ __global__ __launch_bounds__(NT) void k_downsweep(
   const int shift = 8 * pass;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t tile0 = static_cast<int64_t>(blockIdx.x) * kSortTile;
+  const int64_t rem = n - tile0;
+  const int valid = rem < kSortTile ? static_cast<int>(rem) : kSortTile;
 
-  for (int q = 0; q < NT / 64; ++q) cnt[q][threadIdx.x] = 0u;
+  for (int e = threadIdx.x; e < (DT / 64) * 256; e += DT) (&cnt[0][0])[e] = 0u;
   __syncthreads();
 
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kSortTile + w * (SLOTS * 64);
-  uint64_t key[SLOTS];
-  uint32_t val[SLOTS], rank[SLOTS];
-  uint32_t dig[SLOTS];
+  const int64_t base = tile0 + w * (DSLOTS * 64);
+  uint64_t key[DSLOTS];
+  uint32_t val[DSLOTS], rank[DSLOTS];
+  uint32_t dig[DSLOTS];
 #pragma unroll
-  for (int j = 0; j < SLOTS; ++j) {
+  for (int j = 0; j < DSLOTS; ++j) {
     const int64_t k = base + j * 64 + lane;
     const bool ok = k < n;
     key[j] = ok ? pass_key(in, k, first, kmin, esc) : 0ull;
     val[j] = ok ? (first ? static_cast<uint32_t>(k) : vin[k]) : 0u;
+  }
+#pragma unroll
+  for (int j = 0; j < DSLOTS; ++j) {
+    const bool ok = base + j * 64 + lane < n;
     const uint32_t d = static_cast<uint32_t>(key[j] >> shift) & 255u;
     dig[j] = ok ? d : 256u;
     // peers: valid lanes of this slot with the same digit
@@ -224,23 +269,46 @@ __global__ __launch_bounds__(NT) void k_downsweep(
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  // digit bases: global digit offset + this tile's offset + earlier waves
+  // Tile-local start of each digit and of each wave's share of it; gdelta
+  // turns a tile-local position into the global one.
   {
+    // threads 0..255 own one digit each; the rest add zeros to the scans
     const uint32_t d = threadIdx.x;
-    const uint32_t dbase = block_excl_scan<NT>(digit_tot[d], sh, static_cast<uint32_t *>(nullptr));
-    uint32_t acc = dbase + tile_off[static_cast<int64_t>(d) * tiles + blockIdx.x];
-    for (int q = 0; q < NT / 64; ++q) {
-      gbase[q][d] = acc;
-      acc += cnt[q][d];
+    const bool own = d < 256u;
+    uint32_t tot = 0u;
+    if (own)
+      for (int q = 0; q < DT / 64; ++q) tot += cnt[q][d];
+    const uint32_t lstart = block_excl_scan<DT>(tot, sh, static_cast<uint32_t *>(nullptr));
+    const uint32_t dbase =
+        block_excl_scan<DT>(own ? digit_tot[d] : 0u, sh, static_cast<uint32_t *>(nullptr));
+    if (own) {
+      gdelta[d] = dbase + tile_off[static_cast<int64_t>(d) * tiles + blockIdx.x] - lstart;
+      uint32_t acc = lstart;
+      for (int q = 0; q < DT / 64; ++q) {
+        const uint32_t c = cnt[q][d];
+        cnt[q][d] = acc;
+        acc += c;
+      }
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < SLOTS; ++j) {
+  for (int j = 0; j < DSLOTS; ++j) {
     if (dig[j] < 256u) {
-      const uint32_t dst = gbase[w][dig[j]] + rank[j];
-      if (!last) out[dst] = key[j];
-      vout[dst] = val[j];
+      const uint32_t lp = cnt[w][dig[j]] + rank[j];
+      lkey[lp] = key[j];
+      lval[lp] = val[j];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < DSLOTS; ++j) {
+    const int t = j * DT + threadIdx.x;
+    if (t < valid) {
+      const uint64_t kk = lkey[t];
+      const uint32_t dst = gdelta[static_cast<uint32_t>(kk >> shift) & 255u] + t;
+      if (!last) out[dst] = kk;
+      vout[dst] = lval[t];
     }
   }
 }
@@ -284,14 +352,16 @@ hipError_t launch_sort_stage(const cmc_state &s, const Workspace &w, bool normal
                              hipStream_t st) {
   uint64_t *pi = reinterpret_cast<uint64_t *>(w.pass_info);
   const unsigned tiles = static_cast<unsigned>(w.sort_tiles);
+  const unsigned kr_blocks = std::min<unsigned>(tiles, 1024u);
+  uint64_t *kr_part = reinterpret_cast<uint64_t *>(w.red_part);
   k_sort_prep<<<1, 1, 0, st>>>(s.sc, pi);
-  k_key_range<<<tiles, NT, 0, st>>>(w.keys[0], pi);
-  k_plan<<<1, 1, 0, st>>>(pi, s.sc);
+  k_key_range<<<kr_blocks, NT, 0, st>>>(w.keys[0], pi, kr_part);
+  k_plan<<<1, NT, 0, st>>>(kr_part, static_cast<int>(kr_blocks), pi, s.sc);
   for (int pass = 0; pass < 8; ++pass) {
     k_upsweep<<<tiles, NT, 0, st>>>(w.keys[0], w.keys[1], pi, pass, w.tile_hist, w.sort_tiles);
     k_scan_digits<<<256, NT, 0, st>>>(w.tile_hist, pi, pass, w.tile_off, w.hist_all,
                                       w.sort_tiles);
-    k_downsweep<<<tiles, NT, 0, st>>>(w.keys[0], w.keys[1], w.vals[0], w.vals[1], w.keys[0],
+    k_downsweep<<<tiles, DT, 0, st>>>(w.keys[0], w.keys[1], w.vals[0], w.vals[1], w.keys[0],
                                       w.keys[1], w.vals[0], w.vals[1], pi, pass, w.tile_off,
                                       w.hist_all, w.sort_tiles);
   }

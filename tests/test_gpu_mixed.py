@@ -99,13 +99,22 @@ def test_orbit_mixed(cmc, ora):
     rn, vrn, vtn, so, d = ora.orbit(st, tab, 5, 1, details=True)
     fin = np.isfinite(rn)
     assert np.array_equal(np.isfinite(h["r_new"]), fin)
-    e = np.abs(h["r_new"][fin] - rn[fin]) / rn[fin]
+    # an FP32 trial angle moves r by ~1e-7 of the orbit's half-width r_a,
+    # which near a turning point is large relative to r itself
+    ra = np.nan_to_num(0.5 * (d["rmax"] - d["rmin"]))[fin]
+    e = np.abs(h["r_new"][fin] - rn[fin]) / np.maximum(rn[fin], ra)
     flips = int(np.sum(e > MTOL))
+    print("orbit mixed: max scaled r error", e[e <= MTOL].max(), "flips", flips)
     assert flips <= max(3, 2e-5 * n), flips
     ok = e <= MTOL
     J = d["J"][fin][ok]
-    # J conserved exactly by construction, E through Q at the new radius
+    # J conserved by construction; E through Q at the new radius, in the old
+    # potential
     assert rel(h["r_new"][fin][ok] * h["vt"][fin][ok], J, np.abs(J).max() * 1e-9) < MTOL
+    idx = np.nonzero(fin)[0][ok][:: 20]
+    e_new = np.array([ora.phi_at(st.r, tab, h["r_new"][i]) for i in idx]) + \
+        0.5 * (h["vr"][idx] ** 2 + h["vt"][idx] ** 2)
+    assert rel(e_new, d["E"][idx]) < MTOL
     assert abs(cl.scalars()["trials"] / so["trials"] - 1) < 1e-3
 
 
@@ -131,12 +140,25 @@ def test_step_mixed_lockstep(cmc, ora, n, gamma, ms):
         oo = np.argsort(new.id)
         assert np.array_equal(h["id"][og], new.id[oo])
         rg, ro = h["r"][og], new.r[oo]
-        e = np.abs(rg - ro) / ro
+        # scale: the larger of the new radius and the radius before the step
+        # (a bound on the orbit's size; see test_orbit_mixed)
+        rold = np.zeros(ro.size)
+        io = np.argsort(st.id)
+        pos = np.searchsorted(st.id[io], new.id[oo])
+        rold = st.r[io][pos]
+        e = np.abs(rg - ro) / np.maximum(ro, rold)
         flips = int(np.sum(e > MTOL))
         assert flips <= max(3, 2e-5 * n), (k, flips)
         ok = e <= MTOL
-        vs = np.hypot(new.vr, new.vt).max()
-        assert rel(h["vt"][og][ok], new.vt[oo][ok], vs * 1e-3) < MTOL
+        # J = r vt is what the orbit conserves.  The FP32 kick leaves an
+        # error of ~1e-7 of the pair's relative speed in vt, so J is compared
+        # on the scale r max(|v|, v_rms)
+        jg = h["r"][og][ok] * h["vt"][og][ok]
+        jo = new.r[oo][ok] * new.vt[oo][ok]
+        sp = np.hypot(new.vr, new.vt)[oo][ok]
+        vrms = np.sqrt(np.mean(new.vr ** 2 + new.vt ** 2))
+        dj = np.abs(jg - jo) / (new.r[oo][ok] * np.maximum(sp, vrms))
+        assert dj.max() < MTOL, dj.max()
         st = new
 
 

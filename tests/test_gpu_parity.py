@@ -248,6 +248,39 @@ def test_orbit_generic_edge_cases(cmc, ora):
     assert s["n_esc"] == so["n_esc"] and s["trials"] == so["trials"]
 
 
+def _radii_state(ora, r, seed):
+    rng = np.random.default_rng(seed)
+    n = r.size
+    m = np.full(n, 1.0 / n)
+    v = 0.5 * rng.standard_normal((n, 2))
+    return ora.State(np.ascontiguousarray(r), v[:, 0].copy(), np.abs(v[:, 1]),
+                     m, np.arange(n, dtype=np.uint32) * 7 + 3)
+
+
+@pytest.mark.parametrize("case", ["all_equal", "wide_range", "centre_star", "two_clumps"])
+def test_orbit_interval_lookup_edges(cmc, ora, case):
+    """Tables that stress the lookup of a trial radius's interval: one radius
+    for every star, radii over 16 decades (long empty stretches), a star at
+    r = 0, and two dense clumps far apart."""
+    rng = np.random.default_rng(11)
+    if case == "all_equal":
+        r = np.full(5000, 0.75)
+    elif case == "wide_range":
+        r = np.sort(10.0 ** rng.uniform(-8, 8, 6000))
+    elif case == "centre_star":
+        r = np.sort(np.concatenate([[0.0], rng.lognormal(0, 1, 3000)]))
+    else:
+        r = np.sort(np.concatenate([1e-3 * (1 + 1e-6 * rng.random(3000)),
+                                    1e3 * (1 + 1e-6 * rng.random(3000))]))
+    st = _radii_state(ora, r, 12)
+    h, s, (rn, vrn, vtn, so, d), tab = _orbit_case(cmc, ora, st, seed=3, step=2)
+    fin = np.isfinite(rn)
+    assert np.array_equal(np.isfinite(h["r_new"]), fin)
+    assert rel(h["r_new"][fin], rn[fin]) < TOL
+    assert s["n_esc"] == so["n_esc"] and s["trials"] == so["trials"]
+    assert s["capped"] == so["capped"]
+
+
 # ---------------------------------------------------------------- whole step
 @pytest.mark.parametrize("n,gamma,ms,steps", [(10_000, 0.11, 0, 10), (4_001, 0.01, 1, 4)])
 def test_step_lockstep(cmc, ora, n, gamma, ms, steps):
