@@ -4,7 +4,10 @@ one MI355X: star-updates per second, per-phase times from HIP events recorded
 on the stream the kernels run on, the roofline of the dominant phase, and the
 FP64 oracle timed on the host for reference.
 
-python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision fp64]
+python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision fp64|mixed]
+
+The other precision form runs on the same initial model right after the
+timed run and is reported beside it ("other_precision").
 """
 from __future__ import annotations
 
@@ -19,15 +22,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "star-updates/s (sort+Φ+relax+orbit) at N=1e6/1e7, mixed vs FP64, % HBM roofline"
 
-# Seeded synthetic workloads (Plummer models; see the design doc for the recipe).
+# Seeded synthetic Plummer workloads, each with the precision it is quoted in.
 WORKLOADS = {
     # headline: 10^7 stars, broken power-law masses stored as f32, ln(0.01 N)
     "plummer_n1e7_broken_power_law": dict(n=10_000_000, mass_spectrum=1, m_f32=True,
-                                          gamma=0.01, seed=1),
+                                          gamma=0.01, seed=1, precision="mixed"),
     "plummer_n1e6_equal_mass": dict(n=1_000_000, mass_spectrum=0, m_f32=False, gamma=0.11,
-                                    seed=1),
+                                    seed=1, precision="mixed"),
     "plummer_n1e5_equal_mass": dict(n=100_000, mass_spectrum=0, m_f32=False, gamma=0.11,
-                                    seed=1),
+                                    seed=1, precision="fp64"),
 }
 DEFAULT_WORKLOAD = "plummer_n1e7_broken_power_law"
 
@@ -74,8 +77,11 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
+                    help="default: the precision the workload is quoted in")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other", action="store_true",
+                    help="skip the run of the other precision form")
     ap.add_argument("--plain", action="store_true",
                     help="time plain cmc_step calls only (no per-phase events); for profilers")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -83,8 +89,8 @@ def main() -> int:
                          "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "sharding of this step is a design, not a build: see DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding the "
+              "step over several GPUs is not built", file=sys.stderr)
         return 2
 
     import torch
@@ -99,30 +105,24 @@ def main() -> int:
         nb = args.copy_mib << 20
         src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
+        dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        e0.record()
         for _ in range(args.steps):
             dst.copy_(src)
+        e1.record()
         torch.cuda.synchronize()
-        el = time.perf_counter() - t0
+        el = e0.elapsed_time(e1) * 1e-3
         print(json.dumps({"mode": "copy", "bytes_per_copy": nb, "copies": args.steps,
                           "GBs_read_plus_write": 2 * nb * args.steps / el / 1e9}), flush=True)
         return 0
     wl = WORKLOADS[args.workload]
-    prec = P.CMC_FP64 if args.precision == "fp64" else P.CMC_MIXED
-    n0 = wl["n"]
-    cl = P.Cluster(n0, m_f32=wl["m_f32"])
-    P.cmc_init_plummer(cl, n0, wl["seed"], wl["mass_spectrum"])
-    params = P.Params(seed=wl["seed"], gamma=wl["gamma"], precision=prec)
-
-    for k in range(args.warmup):
-        params.step = k
-        P.cmc_step(cl, params)
-    torch.cuda.synchronize()
-    print(f"# warmup done: {args.warmup} steps, n={cl.n}", file=sys.stderr, flush=True)
-
+    precision = args.precision or wl["precision"]
     K = args.steps
     if args.plain:
+        prec = P.CMC_FP64 if precision == "fp64" else P.CMC_MIXED
+        cl, params = setup(P, wl, prec, args.warmup)
         n_start = cl.n
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -134,20 +134,94 @@ def main() -> int:
         print(json.dumps({"metric": METRIC, "value": n_start * K / el, "unit": "star-updates/s",
                           "n_gpus": 1, "steps": K, "warmup": args.warmup,
                           "ms_per_step": el / K * 1e3, "mode": "plain", "n_start": n_start,
-                          "n_end": cl.n, "workload": args.workload}), flush=True)
+                          "n_end": cl.n, "workload": args.workload, "precision": precision}),
+              flush=True)
         return 0
+
+    run = timed_run(P, EventSet, wl, precision, K, args.warmup)
+    other = "fp64" if precision == "mixed" else "mixed"
+    run_o = None if args.no_other else timed_run(P, EventSet, wl, other, K, args.warmup)
+
+    m_bytes = 4 if wl["m_f32"] else 8
+    ab = alg_bytes(m_bytes)
+    phase_ms, n_mean = run["phases_ms"], run["n_mean"]
+    # timestep + relax are the relaxation unit of the algorithmic-byte table
+    unit_ms = {"potential": phase_ms["potential"],
+               "relax": phase_ms["timestep"] + phase_ms["relax"],
+               "orbit": phase_ms["orbit"], "sort": phase_ms["sort"]}
+    dom = max(unit_ms, key=unit_ms.get)
+    dom_gbs = ab[dom] * n_mean / (unit_ms[dom] * 1e-3) / 1e9
+    step_bytes = sum(ab.values())
+    value = run["value"]
+    traffic = measured_traffic(args.workload, precision, dom)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "star-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": run["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": wl["n"], "precision": precision,
+                   "mass_spectrum": wl["mass_spectrum"], "m_f32": wl["m_f32"],
+                   "gamma": wl["gamma"], "seed": wl["seed"]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": dom_gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS, "traffic": traffic,
+                     "alg_bytes_per_star": ab[dom],
+                     "launch_ms": unit_ms[dom], "stars_per_launch": n_mean},
+        "step_roofline": {"alg_bytes_per_star": step_bytes,
+                          "achieved_GBs": value * step_bytes / 1e9,
+                          "frac": value * step_bytes / 1e9 / HBM_PEAK_GBS},
+        "phases_ms": phase_ms,
+        "final": run["final"],
+    }
+    if run_o is not None:
+        out["other_precision"] = {"precision": other, "value": run_o["value"],
+                                  "ms_per_step": run_o["ms_per_step"],
+                                  "phases_ms": run_o["phases_ms"], "final": run_o["final"]}
+    if not args.no_cpu_baseline:
+        print("# timing the oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def setup(P, wl, prec, warmup):
+    import torch
+    n0 = wl["n"]
+    cl = P.Cluster(n0, m_f32=wl["m_f32"])
+    P.cmc_init_plummer(cl, n0, wl["seed"], wl["mass_spectrum"])
+    params = P.Params(seed=wl["seed"], gamma=wl["gamma"], precision=prec)
+    for k in range(warmup):
+        params.step = k
+        P.cmc_step(cl, params)
+    torch.cuda.synchronize()
+    print(f"# warmup done: {warmup} steps, n={cl.n}", file=sys.stderr, flush=True)
+    return cl, params
+
+
+def timed_run(P, EventSet, wl, precision, K, warmup) -> dict:
+    """K whole steps after the warm-up, with inputs resident in HBM; per-phase
+    times from HIP events on the library's stream."""
+    import torch
+    prec = P.CMC_FP64 if precision == "fp64" else P.CMC_MIXED
+    cl, params = setup(P, wl, prec, warmup)
     ev = [EventSet(6) for _ in range(K)]
     nlog = torch.zeros(K + 1, dtype=torch.int64, device="cuda")
     nlog[0].copy_(cl.sc[0])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(K):
-        params.step = args.warmup + k
+        params.step = warmup + k
         P.cmc_step_timed(cl, params, ev[k].h)
         nlog[k + 1].copy_(cl.sc[0])
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-
     counts = nlog.cpu().tolist()
     updates = float(sum(counts[:K]))  # stars entering each timed step
     phase_ms = {ph: 0.0 for ph in PHASES}
@@ -156,51 +230,47 @@ def main() -> int:
             phase_ms[ph] += ev[k].elapsed(i, i + 1)
     for e in ev:
         e.close()
-    phase_ms = {ph: v / K for ph, v in phase_ms.items()}
     sc = cl.scalars()
-
-    m_bytes = 4 if wl["m_f32"] else 8
-    ab = alg_bytes(m_bytes)
     n_mean = updates / K
-    # timestep + relax are the relaxation unit of the algorithmic-byte table
-    unit_ms = {"potential": phase_ms["potential"],
-               "relax": phase_ms["timestep"] + phase_ms["relax"],
-               "orbit": phase_ms["orbit"], "sort": phase_ms["sort"]}
-    dom = max(unit_ms, key=unit_ms.get)
-    dom_gbs = ab[dom] * n_mean / (unit_ms[dom] * 1e-3) / 1e9
-    step_bytes = sum(ab.values())
-    value = updates / el
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "star-updates/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": el / K * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "n": n0, "precision": args.precision,
-                   "mass_spectrum": wl["mass_spectrum"], "m_f32": wl["m_f32"],
-                   "gamma": wl["gamma"], "seed": wl["seed"]},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": dom_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "alg_bytes_per_star": ab[dom]},
-        "step_roofline": {"alg_bytes_per_star": step_bytes,
-                          "achieved_GBs": value * step_bytes / 1e9,
-                          "frac": value * step_bytes / 1e9 / HBM_PEAK_GBS},
-        "phases_ms": phase_ms,
-        "final": {"n": sc["n"], "dt": sc["dt"], "status": sc["status"],
-                  "trials_per_star": sc["trials"] / max(n_mean, 1), "dt_iters": sc["dt_iters"]},
-    }
-    if not args.no_cpu_baseline:
-        print("# timing the oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl)
-    print(json.dumps(out), flush=True)
-    return 0
+    print(f"# {precision}: {el / K * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+    return {"value": updates / el, "ms_per_step": el / K * 1e3, "n_mean": n_mean,
+            "phases_ms": {ph: v / K for ph, v in phase_ms.items()},
+            "final": {"n": sc["n"], "dt": sc["dt"], "status": sc["status"],
+                      "trials_per_star": sc["trials"] / max(n_mean, 1),
+                      "dt_iters": sc["dt_iters"]}}
+
+
+def sources_sha256() -> str:
+    """Hash of the kernel sources, to tell whether recorded counters still
+    describe the library being timed."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1206_5878_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, precision: str, phase: str):
+    """HBM bytes per launch of the phase's kernels from the FETCH_SIZE and
+    WRITE_SIZE counter runs recorded under profiles/ (scaled by the copy
+    calibration there), or None when they were taken on other sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("sources_sha256") != sources_sha256():
+        return None
+    v = kv.get(f"{phase}_bytes_per_launch")
+    return float(v) if v else None
 
 
 if __name__ == "__main__":
