@@ -60,6 +60,12 @@ def lib():
         L.ora_u01f.argtypes = [C.c_uint32]
         L.ora_u01f.restype = C.c_float
         L.ora_plummer.argtypes = [C.c_int64, C.c_uint64, C.c_int, _dp, _dp, _dp, _dp, _up]
+        L.ora_king.argtypes = [C.c_int64, C.c_uint64, C.c_double, C.c_int, _dp, _dp, _dp, _dp,
+                               _up]
+        L.ora_king_profile.argtypes = [C.c_double, _dp, _dp, _dp, C.c_int, _dp]
+        L.ora_king_profile.restype = C.c_int
+        L.ora_king_density.argtypes = [C.c_double]
+        L.ora_king_density.restype = C.c_double
         L.ora_sort_perm.argtypes = [C.c_int64, _dp, _ip]
         L.ora_potential.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp]
         L.ora_phi_at.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, C.c_double]
@@ -140,6 +146,31 @@ def sort_perm(key: np.ndarray) -> np.ndarray:
     perm = np.empty(key.shape[0], dtype=np.int64)
     lib().ora_sort_perm(key.shape[0], key, perm)
     return perm
+
+
+def king_profile(w0: float, cap: int = 4096):
+    """King (1966) profile: node arrays r, W, M and (r_t, M_t, W_pot)."""
+    r = np.empty(cap); W = np.empty(cap); M = np.empty(cap); tail = np.empty(3)
+    k = lib().ora_king_profile(float(w0), r, W, M, cap, tail)
+    return r[:k], W[:k], M[:k], tuple(tail)
+
+
+def king_density(W: float) -> float:
+    return lib().ora_king_density(float(W))
+
+
+def king_unsorted(n: int, seed: int, w0: float, mass_spectrum: int = 0):
+    r = np.empty(max(n, 1)); vr = np.empty_like(r); vt = np.empty_like(r); m = np.empty_like(r)
+    id_ = np.empty(max(n, 1), np.uint32)
+    lib().ora_king(n, seed, float(w0), mass_spectrum, r, vr, vt, m, id_)
+    return r[:n], vr[:n], vt[:n], m[:n], id_[:n]
+
+
+def king(n: int, seed: int, w0: float, mass_spectrum: int = 0) -> State:
+    """A King model, sorted by radius (as the device init leaves it)."""
+    r, vr, vt, m, id_ = king_unsorted(n, seed, w0, mass_spectrum)
+    p = sort_perm(r)
+    return State(r[p], vr[p], vt[p], m[p], id_[p])
 
 
 def plummer(n: int, seed: int, mass_spectrum: int = 0) -> State:

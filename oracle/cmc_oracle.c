@@ -89,21 +89,43 @@ static void draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t 
  * speed v = q sqrt(2) (1+r^2)^(-1/4) with q drawn by rejection on
  * q^2 (1-q^2)^(7/2) under the bound 0.1; isotropic direction cos(theta) =
  * 2 X6 - 1.  Then Henon units: r * 3pi/16, v * sqrt(16/(3pi)). */
-void ora_plummer(int64_t n, uint64_t seed, int mass_spectrum, double *r, double *vr,
-                 double *vt, double *m, uint32_t *id) {
-  const double rscale = 3.0 * PI / 16.0;
-  const double vscale = sqrt(16.0 / (3.0 * PI));
-  double *raw = NULL;
-  ksum total = {0.0, 0.0};
-  if (mass_spectrum) raw = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
-
-  /* Broken power law dN/dm ~ m^-1.3 on [0.1,0.5], m^-2.3 on [0.5,100],
-   * continuous at 0.5; segment weights from the integrals. */
+/* Masses: 1/n each, or the broken power law dN/dm ~ m^-1.3 on [0.1,0.5],
+ * m^-2.3 on [0.5,100] (continuous at 0.5; segment weights from the
+ * integrals), drawn by inverse CDF per segment and divided by their sum. */
+static void draw_masses(int64_t n, uint64_t seed, int mass_spectrum, double *m) {
+  if (!mass_spectrum) {
+    for (int64_t i = 0; i < n; ++i) m[i] = 1.0 / (double)n;
+    return;
+  }
   const double ma = 0.1, mb = 0.5, mc = 100.0;
   const double ia = (pow(ma, -0.3) - pow(mb, -0.3)) / 0.3;
   const double ib = 0.5 * (pow(mb, -1.3) - pow(mc, -1.3)) / 1.3;
   const double f1 = ia / (ia + ib);
+  ksum total = {0.0, 0.0};
+  for (int64_t i = 0; i < n; ++i) {
+    uint32_t w[4];
+    draw(seed, (uint32_t)i, 0u, ORA_P_INIT_MASS, 0u, w);
+    double us = ora_u01(w[1], w[0]);
+    double um = ora_u01(w[3], w[2]);
+    double mm;
+    if (us < f1) {
+      double lo = pow(ma, -0.3), hi = pow(mb, -0.3);
+      mm = pow(lo - um * (lo - hi), -1.0 / 0.3);
+    } else {
+      double lo = pow(mb, -1.3), hi = pow(mc, -1.3);
+      mm = pow(lo - um * (lo - hi), -1.0 / 1.3);
+    }
+    m[i] = mm;
+    kadd(&total, mm);
+  }
+  double tot = kval(&total);
+  for (int64_t i = 0; i < n; ++i) m[i] = m[i] / tot;
+}
 
+void ora_plummer(int64_t n, uint64_t seed, int mass_spectrum, double *r, double *vr,
+                 double *vt, double *m, uint32_t *id) {
+  const double rscale = 3.0 * PI / 16.0;
+  const double vscale = sqrt(16.0 / (3.0 * PI));
   for (int64_t i = 0; i < n; ++i) {
     uint32_t w[4];
     draw(seed, (uint32_t)i, 0u, ORA_P_INIT_POS, 0u, w);
@@ -133,30 +155,156 @@ void ora_plummer(int64_t n, uint64_t seed, int mass_spectrum, double *r, double 
     vr[i] = v * vscale * c;
     vt[i] = v * vscale * s;
     id[i] = (uint32_t)i;
+  }
+  draw_masses(n, seed, mass_spectrum, m);
+}
 
-    if (mass_spectrum) {
-      draw(seed, (uint32_t)i, 0u, ORA_P_INIT_MASS, 0u, w);
-      double us = ora_u01(w[1], w[0]);
-      double um = ora_u01(w[3], w[2]);
-      double mm;
-      if (us < f1) {
-        double lo = pow(ma, -0.3), hi = pow(mb, -0.3);
-        mm = pow(lo - um * (lo - hi), -1.0 / 0.3);
-      } else {
-        double lo = pow(mb, -1.3), hi = pow(mc, -1.3);
-        mm = pow(lo - um * (lo - hi), -1.0 / 1.3);
-      }
-      raw[i] = mm;
-      kadd(&total, mm);
-    } else {
-      m[i] = 1.0 / (double)n;
+/* ------------------------------------------------------------------------- */
+/* King (1966) model with central potential W0 (an initial model the paper does
+ * not use; the ensemble workload does).  Units G = sigma = r_K = 1: the
+ * dimensionless potential W(r) solves the Poisson equation
+ *   (1/r^2) d/dr (r^2 dW/dr) = -9 rho(W) / rho(W0),
+ *   rho(W) = e^W erf(sqrt W) - sqrt(4W/pi) (1 + 2W/3)   (King's lowered
+ *   isothermal distribution f ~ e^(W - v^2/2) - 1 integrated over v),
+ * with W(0) = W0, W'(0) = 0; the enclosed mass is M(r) = -r^2 dW/dr, and the
+ * tidal radius is where W reaches 0.  Integration: RK4 in t = ln r on
+ * (W, U = r^2 W'), step 0.005, from r = 1e-4 where the series
+ *   W = W0 - 1.5 r^2 + 0.675 a r^4,  U = -3 r^3 + 2.7 a r^5,
+ *   a = rho'(W0)/rho(W0) = (e^W0 erf(sqrt W0) - sqrt(4 W0/pi)) / rho(W0),
+ * holds (obtained by inserting W = W0 - 1.5 r^2 + b r^4 and
+ * rho/rho0 = 1 + a (W - W0) into the equation).  The last step, in which W
+ * turns non-positive, is cut at the zero of the linear interpolant of W. */
+static double king_rho(double W) {
+  if (!(W > 0.0)) return 0.0;
+  if (W < 0.1) {
+    /* e^W erf(sqrt W) = (2/sqrt pi) sqrt W sum_{j>=0} (2W)^j / (2j+1)!!; the
+     * first two terms cancel against sqrt(4W/pi)(1 + 2W/3) */
+    double term = 4.0 * W * W / 15.0, sum = 0.0;
+    for (int j = 2; j < 12; ++j) {
+      sum += term;
+      term *= 2.0 * W / (2.0 * j + 3.0);
     }
+    return (2.0 / sqrt(PI)) * sqrt(W) * sum;
   }
-  if (mass_spectrum) {
-    double tot = kval(&total);
-    for (int64_t i = 0; i < n; ++i) m[i] = raw[i] / tot;
-    free(raw);
+  return exp(W) * erf(sqrt(W)) - sqrt(4.0 * W / PI) * (1.0 + 2.0 * W / 3.0);
+}
+
+double ora_king_density(double W) { return king_rho(W); }
+
+static void king_rhs(double t, double W, double U, double rho0, double *dW, double *dU) {
+  double r = exp(t);
+  *dW = U / r;                                 /* r dW/dr */
+  *dU = -9.0 * r * r * r * king_rho(W) / rho0; /* r dU/dr */
+}
+
+int ora_king_profile(double w0, double *rk, double *Wk, double *Mk, int cap, double *tail) {
+  const double h = 0.005;
+  double rho0 = king_rho(w0);
+  double a = (exp(w0) * erf(sqrt(w0)) - sqrt(4.0 * w0 / PI)) / rho0;
+  double r = 1e-4;
+  double W = w0 - 1.5 * r * r + 0.675 * a * r * r * r * r;
+  double U = -3.0 * r * r * r + 2.7 * a * r * r * r * r * r;
+  double t = log(r);
+  int k = 0;
+  rk[0] = r;
+  Wk[0] = W;
+  Mk[0] = -U;
+  double rt = r, Mt = -U;
+  while (k + 2 < cap) {
+    double k1W, k1U, k2W, k2U, k3W, k3U, k4W, k4U;
+    king_rhs(t, W, U, rho0, &k1W, &k1U);
+    king_rhs(t + 0.5 * h, W + 0.5 * h * k1W, U + 0.5 * h * k1U, rho0, &k2W, &k2U);
+    king_rhs(t + 0.5 * h, W + 0.5 * h * k2W, U + 0.5 * h * k2U, rho0, &k3W, &k3U);
+    king_rhs(t + h, W + h * k3W, U + h * k3U, rho0, &k4W, &k4U);
+    double Wn = W + (h / 6.0) * (k1W + 2.0 * k2W + 2.0 * k3W + k4W);
+    double Un = U + (h / 6.0) * (k1U + 2.0 * k2U + 2.0 * k3U + k4U);
+    if (!(Wn > 0.0)) {
+      double f = W / (W - Wn);
+      rt = exp(t + f * h);
+      Mt = -(U + f * (Un - U));
+      break;
+    }
+    W = Wn;
+    U = Un;
+    t = t + h;
+    ++k;
+    rk[k] = exp(t);
+    Wk[k] = W;
+    Mk[k] = -U;
+    rt = rk[k];
+    Mt = -U;
   }
+  ++k;
+  rk[k] = rt;
+  Wk[k] = 0.0;
+  Mk[k] = Mt;
+  /* potential energy W_pot = -int M dM / r (G = 1), trapezoid rule in M */
+  double wpot = 0.0;
+  for (int q = 0; q < k; ++q)
+    wpot -= 0.5 * (Mk[q] / rk[q] + Mk[q + 1] / rk[q + 1]) * (Mk[q + 1] - Mk[q]);
+  tail[0] = rt;
+  tail[1] = Mt;
+  tail[2] = wpot;
+  return k + 1;
+}
+
+/* Stars of a King model: r from the inverse of M(r) (linear between the
+ * profile nodes, M = 3 r^3 inside the first node), speed by rejection from
+ * v^2 (e^(W - v^2/2) - 1) on [0, sqrt(2W)] under the bound
+ * max_v v^2 e^(W - v^2/2) = 2 e^(W-1) (W >= 1) or 2W (W < 1), isotropic
+ * direction; then units G = M = 1 and E = W_pot/2 (virial equilibrium)
+ * scaled to -1/4: lengths by s = -4 E / M_t^2, speeds by 1/sqrt(M_t s). */
+#define ORA_KING_NODES 4096
+void ora_king(int64_t n, uint64_t seed, double w0, int mass_spectrum, double *r, double *vr,
+              double *vt, double *m, uint32_t *id) {
+  double *rk = (double *)malloc(3 * ORA_KING_NODES * sizeof(double));
+  double *Wk = rk + ORA_KING_NODES, *Mk = Wk + ORA_KING_NODES, tail[3];
+  int nodes = ora_king_profile(w0, rk, Wk, Mk, ORA_KING_NODES, tail);
+  double Mt = tail[1], wpot = tail[2];
+  double s = -4.0 * (0.5 * wpot) / (Mt * Mt);
+  for (int64_t i = 0; i < n; ++i) {
+    uint32_t w[4];
+    draw(seed, (uint32_t)i, 0u, ORA_P_INIT_POS, 0u, w);
+    double x1 = ora_u01(w[1], w[0]);
+    double x6 = ora_u01(w[3], w[2]);
+    double target = x1 * Mt, rr, Wr;
+    if (target < Mk[0]) {
+      rr = cbrt(target / 3.0);
+      Wr = w0 - 1.5 * rr * rr;
+    } else {
+      int lo = 0, hi = nodes - 1; /* Mk[lo] <= target < Mk[hi] */
+      while (hi - lo > 1) {
+        int mid = (lo + hi) / 2;
+        if (Mk[mid] <= target)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      double f = (target - Mk[lo]) / (Mk[hi] - Mk[lo]);
+      rr = rk[lo] + f * (rk[hi] - rk[lo]);
+      Wr = Wk[lo] + f * (Wk[hi] - Wk[lo]);
+    }
+    double v = 0.0;
+    if (Wr > 0.0) {
+      double vmax = sqrt(2.0 * Wr);
+      double bound = (Wr >= 1.0) ? 2.0 * exp(Wr - 1.0) : 2.0 * Wr;
+      for (uint32_t j = 0; j < 1000000u; ++j) {
+        draw(seed, (uint32_t)i, 0u, ORA_P_INIT_SPEED, j, w);
+        v = vmax * ora_u01(w[1], w[0]);
+        double x5 = ora_u01(w[3], w[2]);
+        if (x5 * bound < v * v * expm1(Wr - 0.5 * v * v)) break;
+      }
+    }
+    double c = 2.0 * x6 - 1.0;
+    double sn = sqrt((1.0 - c) * (1.0 + c));
+    double vv = v / sqrt(Mt * s);
+    r[i] = rr * s;
+    vr[i] = vv * c;
+    vt[i] = vv * sn;
+    id[i] = (uint32_t)i;
+  }
+  draw_masses(n, seed, mass_spectrum, m);
+  free(rk);
 }
 
 /* ------------------------------------------------------------------------- */

@@ -58,6 +58,17 @@ float ora_u01f(uint32_t hi);              /* (2x+1) 2^-24, x = top 23 bits   */
 void ora_plummer(int64_t n, uint64_t seed, int mass_spectrum, double *r, double *vr,
                  double *vt, double *m, uint32_t *id);
 
+/* King density rho(W) up to a constant: e^W erf(sqrt W) - sqrt(4W/pi)(1 + 2W/3). */
+double ora_king_density(double W);
+
+/* King (1966) profile for central potential w0: nodes (r, W, M) into
+ * rk/Wk/Mk (at most cap), tail = (r_t, M_t, W_pot); returns the node count. */
+int ora_king_profile(double w0, double *rk, double *Wk, double *Mk, int cap, double *tail);
+
+/* n stars of a King model, unsorted, in Henon units (see cmc_oracle.c). */
+void ora_king(int64_t n, uint64_t seed, double w0, int mass_spectrum, double *r, double *vr,
+              double *vt, double *m, uint32_t *id);
+
 /* ---- step 6 of Sec. 2.1: sort ------------------------------------------- */
 /* perm[p] = old index of the star that lands at position p, ascending in the
  * key, equal keys in old-index order (a stable sort). */

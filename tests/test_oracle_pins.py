@@ -482,3 +482,89 @@ def test_step_energy_drift_and_determinism(ora):
     for k in range(5):
         again, _ = ora.step(again, 1, k, 0.11)
     assert np.array_equal(again.r, cur.r) and np.array_equal(again.id, cur.id)
+
+
+# ---------------------------------------------------------------- King models
+def test_king_density_is_the_lowered_isothermal_df(ora):
+    """rho(W) is, up to a constant, the integral over speeds of King's
+    distribution function f = e^(W - v^2/2) - 1 (v < sqrt(2W)); checked by
+    quadrature, also in the small-W series branch."""
+    from scipy.integrate import quad
+
+    def by_df(W):
+        return quad(lambda v: (np.expm1(W - 0.5 * v * v)) * v * v, 0.0, np.sqrt(2 * W),
+                    epsabs=0, epsrel=1e-13)[0]
+
+    ref = by_df(6.0) / ora.king_density(6.0)
+    for W in (1e-4, 0.03, 0.0999, 0.1001, 0.5, 2.0, 9.0):
+        assert abs(by_df(W) / ora.king_density(W) / ref - 1) < 1e-9, W
+    assert ora.king_density(0.0) == 0.0 and ora.king_density(-1.0) == 0.0
+
+
+@pytest.mark.parametrize("w0,c", [(3, 0.67), (5, 1.03), (6, 1.26), (7, 1.53), (9, 2.12),
+                                  (12, 2.74)])
+def test_king_concentration(ora, w0, c):
+    """Concentration log10(r_t / r_K) against King's (1966) tabulation."""
+    r, W, M, (rt, Mt, wpot) = ora.king_profile(w0)
+    assert abs(np.log10(rt) - c) < 0.01
+    assert np.all(np.diff(r) > 0) and np.all(np.diff(M) > 0) and np.all(np.diff(W) < 0)
+
+
+def test_king_profile_against_independent_integration(ora):
+    """The RK4 profile against scipy's adaptive DOP853 on the same Poisson
+    equation with the density taken from the distribution-function
+    quadrature: tidal radius, total mass and W at the nodes."""
+    from scipy.integrate import quad, solve_ivp
+
+    w0 = 6.0
+
+    def rho(W):
+        if W <= 0:
+            return 0.0
+        return quad(lambda v: np.expm1(W - 0.5 * v * v) * v * v, 0.0, np.sqrt(2 * W),
+                    epsabs=0, epsrel=1e-13)[0]
+
+    rho0 = rho(w0)
+
+    def rhs(r, y):
+        W, U = y
+        return [U / (r * r), -9.0 * r * r * rho(W) / rho0]
+
+    def edge(r, y):
+        return y[0]
+    edge.terminal = True
+    r0 = 1e-5
+    sol = solve_ivp(rhs, (r0, 100.0), [w0 - 1.5 * r0 * r0, -3.0 * r0 ** 3], method="DOP853",
+                    rtol=1e-11, atol=1e-14, events=edge, dense_output=True)
+    rt_ref = sol.t_events[0][0]
+    mt_ref = -sol.y_events[0][0][1]
+    r, W, M, (rt, Mt, wpot) = ora.king_profile(w0)
+    assert abs(rt / rt_ref - 1) < 1e-5 and abs(Mt / mt_ref - 1) < 1e-6
+    sel = r[1:-1][:: 97]
+    assert np.max(np.abs(W[1:-1][:: 97] - sol.sol(sel)[0])) < 1e-7
+    # W_pot of the trapezoid rule against the dense solution
+    rr = np.linspace(r[1], rt_ref, 200_001)
+    Mr = -sol.sol(rr)[1]
+    wp_ref = -np.trapezoid(Mr * np.gradient(Mr, rr) / rr, rr)
+    assert abs(wpot / wp_ref - 1) < 1e-4
+
+
+def test_king_sample(ora):
+    """A sampled King W0 = 6 model: Henon units (virial ratio 1, E = -1/4
+    within the sampling noise), radii distributed as the profile's M(r)."""
+    from scipy import stats
+    n = 60_000
+    st = ora.king(n, 5, 6.0)
+    d = ora.diagnostics(st)
+    assert abs(d["virial"] - 1) < 5 / np.sqrt(n)
+    assert abs(d["E"] + 0.25) < 0.02
+    assert abs(d["M"] - 1) < 1e-12
+    r, W, M, (rt, Mt, wpot) = ora.king_profile(6.0)
+    s = -4.0 * (0.5 * wpot) / Mt ** 2
+    cdf = lambda x: np.interp(x / s, r, M / Mt)
+    assert stats.kstest(st.r, cdf).pvalue > 1e-3
+    assert st.r.max() <= rt * s * (1 + 1e-12)
+    # the speeds stay below the local escape speed of the model
+    Wr = np.interp(st.r / s, r, W)
+    vmod = np.hypot(st.vr, st.vt) * np.sqrt(Mt * s)
+    assert np.all(vmod <= np.sqrt(2 * Wr) * (1 + 1e-9) + 1e-12)
