@@ -61,9 +61,13 @@ extern "C" {
                        and an accept/reject decision within that of its
                        threshold may flip.                                      */
 
+/* Initial models of cmc_init_model (and of the ensemble) */
+#define CMC_MODEL_PLUMMER 0 /* Plummer sphere (Sec. 2.1 opening paragraph)      */
+#define CMC_MODEL_KING 1    /* King (1966) model with central potential W0     */
+
 /* Device-resident scalars of one cluster (128 bytes, caller-owned). */
 typedef struct cmc_scalars {
-  int64_t n;          /* active star count (set by cmc_init_plummer / cmc_sort) */
+  int64_t n;          /* active star count (set by cmc_init_* / cmc_sort)       */
   double dt;          /* timestep: solved by cmc_timestep, read by cmc_relax    */
   uint32_t status;    /* sticky CMC_ST_* bits                                   */
   uint32_t dt_iters;  /* Newton iterations the last dt solve used               */
@@ -72,8 +76,9 @@ typedef struct cmc_scalars {
   int64_t violations; /* trials with g(s) > F in the last orbit pass            */
   int64_t capped;     /* stars that hit trial_cap in the last orbit pass        */
   double e_esc;       /* sum of m E over the last orbit pass's escapers         */
-  double mass_norm;   /* total raw mass drawn by cmc_init_plummer               */
-  int64_t reserved[7];
+  double mass_norm;   /* total raw mass drawn by cmc_init_*                     */
+  int64_t step;       /* steps taken with cmc_params.step == CMC_STEP_DEVICE    */
+  int64_t reserved[6];
 } cmc_scalars;
 
 /* One cluster.  Every array has `cap` entries of device memory.
@@ -106,9 +111,13 @@ typedef struct cmc_state {
 } cmc_state;
 
 /* Parameters of one step. */
+#define CMC_STEP_DEVICE 0xFFFFFFFFu
+
 typedef struct cmc_params {
   uint64_t seed;       /* Philox key                                              */
-  uint32_t step;       /* step index: Philox counter word 1                       */
+  uint32_t step;       /* step index: Philox counter word 1; CMC_STEP_DEVICE: use
+                          sc->step and advance it (for calls replayed from a
+                          captured hipGraph)                                      */
   int32_t precision;   /* CMC_FP64 or CMC_MIXED                                   */
   double gamma;        /* Coulomb logarithm ln(gamma N), N = active stars         */
   double target;       /* mean sin^2(beta/2) over pairs that fixes dt (0.03)      */
@@ -130,6 +139,21 @@ size_t cmc_workspace_bytes(int64_t cap);
  * the other scalars.  CMC_ERANGE if n > cap. */
 int cmc_init_plummer(cmc_state *s, int64_t n, uint64_t seed, int32_t mass_spectrum,
                      void *stream);
+
+/* Initial model by kind: CMC_MODEL_PLUMMER as cmc_init_plummer, or
+ * CMC_MODEL_KING (King 1966, central potential w0 in (0, 16]; the paper
+ * names no initial model besides Plummer, so this one follows King's
+ * definition).  King: in units G = sigma = r_K = 1, W'' + 2W'/r =
+ * -9 rho(W)/rho(W0) with rho(W) = e^W erf(sqrt W) - sqrt(4W/pi)(1 + 2W/3)
+ * and M(r) = -r^2 W', integrated by RK4 in ln r (step 0.005, series start at
+ * r = 1e-4) until W = 0; r from the inverse of M(r), linear between the RK4
+ * nodes; speed by rejection on v^2 (e^(W - v^2/2) - 1), v < sqrt(2W), bounded
+ * by 2 e^(W-1) (W >= 1) or 2W; isotropic direction; scaled to G = M = 1,
+ * E = -1/4 with E = W_pot/2 (W_pot by the trapezoid rule over the nodes).
+ * Philox purposes and counters as for Plummer.  Masses as mass_spectrum.
+ * CMC_EINVAL for an unknown model or w0 out of range. */
+int cmc_init_model(cmc_state *s, int64_t n, uint64_t seed, int32_t model, int32_t mass_spectrum,
+                   double w0, void *stream);
 
 /* Sort (Sec. 2.1 step 6): order the stars by r_new ascending (key = bit
  * pattern of r_new + 0.0, so +inf and NaN go last), equal keys in their
@@ -184,6 +208,66 @@ int cmc_diagnostics(const cmc_state *s, double *out_dev, void *stream);
  * for i < n.  The generator every random draw above goes through. */
 int cmc_philox(uint64_t key, const uint32_t *ctr_dev, uint32_t *out_dev, int64_t n,
                void *stream);
+
+/* ---- ensembles ----------------------------------------------------------------
+ * Independent clusters of uneven N advanced together: every kernel of a step
+ * is one launch over all clusters (a per-launch map gives each block its
+ * cluster), per-cluster reductions, Delta t solves, potential scans and sorts
+ * never cross a cluster, and each cluster keeps its own state arrays and
+ * workspace (a cmc_state each, as for the single-cluster calls).  Sec. 2.1's
+ * step applies to each cluster unchanged; the ensemble is this library's
+ * batching of it. */
+
+/* What cluster c of an ensemble starts as and relaxes with. */
+typedef struct cmc_cluster_spec {
+  int64_t n;             /* stars of the initial model (<= the state's cap)      */
+  uint64_t seed;         /* the cluster's Philox key                             */
+  double gamma;          /* Coulomb logarithm ln(gamma N) of the cluster         */
+  int32_t model;         /* CMC_MODEL_PLUMMER or CMC_MODEL_KING                  */
+  int32_t mass_spectrum; /* 0 or 1, as cmc_init_plummer                          */
+  double w0;             /* King central potential                               */
+} cmc_cluster_spec;
+
+#define CMC_SHAPES 16
+
+/* Host handle of an ensemble, filled by cmc_batch_prepare.  `dev` is device
+ * memory of cmc_batch_device_bytes() bytes, 256-byte aligned, owned by the
+ * caller; it holds the cluster table and the launch maps. */
+typedef struct cmc_batch {
+  int32_t clusters;
+  int32_t m_f32;                /* mass storage (every cluster alike)            */
+  void *dev;
+  size_t dev_bytes;
+  int64_t total[CMC_SHAPES];    /* blocks per launch shape over all clusters     */
+  int32_t top_entries;          /* LDS entries of the orbit table's top levels   */
+  int32_t reserved[3];
+} cmc_batch;
+
+/* Device bytes of the ensemble tables for these states (0 if invalid). */
+size_t cmc_batch_device_bytes(const cmc_state *states, int32_t clusters);
+
+/* Checks the states and specs (CMC_EINVAL / CMC_EWORKSPACE / CMC_ERANGE as the
+ * single-cluster calls; masses must be all f32 or all f64; clusters in
+ * [1, 65535]), fills *b and copies the tables into `dev`.  A setup call: it
+ * blocks until the copy is done (hipMemcpy), so it is not capturable.  The
+ * states' arrays must stay where they are for as long as b is used. */
+int cmc_batch_prepare(cmc_batch *b, const cmc_state *states, const cmc_cluster_spec *specs,
+                      int32_t clusters, void *dev, size_t dev_bytes);
+
+/* Initial model of every cluster (as cmc_init_model with its spec). */
+int cmc_batch_init(const cmc_batch *b, void *stream);
+
+/* One step of every cluster (as cmc_step); p->seed and p->gamma are ignored
+ * (each cluster has its own).  With p->step == CMC_STEP_DEVICE the step index
+ * is each cluster's sc->step, advanced at the end: a call captured once in a
+ * hipGraph then advances the ensemble each time the graph is replayed. */
+int cmc_batch_step(const cmc_batch *b, const cmc_params *p, void *stream);
+
+/* cmc_potential of every cluster (public phi, mcum, ssuf). */
+int cmc_batch_potential(const cmc_batch *b, int32_t precision, void *stream);
+
+/* cmc_diagnostics of every cluster: out_dev[9c .. 9c+8] for cluster c. */
+int cmc_batch_diagnostics(const cmc_batch *b, double *out_dev, void *stream);
 
 /* Text for a CMC_E* code. */
 const char *cmc_strerror(int code);

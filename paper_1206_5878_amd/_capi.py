@@ -14,19 +14,25 @@ LIB_PATH = os.path.join(HERE, "libcmc.so")
 
 CMC_OK, CMC_EINVAL, CMC_EWORKSPACE, CMC_EHIP, CMC_ERANGE = 0, -1, -2, -3, -4
 CMC_FP64, CMC_MIXED = 0, 1
+CMC_MODEL_PLUMMER, CMC_MODEL_KING = 0, 1
+CMC_STEP_DEVICE = 0xFFFFFFFF
 ST_NONFINITE, ST_TRIAL_CAP, ST_BOUND, ST_ESCAPER = 0x01, 0x02, 0x04, 0x08
 ST_DT_DEGEN, ST_NUMERIC, ST_DT_NOCONV = 0x10, 0x20, 0x40
 
-EXPORTS = ("cmc_workspace_bytes", "cmc_init_plummer", "cmc_sort", "cmc_potential",
+EXPORTS = ("cmc_workspace_bytes", "cmc_init_plummer", "cmc_init_model", "cmc_sort", "cmc_potential",
            "cmc_timestep", "cmc_relax", "cmc_orbit", "cmc_step", "cmc_step_timed",
-           "cmc_diagnostics", "cmc_philox", "cmc_strerror", "cmc_abi_version")
+           "cmc_diagnostics", "cmc_philox", "cmc_strerror", "cmc_abi_version",
+           "cmc_batch_device_bytes", "cmc_batch_prepare", "cmc_batch_init", "cmc_batch_step",
+           "cmc_batch_potential", "cmc_batch_diagnostics")
+CMC_SHAPES = 16
 
 
 class cmc_scalars(C.Structure):
     _fields_ = [("n", C.c_int64), ("dt", C.c_double), ("status", C.c_uint32),
                 ("dt_iters", C.c_uint32), ("n_esc", C.c_int64), ("trials", C.c_int64),
                 ("violations", C.c_int64), ("capped", C.c_int64), ("e_esc", C.c_double),
-                ("mass_norm", C.c_double), ("reserved", C.c_int64 * 7)]
+                ("mass_norm", C.c_double), ("step", C.c_int64),
+                ("reserved", C.c_int64 * 6)]
 
 
 class cmc_state(C.Structure):
@@ -41,6 +47,17 @@ class cmc_params(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("step", C.c_uint32), ("precision", C.c_int32),
                 ("gamma", C.c_double), ("target", C.c_double), ("bound_factor", C.c_double),
                 ("trial_cap", C.c_int32), ("dt_iters", C.c_int32)]
+
+
+class cmc_cluster_spec(C.Structure):
+    _fields_ = [("n", C.c_int64), ("seed", C.c_uint64), ("gamma", C.c_double),
+                ("model", C.c_int32), ("mass_spectrum", C.c_int32), ("w0", C.c_double)]
+
+
+class cmc_batch(C.Structure):
+    _fields_ = [("clusters", C.c_int32), ("m_f32", C.c_int32), ("dev", C.c_void_p),
+                ("dev_bytes", C.c_size_t), ("total", C.c_int64 * CMC_SHAPES),
+                ("top_entries", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 assert C.sizeof(cmc_scalars) == 128
@@ -65,11 +82,22 @@ def lib() -> C.CDLL:
         L.cmc_workspace_bytes.argtypes = [C.c_int64]
         L.cmc_workspace_bytes.restype = C.c_size_t
         L.cmc_init_plummer.argtypes = [sp, C.c_int64, C.c_uint64, C.c_int32, vp]
+        L.cmc_init_model.argtypes = [sp, C.c_int64, C.c_uint64, C.c_int32, C.c_int32,
+                                     C.c_double, vp]
         L.cmc_sort.argtypes = [sp, vp]
         L.cmc_potential.argtypes = [sp, C.c_int32, vp]
         for f in ("cmc_timestep", "cmc_relax", "cmc_orbit", "cmc_step"):
             getattr(L, f).argtypes = [sp, pp, vp]
         L.cmc_step_timed.argtypes = [sp, pp, C.POINTER(C.c_void_p), vp]
+        bp = C.POINTER(cmc_batch)
+        L.cmc_batch_device_bytes.argtypes = [sp, C.c_int32]
+        L.cmc_batch_device_bytes.restype = C.c_size_t
+        L.cmc_batch_prepare.argtypes = [bp, sp, C.POINTER(cmc_cluster_spec), C.c_int32, vp,
+                                        C.c_size_t]
+        L.cmc_batch_init.argtypes = [bp, vp]
+        L.cmc_batch_step.argtypes = [bp, pp, vp]
+        L.cmc_batch_potential.argtypes = [bp, C.c_int32, vp]
+        L.cmc_batch_diagnostics.argtypes = [bp, vp, vp]
         L.cmc_diagnostics.argtypes = [sp, vp, vp]
         L.cmc_philox.argtypes = [C.c_uint64, vp, vp, C.c_int64, vp]
         L.cmc_strerror.argtypes = [C.c_int]

@@ -114,6 +114,12 @@ class Cluster:
 
 
 # ---------------------------------------------------------------- ABI calls
+def cmc_init_model(cl: Cluster, n: int, seed: int, model: int, mass_spectrum: int = 0,
+                   w0: float = 0.0, stream=None):
+    A.check(A.lib().cmc_init_model(cl.c, n, seed, model, mass_spectrum, w0, _stream(stream)),
+            "cmc_init_model")
+
+
 def cmc_init_plummer(cl: Cluster, n: int, seed: int, mass_spectrum: int = 0, stream=None):
     A.check(A.lib().cmc_init_plummer(cl.c, n, seed, mass_spectrum, _stream(stream)),
             "cmc_init_plummer")
@@ -172,3 +178,70 @@ def cmc_step_timed(cl: Cluster, p: Params, events, stream=None):
     pc = p.c()
     arr = (C.c_void_p * 6)(*events)
     A.check(A.lib().cmc_step_timed(cl.c, C.byref(pc), arr, _stream(stream)), "cmc_step_timed")
+
+
+# ---------------------------------------------------------------- ensembles
+_DIAG_KEYS = ("T", "W", "E", "virial", "M", "r01", "r10", "r50", "r90")
+
+
+class Ensemble:
+    """Independent clusters advanced by the same launches (cmc_batch_*).
+
+    specs: one dict per cluster with keys n, seed, gamma, model, and
+    optionally mass_spectrum, w0, cap (default n)."""
+
+    def __init__(self, specs, m_f32: bool = False, device: str = "cuda"):
+        L = A.lib()
+        self.specs = [dict(s) for s in specs]
+        self.clusters = [Cluster(int(s.get("cap", s["n"])), m_f32=m_f32, device=device)
+                         for s in self.specs]
+        k = len(self.clusters)
+        self._states = (A.cmc_state * k)(*[cl._c for cl in self.clusters])
+        self._specs = (A.cmc_cluster_spec * k)(*[
+            A.cmc_cluster_spec(int(s["n"]), int(s["seed"]), float(s["gamma"]), int(s["model"]),
+                               int(s.get("mass_spectrum", 0)), float(s.get("w0", 0.0)))
+            for s in self.specs])
+        nbytes = int(L.cmc_batch_device_bytes(self._states, k))
+        if nbytes == 0:
+            raise A.CmcError("invalid ensemble states")
+        self.dev = torch.zeros(nbytes + 256, dtype=torch.uint8, device=torch.device(device))
+        base = self.dev.data_ptr()
+        self.handle = A.cmc_batch()
+        A.check(L.cmc_batch_prepare(C.byref(self.handle), self._states, self._specs, k,
+                                    C.c_void_p(base + (-base) % 256), nbytes),
+                "cmc_batch_prepare")
+
+    def __len__(self):
+        return len(self.clusters)
+
+    def init(self, stream=None):
+        A.check(A.lib().cmc_batch_init(C.byref(self.handle), _stream(stream)), "cmc_batch_init")
+
+    def step(self, p: Params, stream=None):
+        pc = p.c()
+        A.check(A.lib().cmc_batch_step(C.byref(self.handle), C.byref(pc), _stream(stream)),
+                "cmc_batch_step")
+
+    def potential(self, precision: int = A.CMC_FP64, stream=None):
+        A.check(A.lib().cmc_batch_potential(C.byref(self.handle), precision, _stream(stream)),
+                "cmc_batch_potential")
+
+    def diagnostics(self, stream=None) -> list:
+        out = torch.zeros(9 * len(self), dtype=torch.float64, device=self.dev.device)
+        A.check(A.lib().cmc_batch_diagnostics(C.byref(self.handle), C.c_void_p(out.data_ptr()),
+                                              _stream(stream)), "cmc_batch_diagnostics")
+        v = out.cpu().numpy().reshape(-1, 9)
+        return [dict(zip(_DIAG_KEYS, row)) for row in v]
+
+    def capture(self, p: Params) -> torch.cuda.CUDAGraph:
+        """A graph of one ensemble step that advances the step index on the
+        device (CMC_STEP_DEVICE): replay it once per step."""
+        q = Params(**{**p.__dict__, "step": A.CMC_STEP_DEVICE})
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                self.step(q, stream=s)
+        torch.cuda.current_stream().wait_stream(s)
+        return g

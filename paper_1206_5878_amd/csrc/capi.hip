@@ -6,6 +6,46 @@
 
 using cmc::Workspace;
 
+namespace cmc {
+
+ClusterArgs cluster_args(const cmc_state &s, uint64_t seed, double gamma) {
+  ClusterArgs a{};
+  a.s = s;
+  a.w = layout(s.cap, s.work);
+  a.top = orbit_top(a.w, s.cap);
+  a.seed = seed;
+  a.gamma = gamma;
+  a.model = CMC_MODEL_PLUMMER;
+  a.mass_spectrum = 0;
+  a.w0 = 0.0;
+  a.n_init = 0;
+  a.bracket_blocks = blocks_of(kShBracket, a.w, s.cap);
+  return a;
+}
+
+// potential, timestep, relax, orbit, sort; events (if given) between them
+hipError_t launch_step(const Target &t, bool m_f32, const cmc_params &p, void *const *events,
+                       hipStream_t st) {
+  auto mark = [&](int i) -> hipError_t {
+    return events ? hipEventRecord(static_cast<hipEvent_t>(events[i]), st) : hipSuccess;
+  };
+  hipError_t e = mark(0);
+  if (e == hipSuccess) e = launch_potential(t, m_f32, p.precision, false, st);
+  if (e == hipSuccess) e = mark(1);
+  if (e == hipSuccess) e = launch_timestep(t, m_f32, p, st);
+  if (e == hipSuccess) e = mark(2);
+  if (e == hipSuccess) e = launch_relax(t, m_f32, p, st);
+  if (e == hipSuccess) e = mark(3);
+  if (e == hipSuccess) e = launch_orbit(t, m_f32, p, true, st);
+  if (e == hipSuccess) e = mark(4);
+  if (e == hipSuccess) e = launch_sort_stage(t, m_f32, false, st);
+  if (e == hipSuccess && p.step == CMC_STEP_DEVICE) e = launch_step_advance(t, st);
+  if (e == hipSuccess) e = mark(5);
+  return e;
+}
+
+}  // namespace cmc
+
 static_assert(sizeof(cmc_scalars) == 128, "cmc_scalars is 128 bytes in the ABI");
 
 namespace {
@@ -32,6 +72,15 @@ int check_params(const cmc_params *p) {
 }
 
 int status_of(hipError_t e) { return e == hipSuccess ? CMC_OK : CMC_EHIP; }
+
+// The launch target of a single-cluster call.
+struct Single {
+  cmc::ClusterArgs a;
+  cmc::Target t() const { return cmc::Target{&a, nullptr}; }
+};
+Single single(const cmc_state &s, uint64_t seed, double gamma) {
+  return Single{cmc::cluster_args(s, seed, gamma)};
+}
 
 hipStream_t as_stream(void *stream) { return static_cast<hipStream_t>(stream); }
 
@@ -63,24 +112,37 @@ const char *cmc_strerror(int code) {
   }
 }
 
-int cmc_init_plummer(cmc_state *s, int64_t n, uint64_t seed, int32_t mass_spectrum,
-                     void *stream) {
+int cmc_init_model(cmc_state *s, int64_t n, uint64_t seed, int32_t model, int32_t mass_spectrum,
+                   double w0, void *stream) {
   Workspace w;
   int rc = check_state(s, &w);
   if (rc) return rc;
   if (n < 0) return CMC_EINVAL;
   if (n > s->cap) return CMC_ERANGE;
   if (mass_spectrum != 0 && mass_spectrum != 1) return CMC_EINVAL;
-  return status_of(cmc::launch_init_plummer(*s, w, n, seed, mass_spectrum, as_stream(stream)));
+  if (model != CMC_MODEL_PLUMMER && model != CMC_MODEL_KING) return CMC_EINVAL;
+  if (model == CMC_MODEL_KING && !(w0 > 0.0 && w0 <= 16.0)) return CMC_EINVAL;
+  Single one = single(*s, seed, 1.0);
+  one.a.model = model;
+  one.a.mass_spectrum = mass_spectrum;
+  one.a.w0 = w0;
+  one.a.n_init = n;
+  return status_of(cmc::launch_init(one.t(), s->m_f32 != 0, as_stream(stream)));
+}
+
+int cmc_init_plummer(cmc_state *s, int64_t n, uint64_t seed, int32_t mass_spectrum,
+                     void *stream) {
+  return cmc_init_model(s, n, seed, CMC_MODEL_PLUMMER, mass_spectrum, 0.0, stream);
 }
 
 int cmc_sort(cmc_state *s, void *stream) {
   Workspace w;
   int rc = check_state(s, &w);
   if (rc) return rc;
-  hipError_t e = cmc::launch_stage_from_state(*s, w, as_stream(stream));
+  const Single one = single(*s, 0, 1.0);
+  hipError_t e = cmc::launch_stage_from_state(one.t(), s->m_f32 != 0, as_stream(stream));
   if (e != hipSuccess) return CMC_EHIP;
-  return status_of(cmc::launch_sort_stage(*s, w, false, as_stream(stream)));
+  return status_of(cmc::launch_sort_stage(one.t(), s->m_f32 != 0, false, as_stream(stream)));
 }
 
 int cmc_potential(cmc_state *s, int32_t precision, void *stream) {
@@ -88,7 +150,9 @@ int cmc_potential(cmc_state *s, int32_t precision, void *stream) {
   int rc = check_state(s, &w);
   if (rc) return rc;
   if (precision != CMC_FP64 && precision != CMC_MIXED) return CMC_EINVAL;
-  return status_of(cmc::launch_potential(*s, w, precision, true, as_stream(stream)));
+  const Single one = single(*s, 0, 1.0);
+  return status_of(
+      cmc::launch_potential(one.t(), s->m_f32 != 0, precision, true, as_stream(stream)));
 }
 
 int cmc_timestep(cmc_state *s, const cmc_params *p, void *stream) {
@@ -96,7 +160,8 @@ int cmc_timestep(cmc_state *s, const cmc_params *p, void *stream) {
   int rc = check_state(s, &w);
   if (rc) return rc;
   if ((rc = check_params(p))) return rc;
-  return status_of(cmc::launch_timestep(*s, w, *p, as_stream(stream)));
+  const Single one = single(*s, p->seed, p->gamma);
+  return status_of(cmc::launch_timestep(one.t(), s->m_f32 != 0, *p, as_stream(stream)));
 }
 
 int cmc_relax(cmc_state *s, const cmc_params *p, void *stream) {
@@ -104,7 +169,8 @@ int cmc_relax(cmc_state *s, const cmc_params *p, void *stream) {
   int rc = check_state(s, &w);
   if (rc) return rc;
   if ((rc = check_params(p))) return rc;
-  return status_of(cmc::launch_relax(*s, w, *p, as_stream(stream)));
+  const Single one = single(*s, p->seed, p->gamma);
+  return status_of(cmc::launch_relax(one.t(), s->m_f32 != 0, *p, as_stream(stream)));
 }
 
 int cmc_orbit(cmc_state *s, const cmc_params *p, void *stream) {
@@ -112,8 +178,9 @@ int cmc_orbit(cmc_state *s, const cmc_params *p, void *stream) {
   int rc = check_state(s, &w);
   if (rc) return rc;
   if ((rc = check_params(p))) return rc;
-  hipError_t e = cmc::launch_table_pack(*s, w, as_stream(stream));
-  if (e == hipSuccess) e = cmc::launch_orbit(*s, w, *p, false, as_stream(stream));
+  const Single one = single(*s, p->seed, p->gamma);
+  hipError_t e = cmc::launch_table_pack(one.t(), as_stream(stream));
+  if (e == hipSuccess) e = cmc::launch_orbit(one.t(), s->m_f32 != 0, *p, false, as_stream(stream));
   return status_of(e);
 }
 
@@ -123,21 +190,8 @@ static int run_step(cmc_state *s, const cmc_params *p, void *const *events, hipS
   int rc = check_state(s, &w);
   if (rc) return rc;
   if ((rc = check_params(p))) return rc;
-  auto mark = [&](int i) -> hipError_t {
-    return events ? hipEventRecord(static_cast<hipEvent_t>(events[i]), st) : hipSuccess;
-  };
-  hipError_t e = mark(0);
-  if (e == hipSuccess) e = cmc::launch_potential(*s, w, p->precision, false, st);
-  if (e == hipSuccess) e = mark(1);
-  if (e == hipSuccess) e = cmc::launch_timestep(*s, w, *p, st);
-  if (e == hipSuccess) e = mark(2);
-  if (e == hipSuccess) e = cmc::launch_relax(*s, w, *p, st);
-  if (e == hipSuccess) e = mark(3);
-  if (e == hipSuccess) e = cmc::launch_orbit(*s, w, *p, true, st);
-  if (e == hipSuccess) e = mark(4);
-  if (e == hipSuccess) e = cmc::launch_sort_stage(*s, w, false, st);
-  if (e == hipSuccess) e = mark(5);
-  return status_of(e);
+  const Single one = single(*s, p->seed, p->gamma);
+  return status_of(cmc::launch_step(one.t(), s->m_f32 != 0, *p, events, st));
 }
 
 int cmc_step(cmc_state *s, const cmc_params *p, void *stream) {
@@ -156,7 +210,8 @@ int cmc_diagnostics(const cmc_state *s, double *out_dev, void *stream) {
   int rc = check_state(s, &w);
   if (rc) return rc;
   if (!out_dev) return CMC_EINVAL;
-  return status_of(cmc::launch_diagnostics(*s, w, out_dev, as_stream(stream)));
+  const Single one = single(*s, 0, 1.0);
+  return status_of(cmc::launch_diagnostics(one.t(), s->m_f32 != 0, out_dev, as_stream(stream)));
 }
 
 int cmc_philox(uint64_t key, const uint32_t *ctr_dev, uint32_t *out_dev, int64_t n,

@@ -185,8 +185,8 @@ struct alignas(16) OrbitRec {
 };
 constexpr int kMaxLevels = 12;  // 8^11 > 2^32 stars
 struct Levels {
-  RPhi *lev[kMaxLevels];
-  int nlev;  // levels in use for the capacity; the top one has <= 8 entries
+  RPhi *const *lev;  // the workspace's level pointers, [kMaxLevels]
+  int nlev;          // levels in use for the capacity; the top one has <= 8 entries
 };
 // ---------------------------------------------------------------- radial index
 // Buckets over the sorted radii.  The bucket of a radius x >= r_0 is
@@ -240,6 +240,8 @@ constexpr int kSortTile = 4096;  // keys per radix tile (256 threads x 16)
 constexpr int kPotTile = 2048;   // stars per potential tile (256 x 8)
 constexpr int kBlock = 256;
 constexpr int kRedBlocks = 2048;  // grid of the grid-stride reduction kernels
+constexpr int kKingNodes = 4096;  // nodes of a King profile: (r, W, M) each
+constexpr int kKingTab = 3 * kKingNodes + 8;
 
 struct Workspace {
   RPhi *lev[kMaxLevels];    // level L: [ceil(cap / 8^L)]
@@ -262,13 +264,14 @@ struct Workspace {
   uint32_t *rx_start;       // [rx_nb + 1] radial index buckets
   uint32_t *rx_tile;        // [cdiv(rx_nb + 1, 4096)] prefix-maximum tiles
   RIndexCtl *rx_ctl;        // [1]
+  double *king;             // [kKingTab] King model profile (initial model only)
   int64_t rx_nb;
   int rx_lg_nb;
   int64_t sort_tiles, pot_tiles, pair_blocks, star_blocks;
   size_t bytes;
 };
 
-inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 inline Workspace layout(int64_t cap, void *base) {
   Workspace w{};
@@ -318,16 +321,14 @@ inline Workspace layout(int64_t cap, void *base) {
   w.rx_start = reinterpret_cast<uint32_t *>(take(4 * (w.rx_nb + 1)));
   w.rx_tile = reinterpret_cast<uint32_t *>(take(4 * cdiv(w.rx_nb + 1, 4096)));
   w.rx_ctl = reinterpret_cast<RIndexCtl *>(take(sizeof(RIndexCtl)));
+  w.king = reinterpret_cast<double *>(take(8 * kKingTab));
   w.bytes = (off + 255) & ~size_t(255);
   return w;
 }
 
-inline Levels levels_of(const Workspace &w) {
-  Levels L{};
-  for (int i = 0; i < kMaxLevels; ++i) L.lev[i] = w.lev[i];
-  L.nlev = w.nlev;
-  return L;
-}
+// A view of the workspace's levels (no copy: kernels index it with
+// run-time level numbers).
+__host__ __device__ inline Levels levels_of(const Workspace &w) { return Levels{w.lev, w.nlev}; }
 
 // Write star k's table entries (level 0, every level L whose stride divides
 // k, and M, S).
@@ -343,32 +344,166 @@ __device__ __forceinline__ void put_table(const Levels &lv, MS *ms, int64_t k, d
   }
 }
 
+// ---------------------------------------------------------------- launch context
+// What a kernel knows about the cluster it works on.  One cluster: the
+// arguments travel by value and block b of the launch is block b of the
+// cluster.  An ensemble: one launch covers every cluster, each cluster owns
+// its own arrays and workspace, and a per-shape map names the cluster of
+// each block and the cluster's first block.
+struct OrbitTop {             // top levels of the orbit table kept in LDS
+  int32_t off[kMaxLevels];    // LDS entry offset of level L, for L >= ltop
+  int32_t len[kMaxLevels];    // entries of level L at the capacity
+  int32_t ltop, entries;
+};
+struct ClusterArgs {
+  cmc_state s;                // the cluster's arrays (device pointers)
+  Workspace w;                // its workspace
+  OrbitTop top;
+  uint64_t seed;              // Philox key
+  double gamma;               // Coulomb logarithm ln(gamma N)
+  int32_t model;              // initial model: CMC_MODEL_PLUMMER or CMC_MODEL_KING
+  int32_t mass_spectrum;      // 1: broken power-law masses
+  double w0;                  // King central potential W0
+  int64_t n_init;             // stars the initial model draws
+  int64_t bracket_blocks;     // blocks of the cluster in the bracket kernel
+};
+
+struct One {
+  ClusterArgs a;
+  __device__ __forceinline__ int index() const { return 0; }
+  __device__ __forceinline__ const ClusterArgs &args() const { return a; }
+  __device__ __forceinline__ int64_t block() const { return blockIdx.x; }
+  __device__ __forceinline__ int64_t nblocks() const { return gridDim.x; }
+};
+struct Many {
+  const ClusterArgs *a;       // [clusters]
+  const uint16_t *map;        // [blocks of the launch]: the block's cluster
+  const int64_t *first;       // [clusters + 1]: first block of each cluster
+  __device__ __forceinline__ int c() const { return map[blockIdx.x]; }
+  __device__ __forceinline__ int index() const { return c(); }
+  __device__ __forceinline__ const ClusterArgs &args() const { return a[c()]; }
+  __device__ __forceinline__ int64_t block() const { return blockIdx.x - first[c()]; }
+  __device__ __forceinline__ int64_t nblocks() const {
+    const int cc = c();
+    return first[cc + 1] - first[cc];
+  }
+};
+
+// The step index of a call: its own, or the cluster's device counter for
+// calls replayed from a captured graph.
+__device__ __forceinline__ uint32_t step_of(const ClusterArgs &A, uint32_t step) {
+  return step == CMC_STEP_DEVICE ? static_cast<uint32_t>(A.s.sc->step) : step;
+}
+
+// Launch shapes: blocks per cluster of each kind of grid.
+enum Shape : int {
+  kShOne,       // one block per cluster
+  kShStar,      // one thread per star, 256 per block
+  kShPair,      // one thread per pair
+  kShDtEval,    // grid-stride over pairs, at most kRedBlocks blocks
+  kShPotTile,   // potential tiles
+  kShSortTile,  // radix tiles
+  kShKeyRange,  // grid-stride over keys, at most 1024 blocks
+  kShDigit,     // one block per radix digit
+  kShBracket,   // resident blocks of the bracket kernel
+  kShTrials,    // wavefront chunks of the trial kernel
+  kShRxClear,   // grid-stride clear of the bucket index
+  kShRxTile,    // prefix-maximum tiles of the bucket index
+  kShDiag,      // grid-stride diagnostics partials
+  kShapes
+};
+constexpr int kBracketThreads = 512;
+constexpr int kBracketBlocks = 1024;  // resident bracket blocks of one cluster
+constexpr int kTrialChunk = 128;      // stars per wavefront chunk of the trial kernel
+constexpr int kRxTile = 4096;         // bucket-index entries per prefix-maximum tile
+__host__ __device__ inline int64_t blocks_of(Shape sh, const Workspace &w, int64_t cap) {
+  const int64_t c = cap > 0 ? cap : 1;
+  switch (sh) {
+    case kShOne: return 1;
+    case kShStar: return w.star_blocks;
+    case kShPair: return w.pair_blocks;
+    case kShDtEval: return w.pair_blocks < kRedBlocks ? w.pair_blocks : kRedBlocks;
+    case kShPotTile: return w.pot_tiles;
+    case kShSortTile: return w.sort_tiles;
+    case kShKeyRange: return w.sort_tiles < 1024 ? w.sort_tiles : 1024;
+    case kShDigit: return 256;
+    case kShBracket: {
+      const int64_t b = cdiv(c, kBracketThreads);
+      return b < kBracketBlocks ? b : kBracketBlocks;
+    }
+    case kShTrials: return cdiv(c, int64_t(kTrialChunk) * (kBlock / 64));
+    case kShRxClear: {
+      const int64_t b = cdiv(w.rx_nb + 1, kBlock);
+      return b < 4096 ? b : 4096;
+    }
+    case kShRxTile: return cdiv(w.rx_nb + 1, kRxTile);
+    case kShDiag: return w.star_blocks < kRedBlocks ? w.star_blocks : kRedBlocks;
+    default: return 1;
+  }
+}
+
+// Host side of a launch: one cluster, or an ensemble whose tables live in
+// device memory (see batch.hip).
+struct BatchDev {
+  int32_t clusters;
+  const ClusterArgs *args;              // device [clusters]
+  const uint16_t *map[kShapes];         // device, per shape
+  const int64_t *first[kShapes];        // device, per shape [clusters + 1]
+  int64_t total[kShapes];               // blocks per shape over all clusters
+  int32_t top_entries;                  // largest OrbitTop::entries
+  int32_t any_f32, any_f64;             // mass storage kinds present
+};
+struct Target {
+  const ClusterArgs *one;               // host struct, or null
+  const BatchDev *many;                 // or an ensemble
+};
+struct OneL {
+  const ClusterArgs &a;
+  One ctx(Shape) const { return One{a}; }
+  unsigned grid(Shape sh) const { return static_cast<unsigned>(blocks_of(sh, a.w, a.s.cap)); }
+  int top_entries() const { return a.top.entries; }
+};
+struct ManyL {
+  const BatchDev &d;
+  Many ctx(Shape sh) const { return Many{d.args, d.map[sh], d.first[sh]}; }
+  unsigned grid(Shape sh) const { return static_cast<unsigned>(d.total[sh]); }
+  int top_entries() const { return d.top_entries; }
+};
+
+// The orbit table's LDS-resident top levels for a capacity.
+OrbitTop orbit_top(const Workspace &w, int64_t cap);
+ClusterArgs cluster_args(const cmc_state &s, uint64_t seed, double gamma);
+
+
 // ---------------------------------------------------------------- launchers
-// Defined in the translation units; each returns hipGetLastError().
+// Defined in the translation units; each returns hipGetLastError().  Masses
+// are f32 or f64 per cluster; an ensemble must not mix the two.
 // public_arrays: also write phi, mcum, ssuf of the state (the orbit pass
 // reads only the workspace table)
-hipError_t launch_potential(const cmc_state &s, const Workspace &w, int precision,
-                            bool public_arrays, hipStream_t st);
-hipError_t launch_timestep(const cmc_state &s, const Workspace &w, const cmc_params &p,
-                           hipStream_t st);
-hipError_t launch_relax(const cmc_state &s, const Workspace &w, const cmc_params &p,
+hipError_t launch_potential(const Target &t, bool m_f32, int precision, bool public_arrays,
+                            hipStream_t st);
+hipError_t launch_timestep(const Target &t, bool m_f32, const cmc_params &p, hipStream_t st);
+hipError_t launch_relax(const Target &t, bool m_f32, const cmc_params &p, hipStream_t st);
+hipError_t launch_orbit(const Target &t, bool m_f32, const cmc_params &p, bool to_stage,
                         hipStream_t st);
-hipError_t launch_orbit(const cmc_state &s, const Workspace &w, const cmc_params &p,
-                        bool to_stage, hipStream_t st);
-hipError_t launch_table_pack(const cmc_state &s, const Workspace &w, hipStream_t st);
-// radial index over the sorted radii s.r[0, sc->n)
-hipError_t launch_rindex(const cmc_state &s, const Workspace &w, hipStream_t st);
-inline RIndex rindex_of(const cmc_state &s, const Workspace &w) {
-  return RIndex{s.r, w.rx_start, w.rx_ctl};
-}
-hipError_t launch_stage_from_state(const cmc_state &s, const Workspace &w, hipStream_t st);
-hipError_t launch_sort_stage(const cmc_state &s, const Workspace &w, bool normalise_mass,
+hipError_t launch_table_pack(const Target &t, hipStream_t st);
+hipError_t launch_rindex(const Target &t, hipStream_t st);
+hipError_t launch_stage_from_state(const Target &t, bool m_f32, hipStream_t st);
+hipError_t launch_sort_stage(const Target &t, bool m_f32, bool normalise_mass,
                              hipStream_t st);
-hipError_t launch_init_plummer(const cmc_state &s, const Workspace &w, int64_t n,
-                               uint64_t seed, int mass_spectrum, hipStream_t st);
-hipError_t launch_diagnostics(const cmc_state &s, const Workspace &w, double *out,
-                              hipStream_t st);
+hipError_t launch_init(const Target &t, bool m_f32, hipStream_t st);
+hipError_t launch_diagnostics(const Target &t, bool m_f32, double *out, hipStream_t st);
 hipError_t launch_philox(uint64_t key, const uint32_t *ctr, uint32_t *out, int64_t n,
                          hipStream_t st);
+hipError_t launch_step(const Target &t, bool m_f32, const cmc_params &p, void *const *events,
+                       hipStream_t st);
+hipError_t launch_step_advance(const Target &t, hipStream_t st);
+
+// Run F<One or Many launch> on the target.
+template <class F>
+hipError_t dispatch(const Target &t, F &&f) {
+  if (t.many) return f(ManyL{*t.many});
+  return f(OneL{*t.one});
+}
 
 }  // namespace cmc

@@ -9,18 +9,18 @@ namespace {
 
 constexpr int NT = kBlock;
 
-template <typename MT>
-__global__ __launch_bounds__(NT) void k_diag(const double *__restrict__ vr,
-                                             const double *__restrict__ vt,
-                                             const MT *__restrict__ m,
-                                             const double *__restrict__ phi,
-                                             const cmc_scalars *__restrict__ sc,
-                                             double *__restrict__ part) {
+template <class Ctx, typename MT>
+__global__ __launch_bounds__(NT) void k_diag(Ctx ctx) {
   __shared__ double sh[NT / 64];
-  const int64_t n = sc->n;
+  const ClusterArgs &A = ctx.args();
+  const double *__restrict__ vr = A.s.vr;
+  const double *__restrict__ vt = A.s.vt;
+  const MT *__restrict__ m = static_cast<const MT *>(A.s.m);
+  const double *__restrict__ phi = A.s.phi;
+  const int64_t n = A.s.sc->n;
+  const int64_t blk = ctx.block();
   double t = 0.0, wv = 0.0;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * NT) {
+  for (int64_t i = blk * NT + threadIdx.x; i < n; i += ctx.nblocks() * NT) {
     const double mi = load_mass(m, i);
     t += 0.5 * mi * (vr[i] * vr[i] + vt[i] * vt[i]);
     wv += 0.5 * mi * phi[i];
@@ -28,26 +28,30 @@ __global__ __launch_bounds__(NT) void k_diag(const double *__restrict__ vr,
   t = block_sum<NT>(t, sh);
   wv = block_sum<NT>(wv, sh);
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = t;
-    part[2 * blockIdx.x + 1] = wv;
+    A.w.red_part[2 * blk] = t;
+    A.w.red_part[2 * blk + 1] = wv;
   }
 }
 
-__global__ __launch_bounds__(NT) void k_diag_final(const double *__restrict__ part, int nblocks,
-                                                   const double *__restrict__ r,
-                                                   const double *__restrict__ mcum,
-                                                   const cmc_scalars *__restrict__ sc,
-                                                   double *__restrict__ out) {
+// One block per cluster; cluster c writes out[9 c .. 9 c + 8].
+template <class Ctx>
+__global__ __launch_bounds__(NT) void k_diag_final(Ctx ctx, double *__restrict__ out_all) {
   __shared__ double sh[NT / 64];
+  const ClusterArgs &A = ctx.args();
+  const double *__restrict__ part = A.w.red_part;
+  const int64_t nblocks = blocks_of(kShDiag, A.w, A.s.cap);
+  const double *__restrict__ r = A.s.r;
+  const double *__restrict__ mcum = A.s.mcum;
+  double *__restrict__ out = out_all + 9 * ctx.index();
   double T = 0.0, W = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += NT) {
+  for (int64_t b = threadIdx.x; b < nblocks; b += NT) {
     T += part[2 * b];
     W += part[2 * b + 1];
   }
   T = block_sum<NT>(T, sh);
   W = block_sum<NT>(W, sh);
   if (threadIdx.x != 0) return;
-  const int64_t n = sc->n;
+  const int64_t n = A.s.sc->n;
   const double M = n > 0 ? mcum[n - 1] : 0.0;
   out[0] = T;
   out[1] = W;
@@ -80,20 +84,18 @@ __global__ __launch_bounds__(NT) void k_philox(uint64_t key, const uint32_t *__r
   out[4 * i + 3] = w.w;
 }
 
-template <typename MT>
-hipError_t run(const cmc_state &s, const Workspace &w, double *out, hipStream_t st) {
-  const int nb = static_cast<int>(w.star_blocks < kRedBlocks ? w.star_blocks : kRedBlocks);
-  k_diag<MT><<<nb, NT, 0, st>>>(s.vr, s.vt, static_cast<const MT *>(s.m), s.phi, s.sc,
-                                w.red_part);
-  k_diag_final<<<1, NT, 0, st>>>(w.red_part, nb, s.r, s.mcum, s.sc, out);
-  return hipGetLastError();
-}
-
 }  // namespace
 
-hipError_t launch_diagnostics(const cmc_state &s, const Workspace &w, double *out,
-                              hipStream_t st) {
-  return s.m_f32 ? run<float>(s, w, out, st) : run<double>(s, w, out, st);
+hipError_t launch_diagnostics(const Target &t, bool m_f32, double *out, hipStream_t st) {
+  return dispatch(t, [&](const auto &l) {
+    using C = decltype(l.ctx(kShDiag));
+    if (m_f32)
+      k_diag<C, float><<<l.grid(kShDiag), NT, 0, st>>>(l.ctx(kShDiag));
+    else
+      k_diag<C, double><<<l.grid(kShDiag), NT, 0, st>>>(l.ctx(kShDiag));
+    k_diag_final<<<l.grid(kShOne), NT, 0, st>>>(l.ctx(kShOne), out);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_philox(uint64_t key, const uint32_t *ctr, uint32_t *out, int64_t n,

@@ -29,6 +29,7 @@
 // table finds.  The interval of a trial radius comes from the radial bucket
 // index (rindex.hip).
 #include <algorithm>
+#include <type_traits>
 
 #include "cmc_internal.hpp"
 
@@ -37,7 +38,6 @@ namespace {
 
 constexpr int NT = kBlock;
 constexpr int BT = 512;         // threads per block of the bracket kernel
-constexpr int kBracketGrid = 1024;  // its blocks (each loops over tiles)
 constexpr int kChunk = 128;     // stars per wavefront in the trial kernel
 constexpr int kGroupBatch = 8;  // group searches whose loads are in flight together
 static_assert(16 % kGroupBatch == 0, "batches split the 16 searches of a group");
@@ -186,17 +186,13 @@ __device__ __forceinline__ void group_descend2(const Levels &lv, int ltop, int64
 }
 
 // ---------------------------------------------------------------- LDS top
-// The levels [ltop, nlev) -- a few thousand entries -- are copied into LDS by
-// every block of the bracket kernel; each lane descends them on its own.
-struct TopLevels {
-  int32_t off[kMaxLevels];  // LDS entry offset of level L, for L >= ltop
-  int32_t len[kMaxLevels];  // entries of level L at the capacity
-  int32_t ltop, entries;
-};
+// The levels [ltop, nlev) -- a few thousand entries, see orbit_top() -- are
+// copied into LDS by every block of the bracket kernel; each lane descends
+// them on its own.
 constexpr int kTopBytes = 48 * 1024;
 
 template <class Pred>
-__device__ __forceinline__ int32_t top_descend(const RPhi *top, const TopLevels &tl, int nlev,
+__device__ __forceinline__ int32_t top_descend(const RPhi *top, const OrbitTop &tl, int nlev,
                                                int64_t n, const Pred &pred) {
   if (!pred(0, top[tl.off[nlev - 1]])) return -1;
   int64_t s = 0;
@@ -261,18 +257,29 @@ __device__ __forceinline__ void or_status(cmc_scalars *sc, uint32_t fl) {
   }
 }
 
-template <typename MT, bool TO_STAGE>
+template <class Ctx, typename MT, bool TO_STAGE>
 __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4)))
-void k_orbit_bracket(Levels lv, TopLevels tl, RIndex ix, const MS *__restrict__ ms,
-                     const MT *__restrict__ m, double *__restrict__ vr,
-                     double *__restrict__ vt, const uint32_t *__restrict__ id,
-                     double *__restrict__ r_new, StageRec *__restrict__ stage,
-                     uint64_t *__restrict__ keys, OrbitRec *__restrict__ orec,
-                     cmc_scalars *__restrict__ sc, double *__restrict__ part, uint64_t seed,
-                     uint32_t step, double bound_factor) {
+void k_orbit_bracket(Ctx ctx, uint32_t step_arg, double bound_factor) {
   extern __shared__ RPhi top[];
   __shared__ double shd[BT / 64];
   __shared__ GParams prm[2 * BT];
+  const ClusterArgs &A = ctx.args();
+  const uint32_t step = step_of(A, step_arg);
+  const Levels lv = levels_of(A.w);
+  const OrbitTop &tl = A.top;
+  const RIndex ix{A.s.r, A.w.rx_start, A.w.rx_ctl};
+  const MS *__restrict__ ms = A.w.ms;
+  const MT *__restrict__ m = static_cast<const MT *>(A.s.m);
+  double *__restrict__ vr = A.s.vr;
+  double *__restrict__ vt = A.s.vt;
+  const uint32_t *__restrict__ id = A.s.id;
+  double *__restrict__ r_new = A.s.r_new;
+  StageRec *__restrict__ stage = A.w.stage;
+  uint64_t *__restrict__ keys = A.w.keys[0];
+  OrbitRec *__restrict__ orec = A.w.orec;
+  cmc_scalars *__restrict__ sc = A.s.sc;
+  double *__restrict__ part = A.w.red_part;
+  const uint64_t seed = A.seed;
   const RIndexCtl ictl = *ix.ctl;
   const int64_t n = ictl.n;
   const RPhi *tab = lv.lev[0];
@@ -284,7 +291,8 @@ void k_orbit_bracket(Levels lv, TopLevels tl, RIndex ix, const MS *__restrict__ 
   double c_esc = 0.0, e_esc = 0.0;
   uint32_t fl = 0;
   const int64_t tiles = (n + BT - 1) / BT;
-  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {  // block-uniform
+  const int64_t blk = ctx.block(), nblk = ctx.nblocks();
+  for (int64_t tile = blk; tile < tiles; tile += nblk) {  // block-uniform
     const int64_t i = tile * BT + threadIdx.x;
     double E = 0.0, J = 0.0, J2 = 0.0, vri = 0.0, vti = 0.0;
     if (i < n) {
@@ -311,8 +319,8 @@ void k_orbit_bracket(Levels lv, TopLevels tl, RIndex ix, const MS *__restrict__ 
     if (i < n) {
       OrbitRec rec{E, J, 0.0, 0.0, -1.0, 0, 0};
       if (!(E < 0.0)) {  // unbound: leaves the cluster
-        c_esc = 1.0;
-        e_esc = load_mass(m, i) * E;
+        c_esc += 1.0;
+        e_esc += load_mass(m, i) * E;
         fl |= CMC_ST_ESCAPER;
         if (E != E) fl |= CMC_ST_NONFINITE;
         emit<TO_STAGE>(i, kInf, vri, vti, load_mass(m, i), id[i], r_new, vr, vt, stage, keys);
@@ -382,26 +390,37 @@ void k_orbit_bracket(Levels lv, TopLevels tl, RIndex ix, const MS *__restrict__ 
   c_esc = block_sum<BT>(c_esc, shd);
   e_esc = block_sum<BT>(e_esc, shd);
   if (threadIdx.x == 0) {
-    part[2 * static_cast<int64_t>(blockIdx.x)] = c_esc;
-    part[2 * static_cast<int64_t>(blockIdx.x) + 1] = e_esc;
+    part[2 * blk] = c_esc;
+    part[2 * blk + 1] = e_esc;
   }
 }
 
-template <typename MT, bool TO_STAGE, bool MIXED>
+template <class Ctx, typename MT, bool TO_STAGE, bool MIXED>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5)))
-void k_orbit_trials(Levels lv, RIndex ix, const MS *__restrict__ ms, const MT *__restrict__ m,
-                    double *__restrict__ vr, double *__restrict__ vt,
-                    const uint32_t *__restrict__ id, double *__restrict__ r_new,
-                    StageRec *__restrict__ stage, uint64_t *__restrict__ keys,
-                    const OrbitRec *__restrict__ orec, cmc_scalars *__restrict__ sc,
-                    double *__restrict__ part, uint64_t seed, uint32_t step,
-                    int32_t trial_cap) {
+void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap) {
   __shared__ double shd[NT / 64];
+  const ClusterArgs &A = ctx.args();
+  const uint32_t step = step_of(A, step_arg);
+  const Levels lv = levels_of(A.w);
+  const RIndex ix{A.s.r, A.w.rx_start, A.w.rx_ctl};
+  const MS *__restrict__ ms = A.w.ms;
+  const MT *__restrict__ m = static_cast<const MT *>(A.s.m);
+  double *__restrict__ vr = A.s.vr;
+  double *__restrict__ vt = A.s.vt;
+  const uint32_t *__restrict__ id = A.s.id;
+  double *__restrict__ r_new = A.s.r_new;
+  StageRec *__restrict__ stage = A.w.stage;
+  uint64_t *__restrict__ keys = A.w.keys[0];
+  const OrbitRec *__restrict__ orec = A.w.orec;
+  cmc_scalars *__restrict__ sc = A.s.sc;
+  double *__restrict__ part = A.w.red_part + 2 * A.w.star_blocks;
+  const uint64_t seed = A.seed;
   const RIndexCtl ictl = *ix.ctl;
   const int64_t n = ictl.n;
+  const int64_t blk = ctx.block();
   const int lane = threadIdx.x & 63;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int64_t wave = static_cast<int64_t>(blockIdx.x) * (NT / 64) + (threadIdx.x >> 6);
+  const int64_t wave = blk * (NT / 64) + (threadIdx.x >> 6);
   const int64_t c_end0 = (wave + 1) * kChunk;
   const int64_t c_end = c_end0 < n ? c_end0 : n;
   int64_t cursor = wave * kChunk;  // wave-uniform
@@ -523,7 +542,7 @@ void k_orbit_trials(Levels lv, RIndex ix, const MS *__restrict__ ms, const MT *_
   const double t_viol = block_sum<NT>(static_cast<double>(c_viol), shd);
   const double t_cap = block_sum<NT>(static_cast<double>(c_cap), shd);
   if (threadIdx.x == 0) {
-    double *pp = part + 3 * static_cast<int64_t>(blockIdx.x);
+    double *pp = part + 3 * blk;
     pp[0] = t_tr;
     pp[1] = t_viol;
     pp[2] = t_cap;
@@ -532,10 +551,16 @@ void k_orbit_trials(Levels lv, RIndex ix, const MS *__restrict__ ms, const MT *_
 
 constexpr int FT = 1024;
 
-__global__ __launch_bounds__(FT) void k_orbit_sum(const double *__restrict__ pa, int64_t na,
-                                                  const double *__restrict__ pb, int64_t nb,
-                                                  cmc_scalars *__restrict__ sc) {
+// One block per cluster: the cluster's bracket and trial partials.
+template <class Ctx>
+__global__ __launch_bounds__(FT) void k_orbit_sum(Ctx ctx) {
   __shared__ double sh[FT / 64];
+  const ClusterArgs &A = ctx.args();
+  const double *__restrict__ pa = A.w.red_part;
+  const double *__restrict__ pb = A.w.red_part + 2 * A.w.star_blocks;
+  const int64_t na = A.bracket_blocks;
+  const int64_t nb = blocks_of(kShTrials, A.w, A.s.cap);
+  cmc_scalars *__restrict__ sc = A.s.sc;
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int64_t b = threadIdx.x; b < na; b += FT) {
     v[0] += pa[2 * b];
@@ -557,20 +582,41 @@ __global__ __launch_bounds__(FT) void k_orbit_sum(const double *__restrict__ pa,
 
 // The standalone orbit call reads the state's phi, mcum, ssuf: pack them into
 // the table layout first.
-__global__ __launch_bounds__(NT) void k_table_pack(const double *__restrict__ r,
-                                                   const double *__restrict__ phi,
-                                                   const double *__restrict__ mcum,
-                                                   const double *__restrict__ ssuf,
-                                                   const cmc_scalars *__restrict__ sc, Levels lv,
-                                                   MS *__restrict__ ms) {
-  const int64_t k = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
-  if (k >= sc->n) return;
-  put_table(lv, ms, k, r[k], phi[k], mcum[k], ssuf[k]);
+template <class Ctx>
+__global__ __launch_bounds__(NT) void k_table_pack(Ctx ctx) {
+  const ClusterArgs &A = ctx.args();
+  const int64_t k = ctx.block() * NT + threadIdx.x;
+  if (k >= A.s.sc->n) return;
+  put_table(levels_of(A.w), A.w.ms, k, A.s.r[k], A.s.phi[k], A.s.mcum[k], A.s.ssuf[k]);
 }
 
+template <class L, typename MT, bool TO_STAGE>
+hipError_t run2(const L &l, const cmc_params &p, hipStream_t st) {
+  const int32_t cap = p.trial_cap > 0 ? p.trial_cap : 10000;
+  const double bf = p.bound_factor > 0.0 ? p.bound_factor : 1.2;
+  using Cb = decltype(l.ctx(kShBracket));
+  using Ct = decltype(l.ctx(kShTrials));
+  k_orbit_bracket<Cb, MT, TO_STAGE>
+      <<<l.grid(kShBracket), BT, sizeof(RPhi) * l.top_entries(), st>>>(l.ctx(kShBracket), p.step,
+                                                                       bf);
+  if (p.precision == CMC_MIXED)
+    k_orbit_trials<Ct, MT, TO_STAGE, true><<<l.grid(kShTrials), NT, 0, st>>>(l.ctx(kShTrials),
+                                                                             p.step, cap);
+  else
+    k_orbit_trials<Ct, MT, TO_STAGE, false><<<l.grid(kShTrials), NT, 0, st>>>(
+        l.ctx(kShTrials), p.step, cap);
+  k_orbit_sum<<<l.grid(kShOne), FT, 0, st>>>(l.ctx(kShOne));
+  return hipGetLastError();
+}
+
+}  // namespace
+
+static_assert(sizeof(OrbitRec) == 48, "orbit record layout");
+static_assert(BT == kBracketThreads && kChunk == kTrialChunk, "launch shapes");
+
 // Levels from the top down while they fit kTopBytes of LDS.
-TopLevels top_levels(const Workspace &w, int64_t cap) {
-  TopLevels tl{};
+OrbitTop orbit_top(const Workspace &w, int64_t cap) {
+  OrbitTop tl{};
   int64_t tot = 0;
   tl.ltop = w.nlev;
   for (int L = w.nlev - 1; L >= 0; --L) {
@@ -586,55 +632,23 @@ TopLevels top_levels(const Workspace &w, int64_t cap) {
   return tl;
 }
 
-template <typename MT, bool TO_STAGE>
-hipError_t run2(const cmc_state &s, const Workspace &w, const cmc_params &p, hipStream_t st) {
-  const bool mixed = p.precision == CMC_MIXED;
-  const MT *m = static_cast<const MT *>(s.m);
-  const int32_t cap = p.trial_cap > 0 ? p.trial_cap : 10000;
-  const double bf = p.bound_factor > 0.0 ? p.bound_factor : 1.2;
-  const Levels lv = levels_of(w);
-  const TopLevels tl = top_levels(w, s.cap > 0 ? s.cap : 1);
-  const int64_t nga = std::min<int64_t>(cdiv(s.cap > 0 ? s.cap : 1, BT), kBracketGrid);
-  const int64_t nbb = cdiv(s.cap, int64_t(kChunk) * (NT / 64));
-  double *pa = w.red_part, *pb = w.red_part + 2 * w.star_blocks;
-  const RIndex ix = rindex_of(s, w);
-  hipError_t e = launch_rindex(s, w, st);
+hipError_t launch_table_pack(const Target &t, hipStream_t st) {
+  return dispatch(t, [&](const auto &l) {
+    k_table_pack<<<l.grid(kShStar), NT, 0, st>>>(l.ctx(kShStar));
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_orbit(const Target &t, bool m_f32, const cmc_params &p, bool to_stage,
+                        hipStream_t st) {
+  hipError_t e = launch_rindex(t, st);
   if (e != hipSuccess) return e;
-  k_orbit_bracket<MT, TO_STAGE>
-      <<<static_cast<unsigned>(nga), BT, sizeof(RPhi) * tl.entries, st>>>(
-          lv, tl, ix, w.ms, m, s.vr, s.vt, s.id, s.r_new, w.stage, w.keys[0], w.orec, s.sc, pa,
-          p.seed, p.step, bf);
-  if (mixed)
-    k_orbit_trials<MT, TO_STAGE, true><<<static_cast<unsigned>(nbb), NT, 0, st>>>(
-        lv, ix, w.ms, m, s.vr, s.vt, s.id, s.r_new, w.stage, w.keys[0], w.orec, s.sc, pb, p.seed,
-        p.step, cap);
-  else
-    k_orbit_trials<MT, TO_STAGE, false><<<static_cast<unsigned>(nbb), NT, 0, st>>>(
-        lv, ix, w.ms, m, s.vr, s.vt, s.id, s.r_new, w.stage, w.keys[0], w.orec, s.sc, pb, p.seed,
-        p.step, cap);
-  k_orbit_sum<<<1, FT, 0, st>>>(pa, nga, pb, nbb, s.sc);
-  return hipGetLastError();
-}
-
-template <typename MT>
-hipError_t run(const cmc_state &s, const Workspace &w, const cmc_params &p, bool to_stage,
-               hipStream_t st) {
-  return to_stage ? run2<MT, true>(s, w, p, st) : run2<MT, false>(s, w, p, st);
-}
-
-}  // namespace
-
-static_assert(sizeof(OrbitRec) == 48, "orbit record layout");
-
-hipError_t launch_table_pack(const cmc_state &s, const Workspace &w, hipStream_t st) {
-  k_table_pack<<<static_cast<unsigned>(w.star_blocks), NT, 0, st>>>(s.r, s.phi, s.mcum, s.ssuf,
-                                                                    s.sc, levels_of(w), w.ms);
-  return hipGetLastError();
-}
-
-hipError_t launch_orbit(const cmc_state &s, const Workspace &w, const cmc_params &p,
-                        bool to_stage, hipStream_t st) {
-  return s.m_f32 ? run<float>(s, w, p, to_stage, st) : run<double>(s, w, p, to_stage, st);
+  return dispatch(t, [&](const auto &l) {
+    using L = std::decay_t<decltype(l)>;
+    if (m_f32)
+      return to_stage ? run2<L, float, true>(l, p, st) : run2<L, float, false>(l, p, st);
+    return to_stage ? run2<L, double, true>(l, p, st) : run2<L, double, false>(l, p, st);
+  });
 }
 
 }  // namespace cmc

@@ -8,6 +8,8 @@
 // HBM-bound: reads r and m, writes the
 // orbit table ((r, Phi) and (M, S) per star plus the sampled search levels)
 // and, for the standalone call, the state's phi, mcum, ssuf.
+#include <type_traits>
+
 #include "cmc_internal.hpp"
 
 namespace cmc {
@@ -50,15 +52,15 @@ __device__ __forceinline__ double m_over_r(double m, double r) {
   return MIXED ? static_cast<double>(static_cast<float>(m) / static_cast<float>(r)) : m / r;
 }
 
-template <typename MT, bool MIXED>
-__global__ __launch_bounds__(PT) void k_pot_tile_sums(const double *__restrict__ r,
-                                                      const MT *__restrict__ m,
-                                                      const cmc_scalars *__restrict__ sc,
-                                                      double *__restrict__ tsum,
-                                                      int64_t tiles) {
+template <class Ctx, typename MT, bool MIXED>
+__global__ __launch_bounds__(PT) void k_pot_tile_sums(Ctx ctx) {
   __shared__ double sh[PT / 64];
-  const int64_t n = sc->n;
-  const int64_t t = blockIdx.x;
+  const ClusterArgs &A = ctx.args();
+  const double *__restrict__ r = A.s.r;
+  const MT *__restrict__ m = static_cast<const MT *>(A.s.m);
+  const int64_t n = A.s.sc->n;
+  const int64_t tiles = A.w.pot_tiles;
+  const int64_t t = ctx.block();
   const int64_t base = t * kPotTile + static_cast<int64_t>(threadIdx.x) * PJ;
   Acc<MIXED> sm, sq;
 #pragma unroll
@@ -73,17 +75,21 @@ __global__ __launch_bounds__(PT) void k_pot_tile_sums(const double *__restrict__
   const double tm = block_sum<PT>(sm.value(), sh);
   const double tq = block_sum<PT>(sq.value(), sh);
   if (threadIdx.x == 0) {
-    tsum[t] = tm;
-    tsum[tiles + t] = tq;
+    A.w.pot_tsum[t] = tm;
+    A.w.pot_tsum[tiles + t] = tq;
   }
 }
 
 constexpr int ST = 1024;
 
-__global__ __launch_bounds__(ST) void k_pot_tile_scan(const double *__restrict__ tsum,
-                                                      double *__restrict__ carry,
-                                                      int64_t tiles) {
+// One block per cluster.
+template <class Ctx>
+__global__ __launch_bounds__(ST) void k_pot_tile_scan(Ctx ctx) {
   __shared__ double sh[ST / 64];
+  const ClusterArgs &A = ctx.args();
+  const double *__restrict__ tsum = A.w.pot_tsum;
+  double *__restrict__ carry = A.w.pot_carry;
+  const int64_t tiles = A.w.pot_tiles;
   const int64_t per = (tiles + ST - 1) / ST;
   const int64_t b = static_cast<int64_t>(threadIdx.x) * per;
   const int64_t e = b + per < tiles ? b + per : tiles;
@@ -106,18 +112,17 @@ __global__ __launch_bounds__(ST) void k_pot_tile_scan(const double *__restrict__
   }
 }
 
-template <typename MT, bool PUBLIC, bool MIXED>
-__global__ __launch_bounds__(PT) void k_pot_apply(const double *__restrict__ r,
-                                                  const MT *__restrict__ m,
-                                                  const cmc_scalars *__restrict__ sc,
-                                                  const double *__restrict__ carry,
-                                                  int64_t tiles, double *__restrict__ phi,
-                                                  double *__restrict__ mcum,
-                                                  double *__restrict__ ssuf, Levels lv,
-                                                  MS *__restrict__ ms) {
+template <class Ctx, typename MT, bool PUBLIC, bool MIXED>
+__global__ __launch_bounds__(PT) void k_pot_apply(Ctx ctx) {
   __shared__ double sh[PT / 64];
-  const int64_t n = sc->n;
-  const int64_t t = blockIdx.x;
+  const ClusterArgs &A = ctx.args();
+  const double *__restrict__ r = A.s.r;
+  const MT *__restrict__ m = static_cast<const MT *>(A.s.m);
+  const double *__restrict__ carry = A.w.pot_carry;
+  const int64_t n = A.s.sc->n;
+  const int64_t tiles = A.w.pot_tiles;
+  const Levels lv = levels_of(A.w);
+  const int64_t t = ctx.block();
   const int64_t base = t * kPotTile + static_cast<int64_t>(threadIdx.x) * PJ;
   double rr[PJ], pm[PJ], sq[PJ];
   Acc<MIXED> am;
@@ -152,44 +157,41 @@ __global__ __launch_bounds__(PT) void k_pot_apply(const double *__restrict__ r,
       const double S = cq + sq[j];
       const double ph = -(M / rr[j] + S);
       if (PUBLIC) {
-        mcum[k] = M;
-        ssuf[k] = S;
-        phi[k] = ph;
+        A.s.mcum[k] = M;
+        A.s.ssuf[k] = S;
+        A.s.phi[k] = ph;
       }
-      put_table(lv, ms, k, rr[j], ph, M, S);
+      put_table(lv, A.w.ms, k, rr[j], ph, M, S);
     }
   }
 }
 
-template <typename MT, bool MIXED>
-hipError_t run(const cmc_state &s, const Workspace &w, bool pub, hipStream_t st) {
-  const MT *m = static_cast<const MT *>(s.m);
-  const int64_t tiles = w.pot_tiles;
-  const dim3 grid(static_cast<unsigned>(tiles));
-  k_pot_tile_sums<MT, MIXED><<<grid, PT, 0, st>>>(s.r, m, s.sc, w.pot_tsum, tiles);
-  k_pot_tile_scan<<<1, ST, 0, st>>>(w.pot_tsum, w.pot_carry, tiles);
-  const Levels lv = levels_of(w);
+template <class L, typename MT, bool MIXED>
+hipError_t run(const L &l, bool pub, hipStream_t st) {
+  k_pot_tile_sums<decltype(l.ctx(kShPotTile)), MT, MIXED>
+      <<<l.grid(kShPotTile), PT, 0, st>>>(l.ctx(kShPotTile));
+  k_pot_tile_scan<<<l.grid(kShOne), ST, 0, st>>>(l.ctx(kShOne));
   if (pub)
-    k_pot_apply<MT, true, MIXED><<<grid, PT, 0, st>>>(s.r, m, s.sc, w.pot_carry, tiles, s.phi,
-                                                       s.mcum, s.ssuf, lv, w.ms);
+    k_pot_apply<decltype(l.ctx(kShPotTile)), MT, true, MIXED>
+        <<<l.grid(kShPotTile), PT, 0, st>>>(l.ctx(kShPotTile));
   else
-    k_pot_apply<MT, false, MIXED><<<grid, PT, 0, st>>>(s.r, m, s.sc, w.pot_carry, tiles, s.phi,
-                                                        s.mcum, s.ssuf, lv, w.ms);
+    k_pot_apply<decltype(l.ctx(kShPotTile)), MT, false, MIXED>
+        <<<l.grid(kShPotTile), PT, 0, st>>>(l.ctx(kShPotTile));
   return hipGetLastError();
-}
-
-template <typename MT>
-hipError_t run_p(const cmc_state &s, const Workspace &w, int precision, bool pub,
-                 hipStream_t st) {
-  return precision == CMC_MIXED ? run<MT, true>(s, w, pub, st) : run<MT, false>(s, w, pub, st);
 }
 
 }  // namespace
 
-hipError_t launch_potential(const cmc_state &s, const Workspace &w, int precision,
-                            bool public_arrays, hipStream_t st) {
-  return s.m_f32 ? run_p<float>(s, w, precision, public_arrays, st)
-                 : run_p<double>(s, w, precision, public_arrays, st);
+hipError_t launch_potential(const Target &t, bool m_f32, int precision, bool public_arrays,
+                            hipStream_t st) {
+  return dispatch(t, [&](const auto &l) {
+    const bool mx = precision == CMC_MIXED;
+    if (m_f32)
+      return mx ? run<std::decay_t<decltype(l)>, float, true>(l, public_arrays, st)
+                : run<std::decay_t<decltype(l)>, float, false>(l, public_arrays, st);
+    return mx ? run<std::decay_t<decltype(l)>, double, true>(l, public_arrays, st)
+              : run<std::decay_t<decltype(l)>, double, false>(l, public_arrays, st);
+  });
 }
 
 }  // namespace cmc

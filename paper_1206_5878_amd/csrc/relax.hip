@@ -7,6 +7,8 @@
 // evaluation and a one-block update.  One thread per pair otherwise.  The
 // mixed form computes the pair terms and the kick in FP32 and keeps the
 // centre-of-mass velocity, the sums and the Newton solve in FP64.
+#include <type_traits>
+
 #include "cmc_internal.hpp"
 
 namespace cmc {
@@ -108,20 +110,24 @@ __device__ __forceinline__ double beta_of(double tp, double dt) {
 // dt_state slots
 enum { kX = 0, kLo, kHi, kDone, kIt, kCnt, kZero, kInfN, kLogSum };
 
-template <typename MT, bool MIXED>
-__global__ __launch_bounds__(NT) void k_pair_tp(const double *__restrict__ r,
-                                                const MT *__restrict__ m,
-                                                const double *__restrict__ vr,
-                                                const double *__restrict__ vt,
-                                                const uint32_t *__restrict__ id,
-                                                const cmc_scalars *__restrict__ sc,
-                                                double *__restrict__ tp_out,
-                                                double *__restrict__ part, uint64_t seed,
-                                                uint32_t step, double gamma) {
+template <class Ctx, typename MT, bool MIXED>
+__global__ __launch_bounds__(NT) void k_pair_tp(Ctx ctx, uint32_t step_arg) {
   __shared__ double sh[NT / 64];
-  const int64_t n = sc->n;
+  const ClusterArgs &A = ctx.args();
+  const uint32_t step = step_of(A, step_arg);
+  const double *__restrict__ r = A.s.r;
+  const MT *__restrict__ m = static_cast<const MT *>(A.s.m);
+  const double *__restrict__ vr = A.s.vr;
+  const double *__restrict__ vt = A.s.vt;
+  const uint32_t *__restrict__ id = A.s.id;
+  double *__restrict__ tp_out = A.w.pair_tp;
+  double *__restrict__ part = A.w.pair_part;
+  const uint64_t seed = A.seed;
+  const double gamma = A.gamma;
+  const int64_t n = A.s.sc->n;
   const int64_t np = n / 2;
-  const int64_t p = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  const int64_t blk = ctx.block();
+  const int64_t p = blk * NT + threadIdx.x;
   double cnt = 0.0, nz = 0.0, ni = 0.0, ls = 0.0;
   if (p < np) {
     const PairGeo g =
@@ -144,20 +150,25 @@ __global__ __launch_bounds__(NT) void k_pair_tp(const double *__restrict__ r,
   ni = block_sum<NT>(ni, sh);
   ls = block_sum<NT>(ls, sh);
   if (threadIdx.x == 0) {
-    part[4 * blockIdx.x + 0] = cnt;
-    part[4 * blockIdx.x + 1] = nz;
-    part[4 * blockIdx.x + 2] = ni;
-    part[4 * blockIdx.x + 3] = ls;
+    part[4 * blk + 0] = cnt;
+    part[4 * blk + 1] = nz;
+    part[4 * blk + 2] = ni;
+    part[4 * blk + 3] = ls;
   }
 }
 
 constexpr int IT = 1024;
 
 // Reduce the pair counts, detect the degenerate cases, pick the start point.
-__global__ __launch_bounds__(IT) void k_dt_init(const double *__restrict__ part,
-                                                int64_t nblocks, double *__restrict__ st,
-                                                cmc_scalars *__restrict__ sc, double target) {
+// One block per cluster.
+template <class Ctx>
+__global__ __launch_bounds__(IT) void k_dt_init(Ctx ctx, double target) {
   __shared__ double sh[IT / 64];
+  const ClusterArgs &A = ctx.args();
+  const double *__restrict__ part = A.w.pair_part;
+  const int64_t nblocks = A.w.pair_blocks;
+  double *__restrict__ st = A.w.dt_state;
+  cmc_scalars *__restrict__ sc = A.s.sc;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t b = threadIdx.x; b < nblocks; b += IT)
     for (int q = 0; q < 4; ++q) v[q] += part[4 * b + q];
@@ -194,18 +205,19 @@ __global__ __launch_bounds__(IT) void k_dt_init(const double *__restrict__ part,
 
 // One Newton evaluation: block partials of sum sin^2(beta/2) and of
 // d/dx sin^2(beta/2) = (1/4) beta sin(beta) (beta < pi) at dt = exp(x).
-template <bool MIXED>
-__global__ __launch_bounds__(NT) void k_dt_eval(const double *__restrict__ tp,
-                                                const cmc_scalars *__restrict__ sc,
-                                                const double *__restrict__ st,
-                                                double *__restrict__ part) {
+template <class Ctx, bool MIXED>
+__global__ __launch_bounds__(NT) void k_dt_eval(Ctx ctx) {
   __shared__ double sh[NT / 64];
+  const ClusterArgs &A = ctx.args();
+  const double *__restrict__ tp = A.w.pair_tp;
+  const double *__restrict__ st = A.w.dt_state;
+  double *__restrict__ part = A.w.red_part;
   if (st[kDone] != 0.0) return;
-  const int64_t np = sc->n / 2;
+  const int64_t np = A.s.sc->n / 2;
   const double dt = exp(st[kX]);
+  const int64_t blk = ctx.block();
   double h = 0.0, d = 0.0;
-  for (int64_t p = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; p < np;
-       p += static_cast<int64_t>(gridDim.x) * NT) {
+  for (int64_t p = blk * NT + threadIdx.x; p < np; p += ctx.nblocks() * NT) {
     const double t = tp[p];
     if (t >= 0.0) {
       const double b = beta_of(t, dt);
@@ -226,22 +238,28 @@ __global__ __launch_bounds__(NT) void k_dt_eval(const double *__restrict__ tp,
   h = block_sum<NT>(h, sh);
   d = block_sum<NT>(d, sh);
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x + 0] = h;
-    part[2 * blockIdx.x + 1] = d;
+    part[2 * blk + 0] = h;
+    part[2 * blk + 1] = d;
   }
 }
 
 // Sum the partials in block order and take one safeguarded Newton step on
 // G(x) = ln F(x) - ln target (dG/dx = F'/F), keeping a bracket [lo, hi] of the
 // root; converged when the step falls below 1e-14 relative.
-__global__ __launch_bounds__(NT) void k_dt_update(const double *__restrict__ part,
-                                                  int nblocks, double *__restrict__ st,
-                                                  cmc_scalars *__restrict__ sc, double target,
-                                                  double xtol, int32_t last_iter) {
+// One block per cluster; the partials are those of the cluster's k_dt_eval
+// blocks.
+template <class Ctx>
+__global__ __launch_bounds__(NT) void k_dt_update(Ctx ctx, double target, double xtol,
+                                                  int32_t last_iter) {
   __shared__ double sh[NT / 64];
+  const ClusterArgs &A = ctx.args();
+  const double *__restrict__ part = A.w.red_part;
+  const int64_t nblocks = A.w.pair_blocks < kRedBlocks ? A.w.pair_blocks : kRedBlocks;
+  double *__restrict__ st = A.w.dt_state;
+  cmc_scalars *__restrict__ sc = A.s.sc;
   if (st[kDone] != 0.0) return;
   double H = 0.0, D = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += NT) {
+  for (int64_t b = threadIdx.x; b < nblocks; b += NT) {
     H += part[2 * b];
     D += part[2 * b + 1];
   }
@@ -288,19 +306,22 @@ __global__ __launch_bounds__(NT) void k_dt_update(const double *__restrict__ par
 }
 
 // ---------------------------------------------------------------- kicks
-template <typename MT, bool MIXED>
-__global__ __launch_bounds__(NT) void k_relax(const double *__restrict__ r,
-                                              const MT *__restrict__ m,
-                                              double *__restrict__ vr,
-                                              double *__restrict__ vt,
-                                              const uint32_t *__restrict__ id,
-                                              const cmc_scalars *__restrict__ sc,
-                                              uint64_t seed, uint32_t step, double gamma) {
-  const int64_t n = sc->n;
+template <class Ctx, typename MT, bool MIXED>
+__global__ __launch_bounds__(NT) void k_relax(Ctx ctx, uint32_t step_arg) {
+  const ClusterArgs &A = ctx.args();
+  const uint32_t step = step_of(A, step_arg);
+  const double *__restrict__ r = A.s.r;
+  const MT *__restrict__ m = static_cast<const MT *>(A.s.m);
+  double *__restrict__ vr = A.s.vr;
+  double *__restrict__ vt = A.s.vt;
+  const uint32_t *__restrict__ id = A.s.id;
+  const uint64_t seed = A.seed;
+  const double gamma = A.gamma;
+  const int64_t n = A.s.sc->n;
   const int64_t np = n / 2;
-  const int64_t p = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  const int64_t p = ctx.block() * NT + threadIdx.x;
   if (p >= np) return;
-  const double dt = sc->dt;
+  const double dt = A.s.sc->dt;
   const PairGeo g =
       pair_geometry<MT, MIXED>(p, n, r, m, vr, vt, id, seed, step, coulomb_log(gamma, n));
   const double beta = beta_of(g.tp, dt);
@@ -391,60 +412,51 @@ __global__ __launch_bounds__(NT) void k_relax(const double *__restrict__ r,
   vt[b] = hypot(n2y, n2z);
 }
 
-template <typename MT, bool MIXED>
-hipError_t run_timestep(const cmc_state &s, const Workspace &w, const cmc_params &p,
-                        hipStream_t st) {
-  const MT *m = static_cast<const MT *>(s.m);
-  const unsigned pb = static_cast<unsigned>(w.pair_blocks);
+template <class L, typename MT, bool MIXED>
+hipError_t run_timestep(const L &l, const cmc_params &p, hipStream_t st) {
   // Newton stops once its step in ln dt is below what the terms resolve:
   // FP64 terms to ~1e-16, FP32 terms (mixed) to ~1e-7 each
   const double kXTol = MIXED ? 1e-7 : 1e-14;
-  k_pair_tp<MT, MIXED><<<pb, NT, 0, st>>>(s.r, m, s.vr, s.vt, s.id, s.sc, w.pair_tp,
-                                          w.pair_part, p.seed, p.step, p.gamma);
-  k_dt_init<<<1, IT, 0, st>>>(w.pair_part, w.pair_blocks, w.dt_state, s.sc, p.target);
+  k_pair_tp<decltype(l.ctx(kShPair)), MT, MIXED><<<l.grid(kShPair), NT, 0, st>>>(
+      l.ctx(kShPair), p.step);
+  k_dt_init<<<l.grid(kShOne), IT, 0, st>>>(l.ctx(kShOne), p.target);
   const int iters = p.dt_iters > 0 ? p.dt_iters : 10;
-  const int eb = static_cast<int>(w.pair_blocks < kRedBlocks ? w.pair_blocks : kRedBlocks);
   for (int i = 0; i < iters; ++i) {
-    k_dt_eval<MIXED><<<eb, NT, 0, st>>>(w.pair_tp, s.sc, w.dt_state, w.red_part);
-    k_dt_update<<<1, NT, 0, st>>>(w.red_part, eb, w.dt_state, s.sc, p.target, kXTol,
-                                  i == iters - 1 ? 1 : 0);
+    k_dt_eval<decltype(l.ctx(kShDtEval)), MIXED><<<l.grid(kShDtEval), NT, 0, st>>>(
+        l.ctx(kShDtEval));
+    k_dt_update<<<l.grid(kShOne), NT, 0, st>>>(l.ctx(kShOne), p.target, kXTol,
+                                               i == iters - 1 ? 1 : 0);
   }
   return hipGetLastError();
 }
 
-template <typename MT, bool MIXED>
-hipError_t run_relax(const cmc_state &s, const Workspace &w, const cmc_params &p,
-                     hipStream_t st) {
-  const MT *m = static_cast<const MT *>(s.m);
-  k_relax<MT, MIXED><<<static_cast<unsigned>(w.pair_blocks), NT, 0, st>>>(
-      s.r, m, s.vr, s.vt, s.id, s.sc, p.seed, p.step, p.gamma);
+template <class L, typename MT, bool MIXED>
+hipError_t run_relax(const L &l, const cmc_params &p, hipStream_t st) {
+  k_relax<decltype(l.ctx(kShPair)), MT, MIXED><<<l.grid(kShPair), NT, 0, st>>>(
+      l.ctx(kShPair), p.step);
   return hipGetLastError();
-}
-
-template <typename MT>
-hipError_t timestep_p(const cmc_state &s, const Workspace &w, const cmc_params &p,
-                      hipStream_t st) {
-  return p.precision == CMC_MIXED ? run_timestep<MT, true>(s, w, p, st)
-                                  : run_timestep<MT, false>(s, w, p, st);
-}
-
-template <typename MT>
-hipError_t relax_p(const cmc_state &s, const Workspace &w, const cmc_params &p,
-                   hipStream_t st) {
-  return p.precision == CMC_MIXED ? run_relax<MT, true>(s, w, p, st)
-                                  : run_relax<MT, false>(s, w, p, st);
 }
 
 }  // namespace
 
-hipError_t launch_timestep(const cmc_state &s, const Workspace &w, const cmc_params &p,
-                           hipStream_t st) {
-  return s.m_f32 ? timestep_p<float>(s, w, p, st) : timestep_p<double>(s, w, p, st);
+hipError_t launch_timestep(const Target &t, bool m_f32, const cmc_params &p, hipStream_t st) {
+  return dispatch(t, [&](const auto &l) {
+    using L = std::decay_t<decltype(l)>;
+    const bool mx = p.precision == CMC_MIXED;
+    if (m_f32)
+      return mx ? run_timestep<L, float, true>(l, p, st) : run_timestep<L, float, false>(l, p, st);
+    return mx ? run_timestep<L, double, true>(l, p, st) : run_timestep<L, double, false>(l, p, st);
+  });
 }
 
-hipError_t launch_relax(const cmc_state &s, const Workspace &w, const cmc_params &p,
-                        hipStream_t st) {
-  return s.m_f32 ? relax_p<float>(s, w, p, st) : relax_p<double>(s, w, p, st);
+hipError_t launch_relax(const Target &t, bool m_f32, const cmc_params &p, hipStream_t st) {
+  return dispatch(t, [&](const auto &l) {
+    using L = std::decay_t<decltype(l)>;
+    const bool mx = p.precision == CMC_MIXED;
+    if (m_f32)
+      return mx ? run_relax<L, float, true>(l, p, st) : run_relax<L, float, false>(l, p, st);
+    return mx ? run_relax<L, double, true>(l, p, st) : run_relax<L, double, false>(l, p, st);
+  });
 }
 
 }  // namespace cmc

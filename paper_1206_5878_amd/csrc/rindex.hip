@@ -16,9 +16,14 @@ namespace {
 
 constexpr int NT = kBlock;
 
-__global__ void k_rindex_prep(const double *__restrict__ r, const cmc_scalars *__restrict__ sc,
-                              int lg_nb, RIndexCtl *__restrict__ ctl) {
-  const int64_t n = sc->n;
+// One thread per cluster.
+template <class Ctx>
+__global__ void k_rindex_prep(Ctx ctx) {
+  const ClusterArgs &A = ctx.args();
+  const double *__restrict__ r = A.s.r;
+  const int lg_nb = A.w.rx_lg_nb;
+  RIndexCtl *__restrict__ ctl = A.w.rx_ctl;
+  const int64_t n = A.s.sc->n;
   RIndexCtl c{0ull, 0ull, 0u, static_cast<uint32_t>(n > 0 ? n : 0)};
   if (n > 0) {
     c.lo = rbits(r[0]);
@@ -39,19 +44,25 @@ __device__ __forceinline__ int64_t bucket(double x, const RIndexCtl &c) {
 }
 
 constexpr int kScanTile = NT * 16;
+static_assert(kScanTile == kRxTile, "prefix-maximum tile");
 
-__global__ __launch_bounds__(NT) void k_rindex_clear(uint32_t *__restrict__ start, int64_t len) {
-  for (int64_t b = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; b < len;
-       b += static_cast<int64_t>(gridDim.x) * NT)
+template <class Ctx>
+__global__ __launch_bounds__(NT) void k_rindex_clear(Ctx ctx) {
+  const ClusterArgs &A = ctx.args();
+  uint32_t *__restrict__ start = A.w.rx_start;
+  const int64_t len = A.w.rx_nb + 1;
+  for (int64_t b = ctx.block() * NT + threadIdx.x; b < len; b += ctx.nblocks() * NT)
     start[b] = 0u;
 }
 
-__global__ __launch_bounds__(NT) void k_rindex_ends(const double *__restrict__ r,
-                                                    const RIndexCtl *__restrict__ ctl,
-                                                    uint32_t *__restrict__ start) {
-  const RIndexCtl c = *ctl;
+template <class Ctx>
+__global__ __launch_bounds__(NT) void k_rindex_ends(Ctx ctx) {
+  const ClusterArgs &A = ctx.args();
+  const double *__restrict__ r = A.s.r;
+  uint32_t *__restrict__ start = A.w.rx_start;
+  const RIndexCtl c = *A.w.rx_ctl;
   const int64_t n = c.n;
-  const int64_t k = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  const int64_t k = ctx.block() * NT + threadIdx.x;
   if (k >= n) return;
   const int64_t bk = bucket(r[k], c);
   if (k == n - 1 || bucket(r[k + 1], c) != bk) start[bk + 1] = static_cast<uint32_t>(k + 1);
@@ -83,10 +94,15 @@ __device__ __forceinline__ uint32_t block_excl_max(uint32_t v, uint32_t *sh) {
   return base > exc ? base : exc;
 }
 
-__global__ __launch_bounds__(NT) void k_rindex_tilemax(const uint32_t *__restrict__ start,
-                                                       int64_t len, uint32_t *__restrict__ tmax) {
+template <class Ctx>
+__global__ __launch_bounds__(NT) void k_rindex_tilemax(Ctx ctx) {
   __shared__ uint32_t sh[NT / 64];
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile;
+  const ClusterArgs &A = ctx.args();
+  const uint32_t *__restrict__ start = A.w.rx_start;
+  const int64_t len = A.w.rx_nb + 1;
+  uint32_t *__restrict__ tmax = A.w.rx_tile;
+  const int64_t blk = ctx.block();
+  const int64_t base = blk * kScanTile;
   uint32_t v = 0u;
   for (int j = 0; j < 16; ++j) {
     const int64_t b = base + j * NT + threadIdx.x;
@@ -98,14 +114,18 @@ __global__ __launch_bounds__(NT) void k_rindex_tilemax(const uint32_t *__restric
   if (threadIdx.x == 0) {
     uint32_t m = 0u;
     for (int i = 0; i < NT / 64; ++i) m = sh[i] > m ? sh[i] : m;
-    tmax[blockIdx.x] = m;
+    tmax[blk] = m;
   }
 }
 
-// One block: exclusive prefix maximum over the tile maxima, in place.
-__global__ __launch_bounds__(NT) void k_rindex_tilescan(uint32_t *__restrict__ tmax,
-                                                        int64_t tiles) {
+// One block per cluster: exclusive prefix maximum over the tile maxima, in
+// place.
+template <class Ctx>
+__global__ __launch_bounds__(NT) void k_rindex_tilescan(Ctx ctx) {
   __shared__ uint32_t sh[NT / 64];
+  const ClusterArgs &A = ctx.args();
+  uint32_t *__restrict__ tmax = A.w.rx_tile;
+  const int64_t tiles = cdiv(A.w.rx_nb + 1, kScanTile);
   __shared__ uint32_t blk;
   uint32_t carry = 0u;
   for (int64_t t0 = 0; t0 < tiles; t0 += NT) {
@@ -120,10 +140,15 @@ __global__ __launch_bounds__(NT) void k_rindex_tilescan(uint32_t *__restrict__ t
   }
 }
 
-__global__ __launch_bounds__(NT) void k_rindex_apply(uint32_t *__restrict__ start, int64_t len,
-                                                     const uint32_t *__restrict__ tcarry) {
+template <class Ctx>
+__global__ __launch_bounds__(NT) void k_rindex_apply(Ctx ctx) {
   __shared__ uint32_t sh[NT / 64];
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x * 16;
+  const ClusterArgs &A = ctx.args();
+  uint32_t *__restrict__ start = A.w.rx_start;
+  const int64_t len = A.w.rx_nb + 1;
+  const uint32_t *__restrict__ tcarry = A.w.rx_tile;
+  const int64_t blk = ctx.block();
+  const int64_t base = blk * kScanTile + threadIdx.x * 16;
   uint32_t v[16];
   uint32_t run = 0u;
 #pragma unroll
@@ -133,7 +158,7 @@ __global__ __launch_bounds__(NT) void k_rindex_apply(uint32_t *__restrict__ star
     v[j] = run;
   }
   uint32_t ex = block_excl_max(run, sh);
-  const uint32_t c = tcarry[blockIdx.x];
+  const uint32_t c = tcarry[blk];
   ex = c > ex ? c : ex;
 #pragma unroll
   for (int j = 0; j < 16; ++j)
@@ -142,17 +167,16 @@ __global__ __launch_bounds__(NT) void k_rindex_apply(uint32_t *__restrict__ star
 
 }  // namespace
 
-hipError_t launch_rindex(const cmc_state &s, const Workspace &w, hipStream_t st) {
-  const int64_t len = w.rx_nb + 1;
-  const int64_t tiles = cdiv(len, kScanTile);
-  k_rindex_prep<<<1, 1, 0, st>>>(s.r, s.sc, w.rx_lg_nb, w.rx_ctl);
-  k_rindex_clear<<<static_cast<unsigned>(std::min<int64_t>(cdiv(len, NT), 4096)), NT, 0, st>>>(
-      w.rx_start, len);
-  k_rindex_ends<<<static_cast<unsigned>(w.star_blocks), NT, 0, st>>>(s.r, w.rx_ctl, w.rx_start);
-  k_rindex_tilemax<<<static_cast<unsigned>(tiles), NT, 0, st>>>(w.rx_start, len, w.rx_tile);
-  k_rindex_tilescan<<<1, NT, 0, st>>>(w.rx_tile, tiles);
-  k_rindex_apply<<<static_cast<unsigned>(tiles), NT, 0, st>>>(w.rx_start, len, w.rx_tile);
-  return hipGetLastError();
+hipError_t launch_rindex(const Target &t, hipStream_t st) {
+  return dispatch(t, [&](const auto &l) {
+    k_rindex_prep<<<l.grid(kShOne), 1, 0, st>>>(l.ctx(kShOne));
+    k_rindex_clear<<<l.grid(kShRxClear), NT, 0, st>>>(l.ctx(kShRxClear));
+    k_rindex_ends<<<l.grid(kShStar), NT, 0, st>>>(l.ctx(kShStar));
+    k_rindex_tilemax<<<l.grid(kShRxTile), NT, 0, st>>>(l.ctx(kShRxTile));
+    k_rindex_tilescan<<<l.grid(kShOne), NT, 0, st>>>(l.ctx(kShOne));
+    k_rindex_apply<<<l.grid(kShRxTile), NT, 0, st>>>(l.ctx(kShRxTile));
+    return hipGetLastError();
+  });
 }
 
 }  // namespace cmc

@@ -29,45 +29,50 @@ __device__ __forceinline__ uint64_t radius_key(double x) {
   return __builtin_bit_cast(uint64_t, x + 0.0);
 }
 
-__global__ void k_sort_prep(const cmc_scalars *__restrict__ sc, uint64_t *__restrict__ pi) {
-  pi[kNTotal] = static_cast<uint64_t>(sc->n);
+// One thread per cluster.
+template <class Ctx>
+__global__ void k_sort_prep(Ctx ctx) {
+  const ClusterArgs &A = ctx.args();
+  uint64_t *__restrict__ pi = reinterpret_cast<uint64_t *>(A.w.pass_info);
+  pi[kNTotal] = static_cast<uint64_t>(A.s.sc->n);
   pi[kMinKey] = ~0ull;
   pi[kMaxKey] = 0ull;
   pi[kNonFin] = 0ull;
 }
 
-__global__ __launch_bounds__(NT) void k_stage_from_state(
-    const double *__restrict__ r_new, const double *__restrict__ vr,
-    const double *__restrict__ vt, const void *__restrict__ m, int32_t m_f32,
-    const uint32_t *__restrict__ id, const cmc_scalars *__restrict__ sc,
-    StageRec *__restrict__ stage, uint64_t *__restrict__ keys) {
-  const int64_t n = sc->n;
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+template <class Ctx>
+__global__ __launch_bounds__(NT) void k_stage_from_state(Ctx ctx) {
+  const ClusterArgs &A = ctx.args();
+  const int64_t n = A.s.sc->n;
+  const int64_t i = ctx.block() * NT + threadIdx.x;
   if (i >= n) return;
   StageRec rec;
-  rec.r = r_new[i];
-  rec.vr = vr[i];
-  rec.vt = vt[i];
-  rec.m = m_f32 ? static_cast<double>(static_cast<const float *>(m)[i])
-                : static_cast<const double *>(m)[i];
-  rec.id = id[i];
+  rec.r = A.s.r_new[i];
+  rec.vr = A.s.vr[i];
+  rec.vt = A.s.vt[i];
+  rec.m = A.s.m_f32 ? static_cast<double>(static_cast<const float *>(A.s.m)[i])
+                    : static_cast<const double *>(A.s.m)[i];
+  rec.id = A.s.id[i];
   rec.pad = 0u;
-  stage[i] = rec;
-  keys[i] = radius_key(rec.r);
+  A.w.stage[i] = rec;
+  A.w.keys[0][i] = radius_key(rec.r);
 }
 
 // Per-block min and max of the finite keys and count of non-finite ones;
 // k_plan combines the blocks' partials (no contended atomics).
-__global__ __launch_bounds__(NT) void k_key_range(const uint64_t *__restrict__ keys,
-                                                  const uint64_t *__restrict__ pi,
-                                                  uint64_t *__restrict__ part) {
+template <class Ctx>
+__global__ __launch_bounds__(NT) void k_key_range(Ctx ctx) {
   __shared__ uint64_t smin[NT / 64], smax[NT / 64];
   __shared__ uint32_t snf[NT / 64];
+  const ClusterArgs &A = ctx.args();
+  const uint64_t *__restrict__ keys = A.w.keys[0];
+  const uint64_t *__restrict__ pi = reinterpret_cast<const uint64_t *>(A.w.pass_info);
+  uint64_t *__restrict__ part = reinterpret_cast<uint64_t *>(A.w.red_part);
   const int64_t n = static_cast<int64_t>(pi[kNTotal]);
+  const int64_t blk = ctx.block();
   uint64_t lo = ~0ull, hi = 0ull;
   uint32_t nf = 0;
-  for (int64_t k = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; k < n;
-       k += static_cast<int64_t>(gridDim.x) * NT) {
+  for (int64_t k = blk * NT + threadIdx.x; k < n; k += ctx.nblocks() * NT) {
     const uint64_t x = keys[k];
     if (x < kInfKey) {
       lo = x < lo ? x : lo;
@@ -96,18 +101,23 @@ __global__ __launch_bounds__(NT) void k_key_range(const uint64_t *__restrict__ k
       hi = smax[q] > hi ? smax[q] : hi;
       nf += snf[q];
     }
-    part[3 * blockIdx.x] = lo;
-    part[3 * blockIdx.x + 1] = hi;
-    part[3 * blockIdx.x + 2] = nf;
+    part[3 * blk] = lo;
+    part[3 * blk + 1] = hi;
+    part[3 * blk + 2] = nf;
   }
 }
 
-__global__ __launch_bounds__(NT) void k_plan(const uint64_t *__restrict__ part, int nparts,
-                                             uint64_t *__restrict__ pi,
-                                             cmc_scalars *__restrict__ sc) {
+// One block per cluster.
+template <class Ctx>
+__global__ __launch_bounds__(NT) void k_plan(Ctx ctx) {
   __shared__ uint64_t smin[NT / 64], smax[NT / 64], snf[NT / 64];
+  const ClusterArgs &A = ctx.args();
+  const uint64_t *__restrict__ part = reinterpret_cast<const uint64_t *>(A.w.red_part);
+  const int64_t nparts = blocks_of(kShKeyRange, A.w, A.s.cap);
+  uint64_t *__restrict__ pi = reinterpret_cast<uint64_t *>(A.w.pass_info);
+  cmc_scalars *__restrict__ sc = A.s.sc;
   uint64_t lo = ~0ull, hi = 0ull, nfin = 0ull;
-  for (int b = threadIdx.x; b < nparts; b += NT) {
+  for (int64_t b = threadIdx.x; b < nparts; b += NT) {
     lo = part[3 * b] < lo ? part[3 * b] : lo;
     hi = part[3 * b + 1] > hi ? part[3 * b + 1] : hi;
     nfin += part[3 * b + 2];
@@ -156,11 +166,16 @@ __device__ __forceinline__ uint64_t pass_key(const uint64_t *__restrict__ in, in
   return x < kInfKey ? x - kmin : esc;
 }
 
-__global__ __launch_bounds__(NT) void k_upsweep(const uint64_t *keys0, const uint64_t *keys1,
-                                                const uint64_t *__restrict__ pi, int pass,
-                                                uint32_t *__restrict__ tile_hist,
-                                                int64_t tiles) {
+template <class Ctx>
+__global__ __launch_bounds__(NT) void k_upsweep(Ctx ctx, int pass) {
   __shared__ uint32_t hist[256];
+  const ClusterArgs &A = ctx.args();
+  const uint64_t *keys0 = A.w.keys[0];
+  const uint64_t *keys1 = A.w.keys[1];
+  const uint64_t *__restrict__ pi = reinterpret_cast<const uint64_t *>(A.w.pass_info);
+  uint32_t *__restrict__ tile_hist = A.w.tile_hist;
+  const int64_t tiles = A.w.sort_tiles;
+  const int64_t blk = ctx.block();
   if (static_cast<uint64_t>(pass) >= pi[kPasses]) return;
   const int64_t n = static_cast<int64_t>(pi[kNTotal]);
   const uint64_t *in = (pass & 1) ? keys1 : keys0;
@@ -168,7 +183,7 @@ __global__ __launch_bounds__(NT) void k_upsweep(const uint64_t *keys0, const uin
   const int shift = 8 * pass;
   hist[threadIdx.x] = 0u;
   __syncthreads();
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kSortTile;
+  const int64_t base = blk * kSortTile;
   for (int j = 0; j < SLOTS; ++j) {
     const int64_t k = base + j * NT + threadIdx.x;
     if (k < n) {
@@ -177,18 +192,21 @@ __global__ __launch_bounds__(NT) void k_upsweep(const uint64_t *keys0, const uin
     }
   }
   __syncthreads();
-  tile_hist[static_cast<int64_t>(threadIdx.x) * tiles + blockIdx.x] = hist[threadIdx.x];
+  tile_hist[static_cast<int64_t>(threadIdx.x) * tiles + blk] = hist[threadIdx.x];
 }
 
 // Block d: exclusive scan of digit d's counts over tiles; total in digit_tot[d].
-__global__ __launch_bounds__(NT) void k_scan_digits(const uint32_t *__restrict__ tile_hist,
-                                                    const uint64_t *__restrict__ pi, int pass,
-                                                    uint32_t *__restrict__ tile_off,
-                                                    uint32_t *__restrict__ digit_tot,
-                                                    int64_t tiles) {
+template <class Ctx>
+__global__ __launch_bounds__(NT) void k_scan_digits(Ctx ctx, int pass) {
   __shared__ uint32_t sh[NT / 64];
+  const ClusterArgs &A = ctx.args();
+  const uint32_t *__restrict__ tile_hist = A.w.tile_hist;
+  const uint64_t *__restrict__ pi = reinterpret_cast<const uint64_t *>(A.w.pass_info);
+  uint32_t *__restrict__ tile_off = A.w.tile_off;
+  uint32_t *__restrict__ digit_tot = A.w.hist_all;
+  const int64_t tiles = A.w.sort_tiles;
   if (static_cast<uint64_t>(pass) >= pi[kPasses]) return;
-  const int64_t d = blockIdx.x;
+  const int64_t d = ctx.block();
   const uint32_t *h = tile_hist + d * tiles;
   uint32_t *o = tile_off + d * tiles;
   uint32_t carry = 0u;
@@ -207,30 +225,33 @@ __global__ __launch_bounds__(NT) void k_scan_digits(const uint32_t *__restrict__
 // so they carry no restrict qualifier.  Keys are ranked in registers, placed
 // in digit order in LDS, then written out in LDS order, so consecutive
 // lanes write consecutive addresses of one digit's run.
-__global__ __launch_bounds__(DT) void k_downsweep(
-    const uint64_t *keys0, const uint64_t *keys1, const uint32_t *vals0, const uint32_t *vals1,
-    uint64_t *okeys0, uint64_t *okeys1, uint32_t *ovals0, uint32_t *ovals1,
-    const uint64_t *__restrict__ pi, int pass,
-    const uint32_t *__restrict__ tile_off, const uint32_t *__restrict__ digit_tot,
-    int64_t tiles) {
+template <class Ctx>
+__global__ __launch_bounds__(DT) void k_downsweep(Ctx ctx, int pass) {
   __shared__ uint32_t cnt[DT / 64][256];
   __shared__ uint32_t gdelta[256];
   __shared__ uint32_t sh[DT / 64];
   __shared__ uint64_t lkey[kSortTile];
   __shared__ uint32_t lval[kSortTile];
+  const ClusterArgs &A = ctx.args();
+  const uint64_t *__restrict__ pi = reinterpret_cast<const uint64_t *>(A.w.pass_info);
+  const uint32_t *__restrict__ tile_off = A.w.tile_off;
+  const uint32_t *__restrict__ digit_tot = A.w.hist_all;
+  const int64_t tiles = A.w.sort_tiles;
   const uint64_t passes = pi[kPasses];
   if (static_cast<uint64_t>(pass) >= passes) return;
   const int64_t n = static_cast<int64_t>(pi[kNTotal]);
-  const uint64_t *in = (pass & 1) ? keys1 : keys0;
-  const uint32_t *vin = (pass & 1) ? vals1 : vals0;
-  uint64_t *out = (pass & 1) ? okeys0 : okeys1;
-  uint32_t *vout = (pass & 1) ? ovals0 : ovals1;
+  // the in and out buffers of a pass are the two halves of one ping-pong pair
+  const uint64_t *in = A.w.keys[pass & 1];
+  const uint32_t *vin = A.w.vals[pass & 1];
+  uint64_t *out = A.w.keys[(pass & 1) ^ 1];
+  uint32_t *vout = A.w.vals[(pass & 1) ^ 1];
   const bool first = pass == 0, last = static_cast<uint64_t>(pass) + 1 == passes;
   const uint64_t kmin = pi[kMinKey], esc = pi[kEscKey];
   const int shift = 8 * pass;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int64_t tile0 = static_cast<int64_t>(blockIdx.x) * kSortTile;
+  const int64_t blk = ctx.block();
+  const int64_t tile0 = blk * kSortTile;
   const int64_t rem = n - tile0;
   const int valid = rem < kSortTile ? static_cast<int>(rem) : kSortTile;
 
@@ -282,7 +303,7 @@ __global__ __launch_bounds__(DT) void k_downsweep(
     const uint32_t dbase =
         block_excl_scan<DT>(own ? digit_tot[d] : 0u, sh, static_cast<uint32_t *>(nullptr));
     if (own) {
-      gdelta[d] = dbase + tile_off[static_cast<int64_t>(d) * tiles + blockIdx.x] - lstart;
+      gdelta[d] = dbase + tile_off[static_cast<int64_t>(d) * tiles + blk] - lstart;
       uint32_t acc = lstart;
       for (int q = 0; q < DT / 64; ++q) {
         const uint32_t c = cnt[q][d];
@@ -313,17 +334,22 @@ __global__ __launch_bounds__(DT) void k_downsweep(
   }
 }
 
-__global__ __launch_bounds__(NT) void k_gather(const StageRec *__restrict__ stage,
-                                               const uint32_t *__restrict__ vals0,
-                                               const uint32_t *__restrict__ vals1,
-                                               const uint64_t *__restrict__ pi,
-                                               const cmc_scalars *__restrict__ sc,
-                                               int normalise, double *__restrict__ r,
-                                               double *__restrict__ vr,
-                                               double *__restrict__ vt, void *__restrict__ m,
-                                               int32_t m_f32, uint32_t *__restrict__ id) {
+template <class Ctx>
+__global__ __launch_bounds__(NT) void k_gather(Ctx ctx, int normalise) {
+  const ClusterArgs &A = ctx.args();
+  const StageRec *__restrict__ stage = A.w.stage;
+  const uint32_t *__restrict__ vals0 = A.w.vals[0];
+  const uint32_t *__restrict__ vals1 = A.w.vals[1];
+  const uint64_t *__restrict__ pi = reinterpret_cast<const uint64_t *>(A.w.pass_info);
+  const cmc_scalars *__restrict__ sc = A.s.sc;
+  double *__restrict__ r = A.s.r;
+  double *__restrict__ vr = A.s.vr;
+  double *__restrict__ vt = A.s.vt;
+  void *__restrict__ m = A.s.m;
+  const int32_t m_f32 = A.s.m_f32;
+  uint32_t *__restrict__ id = A.s.id;
   const int64_t kept = static_cast<int64_t>(pi[kNKept]);
-  const int64_t p = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  const int64_t p = ctx.block() * NT + threadIdx.x;
   if (p >= kept) return;
   const uint32_t *vals = (pi[kPasses] & 1ull) ? vals1 : vals0;
   const uint32_t src = pi[kPasses] ? vals[p] : static_cast<uint32_t>(p);
@@ -339,36 +365,42 @@ __global__ __launch_bounds__(NT) void k_gather(const StageRec *__restrict__ stag
   id[p] = rec.id;
 }
 
+// One thread per cluster: the device step counter moves on.
+template <class Ctx>
+__global__ void k_step_advance(Ctx ctx) {
+  ctx.args().s.sc->step += 1;
+}
+
 }  // namespace
 
-hipError_t launch_stage_from_state(const cmc_state &s, const Workspace &w, hipStream_t st) {
-  k_stage_from_state<<<static_cast<unsigned>(w.star_blocks), NT, 0, st>>>(
-      s.r_new, s.vr, s.vt, s.m, s.m_f32, s.id, s.sc, w.stage, w.keys[0]);
-  return hipGetLastError();
+hipError_t launch_step_advance(const Target &t, hipStream_t st) {
+  return dispatch(t, [&](const auto &l) {
+    k_step_advance<<<l.grid(kShOne), 1, 0, st>>>(l.ctx(kShOne));
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_stage_from_state(const Target &t, bool, hipStream_t st) {
+  return dispatch(t, [&](const auto &l) {
+    k_stage_from_state<<<l.grid(kShStar), NT, 0, st>>>(l.ctx(kShStar));
+    return hipGetLastError();
+  });
 }
 
 // Sort the staged records by keys[0] (n = sc->n on entry) into the state.
-hipError_t launch_sort_stage(const cmc_state &s, const Workspace &w, bool normalise_mass,
-                             hipStream_t st) {
-  uint64_t *pi = reinterpret_cast<uint64_t *>(w.pass_info);
-  const unsigned tiles = static_cast<unsigned>(w.sort_tiles);
-  const unsigned kr_blocks = std::min<unsigned>(tiles, 1024u);
-  uint64_t *kr_part = reinterpret_cast<uint64_t *>(w.red_part);
-  k_sort_prep<<<1, 1, 0, st>>>(s.sc, pi);
-  k_key_range<<<kr_blocks, NT, 0, st>>>(w.keys[0], pi, kr_part);
-  k_plan<<<1, NT, 0, st>>>(kr_part, static_cast<int>(kr_blocks), pi, s.sc);
-  for (int pass = 0; pass < 8; ++pass) {
-    k_upsweep<<<tiles, NT, 0, st>>>(w.keys[0], w.keys[1], pi, pass, w.tile_hist, w.sort_tiles);
-    k_scan_digits<<<256, NT, 0, st>>>(w.tile_hist, pi, pass, w.tile_off, w.hist_all,
-                                      w.sort_tiles);
-    k_downsweep<<<tiles, DT, 0, st>>>(w.keys[0], w.keys[1], w.vals[0], w.vals[1], w.keys[0],
-                                      w.keys[1], w.vals[0], w.vals[1], pi, pass, w.tile_off,
-                                      w.hist_all, w.sort_tiles);
-  }
-  k_gather<<<static_cast<unsigned>(w.star_blocks), NT, 0, st>>>(
-      w.stage, w.vals[0], w.vals[1], pi, s.sc, normalise_mass ? 1 : 0, s.r, s.vr, s.vt, s.m,
-      s.m_f32, s.id);
-  return hipGetLastError();
+hipError_t launch_sort_stage(const Target &t, bool, bool normalise_mass, hipStream_t st) {
+  return dispatch(t, [&](const auto &l) {
+    k_sort_prep<<<l.grid(kShOne), 1, 0, st>>>(l.ctx(kShOne));
+    k_key_range<<<l.grid(kShKeyRange), NT, 0, st>>>(l.ctx(kShKeyRange));
+    k_plan<<<l.grid(kShOne), NT, 0, st>>>(l.ctx(kShOne));
+    for (int pass = 0; pass < 8; ++pass) {
+      k_upsweep<<<l.grid(kShSortTile), NT, 0, st>>>(l.ctx(kShSortTile), pass);
+      k_scan_digits<<<l.grid(kShDigit), NT, 0, st>>>(l.ctx(kShDigit), pass);
+      k_downsweep<<<l.grid(kShSortTile), DT, 0, st>>>(l.ctx(kShSortTile), pass);
+    }
+    k_gather<<<l.grid(kShStar), NT, 0, st>>>(l.ctx(kShStar), normalise_mass ? 1 : 0);
+    return hipGetLastError();
+  });
 }
 
 }  // namespace cmc

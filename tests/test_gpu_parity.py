@@ -231,6 +231,21 @@ def test_orbit_plummer(cmc, ora, n, seed):
     assert (s["status"] & ~cmc.ST_ESCAPER & ~cmc.ST_BOUND) == 0
 
 
+def test_orbit_many_tiles_per_block(cmc, ora):
+    """More stars than the bracket kernel's resident blocks cover at once, so
+    every block loops over several tiles: the escaper tallies must add up."""
+    n = 700_000
+    st = ora.plummer(n, 6)
+    st.vr[::997] = 2.5  # escapers spread over all tiles
+    h, s, (rn, vrn, vtn, so, d), tab = _orbit_case(cmc, ora, st, seed=2, step=3)
+    fin = np.isfinite(rn)
+    assert np.array_equal(np.isfinite(h["r_new"]), fin)
+    assert rel(h["r_new"][fin], rn[fin]) < TOL
+    assert s["n_esc"] == so["n_esc"] and so["n_esc"] > 600
+    assert rel(s["e_esc"], so["e_esc"]) < 1e-10
+    assert s["trials"] == so["trials"]
+
+
 @pytest.mark.parametrize("E,J", [(-0.5, 0.9), (-0.5, 0.0), (-0.2, 0.3)])
 def test_orbit_kepler(cmc, ora, E, J):
     st = ora.State(*inputs.kepler_probes(30_000, E, J, 3))
