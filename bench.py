@@ -31,6 +31,10 @@ WORKLOADS = {
                                     seed=1, precision="mixed"),
     "plummer_n1e5_equal_mass": dict(n=100_000, mass_spectrum=0, m_f32=False, gamma=0.11,
                                     seed=1, precision="fp64"),
+    # 64 independent clusters, N log-uniform in [1e4, 1e6], even clusters
+    # Plummer and odd ones King W0 = 6, advanced together by one captured graph
+    "ensemble_64_plummer_king_w6": dict(clusters=64, seed=1, gamma=0.11, w0=6.0, m_f32=False,
+                                        precision="mixed"),
 }
 DEFAULT_WORKLOAD = "plummer_n1e7_broken_power_law"
 
@@ -120,6 +124,8 @@ def main() -> int:
     wl = WORKLOADS[args.workload]
     precision = args.precision or wl["precision"]
     K = args.steps
+    if "clusters" in wl:
+        return ensemble_bench(P, args, wl, precision)
     if args.plain:
         prec = P.CMC_FP64 if precision == "fp64" else P.CMC_MIXED
         cl, params = setup(P, wl, prec, args.warmup)
@@ -187,6 +193,95 @@ def main() -> int:
     if not args.no_cpu_baseline:
         print("# timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def ensemble_specs(P, wl) -> list:
+    """Cluster c: N = floor(10^(4 + 2u)) with u the uniform of Philox word
+    pair (w1:w0) at key = seed, counter (c, 0, 0x40, 0); seed c + 1; Plummer
+    for even c, King W0 for odd c."""
+    import numpy as np
+    k = wl["clusters"]
+    ctr = np.zeros((k, 4), np.uint32)
+    ctr[:, 0] = np.arange(k)
+    ctr[:, 2] = 0x40
+    w = P.cmc_philox(wl["seed"], ctr).astype(np.uint64)
+    x = ((w[:, 1] << np.uint64(32)) | w[:, 0]) >> np.uint64(12)
+    u = (2.0 * x.astype(np.float64) + 1.0) * 2.0 ** -53
+    n = np.floor(10.0 ** (4.0 + 2.0 * u)).astype(np.int64)
+    return [dict(n=int(n[c]), seed=c + 1, gamma=wl["gamma"], model=c % 2, w0=wl["w0"])
+            for c in range(k)]
+
+
+def ensemble_bench(P, args, wl, precision) -> int:
+    """The ensemble advanced by one captured graph per step (device step
+    counter), against the same clusters stepped one by one with the
+    single-cluster call."""
+    import numpy as np
+    import torch
+    prec = P.CMC_FP64 if precision == "fp64" else P.CMC_MIXED
+    specs = ensemble_specs(P, wl)
+    ens = P.Ensemble(specs, m_f32=wl["m_f32"])
+    ens.init()
+    params = P.Params(precision=prec)
+    g = ens.capture(params)
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    n0 = sum(cl.n for cl in ens.clusters)
+    K = args.steps
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(K):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    gpu_ms = e0.elapsed_time(e1) / K
+    n1 = sum(cl.n for cl in ens.clusters)
+    updates = K * 0.5 * (n0 + n1)  # escapers leave a few stars per step
+    stats = [cl.scalars() for cl in ens.clusters]
+    # the same clusters, one single-cluster call each per step
+    ens.init()
+    for k in range(args.warmup):
+        for cl, sp in zip(ens.clusters, specs):
+            P.cmc_step(cl, P.Params(seed=sp["seed"], gamma=sp["gamma"], step=k, precision=prec))
+    torch.cuda.synchronize()
+    m0 = sum(cl.n for cl in ens.clusters)
+    t1 = time.perf_counter()
+    for k in range(K):
+        for cl, sp in zip(ens.clusters, specs):
+            P.cmc_step(cl, P.Params(seed=sp["seed"], gamma=sp["gamma"], step=args.warmup + k,
+                                    precision=prec))
+    torch.cuda.synchronize()
+    el_loop = time.perf_counter() - t1
+    m1 = sum(cl.n for cl in ens.clusters)
+    loop_updates = K * 0.5 * (m0 + m1)
+    out = {
+        "metric": METRIC,
+        "value": updates / el,
+        "unit": "star-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": el / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "clusters": wl["clusters"], "stars": n0,
+                   "n_min": min(s["n"] for s in specs), "n_max": max(s["n"] for s in specs),
+                   "precision": precision, "w0": wl["w0"], "gamma": wl["gamma"],
+                   "seed": wl["seed"], "graph": True},
+        "gpu_ms_per_step": gpu_ms,
+        "per_cluster_calls": {"value": loop_updates / el_loop, "ms_per_step": el_loop / K * 1e3},
+        "final": {"n": n1, "status_or": int(np.bitwise_or.reduce([s["status"] for s in stats])),
+                  "dt_min": min(s["dt"] for s in stats), "dt_max": max(s["dt"] for s in stats)},
+    }
     print(json.dumps(out), flush=True)
     return 0
 
