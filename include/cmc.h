@@ -191,7 +191,12 @@ int cmc_orbit(cmc_state *s, const cmc_params *p, void *stream);
 
 /* One whole step: potential -> timestep -> relax -> orbit -> sort.  The
  * potential table is kept in the workspace; phi, mcum, ssuf of the state are
- * not written (call cmc_potential for them). */
+ * not written (call cmc_potential for them).  The sort's result is that of
+ * cmc_sort; for cap <= CMC_BUCKET_CAP_MAX it starts from where the orbit
+ * pass found each new radius among the old ones (a counting sort on that
+ * position, then each run of equal position sorted by radius), above it it is
+ * cmc_sort's radix sort. */
+#define CMC_BUCKET_CAP_MAX (16383LL * 2048 - 1)
 int cmc_step(cmc_state *s, const cmc_params *p, void *stream);
 
 /* cmc_step that also records events[0] on `stream` before the step and
@@ -240,7 +245,9 @@ typedef struct cmc_batch {
   size_t dev_bytes;
   int64_t total[CMC_SHAPES];    /* blocks per launch shape over all clusters     */
   int32_t top_entries;          /* LDS entries of the orbit table's top levels   */
-  int32_t reserved[3];
+  int32_t bucket_sort;          /* 1: the step sorts by buckets (every capacity  */
+                                /*    <= CMC_BUCKET_CAP_MAX), 0: radix sort      */
+  int32_t reserved[2];
 } cmc_batch;
 
 /* Device bytes of the ensemble tables for these states (0 if invalid). */

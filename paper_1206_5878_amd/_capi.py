@@ -16,6 +16,7 @@ CMC_OK, CMC_EINVAL, CMC_EWORKSPACE, CMC_EHIP, CMC_ERANGE = 0, -1, -2, -3, -4
 CMC_FP64, CMC_MIXED = 0, 1
 CMC_MODEL_PLUMMER, CMC_MODEL_KING = 0, 1
 CMC_STEP_DEVICE = 0xFFFFFFFF
+CMC_BUCKET_CAP_MAX = 16383 * 2048 - 1
 ST_NONFINITE, ST_TRIAL_CAP, ST_BOUND, ST_ESCAPER = 0x01, 0x02, 0x04, 0x08
 ST_DT_DEGEN, ST_NUMERIC, ST_DT_NOCONV = 0x10, 0x20, 0x40
 
@@ -57,7 +58,8 @@ class cmc_cluster_spec(C.Structure):
 class cmc_batch(C.Structure):
     _fields_ = [("clusters", C.c_int32), ("m_f32", C.c_int32), ("dev", C.c_void_p),
                 ("dev_bytes", C.c_size_t), ("total", C.c_int64 * CMC_SHAPES),
-                ("top_entries", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("top_entries", C.c_int32), ("bucket_sort", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 assert C.sizeof(cmc_scalars) == 128

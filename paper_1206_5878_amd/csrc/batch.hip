@@ -104,6 +104,7 @@ BatchDev batch_dev(const cmc_batch &b) {
   d.top_entries = b.top_entries;
   d.any_f32 = b.m_f32;
   d.any_f64 = !b.m_f32;
+  d.bucket_sort = b.bucket_sort;
   return d;
 }
 
@@ -140,7 +141,7 @@ int cmc_batch_prepare(cmc_batch *b, const cmc_state *states, const cmc_cluster_s
   if (rc) return rc;
   const cmc::BatchLayout L = cmc::batch_layout(clusters, total);
   if (dev_bytes < L.bytes) return CMC_EWORKSPACE;
-  int32_t top = 0;
+  int32_t top = 0, bucket = 1;
   for (int c = 0; c < clusters; ++c) {
     const cmc_cluster_spec &sp = specs[c];
     if (sp.n < 0) return CMC_EINVAL;
@@ -158,6 +159,7 @@ int cmc_batch_prepare(cmc_batch *b, const cmc_state *states, const cmc_cluster_s
     a.n_init = sp.n;
     a.bracket_blocks = blocks[cmc::kShBracket][c];
     top = std::max(top, a.top.entries);
+    if (a.w.bkt_bins == 0) bucket = 0;
   }
   // tables: arguments, first block of each cluster per shape, block maps
   std::vector<char> host(L.bytes, 0);
@@ -181,7 +183,8 @@ int cmc_batch_prepare(cmc_batch *b, const cmc_state *states, const cmc_cluster_s
   b->dev_bytes = dev_bytes;
   for (int sh = 0; sh < CMC_SHAPES; ++sh) b->total[sh] = sh < cmc::kShapes ? total[sh] : 0;
   b->top_entries = top;
-  b->reserved[0] = b->reserved[1] = b->reserved[2] = 0;
+  b->bucket_sort = bucket;
+  b->reserved[0] = b->reserved[1] = 0;
   return CMC_OK;
 }
 

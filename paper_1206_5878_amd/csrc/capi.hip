@@ -38,7 +38,10 @@ hipError_t launch_step(const Target &t, bool m_f32, const cmc_params &p, void *c
   if (e == hipSuccess) e = mark(3);
   if (e == hipSuccess) e = launch_orbit(t, m_f32, p, true, st);
   if (e == hipSuccess) e = mark(4);
-  if (e == hipSuccess) e = launch_sort_stage(t, m_f32, false, st);
+  if (e == hipSuccess) {
+    e = bucket_sort_of(t) ? launch_bucket_sort(t, m_f32, st)
+                          : launch_sort_stage(t, m_f32, false, true, st);
+  }
   if (e == hipSuccess && p.step == CMC_STEP_DEVICE) e = launch_step_advance(t, st);
   if (e == hipSuccess) e = mark(5);
   return e;
@@ -142,7 +145,8 @@ int cmc_sort(cmc_state *s, void *stream) {
   const Single one = single(*s, 0, 1.0);
   hipError_t e = cmc::launch_stage_from_state(one.t(), s->m_f32 != 0, as_stream(stream));
   if (e != hipSuccess) return CMC_EHIP;
-  return status_of(cmc::launch_sort_stage(one.t(), s->m_f32 != 0, false, as_stream(stream)));
+  return status_of(
+      cmc::launch_sort_stage(one.t(), s->m_f32 != 0, false, false, as_stream(stream)));
 }
 
 int cmc_potential(cmc_state *s, int32_t precision, void *stream) {

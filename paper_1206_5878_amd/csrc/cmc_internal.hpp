@@ -159,10 +159,30 @@ __device__ __forceinline__ void set_status(cmc_scalars *sc, uint32_t bits) {
 }
 
 // ---------------------------------------------------------------- staging
-// One star as it leaves the orbit pass and enters the sort's final gather.
-struct alignas(8) StageRec {
+// One star as it leaves the orbit pass (or the initial model) and waits for
+// the sort.  The step's records carry the mass in the state's precision:
+// with f32 masses a record is 32 bytes, one aligned quarter of a cache line,
+// so the sort's random reads of records fetch one line each.  The initial
+// model and cmc_sort stage f64 masses (WideRec).
+template <typename MT>
+struct StageRec;
+template <>
+struct alignas(32) StageRec<float> {
+  double r, vr, vt;
+  float m;
+  uint32_t id;
+};
+template <>
+struct alignas(8) StageRec<double> {
   double r, vr, vt, m;
   uint32_t id, pad;
+};
+using WideRec = StageRec<double>;
+// An entry of the step's bucket sort: radius key, and the star's group of old
+// intervals above its staged index (see bucket.hip).
+struct alignas(16) BktEnt {
+  uint64_t key;
+  uint32_t side, pad;
 };
 
 // ---------------------------------------------------------------- orbit table
@@ -241,6 +261,17 @@ constexpr int kPotTile = 2048;   // stars per potential tile (256 x 8)
 constexpr int kBlock = 256;
 constexpr int kRedBlocks = 2048;  // grid of the grid-stride reduction kernels
 constexpr int kKingNodes = 4096;  // nodes of a King profile: (r, W, M) each
+// The step's sort (bucket.hip): bucket b holds the stars whose count of old
+// radii <= r_new lies in [b * kBucketSpan, (b + 1) * kBucketSpan).
+constexpr int kBucketShift = 11;
+constexpr int64_t kBucketSpan = int64_t(1) << kBucketShift;  // old intervals per bucket
+constexpr int kBucketBins = 16384;  // LDS bins of a tile: buckets of kept stars + escapers
+constexpr int64_t kBucketCapMax = (kBucketBins - 1) * kBucketSpan - 1;  // largest capacity served
+static_assert(kBucketCapMax == CMC_BUCKET_CAP_MAX, "the documented bucket-sort limit");
+constexpr int kBucketTile = 16384;      // stars per histogram and scatter tile
+constexpr int kBucketGroupBits = 10;    // at most 1024 groups of intervals per bucket
+constexpr int kBucketSortCap = 4096;    // stars a bucket sorts in LDS
+constexpr uint32_t kBucketEsc = 0xFFFFFFFFu;  // bkey of a star that leaves the cluster
 constexpr int kKingTab = 3 * kKingNodes + 8;
 
 struct Workspace {
@@ -248,7 +279,7 @@ struct Workspace {
   int nlev;
   MS *ms;                   // [cap]
   OrbitRec *orec;           // [cap]
-  StageRec *stage;          // [cap]
+  void *stage;              // [cap] StageRec<MT> of the step, or WideRec
   uint64_t *keys[2];        // [cap]
   uint32_t *vals[2];        // [cap]
   uint32_t *tile_hist;      // [256 * sort_tiles]
@@ -265,6 +296,15 @@ struct Workspace {
   uint32_t *rx_tile;        // [cdiv(rx_nb + 1, 4096)] prefix-maximum tiles
   RIndexCtl *rx_ctl;        // [1]
   double *king;             // [kKingTab] King model profile (initial model only)
+  uint32_t *bkey;           // [cap] old radii <= each staged radius, or kBucketEsc
+  BktEnt *bent;             // [cap] entries grouped by bucket (shares orec's memory)
+  uint32_t *bkt_cnt;        // [bkt_tiles * bkt_bins] per-tile counts, then tile offsets
+  uint32_t *bkt_tot;        // [bkt_bins] stars per bucket
+  uint32_t *bkt_start;      // [bkt_bins + 1] first position of each bucket
+  int64_t *bkt_info;        // [2]: staged stars, kept stars
+  int64_t bkt_bins, bkt_tiles;  // bkt_bins = 0: capacity above kBucketCapMax
+  int32_t bkt_ibits;        // bits of a staged index in BktEnt::side
+  int32_t bkt_gshift;       // interval-in-bucket >> gshift = the entry's group
   int64_t rx_nb;
   int rx_lg_nb;
   int64_t sort_tiles, pot_tiles, pair_blocks, star_blocks;
@@ -300,7 +340,8 @@ inline Workspace layout(int64_t cap, void *base) {
   }
   w.ms = reinterpret_cast<MS *>(take(sizeof(MS) * c));
   w.orec = reinterpret_cast<OrbitRec *>(take(sizeof(OrbitRec) * c));
-  w.stage = reinterpret_cast<StageRec *>(take(sizeof(StageRec) * c));
+  w.stage = take(sizeof(WideRec) * c);
+  static_assert(sizeof(WideRec) >= sizeof(StageRec<float>), "stage holds either record");
   w.keys[0] = reinterpret_cast<uint64_t *>(take(8 * c));
   w.keys[1] = reinterpret_cast<uint64_t *>(take(8 * c));
   w.vals[0] = reinterpret_cast<uint32_t *>(take(4 * c));
@@ -322,6 +363,21 @@ inline Workspace layout(int64_t cap, void *base) {
   w.rx_tile = reinterpret_cast<uint32_t *>(take(4 * cdiv(w.rx_nb + 1, 4096)));
   w.rx_ctl = reinterpret_cast<RIndexCtl *>(take(sizeof(RIndexCtl)));
   w.king = reinterpret_cast<double *>(take(8 * kKingTab));
+  w.bkey = reinterpret_cast<uint32_t *>(take(4 * c));
+  w.bent = reinterpret_cast<BktEnt *>(w.orec);  // orec is dead once the orbit pass ends
+  static_assert(sizeof(BktEnt) <= sizeof(OrbitRec), "bent fits in orec");
+  if (c <= kBucketCapMax) {
+    w.bkt_bins = (c >> kBucketShift) + 2;
+    w.bkt_tiles = cdiv(c, kBucketTile);
+    w.bkt_ibits = 0;
+    while ((int64_t(1) << w.bkt_ibits) < c) ++w.bkt_ibits;
+    const int gbits = 32 - w.bkt_ibits < kBucketGroupBits ? 32 - w.bkt_ibits : kBucketGroupBits;
+    w.bkt_gshift = kBucketShift - gbits;
+    w.bkt_cnt = reinterpret_cast<uint32_t *>(take(4 * w.bkt_tiles * w.bkt_bins));
+    w.bkt_tot = reinterpret_cast<uint32_t *>(take(4 * w.bkt_bins));
+    w.bkt_start = reinterpret_cast<uint32_t *>(take(4 * (w.bkt_bins + 1)));
+    w.bkt_info = reinterpret_cast<int64_t *>(take(8 * 2));
+  }
   w.bytes = (off + 255) & ~size_t(255);
   return w;
 }
@@ -410,6 +466,9 @@ enum Shape : int {
   kShRxClear,   // grid-stride clear of the bucket index
   kShRxTile,    // prefix-maximum tiles of the bucket index
   kShDiag,      // grid-stride diagnostics partials
+  kShBktTile,   // histogram and scatter tiles of the step's sort
+  kShBktGroup,  // groups of 64 buckets
+  kShBktSort,   // one block per bucket of kept stars
   kShapes
 };
 constexpr int kBracketThreads = 512;
@@ -438,6 +497,9 @@ __host__ __device__ inline int64_t blocks_of(Shape sh, const Workspace &w, int64
     }
     case kShRxTile: return cdiv(w.rx_nb + 1, kRxTile);
     case kShDiag: return w.star_blocks < kRedBlocks ? w.star_blocks : kRedBlocks;
+    case kShBktTile: return w.bkt_bins ? w.bkt_tiles : 1;
+    case kShBktGroup: return w.bkt_bins ? cdiv(w.bkt_bins, 64) : 1;
+    case kShBktSort: return w.bkt_bins ? w.bkt_bins - 1 : 1;
     default: return 1;
   }
 }
@@ -452,6 +514,7 @@ struct BatchDev {
   int64_t total[kShapes];               // blocks per shape over all clusters
   int32_t top_entries;                  // largest OrbitTop::entries
   int32_t any_f32, any_f64;             // mass storage kinds present
+  int32_t bucket_sort;                  // every cluster's capacity <= kBucketCapMax
 };
 struct Target {
   const ClusterArgs *one;               // host struct, or null
@@ -489,7 +552,9 @@ hipError_t launch_orbit(const Target &t, bool m_f32, const cmc_params &p, bool t
 hipError_t launch_table_pack(const Target &t, hipStream_t st);
 hipError_t launch_rindex(const Target &t, hipStream_t st);
 hipError_t launch_stage_from_state(const Target &t, bool m_f32, hipStream_t st);
-hipError_t launch_sort_stage(const Target &t, bool m_f32, bool normalise_mass,
+// Radix sort of the staged records by keys[0]: the step's records
+// (StageRec<mass type>) or WideRec.
+hipError_t launch_sort_stage(const Target &t, bool m_f32, bool normalise_mass, bool step_records,
                              hipStream_t st);
 hipError_t launch_init(const Target &t, bool m_f32, hipStream_t st);
 hipError_t launch_diagnostics(const Target &t, bool m_f32, double *out, hipStream_t st);
@@ -498,6 +563,13 @@ hipError_t launch_philox(uint64_t key, const uint32_t *ctr, uint32_t *out, int64
 hipError_t launch_step(const Target &t, bool m_f32, const cmc_params &p, void *const *events,
                        hipStream_t st);
 hipError_t launch_step_advance(const Target &t, hipStream_t st);
+// The step's sort of the orbit pass's staged records (stage, bkey) into the
+// state; capacities above kBucketCapMax take the radix sort instead.
+hipError_t launch_bucket_sort(const Target &t, bool m_f32, hipStream_t st);
+// Whether the target's step sorts by buckets.
+inline bool bucket_sort_of(const Target &t) {
+  return t.many ? t.many->bucket_sort != 0 : t.one->w.bkt_bins > 0;
+}
 
 // Run F<One or Many launch> on the target.
 template <class F>

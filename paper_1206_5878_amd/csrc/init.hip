@@ -144,7 +144,7 @@ __global__ __launch_bounds__(NT) void k_init(Ctx ctx) {
   const uint64_t seed = A.seed;
   const int king = A.model == CMC_MODEL_KING;
   const int mass_spectrum = A.mass_spectrum;
-  StageRec *__restrict__ stage = A.w.stage;
+  WideRec *__restrict__ stage = static_cast<WideRec *>(A.w.stage);
   uint64_t *__restrict__ keys = A.w.keys[0];
   const int64_t blk = ctx.block();
   const int64_t i = blk * NT + threadIdx.x;
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(NT) void k_init(Ctx ctx) {
     }
     const double c = 2.0 * x6 - 1.0;
     const double sn = sqrt((1.0 - c) * (1.0 + c));
-    StageRec rec;
+    WideRec rec;
     rec.r = rr;
     rec.vr = vv * c;
     rec.vt = vv * sn;
@@ -273,7 +273,7 @@ hipError_t launch_init(const Target &t, bool m_f32, hipStream_t st) {
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;
-  return launch_sort_stage(t, m_f32, true, st);
+  return launch_sort_stage(t, m_f32, true, false, st);
 }
 
 }  // namespace cmc

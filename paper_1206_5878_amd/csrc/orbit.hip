@@ -213,22 +213,27 @@ __device__ __forceinline__ int32_t top_descend(const RPhi *top, const OrbitTop &
   return static_cast<int32_t>(s);
 }
 
-// Star outputs: staged record + sort key, or the state arrays in place.
-template <bool TO_STAGE>
-__device__ __forceinline__ void emit(int64_t i, double rn, double vrn, double vtn, double mi,
-                                     uint32_t sid, double *__restrict__ r_new,
+// Star outputs: the staged record, its radix key and c = the number of old
+// radii <= rn, or the state arrays in place.  c is monotone in rn, so the
+// step's sort groups stars by c before it compares radii; escapers and
+// non-finite radii are marked kBucketEsc and dropped.
+template <bool TO_STAGE, typename MT>
+__device__ __forceinline__ void emit(int64_t i, double rn, double vrn, double vtn, MT mi,
+                                     uint32_t sid, int64_t c, double *__restrict__ r_new,
                                      double *__restrict__ vr, double *__restrict__ vt,
-                                     StageRec *__restrict__ stage, uint64_t *__restrict__ keys) {
+                                     StageRec<MT> *__restrict__ stage,
+                                     uint64_t *__restrict__ keys, uint32_t *__restrict__ bkey) {
   if (TO_STAGE) {
-    StageRec rec;
+    StageRec<MT> rec{};
     rec.r = rn;
     rec.vr = vrn;
     rec.vt = vtn;
     rec.m = mi;
     rec.id = sid;
-    rec.pad = 0u;
     stage[i] = rec;
-    keys[i] = __builtin_bit_cast(uint64_t, rn + 0.0);
+    const uint64_t key = rbits(rn);
+    keys[i] = key;
+    bkey[i] = key < 0x7FF0000000000000ull ? static_cast<uint32_t>(c) : kBucketEsc;
   } else {
     r_new[i] = rn;
     vr[i] = vrn;
@@ -274,8 +279,9 @@ void k_orbit_bracket(Ctx ctx, uint32_t step_arg, double bound_factor) {
   double *__restrict__ vt = A.s.vt;
   const uint32_t *__restrict__ id = A.s.id;
   double *__restrict__ r_new = A.s.r_new;
-  StageRec *__restrict__ stage = A.w.stage;
+  StageRec<MT> *__restrict__ stage = static_cast<StageRec<MT> *>(A.w.stage);
   uint64_t *__restrict__ keys = A.w.keys[0];
+  uint32_t *__restrict__ bkey = A.w.bkey;
   OrbitRec *__restrict__ orec = A.w.orec;
   cmc_scalars *__restrict__ sc = A.s.sc;
   double *__restrict__ part = A.w.red_part;
@@ -323,7 +329,7 @@ void k_orbit_bracket(Ctx ctx, uint32_t step_arg, double bound_factor) {
         e_esc += load_mass(m, i) * E;
         fl |= CMC_ST_ESCAPER;
         if (E != E) fl |= CMC_ST_NONFINITE;
-        emit<TO_STAGE>(i, kInf, vri, vti, load_mass(m, i), id[i], r_new, vr, vt, stage, keys);
+        emit<TO_STAGE>(i, kInf, vri, vti, m[i], id[i], 0, r_new, vr, vt, stage, keys, bkey);
       } else {
         const int64_t kmin = kmin_g, kmax = kmax_g;
         double rmin, rmax;
@@ -380,7 +386,8 @@ void k_orbit_bracket(Ctx ctx, uint32_t step_arg, double bound_factor) {
                             (J2 == 0.0 ? 0.0 : J2 / (rn * rn));
           double vrn, vtn;
           finish(rn, qn, J, J2, id[i], step, seed, vrn, vtn, fl);
-          emit<TO_STAGE>(i, rn, vrn, vtn, load_mass(m, i), id[i], r_new, vr, vt, stage, keys);
+          emit<TO_STAGE>(i, rn, vrn, vtn, m[i], id[i], rindex_last_le(ix, ictl, rn) + 1, r_new,
+                         vr, vt, stage, keys, bkey);
         }
       }
       orec[i] = rec;
@@ -409,8 +416,9 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap) {
   double *__restrict__ vt = A.s.vt;
   const uint32_t *__restrict__ id = A.s.id;
   double *__restrict__ r_new = A.s.r_new;
-  StageRec *__restrict__ stage = A.w.stage;
+  StageRec<MT> *__restrict__ stage = static_cast<StageRec<MT> *>(A.w.stage);
   uint64_t *__restrict__ keys = A.w.keys[0];
+  uint32_t *__restrict__ bkey = A.w.bkey;
   const OrbitRec *__restrict__ orec = A.w.orec;
   cmc_scalars *__restrict__ sc = A.s.sc;
   double *__restrict__ part = A.w.red_part + 2 * A.w.star_blocks;
@@ -493,8 +501,9 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap) {
       ++j;
       ++c_tr;
     }
+    int64_t kg = 0;
     if (busy) {
-      const int64_t kg = rindex_last_le(ix, ictl, r0);
+      kg = rindex_last_le(ix, ictl, r0);
       const int64_t k0 = kg < kmin ? kmin : (kg > kmax ? kmax : kg);
       const double q0 = 2.0 * E - 2.0 * phi_in(lv, ms, k0, r0) - J2 / (r0 * r0);
       bool done = false;
@@ -532,7 +541,7 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap) {
         const double rn = r0 + 0.0;
         double vrn, vtn;
         finish(rn, qn, J, J2, sid, step, seed, vrn, vtn, fl);
-        emit<TO_STAGE>(i, rn, vrn, vtn, load_mass(m, i), sid, r_new, vr, vt, stage, keys);
+        emit<TO_STAGE>(i, rn, vrn, vtn, m[i], sid, kg + 1, r_new, vr, vt, stage, keys, bkey);
         busy = false;
       }
     }

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(NT) void k_stage_from_state(Ctx ctx) {
   const int64_t n = A.s.sc->n;
   const int64_t i = ctx.block() * NT + threadIdx.x;
   if (i >= n) return;
-  StageRec rec;
+  WideRec rec;
   rec.r = A.s.r_new[i];
   rec.vr = A.s.vr[i];
   rec.vt = A.s.vt[i];
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(NT) void k_stage_from_state(Ctx ctx) {
                     : static_cast<const double *>(A.s.m)[i];
   rec.id = A.s.id[i];
   rec.pad = 0u;
-  A.w.stage[i] = rec;
+  static_cast<WideRec *>(A.w.stage)[i] = rec;
   A.w.keys[0][i] = radius_key(rec.r);
 }
 
@@ -334,10 +334,10 @@ __global__ __launch_bounds__(DT) void k_downsweep(Ctx ctx, int pass) {
   }
 }
 
-template <class Ctx>
+template <class Ctx, class Rec>
 __global__ __launch_bounds__(NT) void k_gather(Ctx ctx, int normalise) {
   const ClusterArgs &A = ctx.args();
-  const StageRec *__restrict__ stage = A.w.stage;
+  const Rec *__restrict__ stage = static_cast<const Rec *>(A.w.stage);
   const uint32_t *__restrict__ vals0 = A.w.vals[0];
   const uint32_t *__restrict__ vals1 = A.w.vals[1];
   const uint64_t *__restrict__ pi = reinterpret_cast<const uint64_t *>(A.w.pass_info);
@@ -353,11 +353,12 @@ __global__ __launch_bounds__(NT) void k_gather(Ctx ctx, int normalise) {
   if (p >= kept) return;
   const uint32_t *vals = (pi[kPasses] & 1ull) ? vals1 : vals0;
   const uint32_t src = pi[kPasses] ? vals[p] : static_cast<uint32_t>(p);
-  const StageRec rec = stage[src];
+  const Rec rec = stage[src];
   r[p] = rec.r;
   vr[p] = rec.vr;
   vt[p] = rec.vt;
-  const double mm = normalise ? rec.m / sc->mass_norm : rec.m;
+  const double mm = normalise ? static_cast<double>(rec.m) / sc->mass_norm
+                              : static_cast<double>(rec.m);
   if (m_f32)
     static_cast<float *>(m)[p] = static_cast<float>(mm);
   else
@@ -388,7 +389,8 @@ hipError_t launch_stage_from_state(const Target &t, bool, hipStream_t st) {
 }
 
 // Sort the staged records by keys[0] (n = sc->n on entry) into the state.
-hipError_t launch_sort_stage(const Target &t, bool, bool normalise_mass, hipStream_t st) {
+hipError_t launch_sort_stage(const Target &t, bool m_f32, bool normalise_mass, bool step_records,
+                             hipStream_t st) {
   return dispatch(t, [&](const auto &l) {
     k_sort_prep<<<l.grid(kShOne), 1, 0, st>>>(l.ctx(kShOne));
     k_key_range<<<l.grid(kShKeyRange), NT, 0, st>>>(l.ctx(kShKeyRange));
@@ -398,7 +400,12 @@ hipError_t launch_sort_stage(const Target &t, bool, bool normalise_mass, hipStre
       k_scan_digits<<<l.grid(kShDigit), NT, 0, st>>>(l.ctx(kShDigit), pass);
       k_downsweep<<<l.grid(kShSortTile), DT, 0, st>>>(l.ctx(kShSortTile), pass);
     }
-    k_gather<<<l.grid(kShStar), NT, 0, st>>>(l.ctx(kShStar), normalise_mass ? 1 : 0);
+    if (step_records && m_f32)
+      k_gather<decltype(l.ctx(kShStar)), StageRec<float>>
+          <<<l.grid(kShStar), NT, 0, st>>>(l.ctx(kShStar), normalise_mass ? 1 : 0);
+    else
+      k_gather<decltype(l.ctx(kShStar)), WideRec>
+          <<<l.grid(kShStar), NT, 0, st>>>(l.ctx(kShStar), normalise_mass ? 1 : 0);
     return hipGetLastError();
   });
 }

@@ -320,6 +320,79 @@ def test_step_lockstep(cmc, ora, n, gamma, ms, steps):
         st = new
 
 
+def _sort_cover(old_r, new_r):
+    """Shape of the step's bucket sort on these radii, from the oracle's own
+    result: c = old radii <= r_new, buckets of 2048 values of c."""
+    c = np.searchsorted(old_r, new_r, side="right")
+    cnt = np.bincount(c >> 11)
+    runs = np.bincount(c, minlength=(len(cnt) << 11))
+    small = [b for b in range(len(cnt)) if cnt[b] <= 4096]
+    max_run = max((runs[b << 11:(b + 1) << 11].max() for b in small), default=0)
+    return int(cnt.max()), int(max_run)
+
+
+def _step_once(cmc, ora, st, seed, k, gamma, cap=None):
+    cl = cmc.Cluster(cap or st.n)
+    cl.load(st.r, st.vr, st.vt, st.m, st.id)
+    cmc.cmc_step(cl, cmc.Params(seed=seed, step=k, gamma=gamma))
+    new, info = ora.step(st, seed, k, gamma)
+    return cl, new, info
+
+
+def _same_step(cl, new, info):
+    s = cl.scalars()
+    h = cl.host()
+    assert rel(s["dt"], info["dt"]) < TOL
+    assert s["n"] == new.n
+    assert np.array_equal(h["id"], new.id)
+    assert rel(h["r"], new.r) < TOL
+    vs = np.hypot(new.vr, new.vt).max()
+    assert rel(h["vt"], new.vt, vs * 1e-6) < TOL
+    assert np.max(np.abs(h["vr"] ** 2 - new.vr ** 2)) < TOL * 4 * vs**2
+    assert rel(h["m"], new.m) < TOL
+
+
+@pytest.mark.parametrize("case", ["cold", "gap"])
+def test_step_sort_crowded_buckets(cmc, ora, case):
+    """States whose new radii crowd a few stretches of the old ones: a cold
+    Plummer sphere (velocities x 0.3) falls inward, and two shells with a gap
+    send thousands of stars between the same two old radii.  The step's sort
+    then meets buckets above its LDS capacity and long runs of equal
+    position; the result must still be the oracle's."""
+    rng = np.random.default_rng(4)
+    if case == "cold":
+        st = ora.plummer(40_000, 3)
+        st.vr *= 0.3
+        st.vt *= 0.3
+        st.vr[::501] = 3.0  # a few escapers
+    else:
+        r = np.sort(np.concatenate([0.01 * (1 + 0.2 * rng.random(5000)),
+                                    1.0 + 0.2 * rng.random(5000)]))
+        n = r.size
+        st = ora.State(r, 0.3 * rng.standard_normal(n), np.abs(0.3 * rng.standard_normal(n)),
+                       np.full(n, 1.0 / n), np.arange(n, dtype=np.uint32) * 3 + 1)
+    cl, new, info = _step_once(cmc, ora, st, 5, 0, 0.11)
+    most, run = _sort_cover(st.r, new.r)
+    assert most > 4096  # a bucket merge-sorted in global memory
+    if case == "gap":
+        assert run > 32  # a run of equal position sorted by the bitonic network
+    _same_step(cl, new, info)
+
+
+def test_step_radix_sort_for_large_capacity(cmc, ora):
+    """Capacities above CMC_BUCKET_CAP_MAX take the radix sort in the step.
+    (The potential's scan splits its tiles by capacity, so the last bits of
+    the sums, not the order, may differ from a small-capacity run.)"""
+    st = ora.plummer(20_000, 6)
+    big, new, info = _step_once(cmc, ora, st, 2, 1, 0.11, cap=cmc.CMC_BUCKET_CAP_MAX + 1)
+    _same_step(big, new, info)
+    small, _, _ = _step_once(cmc, ora, st, 2, 1, 0.11)
+    hb, hs = big.host(), small.host()
+    assert np.array_equal(hb["id"], hs["id"])
+    assert rel(hb["r"], hs["r"]) < TOL
+    del big
+
+
 def test_diagnostics(cmc, ora):
     st = ora.plummer(30_000, 2)
     cl = upload(cmc, st)
