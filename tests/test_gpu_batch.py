@@ -122,6 +122,33 @@ def test_batch_equals_single_calls(cmc, precision):
             assert sa[key] == sb[key], key
 
 
+def test_batch_radix_sort_for_large_capacity(cmc):
+    """One cluster above CMC_BUCKET_CAP_MAX sends the whole ensemble's step to
+    the radix sort; every cluster must still come out bit for bit as its own
+    single-cluster calls (which use the bucket sort where they can)."""
+    specs = SPECS[:2] + [dict(n=3000, seed=16, gamma=0.11, model=0,
+                              cap=cmc.CMC_BUCKET_CAP_MAX + 1)]
+    ens = cmc.Ensemble(specs)
+    assert ens.handle.bucket_sort == 0
+    assert cmc.Ensemble(SPECS).handle.bucket_sort == 1
+    ens.init()
+    singles = []
+    for s in specs:
+        cl = cmc.Cluster(int(s.get("cap", s["n"])))
+        cmc.cmc_init_model(cl, s["n"], s["seed"], s["model"], s.get("mass_spectrum", 0),
+                           s.get("w0", 0.0))
+        singles.append(cl)
+    for k in range(2):
+        ens.step(cmc.Params(step=k))
+        for cl, s in zip(singles, specs):
+            cmc.cmc_step(cl, cmc.Params(seed=s["seed"], gamma=s["gamma"], step=k))
+    for a, b in zip(ens.clusters, singles):
+        ha, hb = a.host(), b.host()
+        for key in ("r", "vr", "vt", "m", "id"):
+            assert np.array_equal(ha[key], hb[key]), key
+        assert a.scalars()["n"] == b.scalars()["n"]
+
+
 def test_batch_graph_replay(cmc):
     """One captured ensemble step replayed three times, with eager work in
     between, equals three eager steps with explicit indices 0, 1, 2."""
