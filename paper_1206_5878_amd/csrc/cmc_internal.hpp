@@ -273,6 +273,7 @@ constexpr int kBucketGroupBits = 10;    // at most 1024 groups of intervals per 
 constexpr int kBucketSortCap = 4096;    // stars a bucket sorts in LDS
 constexpr uint32_t kBucketEsc = 0xFFFFFFFFu;  // bkey of a star that leaves the cluster
 constexpr int kKingTab = 3 * kKingNodes + 8;
+constexpr int kPhiBins = 2048;  // bins of the potential-bound table (orbit.hip)
 
 struct Workspace {
   RPhi *lev[kMaxLevels];    // level L: [ceil(cap / 8^L)]
@@ -296,6 +297,8 @@ struct Workspace {
   uint32_t *rx_tile;        // [cdiv(rx_nb + 1, 4096)] prefix-maximum tiles
   RIndexCtl *rx_ctl;        // [1]
   double *king;             // [kKingTab] King model profile (initial model only)
+  double *phib;             // [kPhiBins + 1] Phi at the bound table's edge radii
+  uint64_t *phib_ctl;       // [2]: bits of the first edge, shift from bits to bins
   uint32_t *bkey;           // [cap] old radii <= each staged radius, or kBucketEsc
   BktEnt *bent;             // [cap] entries grouped by bucket (shares orec's memory)
   uint32_t *bkt_cnt;        // [bkt_tiles * bkt_bins] per-tile counts, then tile offsets
@@ -363,6 +366,8 @@ inline Workspace layout(int64_t cap, void *base) {
   w.rx_tile = reinterpret_cast<uint32_t *>(take(4 * cdiv(w.rx_nb + 1, 4096)));
   w.rx_ctl = reinterpret_cast<RIndexCtl *>(take(sizeof(RIndexCtl)));
   w.king = reinterpret_cast<double *>(take(8 * kKingTab));
+  w.phib = reinterpret_cast<double *>(take(8 * (kPhiBins + 1)));
+  w.phib_ctl = reinterpret_cast<uint64_t *>(take(8 * 2));
   w.bkey = reinterpret_cast<uint32_t *>(take(4 * c));
   w.bent = reinterpret_cast<BktEnt *>(w.orec);  // orec is dead once the orbit pass ends
   static_assert(sizeof(BktEnt) <= sizeof(OrbitRec), "bent fits in orec");

@@ -94,6 +94,57 @@ __device__ __forceinline__ int64_t interval_in(const RIndex &ix, const RIndexCtl
   return k < kmin ? kmin : (k > kmax ? kmax : k);
 }
 
+// ---------------------------------------------------------------- potential bounds
+// Phi rises outward, so for edge radii x_b <= x < x_(b+1) the potential at a
+// trial radius lies in [Phi(x_b), Phi(x_(b+1))].  The edges are equal steps of
+// the IEEE bit pattern from r_0 (about equal steps in ln r), kPhiBins of them
+// over the table's range; below r_0 the potential is Phi_0, beyond the last
+// edge it lies in [Phi(last edge), 0].
+struct PhiBounds {
+  const double *tab;  // [kPhiBins + 1]
+  uint64_t lo;        // bits of the first edge (r_0)
+  uint32_t shift;
+  double phi0;        // Phi_0
+};
+
+// Whether the trial at x is certainly rejected.  The bounds on Phi bound
+// Q = 2E - 2 Phi - J^2/x^2 and the acceptance ratio g = r_a cos s / sqrt(Q);
+// a rejection is called only when it holds with a margin far above the
+// rounding of the exact test (relative 1e-12 on Q, 1e-12 on g in FP64, 1e-5
+// on the FP32 g of the mixed form), so the exact test would reject as well,
+// and the trial is counted the same way (no bound violation: g < F X2 < F).
+template <bool MIXED>
+__device__ __forceinline__ bool surely_rejected(const PhiBounds &pb, double x, double E,
+                                                double J2, double ra, double cs, double F,
+                                                double X2) {
+  const uint64_t kx = rbits(x);
+  double plo, phi;
+  if (kx < pb.lo) {
+    plo = phi = pb.phi0;
+  } else {
+    const uint64_t b = (kx - pb.lo) >> pb.shift;
+    if (b >= static_cast<uint64_t>(kPhiBins)) {
+      plo = pb.tab[kPhiBins];
+      phi = 0.0;
+    } else {
+      plo = pb.tab[b];
+      phi = pb.tab[b + 1];
+    }
+  }
+  const double c2 = J2 / (x * x);
+  const double mu = 1e-12 * (2.0 * fabs(E) + 2.0 * fabs(plo) + 2.0 * fabs(phi) + c2);
+  const double qmax = 2.0 * E - 2.0 * plo - c2 + mu;
+  if (qmax <= 0.0) return true;
+  const double qmin = 2.0 * E - 2.0 * phi - c2 - mu;
+  if (!(qmin > 0.0)) return false;
+  const double gmax = ra * cs / sqrt(qmin);
+  if (MIXED) {
+    const float pf = static_cast<float>(F) * static_cast<float>(X2);
+    return static_cast<double>(pf) >= gmax * (1.0 + 1e-5);
+  }
+  return F * X2 >= gmax * (1.0 + 1e-12);
+}
+
 // ---------------------------------------------------------------- group search
 // The same search, cooperative: lanes form groups of 8 (group g = lanes
 // 8g..8g+7), and each group runs the searches of its 8 lanes together.  Per
@@ -425,6 +476,8 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap) {
   const uint64_t seed = A.seed;
   const RIndexCtl ictl = *ix.ctl;
   const int64_t n = ictl.n;
+  const PhiBounds pb{A.w.phib, A.w.phib_ctl[0], static_cast<uint32_t>(A.w.phib_ctl[1]),
+                     lv.lev[0][0].phi};
   const int64_t blk = ctx.block();
   const int lane = threadIdx.x & 63;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -502,7 +555,11 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap) {
       ++c_tr;
     }
     int64_t kg = 0;
-    if (busy) {
+    // a trial that is certainly rejected needs no interval (the capped last
+    // trial always looks its interval up: its radius is kept)
+    const bool settled =
+        busy && j < trial_cap && surely_rejected<MIXED>(pb, r0, E, J2, ra, cs, F, X2);
+    if (busy && !settled) {
       kg = rindex_last_le(ix, ictl, r0);
       const int64_t k0 = kg < kmin ? kmin : (kg > kmax ? kmax : kg);
       const double q0 = 2.0 * E - 2.0 * phi_in(lv, ms, k0, r0) - J2 / (r0 * r0);
@@ -558,6 +615,29 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap) {
   }
 }
 
+// One block per cluster: the potential at the bound table's edges (after the
+// radial index is built).
+template <class Ctx>
+__global__ __launch_bounds__(1024) void k_phi_bounds(Ctx ctx) {
+  const ClusterArgs &A = ctx.args();
+  const RIndex ix{A.s.r, A.w.rx_start, A.w.rx_ctl};
+  const RIndexCtl ictl = *ix.ctl;
+  if (ictl.n == 0) return;
+  const Levels lv = levels_of(A.w);
+  uint32_t shift = 0;
+  while (((ictl.hi - ictl.lo) >> shift) >= static_cast<uint64_t>(kPhiBins)) ++shift;
+  for (int j = threadIdx.x; j <= kPhiBins; j += 1024) {
+    uint64_t bits = ictl.lo + (static_cast<uint64_t>(j) << shift);
+    bits = bits < 0x7FF0000000000000ull ? bits : 0x7FF0000000000000ull;
+    const double x = __builtin_bit_cast(double, bits);
+    A.w.phib[j] = phi_in(lv, A.w.ms, rindex_last_le(ix, ictl, x), x);
+  }
+  if (threadIdx.x == 0) {
+    A.w.phib_ctl[0] = ictl.lo;
+    A.w.phib_ctl[1] = shift;
+  }
+}
+
 constexpr int FT = 1024;
 
 // One block per cluster: the cluster's bracket and trial partials.
@@ -605,6 +685,7 @@ hipError_t run2(const L &l, const cmc_params &p, hipStream_t st) {
   const double bf = p.bound_factor > 0.0 ? p.bound_factor : 1.2;
   using Cb = decltype(l.ctx(kShBracket));
   using Ct = decltype(l.ctx(kShTrials));
+  k_phi_bounds<<<l.grid(kShOne), 1024, 0, st>>>(l.ctx(kShOne));
   k_orbit_bracket<Cb, MT, TO_STAGE>
       <<<l.grid(kShBracket), BT, sizeof(RPhi) * l.top_entries(), st>>>(l.ctx(kShBracket), p.step,
                                                                        bf);
