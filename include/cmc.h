@@ -55,9 +55,8 @@ extern "C" {
 /* ---- arithmetic of a call --------------------------------------------------- */
 #define CMC_FP64 0  /* every step in double precision                          */
 #define CMC_MIXED 1 /* fp32 pair terms, kicks and rejection trials (23-bit
-                       uniforms); compensated fp32 potential sums per thread
-                       with fp64 scans and carries; fp64 table, turning points
-                       and Q.  Results differ from CMC_FP64 at ~1e-7 relative,
+                       uniforms); fp32 m/r in the potential with fp64 sums;
+                       fp64 table, turning points and Q.  Results differ from CMC_FP64 at ~1e-7 relative,
                        and an accept/reject decision within that of its
                        threshold may flip.                                      */
 

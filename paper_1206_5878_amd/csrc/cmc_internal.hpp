@@ -257,7 +257,7 @@ __device__ __forceinline__ int64_t rindex_last_le(const RIndex &ix, const RIndex
 
 // ---------------------------------------------------------------- workspace
 constexpr int kSortTile = 4096;  // keys per radix tile (256 threads x 16)
-constexpr int kPotTile = 2048;   // stars per potential tile (256 x 8)
+constexpr int kPotTile = 1024;   // stars per potential tile (4 rounds of 256)
 constexpr int kBlock = 256;
 constexpr int kRedBlocks = 2048;  // grid of the grid-stride reduction kernels
 constexpr int kKingNodes = 4096;  // nodes of a King profile: (r, W, M) each

@@ -3,11 +3,12 @@
 // inclusive prefix of m and S_k the exclusive suffix of m/r.  Device-wide
 // scan in three deterministic passes: per-tile sums, a one-block scan of the
 // tile sums (forward for M, backward for S), and a per-tile apply that adds
-// the carries to in-tile scans.  The mixed form sums each thread's run of 8
-// stars in compensated FP32 and keeps the block scans and carries in FP64.
-// HBM-bound: reads r and m, writes the
-// orbit table ((r, Phi) and (M, S) per star plus the sampled search levels)
-// and, for the standalone call, the state's phi, mcum, ssuf.
+// the carries to in-tile scans.  A tile is 4 rounds of 256 consecutive stars,
+// thread t holding star t of each round, so every load and store of a wave
+// is one contiguous run; the in-tile scans are block scans per round.  The
+// mixed form forms m / r in FP32; every sum is FP64.  HBM-bound: reads r and
+// m, writes the orbit table ((r, Phi) and (M, S) per star plus the sampled
+// search levels) and, for the standalone call, the state's phi, mcum, ssuf.
 #include <type_traits>
 
 #include "cmc_internal.hpp"
@@ -16,40 +17,49 @@ namespace cmc {
 namespace {
 
 constexpr int PT = kBlock;
-constexpr int PJ = kPotTile / kBlock;  // 8 consecutive stars per thread
-
-// Error-free float addition (Knuth's two-sum): s + e == a + b exactly.
-__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
-  s = a + b;
-  const float bb = s - a;
-  e = (a - (s - bb)) + (b - bb);
-}
-
-// Running sum of a thread's run: FP64, or compensated FP32 (sum + error term,
-// read out in FP64) for the mixed form.
-template <bool MIXED>
-struct Acc {
-  double d = 0.0;
-  float s = 0.0f, e = 0.0f;
-  __device__ __forceinline__ void add(double x) {
-    if (MIXED) {
-      float t, err;
-      two_sum(s, static_cast<float>(x), t, err);
-      s = t;
-      e += err;
-    } else {
-      d += x;
-    }
-  }
-  __device__ __forceinline__ double value() const {
-    return MIXED ? static_cast<double>(s) + static_cast<double>(e) : d;
-  }
-};
+constexpr int PJ = kPotTile / PT;  // rounds of PT consecutive stars per tile
 
 // m / r: FP64, or FP32 for the mixed form.
 template <bool MIXED>
 __device__ __forceinline__ double m_over_r(double m, double r) {
   return MIXED ? static_cast<double>(static_cast<float>(m) / static_cast<float>(r)) : m / r;
+}
+
+// Over the block, in thread order: the exclusive prefix of a and the exclusive
+// suffix of b, with both block totals, through one LDS exchange.  The sums
+// run in the same order as block_excl_scan and block_excl_suffix.
+__device__ __forceinline__ void block_scan_pair(double a, double b, double *sh, double &pa,
+                                                double &sb, double &ta, double &tb) {
+  constexpr int NW = PT / 64;
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const double ia = wave_incl_scan(a);
+  const double ib = wave_incl_suffix(b);
+  double ea = __shfl_up(ia, 1, 64);
+  double eb = __shfl_down(ib, 1, 64);
+  if (l == 0) ea = 0.0;
+  if (l == 63) eb = 0.0;
+  if (l == 63) sh[w] = ia;
+  if (l == 0) sh[NW + w] = ib;
+  __syncthreads();
+  double ba = 0.0, bb = 0.0, sa = 0.0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    const double x = sh[i];
+    if (i < w) ba += x;
+    sa += x;
+  }
+  double sbt = 0.0;
+#pragma unroll
+  for (int i = NW - 1; i >= 0; --i) {
+    const double y = sh[NW + i];
+    if (i > w) bb += y;
+    sbt += y;
+  }
+  __syncthreads();
+  pa = ba + ea;
+  sb = bb + eb;
+  ta = sa;
+  tb = sbt;
 }
 
 template <class Ctx, typename MT, bool MIXED>
@@ -61,19 +71,19 @@ __global__ __launch_bounds__(PT) void k_pot_tile_sums(Ctx ctx) {
   const int64_t n = A.s.sc->n;
   const int64_t tiles = A.w.pot_tiles;
   const int64_t t = ctx.block();
-  const int64_t base = t * kPotTile + static_cast<int64_t>(threadIdx.x) * PJ;
-  Acc<MIXED> sm, sq;
+  const int64_t base = t * kPotTile + threadIdx.x;
+  double sm = 0.0, sq = 0.0;
 #pragma unroll
   for (int j = 0; j < PJ; ++j) {
-    const int64_t k = base + j;
+    const int64_t k = base + j * PT;
     if (k < n) {
       const double mk = load_mass(m, k);
-      sm.add(mk);
-      sq.add(m_over_r<MIXED>(mk, r[k]));
+      sm += mk;
+      sq += m_over_r<MIXED>(mk, r[k]);
     }
   }
-  const double tm = block_sum<PT>(sm.value(), sh);
-  const double tq = block_sum<PT>(sq.value(), sh);
+  const double tm = block_sum<PT>(sm, sh);
+  const double tq = block_sum<PT>(sq, sh);
   if (threadIdx.x == 0) {
     A.w.pot_tsum[t] = tm;
     A.w.pot_tsum[tiles + t] = tq;
@@ -81,8 +91,11 @@ __global__ __launch_bounds__(PT) void k_pot_tile_sums(Ctx ctx) {
 }
 
 constexpr int ST = 1024;
+constexpr int SQ = 16;  // tile sums a thread of the tile scan holds in registers
 
-// One block per cluster.
+// One block per cluster; thread t scans tiles [t per, (t+1) per).  Up to SQ
+// tiles per thread are loaded at once (N up to SQ * ST * kPotTile stars);
+// beyond that the thread walks its range.
 template <class Ctx>
 __global__ __launch_bounds__(ST) void k_pot_tile_scan(Ctx ctx) {
   __shared__ double sh[ST / 64];
@@ -93,6 +106,36 @@ __global__ __launch_bounds__(ST) void k_pot_tile_scan(Ctx ctx) {
   const int64_t per = (tiles + ST - 1) / ST;
   const int64_t b = static_cast<int64_t>(threadIdx.x) * per;
   const int64_t e = b + per < tiles ? b + per : tiles;
+  if (per <= SQ) {
+    double vm[SQ], vq[SQ];
+    double sm = 0.0, sq = 0.0;
+#pragma unroll
+    for (int q = 0; q < SQ; ++q) {
+      const bool ok = b + q < e;
+      vm[q] = ok ? tsum[b + q] : 0.0;
+      vq[q] = ok ? tsum[tiles + b + q] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < SQ; ++q) {
+      sm += vm[q];
+      sq += vq[q];
+    }
+    double acc = block_excl_scan<ST>(sm, sh, static_cast<double *>(nullptr));
+#pragma unroll
+    for (int q = 0; q < SQ; ++q) {
+      if (b + q < e) carry[b + q] = acc;
+      acc += vm[q];
+    }
+    acc = block_excl_suffix<ST>(sq, sh, static_cast<double *>(nullptr));
+#pragma unroll
+    for (int q = SQ - 1; q >= 0; --q) {
+      if (b + q < e) {
+        carry[tiles + b + q] = acc;
+        acc += vq[q];
+      }
+    }
+    return;
+  }
   double sm = 0.0, sq = 0.0;
   for (int64_t k = b; k < e; ++k) {
     sm += tsum[k];
@@ -114,7 +157,7 @@ __global__ __launch_bounds__(ST) void k_pot_tile_scan(Ctx ctx) {
 
 template <class Ctx, typename MT, bool PUBLIC, bool MIXED>
 __global__ __launch_bounds__(PT) void k_pot_apply(Ctx ctx) {
-  __shared__ double sh[PT / 64];
+  __shared__ double sh[2 * (PT / 64)];
   const ClusterArgs &A = ctx.args();
   const double *__restrict__ r = A.s.r;
   const MT *__restrict__ m = static_cast<const MT *>(A.s.m);
@@ -123,45 +166,44 @@ __global__ __launch_bounds__(PT) void k_pot_apply(Ctx ctx) {
   const int64_t tiles = A.w.pot_tiles;
   const Levels lv = levels_of(A.w);
   const int64_t t = ctx.block();
-  const int64_t base = t * kPotTile + static_cast<int64_t>(threadIdx.x) * PJ;
-  double rr[PJ], pm[PJ], sq[PJ];
-  Acc<MIXED> am;
+  const int64_t base = t * kPotTile + threadIdx.x;
+  double rr[PJ], mk[PJ], q[PJ];
 #pragma unroll
   for (int j = 0; j < PJ; ++j) {
-    const int64_t k = base + j;
+    const int64_t k = base + j * PT;
     const bool ok = k < n;
     rr[j] = ok ? r[k] : 1.0;
-    const double mk = ok ? load_mass(m, k) : 0.0;
-    am.add(mk);
-    pm[j] = am.value();  // inclusive prefix inside the thread
-    sq[j] = m_over_r<MIXED>(mk, rr[j]);
+    mk[j] = ok ? load_mass(m, k) : 0.0;
+    q[j] = m_over_r<MIXED>(mk[j], rr[j]);
   }
-  const double tm = am.value();
-  Acc<MIXED> aq;
-#pragma unroll
-  for (int j = PJ - 1; j >= 0; --j) {  // exclusive suffix inside the thread
-    const double q = sq[j];
-    sq[j] = aq.value();
-    aq.add(q);
-  }
-  const double tq = aq.value();
-  const double em = block_excl_scan<PT>(tm, sh, static_cast<double *>(nullptr));
-  const double eq = block_excl_suffix<PT>(tq, sh, static_cast<double *>(nullptr));
-  const double cm = carry[t] + em;
-  const double cq = carry[tiles + t] + eq;
+  // M: inclusive prefix, round by round; S: exclusive suffix inside each
+  // round, then the later rounds' totals and the later tiles' carry
+  double M[PJ], S[PJ], tq[PJ];
+  double cm = carry[t];
 #pragma unroll
   for (int j = 0; j < PJ; ++j) {
-    const int64_t k = base + j;
+    double ex, tm;
+    block_scan_pair(mk[j], q[j], sh, ex, S[j], tm, tq[j]);
+    M[j] = cm + (ex + mk[j]);
+    cm += tm;
+  }
+  double cq = carry[tiles + t];
+#pragma unroll
+  for (int j = PJ - 1; j >= 0; --j) {
+    S[j] += cq;
+    cq += tq[j];
+  }
+#pragma unroll
+  for (int j = 0; j < PJ; ++j) {
+    const int64_t k = base + j * PT;
     if (k < n) {
-      const double M = cm + pm[j];
-      const double S = cq + sq[j];
-      const double ph = -(M / rr[j] + S);
+      const double ph = -(M[j] / rr[j] + S[j]);
       if (PUBLIC) {
-        A.s.mcum[k] = M;
-        A.s.ssuf[k] = S;
+        A.s.mcum[k] = M[j];
+        A.s.ssuf[k] = S[j];
         A.s.phi[k] = ph;
       }
-      put_table(lv, A.w.ms, k, rr[j], ph, M, S);
+      put_table(lv, A.w.ms, k, rr[j], ph, M[j], S[j]);
     }
   }
 }
