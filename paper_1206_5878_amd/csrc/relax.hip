@@ -112,7 +112,7 @@ enum { kX = 0, kLo, kHi, kDone, kIt, kCnt, kZero, kInfN, kLogSum };
 
 template <class Ctx, typename MT, bool MIXED>
 __global__ __launch_bounds__(NT) void k_pair_tp(Ctx ctx, uint32_t step_arg) {
-  __shared__ double sh[NT / 64];
+  __shared__ double sh[4 * (NT / 64)];
   const ClusterArgs &A = ctx.args();
   const uint32_t step = step_of(A, step_arg);
   const double *__restrict__ r = A.s.r;
@@ -126,34 +126,40 @@ __global__ __launch_bounds__(NT) void k_pair_tp(Ctx ctx, uint32_t step_arg) {
   const double gamma = A.gamma;
   const int64_t n = A.s.sc->n;
   const int64_t np = n / 2;
+  // the sum of ln t_p only seeds a cold start (no previous dt)
+  const bool cold = !(A.s.sc->dt > 0.0);
   const int64_t blk = ctx.block();
   const int64_t p = blk * NT + threadIdx.x;
-  double cnt = 0.0, nz = 0.0, ni = 0.0, ls = 0.0;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};  // counted, t_p = 0, t_p = inf, sum ln t_p
   if (p < np) {
     const PairGeo g =
         pair_geometry<MT, MIXED>(p, n, r, m, vr, vt, id, seed, step, coulomb_log(gamma, n));
     if (g.wm > 0.0) {
       tp_out[p] = g.tp;
-      cnt = 1.0;
+      v[0] = 1.0;
       if (g.tp == 0.0)
-        nz = 1.0;
+        v[1] = 1.0;
       else if (isinf(g.tp))
-        ni = 1.0;
-      else
-        ls = log(g.tp);
+        v[2] = 1.0;
+      else if (cold)
+        v[3] = log(g.tp);
     } else {
       tp_out[p] = -1.0;  // no relative motion: not counted
     }
   }
-  cnt = block_sum<NT>(cnt, sh);
-  nz = block_sum<NT>(nz, sh);
-  ni = block_sum<NT>(ni, sh);
-  ls = block_sum<NT>(ls, sh);
-  if (threadIdx.x == 0) {
-    part[4 * blk + 0] = cnt;
-    part[4 * blk + 1] = nz;
-    part[4 * blk + 2] = ni;
-    part[4 * blk + 3] = ls;
+  // the four block sums through one LDS exchange (wave order, then waves)
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v[q] = wave_sum(v[q]);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sh[4 * w + q] = v[q];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) t += sh[4 * i + threadIdx.x];
+    part[4 * blk + threadIdx.x] = t;
   }
 }
 
