@@ -7,17 +7,19 @@
 //      consecutive values of c (escapers in a bin of their own);
 //   2. per bucket, exclusive offsets of the tiles (column scan), and per
 //      cluster the bucket starts (the escapers' bin last: they are dropped);
-//   3. per tile, a scatter of 16-byte entries (radius key; group of c inside
-//      the bucket above the staged index) to their bucket;
-//   4. per bucket, one block: a counting sort on the group in LDS, each group
-//      sorted by (radius, staged index), then the staged records gathered in
-//      that order into the state arrays.
+//   3. per tile, a scatter of 16-byte entries (radius key, staged index,
+//      c mod 2048) to their bucket;
+//   4. per bucket, one block: a counting sort on c mod 2048 in LDS (16-bit
+//      counters, two to a word), each run of equal c (about one star) sorted
+//      by (radius, staged index), then the staged records gathered in that
+//      order into the state arrays.
 // The result is the stable sort of the staged stars by radius, the same
 // permutation as the radix sort.  Records move once (one random read each,
 // a whole line for the 32-byte records of f32 masses); entries move once.
 // A bucket has 2048 stars on average: one that holds more than 4096 (a state
 // far from the old one, or many equal radii) is merge-sorted by its block in
-// global memory instead, and a group of more than 48 by a bitonic network.
+// global memory instead, and a run of more than 48 equal c by a bitonic
+// network.
 #include <type_traits>
 
 #include "cmc_internal.hpp"
@@ -27,7 +29,7 @@ namespace {
 
 constexpr int HT = 1024;      // threads of the tile and scan kernels
 constexpr int BT = 512;       // threads of a bucket's sort
-constexpr int kSubMax = 48;   // largest group sorted by insertion
+constexpr int kSubMax = 48;   // longest run of equal c sorted by insertion
 constexpr int kMergeRun = 16; // outputs per thread of a merge step
 
 __device__ __forceinline__ int64_t buckets_of(int64_t n) { return (n >> kBucketShift) + 1; }
@@ -141,9 +143,7 @@ __global__ __launch_bounds__(HT) void k_bkt_start(Ctx ctx) {
   }
 }
 
-// Entries to their buckets: the radius key and side = (c mod 2048) >> gshift
-// above the staged index, so that side orders like the staged index inside a
-// group and the group needs no field of its own.
+// Entries to their buckets at LDS-atomic slots.
 template <class Ctx>
 __global__ __launch_bounds__(HT) void k_bkt_scatter(Ctx ctx) {
   __shared__ uint32_t cur[kBucketBins];
@@ -164,7 +164,6 @@ __global__ __launch_bounds__(HT) void k_bkt_scatter(Ctx ctx) {
   const uint32_t *__restrict__ bkey = A.w.bkey;
   const uint64_t *__restrict__ keys = A.w.keys[0];
   BktEnt *__restrict__ bent = A.w.bent;
-  const int ibits = A.w.bkt_ibits, gshift = A.w.bkt_gshift;
   for (int b = threadIdx.x; b < nb; b += HT) cur[b] = start[b] + row[b];
   __syncthreads();
   const int64_t k1 = k0 + kBucketTile < n ? k0 + kBucketTile : n;
@@ -177,8 +176,8 @@ __global__ __launch_bounds__(HT) void k_bkt_scatter(Ctx ctx) {
         const uint32_t pos = atomicAdd(&cur[bin_of(c, nb)], 1u);
         BktEnt e;
         e.key = keys[k];
-        e.side = (((c & (kBucketSpan - 1)) >> gshift) << ibits) | static_cast<uint32_t>(k);
-        e.pad = 0u;
+        e.idx = static_cast<uint32_t>(k);
+        e.sub = c & (kBucketSpan - 1);
         bent[pos] = e;
       }
     }
@@ -262,14 +261,13 @@ template <typename MT>
 __device__ __forceinline__ void gather(const ClusterArgs &A, const uint32_t *V, int64_t out,
                                        int64_t count) {
   const StageRec<MT> *__restrict__ stage = static_cast<const StageRec<MT> *>(A.w.stage);
-  const uint32_t imask = static_cast<uint32_t>((uint64_t(1) << A.w.bkt_ibits) - 1);
   constexpr int B = 8;  // records in flight per thread
   for (int64_t p0 = 0; p0 < count; p0 += B * BT) {
     StageRec<MT> rec[B];
 #pragma unroll
     for (int q = 0; q < B; ++q) {
       const int64_t p = p0 + q * BT + threadIdx.x;
-      if (p < count) rec[q] = stage[V[p] & imask];
+      if (p < count) rec[q] = stage[V[p]];
     }
 #pragma unroll
     for (int q = 0; q < B; ++q) {
@@ -293,7 +291,7 @@ __device__ void sort_large(const ClusterArgs &A, uint32_t base, int64_t count, u
     for (int s = threadIdx.x; s < m; s += BT) {
       const BktEnt e = bent[r0 + s];
       K[s] = e.key;
-      V[s] = e.side;
+      V[s] = e.idx;
     }
     __syncthreads();
     bitonic_lds(K, V, m);
@@ -312,12 +310,12 @@ __device__ void sort_large(const ClusterArgs &A, uint32_t base, int64_t count, u
   gather<MT>(A, vb[src], base, count);
 }
 
-// One block per bucket.  sub: counts, then starts, of each group; entries
-// (K radius key, V side) are placed by group, then each group is put in
-// (K, V) order: inside a group V orders like the staged index.
+// One block per bucket.  sub: 16-bit counts, then starts, of each value of
+// c mod 2048 (two to a word); entries (K radius key, V staged index) are
+// placed by c, then each run of equal c is put in (K, V) order.
 template <class Ctx, typename MT>
 __global__ __launch_bounds__(BT) void k_bkt_sort(Ctx ctx) {
-  __shared__ uint32_t sub[1 << kBucketGroupBits];
+  __shared__ uint32_t sub[kBucketSpan / 2];
   __shared__ uint64_t K[kBucketSortCap];
   __shared__ uint32_t V[kBucketSortCap];
   __shared__ uint32_t sh[BT / 64];
@@ -335,45 +333,50 @@ __global__ __launch_bounds__(BT) void k_bkt_sort(Ctx ctx) {
   }
   const int cnt = static_cast<int>(count);
   const BktEnt *__restrict__ bent = A.w.bent + base;
-  const int ibits = A.w.bkt_ibits;
-  const int groups = kBucketSpan >> A.w.bkt_gshift;
-  for (int q = threadIdx.x; q < groups; q += BT) sub[q] = 0u;
+  for (int q = threadIdx.x; q < kBucketSpan / 2; q += BT) sub[q] = 0u;
   if (threadIdx.x == 0) big = 0;
   __syncthreads();
   constexpr int PER = kBucketSortCap / BT;
   uint64_t ek[PER];
-  uint32_t ev[PER], rk[PER];
+  uint32_t ev[PER], es[PER], rk[PER];
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int s = j * BT + threadIdx.x;
     ek[j] = 0ull;
     ev[j] = 0u;
+    es[j] = 0u;
     rk[j] = 0u;
     if (s < cnt) {
       const BktEnt e = bent[s];
       ek[j] = e.key;
-      ev[j] = e.side;
-      rk[j] = atomicAdd(&sub[static_cast<uint32_t>(static_cast<uint64_t>(e.side) >> ibits)], 1u);
+      ev[j] = e.idx;
+      es[j] = e.sub & (kBucketSpan - 1);
+      const uint32_t sh16 = (es[j] & 1u) * 16u;  // counts stay below 2^16: cnt <= 4096
+      rk[j] = (atomicAdd(&sub[es[j] >> 1], 1u << sh16) >> sh16) & 0xFFFFu;
     }
   }
   __syncthreads();
   {
-    const int per = (groups + BT - 1) / BT;  // consecutive groups per thread
-    const int g0 = threadIdx.x * per;
-    uint32_t sum = 0u, mx = 0u;
-    for (int q = 0; q < per; ++q) {
-      const uint32_t v = g0 + q < groups ? sub[g0 + q] : 0u;
-      sum += v;
-      mx = v > mx ? v : mx;
+    constexpr int Q = kBucketSpan / 2 / BT;  // words of counts per thread
+    uint32_t v[2 * Q], sum = 0u, mx = 0u;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const uint32_t wd = sub[threadIdx.x * Q + q];
+      v[2 * q] = wd & 0xFFFFu;
+      v[2 * q + 1] = wd >> 16;
+    }
+#pragma unroll
+    for (int q = 0; q < 2 * Q; ++q) {
+      sum += v[q];
+      mx = v[q] > mx ? v[q] : mx;
     }
     if (mx > static_cast<uint32_t>(kSubMax)) big = 1;
     uint32_t acc = block_excl_scan<BT>(sum, sh, static_cast<uint32_t *>(nullptr));
-    for (int q = 0; q < per; ++q) {
-      if (g0 + q < groups) {
-        const uint32_t v = sub[g0 + q];
-        sub[g0 + q] = acc;
-        acc += v;
-      }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const uint32_t lo = acc, hi = acc + v[2 * q];
+      sub[threadIdx.x * Q + q] = lo | (hi << 16);  // starts stay below 2^16 as well
+      acc = hi + v[2 * q + 1];
     }
   }
   __syncthreads();
@@ -381,16 +384,18 @@ __global__ __launch_bounds__(BT) void k_bkt_sort(Ctx ctx) {
   for (int j = 0; j < PER; ++j) {
     const int s = j * BT + threadIdx.x;
     if (s < cnt) {
-      const uint32_t p = sub[static_cast<uint32_t>(static_cast<uint64_t>(ev[j]) >> ibits)] + rk[j];
+      const uint32_t p = ((sub[es[j] >> 1] >> ((es[j] & 1u) * 16u)) & 0xFFFFu) + rk[j];
       K[p] = ek[j];
       V[p] = ev[j];
     }
   }
   __syncthreads();
   if (!big) {
-    for (int q = threadIdx.x; q < groups; q += BT) {
-      const int a = static_cast<int>(sub[q]);
-      const int e = q + 1 < groups ? static_cast<int>(sub[q + 1]) : cnt;
+    for (int q = threadIdx.x; q < kBucketSpan; q += BT) {
+      const int a = static_cast<int>((sub[q >> 1] >> ((q & 1) * 16)) & 0xFFFFu);
+      const int e = q + 1 < kBucketSpan
+                        ? static_cast<int>((sub[(q + 1) >> 1] >> (((q + 1) & 1) * 16)) & 0xFFFFu)
+                        : cnt;
       for (int x = a + 1; x < e; ++x) {
         const uint64_t kx = K[x];
         const uint32_t vx = V[x];

@@ -178,11 +178,11 @@ struct alignas(8) StageRec<double> {
   uint32_t id, pad;
 };
 using WideRec = StageRec<double>;
-// An entry of the step's bucket sort: radius key, and the star's group of old
-// intervals above its staged index (see bucket.hip).
+// An entry of the step's bucket sort: radius key, staged index, and the
+// count of old radii <= r_new modulo the bucket span (see bucket.hip).
 struct alignas(16) BktEnt {
   uint64_t key;
-  uint32_t side, pad;
+  uint32_t idx, sub;
 };
 
 // ---------------------------------------------------------------- orbit table
@@ -269,7 +269,6 @@ constexpr int kBucketBins = 16384;  // LDS bins of a tile: buckets of kept stars
 constexpr int64_t kBucketCapMax = (kBucketBins - 1) * kBucketSpan - 1;  // largest capacity served
 static_assert(kBucketCapMax == CMC_BUCKET_CAP_MAX, "the documented bucket-sort limit");
 constexpr int kBucketTile = 16384;      // stars per histogram and scatter tile
-constexpr int kBucketGroupBits = 10;    // at most 1024 groups of intervals per bucket
 constexpr int kBucketSortCap = 4096;    // stars a bucket sorts in LDS
 constexpr uint32_t kBucketEsc = 0xFFFFFFFFu;  // bkey of a star that leaves the cluster
 constexpr int kKingTab = 3 * kKingNodes + 8;
@@ -306,8 +305,6 @@ struct Workspace {
   uint32_t *bkt_start;      // [bkt_bins + 1] first position of each bucket
   int64_t *bkt_info;        // [2]: staged stars, kept stars
   int64_t bkt_bins, bkt_tiles;  // bkt_bins = 0: capacity above kBucketCapMax
-  int32_t bkt_ibits;        // bits of a staged index in BktEnt::side
-  int32_t bkt_gshift;       // interval-in-bucket >> gshift = the entry's group
   int64_t rx_nb;
   int rx_lg_nb;
   int64_t sort_tiles, pot_tiles, pair_blocks, star_blocks;
@@ -374,10 +371,6 @@ inline Workspace layout(int64_t cap, void *base) {
   if (c <= kBucketCapMax) {
     w.bkt_bins = (c >> kBucketShift) + 2;
     w.bkt_tiles = cdiv(c, kBucketTile);
-    w.bkt_ibits = 0;
-    while ((int64_t(1) << w.bkt_ibits) < c) ++w.bkt_ibits;
-    const int gbits = 32 - w.bkt_ibits < kBucketGroupBits ? 32 - w.bkt_ibits : kBucketGroupBits;
-    w.bkt_gshift = kBucketShift - gbits;
     w.bkt_cnt = reinterpret_cast<uint32_t *>(take(4 * w.bkt_tiles * w.bkt_bins));
     w.bkt_tot = reinterpret_cast<uint32_t *>(take(4 * w.bkt_bins));
     w.bkt_start = reinterpret_cast<uint32_t *>(take(4 * (w.bkt_bins + 1)));
