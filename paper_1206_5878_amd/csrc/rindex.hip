@@ -62,10 +62,10 @@ __global__ __launch_bounds__(NT) void k_rindex_ends(Ctx ctx) {
   uint32_t *__restrict__ start = A.w.rx_start;
   const RIndexCtl c = *A.w.rx_ctl;
   const int64_t n = c.n;
-  const int64_t k = ctx.block() * NT + threadIdx.x;
-  if (k >= n) return;
-  const int64_t bk = bucket(r[k], c);
-  if (k == n - 1 || bucket(r[k + 1], c) != bk) start[bk + 1] = static_cast<uint32_t>(k + 1);
+  for (int64_t k = ctx.block() * NT + threadIdx.x; k < n; k += ctx.nblocks() * NT) {
+    const int64_t bk = bucket(r[k], c);
+    if (k == n - 1 || bucket(r[k + 1], c) != bk) start[bk + 1] = static_cast<uint32_t>(k + 1);
+  }
 }
 
 __device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) {
@@ -149,11 +149,26 @@ __global__ __launch_bounds__(NT) void k_rindex_apply(Ctx ctx) {
   const uint32_t *__restrict__ tcarry = A.w.rx_tile;
   const int64_t blk = ctx.block();
   const int64_t base = blk * kScanTile + threadIdx.x * 16;
+  // 16 consecutive entries per thread, moved as four 16-byte vectors where
+  // the whole vector is in range (start[] is 256-byte aligned)
   uint32_t v[16];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t b = base + 4 * q;
+    if (b + 4 <= len) {
+      const uint4 x = *reinterpret_cast<const uint4 *>(start + b);
+      v[4 * q] = x.x;
+      v[4 * q + 1] = x.y;
+      v[4 * q + 2] = x.z;
+      v[4 * q + 3] = x.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[4 * q + j] = (b + j < len) ? start[b + j] : 0u;
+    }
+  }
   uint32_t run = 0u;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    v[j] = (base + j < len) ? start[base + j] : 0u;
     run = v[j] > run ? v[j] : run;
     v[j] = run;
   }
@@ -161,8 +176,19 @@ __global__ __launch_bounds__(NT) void k_rindex_apply(Ctx ctx) {
   const uint32_t c = tcarry[blk];
   ex = c > ex ? c : ex;
 #pragma unroll
-  for (int j = 0; j < 16; ++j)
-    if (base + j < len) start[base + j] = ex > v[j] ? ex : v[j];
+  for (int j = 0; j < 16; ++j) v[j] = ex > v[j] ? ex : v[j];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t b = base + 4 * q;
+    if (b + 4 <= len) {
+      *reinterpret_cast<uint4 *>(start + b) =
+          make_uint4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (b + j < len) start[b + j] = v[4 * q + j];
+    }
+  }
 }
 
 }  // namespace
@@ -171,7 +197,7 @@ hipError_t launch_rindex(const Target &t, hipStream_t st) {
   return dispatch(t, [&](const auto &l) {
     k_rindex_prep<<<l.grid(kShOne), 1, 0, st>>>(l.ctx(kShOne));
     k_rindex_clear<<<l.grid(kShRxClear), NT, 0, st>>>(l.ctx(kShRxClear));
-    k_rindex_ends<<<l.grid(kShStar), NT, 0, st>>>(l.ctx(kShStar));
+    k_rindex_ends<<<l.grid(kShDiag), NT, 0, st>>>(l.ctx(kShDiag));
     k_rindex_tilemax<<<l.grid(kShRxTile), NT, 0, st>>>(l.ctx(kShRxTile));
     k_rindex_tilescan<<<l.grid(kShOne), NT, 0, st>>>(l.ctx(kShOne));
     k_rindex_apply<<<l.grid(kShRxTile), NT, 0, st>>>(l.ctx(kShRxTile));
