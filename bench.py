@@ -178,6 +178,9 @@ def main() -> int:
                    "gamma": wl["gamma"], "seed": wl["seed"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": dom_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS, "traffic": traffic,
+                     # the measured HBM bytes per launch over the same mean duration
+                     "traffic_GBs": (traffic / (unit_ms[dom] * 1e-3) / 1e9
+                                     if traffic is not None else None),
                      "alg_bytes_per_star": ab[dom],
                      "launch_ms": unit_ms[dom], "stars_per_launch": n_mean},
         "step_roofline": {"alg_bytes_per_star": step_bytes,
