@@ -272,7 +272,7 @@ constexpr int kBucketTile = 16384;      // stars per histogram and scatter tile
 constexpr int kBucketSortCap = 4096;    // stars a bucket sorts in LDS
 constexpr uint32_t kBucketEsc = 0xFFFFFFFFu;  // bkey of a star that leaves the cluster
 constexpr int kKingTab = 3 * kKingNodes + 8;
-constexpr int kPhiBins = 2048;  // bins of the potential-bound table (orbit.hip)
+constexpr int kPhiBins = 16384;  // bins of the potential-bound table (orbit.hip)
 
 struct Workspace {
   RPhi *lev[kMaxLevels];    // level L: [ceil(cap / 8^L)]

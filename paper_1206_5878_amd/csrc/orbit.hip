@@ -615,10 +615,10 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap) {
   }
 }
 
-// One block per cluster: the potential at the bound table's edges (after the
-// radial index is built).
+// The potential at the bound table's edges (after the radial index is built),
+// grid-stride over the edges.
 template <class Ctx>
-__global__ __launch_bounds__(1024) void k_phi_bounds(Ctx ctx) {
+__global__ __launch_bounds__(NT) void k_phi_bounds(Ctx ctx) {
   const ClusterArgs &A = ctx.args();
   const RIndex ix{A.s.r, A.w.rx_start, A.w.rx_ctl};
   const RIndexCtl ictl = *ix.ctl;
@@ -626,13 +626,13 @@ __global__ __launch_bounds__(1024) void k_phi_bounds(Ctx ctx) {
   const Levels lv = levels_of(A.w);
   uint32_t shift = 0;
   while (((ictl.hi - ictl.lo) >> shift) >= static_cast<uint64_t>(kPhiBins)) ++shift;
-  for (int j = threadIdx.x; j <= kPhiBins; j += 1024) {
+  for (int64_t j = ctx.block() * NT + threadIdx.x; j <= kPhiBins; j += ctx.nblocks() * NT) {
     uint64_t bits = ictl.lo + (static_cast<uint64_t>(j) << shift);
     bits = bits < 0x7FF0000000000000ull ? bits : 0x7FF0000000000000ull;
     const double x = __builtin_bit_cast(double, bits);
     A.w.phib[j] = phi_in(lv, A.w.ms, rindex_last_le(ix, ictl, x), x);
   }
-  if (threadIdx.x == 0) {
+  if (ctx.block() == 0 && threadIdx.x == 0) {
     A.w.phib_ctl[0] = ictl.lo;
     A.w.phib_ctl[1] = shift;
   }
@@ -685,7 +685,7 @@ hipError_t run2(const L &l, const cmc_params &p, hipStream_t st) {
   const double bf = p.bound_factor > 0.0 ? p.bound_factor : 1.2;
   using Cb = decltype(l.ctx(kShBracket));
   using Ct = decltype(l.ctx(kShTrials));
-  k_phi_bounds<<<l.grid(kShOne), 1024, 0, st>>>(l.ctx(kShOne));
+  k_phi_bounds<<<l.grid(kShDiag), NT, 0, st>>>(l.ctx(kShDiag));
   k_orbit_bracket<Cb, MT, TO_STAGE>
       <<<l.grid(kShBracket), BT, sizeof(RPhi) * l.top_entries(), st>>>(l.ctx(kShBracket), p.step,
                                                                        bf);

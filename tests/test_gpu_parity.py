@@ -379,6 +379,21 @@ def test_step_sort_crowded_buckets(cmc, ora, case):
     _same_step(cl, new, info)
 
 
+def test_step_all_escape_then_empty(cmc, ora):
+    """Every star unbound: the step's sort drops them all (all in the escaper
+    bin) and N becomes 0; a step on the empty cluster is a no-op."""
+    st = ora.plummer(5000, 8)
+    st.vr[:] = 5.0
+    cl, new, info = _step_once(cmc, ora, st, 4, 0, 0.11)
+    s = cl.scalars()
+    assert new.n == 0 and s["n"] == 0
+    assert s["n_esc"] == 5000
+    assert s["status"] & cmc.ST_ESCAPER
+    cmc.cmc_step(cl, cmc.Params(seed=4, step=1, gamma=0.11))
+    s = cl.scalars()
+    assert s["n"] == 0 and s["n_esc"] == 0 and s["trials"] == 0
+
+
 def test_step_radix_sort_for_large_capacity(cmc, ora):
     """Capacities above CMC_BUCKET_CAP_MAX take the radix sort in the step.
     (The potential's scan splits its tiles by capacity, so the last bits of
