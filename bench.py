@@ -187,11 +187,16 @@ def main() -> int:
                           "achieved_GBs": value * step_bytes / 1e9,
                           "frac": value * step_bytes / 1e9 / HBM_PEAK_GBS},
         "phases_ms": phase_ms,
+        "timing": "hipGraph replays of one captured step; 'calls' times the same number of "
+                  "plain cmc_step_timed calls first, which also give the per-phase split",
+        "gpu_ms_per_step": run["gpu_ms_per_step"],
+        "calls": run["calls"],
         "final": run["final"],
     }
     if run_o is not None:
         out["other_precision"] = {"precision": other, "value": run_o["value"],
                                   "ms_per_step": run_o["ms_per_step"],
+                                  "calls": run_o["calls"],
                                   "phases_ms": run_o["phases_ms"], "final": run_o["final"]}
     if not args.no_cpu_baseline:
         print("# timing the oracle on the host", file=sys.stderr, flush=True)
@@ -304,8 +309,9 @@ def setup(P, wl, prec, warmup):
 
 
 def timed_run(P, EventSet, wl, precision, K, warmup) -> dict:
-    """K whole steps after the warm-up, with inputs resident in HBM; per-phase
-    times from HIP events on the library's stream."""
+    """K whole steps after the warm-up as plain calls, with inputs resident in
+    HBM and per-phase times from HIP events on the library's stream; then K
+    more as replays of one captured step (the headline rate)."""
     import torch
     prec = P.CMC_FP64 if precision == "fp64" else P.CMC_MIXED
     cl, params = setup(P, wl, prec, warmup)
@@ -330,8 +336,31 @@ def timed_run(P, EventSet, wl, precision, K, warmup) -> dict:
         e.close()
     sc = cl.scalars()
     n_mean = updates / K
-    print(f"# {precision}: {el / K * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
-    return {"value": updates / el, "ms_per_step": el / K * 1e3, "n_mean": n_mean,
+    print(f"# {precision}: {el / K * 1e3:.3f} ms/step (calls)", file=sys.stderr, flush=True)
+    # The same cluster continues with K replays of one captured step (the step
+    # index comes from the device counter, set to carry on from the calls).
+    cl.set_scalar("step", warmup + K)
+    g = cl.capture(params)
+    g.replay()  # steps warmup + K: not timed
+    glog = torch.zeros(K + 1, dtype=torch.int64, device="cuda")
+    glog[0].copy_(cl.sc[0])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for k in range(K):
+        g.replay()
+        glog[k + 1].copy_(cl.sc[0])
+    e1.record()
+    torch.cuda.synchronize()
+    gel = time.perf_counter() - t0
+    gupdates = float(sum(glog.cpu().tolist()[:K]))
+    print(f"# {precision}: {gel / K * 1e3:.3f} ms/step (graph replays)", file=sys.stderr,
+          flush=True)
+    return {"value": gupdates / gel, "ms_per_step": gel / K * 1e3,
+            "gpu_ms_per_step": e0.elapsed_time(e1) / K,
+            "calls": {"value": updates / el, "ms_per_step": el / K * 1e3},
+            "n_mean": n_mean,
             "phases_ms": {ph: v / K for ph, v in phase_ms.items()},
             "final": {"n": sc["n"], "dt": sc["dt"], "status": sc["status"],
                       "trials_per_star": sc["trials"] / max(n_mean, 1),

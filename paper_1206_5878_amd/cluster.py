@@ -99,6 +99,19 @@ class Cluster:
         self.id[:n] = torch.as_tensor(np.asarray(id_, np.uint32).view(np.int32), device=dev)
         self.set_scalar("n", n)
 
+    def capture(self, p: Params) -> torch.cuda.CUDAGraph:
+        """A graph of one cmc_step that takes its step index from the device
+        counter and advances it (CMC_STEP_DEVICE): replay it once per step."""
+        q = Params(**{**p.__dict__, "step": A.CMC_STEP_DEVICE})
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                cmc_step(self, q, stream=s)
+        torch.cuda.current_stream().wait_stream(s)
+        return g
+
     def host(self, n: int | None = None) -> dict:
         """Copy the first n (default: active) entries of every array to numpy."""
         n = self.n if n is None else n

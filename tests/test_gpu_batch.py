@@ -172,6 +172,33 @@ def test_batch_graph_replay(cmc):
         assert b.scalars()["step"] == 3
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_single_graph_replay(cmc, precision):
+    """One captured single-cluster step replayed three times, with eager work
+    in between, equals three eager steps with indices 0, 1, 2 bit for bit."""
+    import torch
+    n = 30_000
+    eager = cmc.Cluster(n, m_f32=True)
+    cmc.cmc_init_model(eager, n, 9, cmc.CMC_MODEL_PLUMMER, 1, 0.0)
+    for k in range(3):
+        cmc.cmc_step(eager, cmc.Params(seed=9, step=k, gamma=0.01, precision=precision))
+    graphed = cmc.Cluster(n, m_f32=True)
+    cmc.cmc_init_model(graphed, n, 9, cmc.CMC_MODEL_PLUMMER, 1, 0.0)
+    torch.cuda.synchronize()
+    g = graphed.capture(cmc.Params(seed=9, gamma=0.01, precision=precision))
+    for k in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        _ = cmc.cmc_diagnostics(graphed)  # eager work between replays
+    ha, hb = eager.host(), graphed.host()
+    for key in ("r", "vr", "vt", "m", "id"):
+        assert np.array_equal(ha[key], hb[key]), key
+    sa, sb = eager.scalars(), graphed.scalars()
+    for key in ("n", "dt", "trials", "violations"):
+        assert sa[key] == sb[key], key
+    assert sb["step"] == 3
+
+
 def test_batch_diagnostics(cmc, ora):
     ens = cmc.Ensemble(SPECS[:4])
     ens.init()
