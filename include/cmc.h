@@ -56,9 +56,9 @@ extern "C" {
 #define CMC_FP64 0  /* every step in double precision                          */
 #define CMC_MIXED 1 /* fp32 pair terms, kicks and rejection trials (23-bit
                        uniforms); fp32 m/r in the potential with fp64 sums;
-                       fp64 table, turning points and Q.  Results differ from CMC_FP64 at ~1e-7 relative,
-                       and an accept/reject decision within that of its
-                       threshold may flip.                                      */
+                       fp64 table, turning points and Q.  Results differ
+                       from CMC_FP64 at ~1e-7 relative, and an accept/reject
+                       decision within that of its threshold may flip.          */
 
 /* Initial models of cmc_init_model (and of the ensemble) */
 #define CMC_MODEL_PLUMMER 0 /* Plummer sphere (Sec. 2.1 opening paragraph)      */
@@ -66,7 +66,7 @@ extern "C" {
 
 /* Device-resident scalars of one cluster (128 bytes, caller-owned). */
 typedef struct cmc_scalars {
-  int64_t n;          /* active star count (set by cmc_init_* / cmc_sort)       */
+  int64_t n;          /* active star count (cmc_init_*, cmc_sort, cmc_step)     */
   double dt;          /* timestep: solved by cmc_timestep, read by cmc_relax    */
   uint32_t status;    /* sticky CMC_ST_* bits                                   */
   uint32_t dt_iters;  /* Newton iterations the last dt solve used               */
@@ -189,9 +189,9 @@ int cmc_relax(cmc_state *s, const cmc_params *p, void *stream);
 int cmc_orbit(cmc_state *s, const cmc_params *p, void *stream);
 
 /* One whole step: potential -> timestep -> relax -> orbit -> sort.  The
- * potential table is kept in the workspace; phi, mcum, ssuf of the state are
- * not written (call cmc_potential for them).  The sort's result is that of
- * cmc_sort; for cap <= CMC_BUCKET_CAP_MAX it starts from where the orbit
+ * potential table is kept in the workspace; phi, mcum, ssuf and r_new of the
+ * state are not written (call cmc_potential for them).  The sort's result is
+ * that of cmc_sort; for cap <= CMC_BUCKET_CAP_MAX it starts from where the orbit
  * pass found each new radius among the old ones (a counting sort on that
  * position, then each run of equal position sorted by radius), above it it is
  * cmc_sort's radix sort. */
