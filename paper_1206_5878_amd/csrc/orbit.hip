@@ -27,7 +27,8 @@
 // them, lanes work in groups of 8 so that every node is one coalesced load.
 // Brackets are unique, so this finds the index a bisection over the whole
 // table finds.  The interval of a trial radius comes from the radial bucket
-// index (rindex.hip).
+// index (rindex.hip); a trial that the potential-bound table proves rejected
+// skips that lookup (see surely_rejected).
 #include <algorithm>
 #include <type_traits>
 
