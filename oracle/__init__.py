@@ -270,7 +270,7 @@ def step(st: State, seed: int, step_idx: int, gamma: float, target: float = 0.03
 def diagnostics(st: State, phi=None, mcum=None) -> dict:
     if phi is None:
         phi, mcum, _ = potential(st.r, st.m)
-    out = np.empty(9)
+    out = np.empty(11)
     lib().ora_diagnostics(st.n, st.r, st.vr, st.vt, st.m, _f64(phi), _f64(mcum), out)
     return dict(T=out[0], W=out[1], E=out[2], virial=out[3], M=out[4],
-                r01=out[5], r10=out[6], r50=out[7], r90=out[8])
+                r01=out[5], r10=out[6], r50=out[7], r90=out[8], rc=out[9], rho_c=out[10])

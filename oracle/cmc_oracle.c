@@ -869,4 +869,30 @@ void ora_diagnostics(int64_t n, const double *r, const double *vr, const double 
     }
     out[5 + f] = x;
   }
+  /* Core (the paper's core-collapse runs, after Casertano & Hut 1985): the
+   * density around star i from its radial neighbours -- the 7 consecutive
+   * stars a..a+6 that hold i near their middle, the mass of the 5 strictly
+   * inside over the shell volume between r_a and r_(a+6) -- then the core
+   * density sum rho_i^2 / sum rho_i and the density-weighted radius
+   * sum rho_i r_i / sum rho_i.  A window of zero volume is left out. */
+  ksum S1 = {0.0, 0.0}, S2 = {0.0, 0.0}, SR = {0.0, 0.0};
+  int64_t used = 0;
+  for (int64_t i = 0; n >= 7 && i < n; ++i) {
+    int64_t a = i - 3;
+    if (a < 0) a = 0;
+    if (a > n - 7) a = n - 7;
+    const double lo = r[a], hi = r[a + 6];
+    const double vol = (4.0 * PI / 3.0) * (hi - lo) * (hi * hi + hi * lo + lo * lo);
+    if (!(vol > 0.0)) continue;
+    double inner = 0.0;
+    for (int64_t k = a + 1; k <= a + 5; ++k) inner += m[k];
+    const double rho = inner / vol;
+    kadd(&S1, rho);
+    kadd(&S2, rho * rho);
+    kadd(&SR, rho * r[i]);
+    ++used;
+  }
+  const double s1 = kval(&S1);
+  out[9] = (used > 0 && s1 > 0.0) ? kval(&SR) / s1 : NAN;
+  out[10] = (used > 0 && s1 > 0.0) ? kval(&S2) / s1 : NAN;
 }

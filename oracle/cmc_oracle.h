@@ -148,8 +148,9 @@ void ora_step(int64_t n, double *r, double *vr, double *vt, double *m, uint32_t 
 
 /* ---- diagnostics ------------------------------------------------------------ */
 /* out[0]=T, out[1]=W, out[2]=E=T+W, out[3]=2T/|W|, out[4]=M, out[5..8]=
- * Lagrange radii for 1%, 10%, 50%, 90% of the mass.  Needs phi/mcum of the
- * same state. */
+ * Lagrange radii for 1%, 10%, 50%, 90% of the mass, out[9] = density-weighted
+ * core radius r_c, out[10] = core density rho_c (NaN when n < 7).  Needs
+ * phi/mcum of the same state. */
 void ora_diagnostics(int64_t n, const double *r, const double *vr, const double *vt,
                      const double *m, const double *phi, const double *mcum, double *out);
 

@@ -568,3 +568,65 @@ def test_king_sample(ora):
     Wr = np.interp(st.r / s, r, W)
     vmod = np.hypot(st.vr, st.vt) * np.sqrt(Mt * s)
     assert np.all(vmod <= np.sqrt(2 * Wr) * (1 + 1e-9) + 1e-12)
+
+
+# ---------------------------------------------------------------- core diagnostics
+# The density estimator of the core diagnostics takes the 5 stars strictly
+# inside a window of 7 consecutive radii over the shell volume between the
+# window's ends.  For a locally uniform (Poisson) population that volume is
+# Gamma(6) distributed in units of 1/(number density), so E[rho_i] = rho and
+# E[rho_i^2] = 25/20 rho^2: the core density sum rho_i^2 / sum rho_i is 1.25
+# times the mass-weighted mean density, and the density-weighted radius
+# sum rho_i r_i / sum rho_i is the mass-weighted mean of r weighted by rho.
+
+def _core_state(ora, r, m):
+    order = np.argsort(r, kind="stable")
+    r = np.ascontiguousarray(r[order])
+    n = r.size
+    z = np.zeros(n)
+    return ora.State(r, z.copy(), z.copy(), np.ascontiguousarray(m[order]),
+                     np.arange(n, dtype=np.uint32))
+
+
+def test_core_uniform_sphere(ora):
+    rng = np.random.default_rng(21)
+    n, R = 200_000, 2.0
+    r = R * rng.random(n) ** (1.0 / 3.0)
+    st = _core_state(ora, r, np.full(n, 1.0 / n))
+    d = ora.diagnostics(st)
+    rho0 = 1.0 / (4.0 * np.pi / 3.0 * R**3)
+    assert d["rho_c"] / rho0 == pytest.approx(1.25, rel=0.02)
+    assert d["rc"] == pytest.approx(0.75 * R, rel=0.01)
+
+
+def test_core_plummer_closed_form(ora):
+    from scipy.special import beta
+    st = ora.plummer(200_000, 5)
+    d = ora.diagnostics(st)
+    a = 3.0 * np.pi / 16.0  # Henon-unit Plummer scale
+    rho0 = 3.0 / (4.0 * np.pi * a**3)
+    # int rho^3 dV / int rho^2 dV and int rho^2 r dV / int rho^2 dV for
+    # rho = rho0 (1 + x^2)^(-5/2), x = r/a, through Beta functions
+    mean_rho = rho0 * beta(1.5, 6.0) / beta(1.5, 3.5)
+    mean_r = a * beta(2.0, 3.0) / beta(1.5, 3.5)
+    assert d["rho_c"] == pytest.approx(1.25 * mean_rho, rel=0.02)
+    assert d["rc"] == pytest.approx(mean_r, rel=0.01)
+
+
+def test_core_scaling(ora):
+    """Masses x c scale rho_c by c; radii x s scale rho_c by s^-3 and r_c by s."""
+    st = ora.plummer(20_000, 6)
+    d = ora.diagnostics(st)
+    st2 = _core_state(ora, st.r * 3.0, st.m * 0.5)
+    d2 = ora.diagnostics(st2)
+    assert d2["rho_c"] == pytest.approx(d["rho_c"] * 0.5 / 27.0, rel=1e-12)
+    assert d2["rc"] == pytest.approx(d["rc"] * 3.0, rel=1e-12)
+
+
+def test_core_degenerate(ora):
+    st = _core_state(ora, np.array([0.1, 0.2, 0.3, 0.4, 0.5, 0.6]), np.full(6, 1 / 6))
+    d = ora.diagnostics(st)
+    assert np.isnan(d["rc"]) and np.isnan(d["rho_c"])  # fewer than 7 stars
+    st = _core_state(ora, np.full(50, 0.7), np.full(50, 0.02))
+    d = ora.diagnostics(st)
+    assert np.isnan(d["rc"]) and np.isnan(d["rho_c"])  # every window has zero volume
