@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define CMC_ABI_VERSION 1
+#define CMC_ABI_VERSION 2
 
 /* ---- return codes --------------------------------------------------------- */
 #define CMC_OK 0
@@ -204,8 +204,15 @@ int cmc_step(cmc_state *s, const cmc_params *p, void *stream);
 int cmc_step_timed(cmc_state *s, const cmc_params *p, void *const *events, void *stream);
 
 /* Diagnostics of the sorted state and its table (needs cmc_potential):
- * out_dev[0..8] = T, W = sum m phi / 2, E = T + W, 2T/|W|, M, and the radii
- * holding 1%, 10%, 50%, 90% of the mass. */
+ * out_dev[0..CMC_DIAG_N-1] = T, W = sum m phi / 2, E = T + W, 2T/|W|, M, the
+ * radii holding 1%, 10%, 50%, 90% of the mass, and the core of the paper's
+ * core-collapse runs (Sec. 4, after Casertano & Hut 1985): with rho_i the
+ * mass of the 5 stars strictly inside the window of 7 consecutive radii
+ * a..a+6, a = clamp(i-3, 0, n-7), over the shell volume between r_a and
+ * r_(a+6) (windows of zero volume left out), out_dev[9] = the density-weighted
+ * core radius sum rho_i r_i / sum rho_i and out_dev[10] = the core density
+ * sum rho_i^2 / sum rho_i; both NaN when n < 7. */
+#define CMC_DIAG_N 11
 int cmc_diagnostics(const cmc_state *s, double *out_dev, void *stream);
 
 /* Raw Philox4x32-10 blocks: out_dev[4i..4i+3] = Philox(key, ctr_dev[4i..4i+3])
@@ -272,7 +279,8 @@ int cmc_batch_step(const cmc_batch *b, const cmc_params *p, void *stream);
 /* cmc_potential of every cluster (public phi, mcum, ssuf). */
 int cmc_batch_potential(const cmc_batch *b, int32_t precision, void *stream);
 
-/* cmc_diagnostics of every cluster: out_dev[9c .. 9c+8] for cluster c. */
+/* cmc_diagnostics of every cluster: out_dev[CMC_DIAG_N c .. CMC_DIAG_N c +
+ * CMC_DIAG_N - 1] for cluster c. */
 int cmc_batch_diagnostics(const cmc_batch *b, double *out_dev, void *stream);
 
 /* Text for a CMC_E* code. */

@@ -17,6 +17,7 @@ CMC_FP64, CMC_MIXED = 0, 1
 CMC_MODEL_PLUMMER, CMC_MODEL_KING = 0, 1
 CMC_STEP_DEVICE = 0xFFFFFFFF
 CMC_BUCKET_CAP_MAX = 16383 * 2048 - 1
+CMC_DIAG_N = 11
 ST_NONFINITE, ST_TRIAL_CAP, ST_BOUND, ST_ESCAPER = 0x01, 0x02, 0x04, 0x08
 ST_DT_DEGEN, ST_NUMERIC, ST_DT_NOCONV = 0x10, 0x20, 0x40
 

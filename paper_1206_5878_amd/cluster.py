@@ -167,12 +167,10 @@ def cmc_step(cl: Cluster, p: Params, stream=None):
 
 
 def cmc_diagnostics(cl: Cluster, stream=None) -> dict:
-    out = torch.zeros(9, dtype=torch.float64, device=cl.r.device)
+    out = torch.zeros(A.CMC_DIAG_N, dtype=torch.float64, device=cl.r.device)
     A.check(A.lib().cmc_diagnostics(cl.c, C.c_void_p(out.data_ptr()), _stream(stream)),
             "cmc_diagnostics")
-    v = out.cpu().numpy()
-    return dict(T=v[0], W=v[1], E=v[2], virial=v[3], M=v[4], r01=v[5], r10=v[6], r50=v[7],
-                r90=v[8])
+    return dict(zip(_DIAG_KEYS, out.cpu().numpy()))
 
 
 def cmc_philox(key: int, ctr: np.ndarray, device: str = "cuda", stream=None) -> np.ndarray:
@@ -194,7 +192,7 @@ def cmc_step_timed(cl: Cluster, p: Params, events, stream=None):
 
 
 # ---------------------------------------------------------------- ensembles
-_DIAG_KEYS = ("T", "W", "E", "virial", "M", "r01", "r10", "r50", "r90")
+_DIAG_KEYS = ("T", "W", "E", "virial", "M", "r01", "r10", "r50", "r90", "rc", "rho_c")
 
 
 class Ensemble:
@@ -240,10 +238,11 @@ class Ensemble:
                 "cmc_batch_potential")
 
     def diagnostics(self, stream=None) -> list:
-        out = torch.zeros(9 * len(self), dtype=torch.float64, device=self.dev.device)
+        out = torch.zeros(A.CMC_DIAG_N * len(self), dtype=torch.float64,
+                          device=self.dev.device)
         A.check(A.lib().cmc_batch_diagnostics(C.byref(self.handle), C.c_void_p(out.data_ptr()),
                                               _stream(stream)), "cmc_batch_diagnostics")
-        v = out.cpu().numpy().reshape(-1, 9)
+        v = out.cpu().numpy().reshape(-1, A.CMC_DIAG_N)
         return [dict(zip(_DIAG_KEYS, row)) for row in v]
 
     def capture(self, p: Params) -> torch.cuda.CUDAGraph:

@@ -1,13 +1,19 @@
 // diag.hip -- diagnostics of a sorted state (arXiv:1206.5878, Sec. 2.1 step 6
-// diagnostics; energy check of Sec. 4): T = sum m v^2 / 2, W = sum m Phi / 2,
-// E = T + W, virial ratio 2T/|W|, total mass and the radii enclosing 1%, 10%,
-// 50% and 90% of it.  Raw Philox blocks for inspection live here too.
+// diagnostics; energy check and core-collapse runs of Sec. 4): T = sum m v^2 /
+// 2, W = sum m Phi / 2, E = T + W, virial ratio 2T/|W|, total mass, the radii
+// enclosing 1%, 10%, 50% and 90% of it, and the core: the density around each
+// star from its radial neighbours (the 5 stars strictly inside a window of 7
+// consecutive radii over the shell volume between its ends, after Casertano &
+// Hut's 6th-order estimator), the core density sum rho^2 / sum rho and the
+// density-weighted core radius sum rho r / sum rho.  Raw Philox blocks for
+// inspection live here too.
 #include "cmc_internal.hpp"
 
 namespace cmc {
 namespace {
 
 constexpr int NT = kBlock;
+constexpr int kDiagSums = 6;  // block partials of the diagnostics kernel
 
 template <class Ctx, typename MT>
 __global__ __launch_bounds__(NT) void k_diag(Ctx ctx) {
@@ -17,23 +23,41 @@ __global__ __launch_bounds__(NT) void k_diag(Ctx ctx) {
   const double *__restrict__ vt = A.s.vt;
   const MT *__restrict__ m = static_cast<const MT *>(A.s.m);
   const double *__restrict__ phi = A.s.phi;
+  const double *__restrict__ r = A.s.r;
   const int64_t n = A.s.sc->n;
   const int64_t blk = ctx.block();
-  double t = 0.0, wv = 0.0;
+  // T, W, sum rho, sum rho^2, sum rho r, windows used
+  double v[kDiagSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int64_t i = blk * NT + threadIdx.x; i < n; i += ctx.nblocks() * NT) {
     const double mi = load_mass(m, i);
-    t += 0.5 * mi * (vr[i] * vr[i] + vt[i] * vt[i]);
-    wv += 0.5 * mi * phi[i];
+    v[0] += 0.5 * mi * (vr[i] * vr[i] + vt[i] * vt[i]);
+    v[1] += 0.5 * mi * phi[i];
+    if (n >= 7) {
+      int64_t a = i - 3;
+      a = a < 0 ? 0 : (a > n - 7 ? n - 7 : a);
+      const double lo = r[a], hi = r[a + 6];
+      const double vol = (4.0 * kPi / 3.0) * (hi - lo) * (hi * hi + hi * lo + lo * lo);
+      if (vol > 0.0) {
+        double inner = 0.0;
+#pragma unroll
+        for (int q = 1; q <= 5; ++q) inner += load_mass(m, a + q);
+        const double rho = inner / vol;
+        v[2] += rho;
+        v[3] += rho * rho;
+        v[4] += rho * r[i];
+        v[5] += 1.0;
+      }
+    }
   }
-  t = block_sum<NT>(t, sh);
-  wv = block_sum<NT>(wv, sh);
-  if (threadIdx.x == 0) {
-    A.w.red_part[2 * blk] = t;
-    A.w.red_part[2 * blk + 1] = wv;
-  }
+#pragma unroll
+  for (int q = 0; q < kDiagSums; ++q) v[q] = block_sum<NT>(v[q], sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < kDiagSums; ++q) A.w.red_part[kDiagSums * blk + q] = v[q];
 }
 
-// One block per cluster; cluster c writes out[9 c .. 9 c + 8].
+// One block per cluster; cluster c writes out[CMC_DIAG_N c .. CMC_DIAG_N c +
+// CMC_DIAG_N - 1].
 template <class Ctx>
 __global__ __launch_bounds__(NT) void k_diag_final(Ctx ctx, double *__restrict__ out_all) {
   __shared__ double sh[NT / 64];
@@ -42,15 +66,18 @@ __global__ __launch_bounds__(NT) void k_diag_final(Ctx ctx, double *__restrict__
   const int64_t nblocks = blocks_of(kShDiag, A.w, A.s.cap);
   const double *__restrict__ r = A.s.r;
   const double *__restrict__ mcum = A.s.mcum;
-  double *__restrict__ out = out_all + 9 * ctx.index();
-  double T = 0.0, W = 0.0;
-  for (int64_t b = threadIdx.x; b < nblocks; b += NT) {
-    T += part[2 * b];
-    W += part[2 * b + 1];
-  }
-  T = block_sum<NT>(T, sh);
-  W = block_sum<NT>(W, sh);
+  double *__restrict__ out = out_all + CMC_DIAG_N * ctx.index();
+  double v[kDiagSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t b = threadIdx.x; b < nblocks; b += NT)
+#pragma unroll
+    for (int q = 0; q < kDiagSums; ++q) v[q] += part[kDiagSums * b + q];
+#pragma unroll
+  for (int q = 0; q < kDiagSums; ++q) v[q] = block_sum<NT>(v[q], sh);
   if (threadIdx.x != 0) return;
+  const double T = v[0], W = v[1];
+  const bool core = v[5] > 0.0 && v[2] > 0.0;
+  out[9] = core ? v[4] / v[2] : __builtin_nan("");
+  out[10] = core ? v[3] / v[2] : __builtin_nan("");
   const int64_t n = A.s.sc->n;
   const double M = n > 0 ? mcum[n - 1] : 0.0;
   out[0] = T;

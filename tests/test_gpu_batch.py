@@ -206,5 +206,5 @@ def test_batch_diagnostics(cmc, ora):
     got = ens.diagnostics()
     for d, s in zip(got, SPECS[:4]):
         ref = ora.diagnostics(oracle_init(ora, s))
-        for key in ("T", "W", "E", "virial", "M"):
+        for key in ("T", "W", "E", "virial", "M", "rc", "rho_c"):
             assert rel(d[key], ref[key]) < 1e-11, key

@@ -408,13 +408,40 @@ def test_step_radix_sort_for_large_capacity(cmc, ora):
     del big
 
 
+@pytest.mark.parametrize("case", ["f32_masses", "ties", "tiny"])
+def test_diagnostics_core(cmc, ora, case):
+    """The core density and radius against the oracle: f32 masses (mass
+    spectrum), windows of zero volume (tied radii), and fewer than 7 stars."""
+    if case == "f32_masses":
+        st = ora.plummer(50_001, 3, 1)
+        st.m = st.m.astype(np.float32).astype(np.float64)
+        cl = upload(cmc, st, m_f32=True)
+    elif case == "ties":  # runs of 10 equal radii: some windows have zero volume
+        rng = np.random.default_rng(4)
+        r = np.sort(np.concatenate([np.repeat(rng.lognormal(0, 1, 300), 10),
+                                    rng.lognormal(0, 1, 17_003)]))
+        st = _radii_state(ora, r, 5)
+        cl = upload(cmc, st)
+    else:
+        st = ora.plummer(6, 1)
+        cl = upload(cmc, st)
+    cmc.cmc_potential(cl)
+    d = cmc.cmc_diagnostics(cl)
+    ref = ora.diagnostics(st)
+    for k in ("rc", "rho_c"):
+        if np.isnan(ref[k]):
+            assert np.isnan(d[k]), k
+        else:
+            assert rel(d[k], ref[k]) < TOL, k
+
+
 def test_diagnostics(cmc, ora):
     st = ora.plummer(30_000, 2)
     cl = upload(cmc, st)
     cmc.cmc_potential(cl)
     d = cmc.cmc_diagnostics(cl)
     ref = ora.diagnostics(st)
-    for k in ("T", "W", "E", "virial", "M"):
+    for k in ("T", "W", "E", "virial", "M", "rc", "rho_c"):
         assert rel(d[k], ref[k]) < TOL, k
     # Lagrange radius: the first star whose enclosed mass reaches f M.  With
     # equal masses M_k can equal f M exactly, so the index is checked against
