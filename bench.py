@@ -35,6 +35,10 @@ WORKLOADS = {
     # Plummer and odd ones King W0 = 6, advanced together by one captured graph
     "ensemble_64_plummer_king_w6": dict(clusters=64, seed=1, gamma=0.11, w0=6.0, m_f32=False,
                                         precision="mixed"),
+    # the paper's validation runs (Sec. 4): equal-mass Plummer spheres of 1e5,
+    # 1e6 and 1e7 stars evolved to core collapse; --steps / --warmup unused
+    "core_collapse_plummer_n1e5_1e6_1e7": dict(core_collapse=(100_000, 1_000_000, 10_000_000),
+                                               seed=1, gamma=0.11, precision="mixed"),
 }
 DEFAULT_WORKLOAD = "plummer_n1e7_broken_power_law"
 
@@ -126,6 +130,8 @@ def main() -> int:
     K = args.steps
     if "clusters" in wl:
         return ensemble_bench(P, args, wl, precision)
+    if "core_collapse" in wl:
+        return core_collapse_bench(P, args, wl, precision)
     if args.plain:
         prec = P.CMC_FP64 if precision == "fp64" else P.CMC_MIXED
         cl, params = setup(P, wl, prec, args.warmup)
@@ -365,6 +371,44 @@ def timed_run(P, EventSet, wl, precision, K, warmup) -> dict:
             "final": {"n": sc["n"], "dt": sc["dt"], "status": sc["status"],
                       "trials_per_star": sc["trials"] / max(n_mean, 1),
                       "dt_iters": sc["dt_iters"]}}
+
+
+def core_collapse_bench(P, args, wl, precision) -> int:
+    """Wall-clock to core collapse (Sec. 4 validation runs), with the collapse
+    time in initial half-mass relaxation times next to the paper's."""
+    from paper_1206_5878_amd.evolve import core_collapse_run
+    prec = P.CMC_FP64 if precision == "fp64" else P.CMC_MIXED
+    runs = []
+    for n in wl["core_collapse"]:
+        res = core_collapse_run(n, wl["seed"], gamma=wl["gamma"], precision=prec)
+        res.pop("series")
+        runs.append(res)
+        cc = res["collapse"] or {}
+        print(f"# N={n}: t_cc = {cc.get('t_over_t_rh')} t_rh after {cc.get('steps')} steps, "
+              f"{cc.get('wall_s')} s", file=sys.stderr, flush=True)
+    big = runs[-1]["collapse"] or {}
+    out = {
+        "metric": "wall-clock seconds to core collapse of an equal-mass Plummer sphere",
+        "value": big.get("wall_s"),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": big.get("steps"),
+        "warmup": 0,
+        "ms_per_step": (big["wall_s"] / big["steps"] * 1e3) if big else None,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": list(wl["core_collapse"]),
+                   "precision": precision, "gamma": wl["gamma"], "seed": wl["seed"]},
+        "runs": runs,
+        "paper": {"t_cc_over_t_rh": [17.4, 16.7, 16.6],
+                  "wall": ["11.4 min, 128 processors", "1.17 h, 256 processors",
+                           "12.8 h, 1024 processors"]},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 def sources_sha256() -> str:
