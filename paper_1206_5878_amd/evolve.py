@@ -24,6 +24,22 @@ def half_mass_relaxation_time(n: int, r_h: float, gamma: float = 0.1) -> float:
     return 0.138 * n / math.log(gamma * n) * math.sqrt(r_h ** 3)
 
 
+def density_slope(r, m, r_lo: float, r_hi: float, bins: int = 12) -> float:
+    """Power-law index beta of rho ~ r^-beta between r_lo and r_hi: shell
+    densities (mass over volume) in log-spaced shells, fitted by least
+    squares in log-log."""
+    import numpy as np
+    edges = np.geomspace(r_lo, r_hi, bins + 1)
+    mass, _ = np.histogram(r, bins=edges, weights=m)
+    vol = 4.0 * np.pi / 3.0 * (edges[1:] ** 3 - edges[:-1] ** 3)
+    mid = np.sqrt(edges[1:] * edges[:-1])
+    ok = mass > 0
+    if ok.sum() < 3:
+        return float("nan")
+    slope = np.polyfit(np.log(mid[ok]), np.log(mass[ok] / vol[ok]), 1)[0]
+    return float(-slope)
+
+
 def core_collapse_run(n: int, seed: int = 1, *, gamma: float = 0.11,
                       precision: int = A.CMC_MIXED, t_end: float = 30.0, every: int = 10,
                       collapse: float = 1e4, stop: float = 1e6,
@@ -32,7 +48,9 @@ def core_collapse_run(n: int, seed: int = 1, *, gamma: float = 0.11,
 
     Every `every` steps the potential and diagnostics are taken: t / t_rh,
     r_c / r_h (r_h the current half-mass radius), rho_c, E, N.  The collapse
-    time t_cc is the first sample with rho_c >= collapse * rho_c(0): without
+    time t_cc is the first sample with rho_c >= collapse * rho_c(0), where the
+    density profile's power-law index between 10 r_c and r_h / 2 is also
+    taken (the host copies the state once; not counted in wall_s): without
     binaries nothing halts the collapse, and rho_c climbs by orders of
     magnitude within a small fraction of t_rh.  The run stops once rho_c >=
     stop * rho_c(0), at t = t_end t_rh or after max_steps steps."""
@@ -61,9 +79,15 @@ def core_collapse_run(n: int, seed: int = 1, *, gamma: float = 0.11,
         rows.append((t / trh, float(d["rc"] / d["r50"]), float(d["rho_c"]), float(d["E"]),
                      int(cl.n), steps))
         if cc is None and rows[-1][2] >= collapse * rho0:
-            cc = dict(t_over_t_rh=rows[-1][0], steps=steps, wall_s=time.perf_counter() - wall0,
+            wall = time.perf_counter() - wall0
+            h = cl.host()
+            rh = float(d["r50"])
+            cc = dict(t_over_t_rh=rows[-1][0], steps=steps, wall_s=wall,
                       rc_over_rh=rows[-1][1], rho_c=rows[-1][2],
-                      energy_drift=rows[-1][3] / rows[0][3] - 1.0, n=rows[-1][4])
+                      energy_drift=rows[-1][3] / rows[0][3] - 1.0, n=rows[-1][4],
+                      # outside the core, inside the half-mass radius
+                      density_slope=density_slope(h["r"], h["m"], 10.0 * float(d["rc"]),
+                                                  0.5 * rh))
         if rows[-1][2] >= stop * rho0:
             break
     torch.cuda.synchronize()

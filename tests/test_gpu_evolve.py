@@ -36,6 +36,9 @@ def test_core_collapse_n1e5(P):
     pre = rows[rows[:, 0] < cc["t_over_t_rh"]]
     q = np.array_split(pre[:, 2], 4)
     assert all(np.median(q[i + 1]) > np.median(q[i]) for i in range(3))
+    # the self-similar profile outside the core: rho ~ r^-beta with beta about
+    # 2.3 in the paper (2.23 in the literature it cites)
+    assert 2.1 <= cc["density_slope"] <= 2.5
     # the uncorrected step drifts in energy (the potential-change correction
     # is out of scope); bound it so that a broken step shows
     assert abs(cc["energy_drift"]) < 0.1
