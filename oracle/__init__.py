@@ -85,6 +85,10 @@ def lib():
                                 C.POINTER(OrbitStats)]
         L.ora_step.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _up, _dp, _dp,
                                C.POINTER(Params), C.POINTER(StepOut)]
+        L.ora_step_ex.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _up, _dp, _dp,
+                                  C.POINTER(Params), C.POINTER(StepOut), _vp]
+        L.ora_energy_correction.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.ora_energy_correction.restype = C.c_int64
         L.ora_diagnostics.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
         _lib = L
     return _lib
@@ -252,19 +256,38 @@ def orbit(st: State, table, seed: int, step: int, trial_cap: int = 10000,
 
 
 def step(st: State, seed: int, step_idx: int, gamma: float, target: float = 0.03,
-         dt_fixed: float = 0.0, trial_cap: int = 10000, bound_factor: float = 1.2):
-    """One whole step on a copy of ``st``.  Returns (new_state, info dict)."""
+         dt_fixed: float = 0.0, trial_cap: int = 10000, bound_factor: float = 1.2,
+         moves: bool = False):
+    """One whole step on a copy of ``st``.  Returns (new_state, info dict).
+    moves: also info["moves"], shape (n_after, 3): each new star's
+    (r_old, Phi_old(r_old), Phi_old(r_new)) for ``energy_correction``."""
     s = st.copy()
     phi = np.empty(max(s.n, 1)); mcum = np.empty(max(s.n, 1))
+    mv = np.empty(3 * max(s.n, 1)) if moves else None
     p = Params(seed, step_idx, gamma, target, dt_fixed, trial_cap, bound_factor)
     o = StepOut()
-    lib().ora_step(s.n, s.r, s.vr, s.vt, s.m, s.id, phi, mcum, C.byref(p), C.byref(o))
+    lib().ora_step_ex(s.n, s.r, s.vr, s.vt, s.m, s.id, phi, mcum, C.byref(p), C.byref(o),
+                      mv.ctypes.data if moves else None)
     k = o.n_after
     new = State(s.r[:k], s.vr[:k], s.vt[:k], s.m[:k], s.id[:k])
     info = dict(dt=o.dt, n_after=k, status=o.status,
                 orbit={f: getattr(o.orbit, f) for f, _ in OrbitStats._fields_},
                 phi=phi[:st.n], mcum=mcum[:st.n])
+    if moves:
+        info["moves"] = mv[:3 * k].reshape(k, 3).copy()
     return new, info
+
+
+def energy_correction(st: State, phi, moves) -> tuple:
+    """Sec. 2.1 item 6 on a copy of ``st`` (the state a step left, ``phi`` its
+    potential, ``moves`` that step's info["moves"]).  Returns (state, skipped)."""
+    out = st.copy()
+    mv = _f64(moves).reshape(-1)
+    if mv.shape[0] != 3 * out.n:
+        raise ValueError("moves must hold 3 values per star of the state")
+    k = lib().ora_energy_correction(out.n, out.r, out.m, out.vr, out.vt, _f64(phi),
+                                    mv if out.n else np.zeros(1))
+    return out, int(k)
 
 
 def diagnostics(st: State, phi=None, mcum=None) -> dict:

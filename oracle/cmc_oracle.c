@@ -783,6 +783,12 @@ void ora_orbit(int64_t n, const double *r, const double *phi, const double *mcum
 /* ------------------------------------------------------------------------- */
 void ora_step(int64_t n, double *r, double *vr, double *vt, double *m, uint32_t *id,
               double *phi, double *mcum, const ora_params *p, ora_step_out *out) {
+  ora_step_ex(n, r, vr, vt, m, id, phi, mcum, p, out, NULL);
+}
+
+void ora_step_ex(int64_t n, double *r, double *vr, double *vt, double *m, uint32_t *id,
+                 double *phi, double *mcum, const ora_params *p, ora_step_out *out,
+                 double *moves) {
   size_t nn = (size_t)(n > 0 ? n : 1);
   uint32_t status = 0;
   double *ssuf = (double *)malloc(nn * sizeof(double));
@@ -804,6 +810,15 @@ void ora_step(int64_t n, double *r, double *vr, double *vt, double *m, uint32_t 
             p->bound_factor, rn, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, &st);
   status |= st.status;
 
+  /* The old potential at each star's old and new radius (for the energy
+   * correction of the next potential). */
+  double *phi_rn = NULL;
+  if (moves) {
+    phi_rn = (double *)malloc(nn * sizeof(double));
+    for (int64_t i = 0; i < n; ++i)
+      phi_rn[i] = (rn[i] < INFINITY) ? ora_phi_at(n, r, phi, mcum, ssuf, rn[i]) : NAN;
+  }
+
   int64_t *perm = (int64_t *)malloc(nn * sizeof(int64_t));
   ora_sort_perm(n, rn, perm);
   double *t_r = (double *)malloc(nn * sizeof(double));
@@ -819,8 +834,16 @@ void ora_step(int64_t n, double *r, double *vr, double *vt, double *m, uint32_t 
     t_vt[q] = vt[o];
     t_m[q] = m[o];
     t_id[q] = id[o];
-    if (rn[o] < INFINITY) ++kept;
+    if (rn[o] < INFINITY) {
+      ++kept;
+      if (moves) {
+        moves[3 * q] = r[o];
+        moves[3 * q + 1] = phi[o];
+        moves[3 * q + 2] = phi_rn[o];
+      }
+    }
   }
+  free(phi_rn);
   memcpy(r, t_r, nn * sizeof(double));
   memcpy(vr, t_vr, nn * sizeof(double));
   memcpy(vt, t_vt, nn * sizeof(double));
@@ -841,6 +864,43 @@ void ora_step(int64_t n, double *r, double *vr, double *vt, double *m, uint32_t 
     out->orbit = st;
     out->status = status;
   }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Energy correction (Sec. 2.1 item 6).  A star's new orbit is drawn in the
+ * potential of the old positions, Phi_old; once every star has moved the
+ * potential is Phi_new.  Taking the potential to change linearly in time over
+ * the step, the work it does on a star that goes from r_old to r_new is the
+ * mean of the change dPhi = Phi_new - Phi_old at the two ends, so the star's
+ * energy in the new potential should be E_old + (dPhi(r_old) + dPhi(r_new))/2.
+ * As drawn it is E_old + dPhi(r_new) (its kinetic energy was fixed by
+ * Phi_old(r_new)), so the kinetic energy per unit mass changes by
+ *   dT = (dPhi(r_old) - dPhi(r_new)) / 2,
+ * applied by scaling vr and vt by one factor (vr/vt unchanged).  A star whose
+ * kinetic energy would not stay positive, or that has none to scale, keeps
+ * its velocities and is counted.  Phi_new(r_old) is the defining sum over the
+ * new state, -sum_j m_j / max(r_old, r_j); Phi_new(r_new) is phi. */
+int64_t ora_energy_correction(int64_t n, const double *r, const double *m, double *vr,
+                              double *vt, const double *phi, const double *moves) {
+  int64_t skipped = 0;
+  for (int64_t q = 0; q < n; ++q) {
+    const double r_old = moves[3 * q], phi_old_at_old = moves[3 * q + 1];
+    const double phi_old_at_new = moves[3 * q + 2];
+    ksum s = {0.0, 0.0};
+    for (int64_t j = 0; j < n; ++j) kadd(&s, m[j] / (r_old > r[j] ? r_old : r[j]));
+    const double phi_new_at_old = -kval(&s);
+    const double dT = 0.5 * ((phi_new_at_old - phi_old_at_old) - (phi[q] - phi_old_at_new));
+    if (dT == 0.0) continue;
+    const double v2 = vr[q] * vr[q] + vt[q] * vt[q];
+    if (!(v2 > 0.0) || !(v2 + 2.0 * dT > 0.0)) {
+      ++skipped;
+      continue;
+    }
+    const double f = sqrt(1.0 + 2.0 * dT / v2);
+    vr[q] *= f;
+    vt[q] *= f;
+  }
+  return skipped;
 }
 
 /* ------------------------------------------------------------------------- */

@@ -146,6 +146,23 @@ typedef struct {
 void ora_step(int64_t n, double *r, double *vr, double *vt, double *m, uint32_t *id,
               double *phi, double *mcum, const ora_params *p, ora_step_out *out);
 
+/* ora_step that also reports, for the star at each position q < n_after of
+ * the new state, moves[3q..3q+2] = (r_old, Phi_old(r_old), Phi_old(r_new)):
+ * its radius before the step and the old potential there and at its new
+ * radius.  moves may be NULL. */
+void ora_step_ex(int64_t n, double *r, double *vr, double *vt, double *m, uint32_t *id,
+                 double *phi, double *mcum, const ora_params *p, ora_step_out *out,
+                 double *moves);
+
+/* ---- energy correction (Sec. 2.1 item 6) ----------------------------------- */
+/* For the state a step produced (n stars, its potential phi) and that step's
+ * moves: dT = (dPhi(r_old) - dPhi(r_new)) / 2 per unit mass with
+ * dPhi = Phi_new - Phi_old, Phi_new(r_old) from the defining sum over the n
+ * stars; vr, vt scaled by sqrt(1 + 2 dT / v^2) in place.  Returns the number
+ * of stars left unchanged because v^2 + 2 dT <= 0 or v = 0 (with dT != 0). */
+int64_t ora_energy_correction(int64_t n, const double *r, const double *m, double *vr,
+                              double *vt, const double *phi, const double *moves);
+
 /* ---- diagnostics ------------------------------------------------------------ */
 /* out[0]=T, out[1]=W, out[2]=E=T+W, out[3]=2T/|W|, out[4]=M, out[5..8]=
  * Lagrange radii for 1%, 10%, 50%, 90% of the mass, out[9] = density-weighted
