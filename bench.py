@@ -90,6 +90,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-other", action="store_true",
                     help="skip the run of the other precision form")
+    ap.add_argument("--uncorrected", action="store_true",
+                    help="core-collapse workload: run without the energy correction")
     ap.add_argument("--plain", action="store_true",
                     help="time plain cmc_step calls only (no per-phase events); for profilers")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -150,7 +152,7 @@ def main() -> int:
               flush=True)
         return 0
 
-    run = timed_run(P, EventSet, wl, precision, K, args.warmup)
+    run = timed_run(P, EventSet, wl, precision, K, args.warmup, corr_too=True)
     other = "fp64" if precision == "mixed" else "mixed"
     run_o = None if args.no_other else timed_run(P, EventSet, wl, other, K, args.warmup)
 
@@ -197,6 +199,9 @@ def main() -> int:
                   "plain cmc_step_timed calls first, which also give the per-phase split",
         "gpu_ms_per_step": run["gpu_ms_per_step"],
         "calls": run["calls"],
+        # the same step with the potential-change energy correction (Sec. 2.1
+        # item 6), which the headline metric's step list leaves out
+        "with_energy_correction": run["with_energy_correction"],
         "final": run["final"],
     }
     if run_o is not None:
@@ -314,10 +319,11 @@ def setup(P, wl, prec, warmup):
     return cl, params
 
 
-def timed_run(P, EventSet, wl, precision, K, warmup) -> dict:
+def timed_run(P, EventSet, wl, precision, K, warmup, corr_too=False) -> dict:
     """K whole steps after the warm-up as plain calls, with inputs resident in
     HBM and per-phase times from HIP events on the library's stream; then K
-    more as replays of one captured step (the headline rate)."""
+    more as replays of one captured step (the headline rate); with corr_too,
+    K more replays of the step with the potential-change energy correction."""
     import torch
     prec = P.CMC_FP64 if precision == "fp64" else P.CMC_MIXED
     cl, params = setup(P, wl, prec, warmup)
@@ -363,7 +369,25 @@ def timed_run(P, EventSet, wl, precision, K, warmup) -> dict:
     gupdates = float(sum(glog.cpu().tolist()[:K]))
     print(f"# {precision}: {gel / K * 1e3:.3f} ms/step (graph replays)", file=sys.stderr,
           flush=True)
-    return {"value": gupdates / gel, "ms_per_step": gel / K * 1e3,
+    corr = None
+    if corr_too:
+        del g
+        q = P.Params(**{**params.__dict__, "energy_corr": 1})
+        gc = cl.capture(q)
+        gc.replay()  # leaves the first correction pending: not timed
+        glog[0].copy_(cl.sc[0])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(K):
+            gc.replay()
+            glog[k + 1].copy_(cl.sc[0])
+        torch.cuda.synchronize()
+        cel = time.perf_counter() - t0
+        corr = {"value": float(sum(glog.cpu().tolist()[:K])) / cel, "ms_per_step": cel / K * 1e3,
+                "corr_skipped_last": int(cl.scalars()["corr_skipped"])}
+        print(f"# {precision}: {cel / K * 1e3:.3f} ms/step (graph replays, energy correction)",
+              file=sys.stderr, flush=True)
+    return {"value": gupdates / gel, "ms_per_step": gel / K * 1e3, "with_energy_correction": corr,
             "gpu_ms_per_step": e0.elapsed_time(e1) / K,
             "calls": {"value": updates / el, "ms_per_step": el / K * 1e3},
             "n_mean": n_mean,
@@ -380,12 +404,14 @@ def core_collapse_bench(P, args, wl, precision) -> int:
     prec = P.CMC_FP64 if precision == "fp64" else P.CMC_MIXED
     runs = []
     for n in wl["core_collapse"]:
-        res = core_collapse_run(n, wl["seed"], gamma=wl["gamma"], precision=prec)
+        res = core_collapse_run(n, wl["seed"], gamma=wl["gamma"], precision=prec,
+                                energy_corr=not args.uncorrected)
         res.pop("series")
         runs.append(res)
         cc = res["collapse"] or {}
         print(f"# N={n}: t_cc = {cc.get('t_over_t_rh')} t_rh after {cc.get('steps')} steps, "
-              f"{cc.get('wall_s')} s", file=sys.stderr, flush=True)
+              f"{cc.get('wall_s')} s, energy drift {cc.get('energy_drift')}, budget "
+              f"{cc.get('energy_budget')}", file=sys.stderr, flush=True)
     big = runs[-1]["collapse"] or {}
     out = {
         "metric": "wall-clock seconds to core collapse of an equal-mass Plummer sphere",
@@ -401,7 +427,8 @@ def core_collapse_bench(P, args, wl, precision) -> int:
         "dtype": "f64" if precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": list(wl["core_collapse"]),
-                   "precision": precision, "gamma": wl["gamma"], "seed": wl["seed"]},
+                   "precision": precision, "gamma": wl["gamma"], "seed": wl["seed"],
+                   "energy_corr": not args.uncorrected},
         "runs": runs,
         "paper": {"t_cc_over_t_rh": [17.4, 16.7, 16.6],
                   "wall": ["11.4 min, 128 processors", "1.17 h, 256 processors",

@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define CMC_ABI_VERSION 2
+#define CMC_ABI_VERSION 3
 
 /* ---- return codes --------------------------------------------------------- */
 #define CMC_OK 0
@@ -77,7 +77,10 @@ typedef struct cmc_scalars {
   double e_esc;       /* sum of m E over the last orbit pass's escapers         */
   double mass_norm;   /* total raw mass drawn by cmc_init_*                     */
   int64_t step;       /* steps taken with cmc_params.step == CMC_STEP_DEVICE    */
-  int64_t reserved[6];
+  int64_t corr_n;     /* stars of the last step's orbit pass whose energy
+                         correction is pending (0: none; see cmc_energy_correction) */
+  int64_t corr_skipped; /* stars the last applied correction left unchanged     */
+  int64_t reserved[4];
 } cmc_scalars;
 
 /* One cluster.  Every array has `cap` entries of device memory.
@@ -123,6 +126,8 @@ typedef struct cmc_params {
   double bound_factor; /* rejection bound F = bound_factor * max endpoint g (1.2) */
   int32_t trial_cap;   /* rejection trials per star before giving up (10000)      */
   int32_t dt_iters;    /* Newton iterations enqueued for dt; 0 = default (10)     */
+  int32_t energy_corr; /* 1: potential-change energy correction (cmc_step)        */
+  int32_t reserved;
 } cmc_params;
 
 /* Bytes of scratch a state of capacity `cap` needs. */
@@ -190,7 +195,10 @@ int cmc_orbit(cmc_state *s, const cmc_params *p, void *stream);
 
 /* One whole step: potential -> timestep -> relax -> orbit -> sort.  The
  * potential table is kept in the workspace; phi, mcum, ssuf and r_new of the
- * state are not written (call cmc_potential for them).  The sort's result is
+ * state are not written (call cmc_potential for them).  With p->energy_corr
+ * = 1 the step first applies the correction pending from the step before
+ * (cmc_energy_correction, right after its potential) and leaves its own
+ * pending; with 0 it leaves none (and a pending one is dropped unapplied).  The sort's result is
  * that of cmc_sort; for cap <= CMC_BUCKET_CAP_MAX it starts from where the orbit
  * pass found each new radius among the old ones (a counting sort on that
  * position, then each run of equal position sorted by radius), above it it is
@@ -200,8 +208,27 @@ int cmc_step(cmc_state *s, const cmc_params *p, void *stream);
 
 /* cmc_step that also records events[0] on `stream` before the step and
  * events[1..5] after its potential, timestep, relax, orbit and sort phases,
- * for per-phase timing.  events: 6 hipEvent_t created by the caller. */
+ * for per-phase timing (with energy_corr, the correction and the radial
+ * index of the orbit pass count to the potential phase).  events: 6
+ * hipEvent_t created by the caller. */
 int cmc_step_timed(cmc_state *s, const cmc_params *p, void *const *events, void *stream);
+
+/* Energy correction (Sec. 2.1 item 6): the orbits of a step are drawn in the
+ * old potential Phi_old; once the stars have moved, the potential is
+ * Phi_new.  Taking the potential to change linearly over the step, each star
+ * that the last cmc_step (with energy_corr = 1) moved from r_old to r_new
+ * gains kinetic energy per unit mass dT = (dPhi(r_old) - dPhi(r_new)) / 2,
+ * dPhi = Phi_new - Phi_old, applied by scaling vr and vt by
+ * sqrt(1 + 2 dT / v^2) (vr/vt unchanged).  A star with v^2 + 2 dT <= 0, or
+ * v = 0 and dT != 0, keeps its velocities; sc->corr_skipped counts them.
+ * Needs the table of cmc_potential of the state that step left; does
+ * nothing when no correction is pending (sc->corr_n = 0) and clears it
+ * after.  The data of a pending correction (old radius and potentials, the
+ * sort's permutation) lives in the workspace; cmc_init_*, cmc_sort and a step
+ * without energy_corr drop it.  Every star's energy moves to the one the
+ * trapezoid rule gives, so apart from escapers and skipped stars the step
+ * conserves T + W exactly (the shell interaction is symmetric). */
+int cmc_energy_correction(cmc_state *s, void *stream);
 
 /* Diagnostics of the sorted state and its table (needs cmc_potential):
  * out_dev[0..CMC_DIAG_N-1] = T, W = sum m phi / 2, E = T + W, 2T/|W|, M, the
@@ -278,6 +305,9 @@ int cmc_batch_step(const cmc_batch *b, const cmc_params *p, void *stream);
 
 /* cmc_potential of every cluster (public phi, mcum, ssuf). */
 int cmc_batch_potential(const cmc_batch *b, int32_t precision, void *stream);
+
+/* cmc_energy_correction of every cluster (needs cmc_batch_potential). */
+int cmc_batch_energy_correction(const cmc_batch *b, void *stream);
 
 /* cmc_diagnostics of every cluster: out_dev[CMC_DIAG_N c .. CMC_DIAG_N c +
  * CMC_DIAG_N - 1] for cluster c. */

@@ -9,11 +9,12 @@ from ._capi import (CMC_BUCKET_CAP_MAX, CMC_FP64, CMC_MIXED, CMC_MODEL_KING, CMC
                     CmcError, ST_BOUND, ST_DT_DEGEN, ST_DT_NOCONV,
                     ST_ESCAPER, ST_NONFINITE, ST_NUMERIC, ST_TRIAL_CAP, lib)
 from . import evolve
-from .cluster import (Cluster, Ensemble, Params, cmc_diagnostics, cmc_init_model, cmc_init_plummer, cmc_orbit,
+from .cluster import (Cluster, Ensemble, Params, cmc_diagnostics, cmc_energy_correction,
+                      cmc_init_model, cmc_init_plummer, cmc_orbit,
                       cmc_philox, cmc_potential, cmc_relax, cmc_sort, cmc_step, cmc_step_timed,
                       cmc_timestep)
 
 __all__ = ["CMC_BUCKET_CAP_MAX", "CMC_FP64", "CMC_MIXED", "CMC_MODEL_KING", "CMC_MODEL_PLUMMER", "CMC_STEP_DEVICE", "CmcError", "Cluster", "Ensemble", "evolve",
-           "Params", "lib", "cmc_diagnostics", "cmc_init_model", "cmc_init_plummer", "cmc_orbit", "cmc_philox", "cmc_potential", "cmc_relax",
+           "Params", "lib", "cmc_diagnostics", "cmc_energy_correction", "cmc_init_model", "cmc_init_plummer", "cmc_orbit", "cmc_philox", "cmc_potential", "cmc_relax",
            "cmc_sort", "cmc_step", "cmc_step_timed", "cmc_timestep", "ST_BOUND", "ST_DT_DEGEN", "ST_DT_NOCONV",
            "ST_ESCAPER", "ST_NONFINITE", "ST_NUMERIC", "ST_TRIAL_CAP"]

@@ -23,9 +23,10 @@ ST_DT_DEGEN, ST_NUMERIC, ST_DT_NOCONV = 0x10, 0x20, 0x40
 
 EXPORTS = ("cmc_workspace_bytes", "cmc_init_plummer", "cmc_init_model", "cmc_sort", "cmc_potential",
            "cmc_timestep", "cmc_relax", "cmc_orbit", "cmc_step", "cmc_step_timed",
-           "cmc_diagnostics", "cmc_philox", "cmc_strerror", "cmc_abi_version",
-           "cmc_batch_device_bytes", "cmc_batch_prepare", "cmc_batch_init", "cmc_batch_step",
-           "cmc_batch_potential", "cmc_batch_diagnostics")
+           "cmc_energy_correction", "cmc_diagnostics", "cmc_philox", "cmc_strerror",
+           "cmc_abi_version", "cmc_batch_device_bytes", "cmc_batch_prepare", "cmc_batch_init",
+           "cmc_batch_step", "cmc_batch_potential", "cmc_batch_energy_correction",
+           "cmc_batch_diagnostics")
 CMC_SHAPES = 16
 
 
@@ -33,8 +34,8 @@ class cmc_scalars(C.Structure):
     _fields_ = [("n", C.c_int64), ("dt", C.c_double), ("status", C.c_uint32),
                 ("dt_iters", C.c_uint32), ("n_esc", C.c_int64), ("trials", C.c_int64),
                 ("violations", C.c_int64), ("capped", C.c_int64), ("e_esc", C.c_double),
-                ("mass_norm", C.c_double), ("step", C.c_int64),
-                ("reserved", C.c_int64 * 6)]
+                ("mass_norm", C.c_double), ("step", C.c_int64), ("corr_n", C.c_int64),
+                ("corr_skipped", C.c_int64), ("reserved", C.c_int64 * 4)]
 
 
 class cmc_state(C.Structure):
@@ -48,7 +49,8 @@ class cmc_state(C.Structure):
 class cmc_params(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("step", C.c_uint32), ("precision", C.c_int32),
                 ("gamma", C.c_double), ("target", C.c_double), ("bound_factor", C.c_double),
-                ("trial_cap", C.c_int32), ("dt_iters", C.c_int32)]
+                ("trial_cap", C.c_int32), ("dt_iters", C.c_int32),
+                ("energy_corr", C.c_int32), ("reserved", C.c_int32)]
 
 
 class cmc_cluster_spec(C.Structure):
@@ -64,6 +66,7 @@ class cmc_batch(C.Structure):
 
 
 assert C.sizeof(cmc_scalars) == 128
+assert C.sizeof(cmc_params) == 56
 
 _lib = None
 
@@ -101,6 +104,8 @@ def lib() -> C.CDLL:
         L.cmc_batch_step.argtypes = [bp, pp, vp]
         L.cmc_batch_potential.argtypes = [bp, C.c_int32, vp]
         L.cmc_batch_diagnostics.argtypes = [bp, vp, vp]
+        L.cmc_energy_correction.argtypes = [sp, vp]
+        L.cmc_batch_energy_correction.argtypes = [bp, vp]
         L.cmc_diagnostics.argtypes = [sp, vp, vp]
         L.cmc_philox.argtypes = [C.c_uint64, vp, vp, C.c_int64, vp]
         L.cmc_strerror.argtypes = [C.c_int]

@@ -26,10 +26,12 @@ class Params:
     bound_factor: float = 1.2
     trial_cap: int = 10000
     dt_iters: int = 0
+    energy_corr: int = 0
 
     def c(self) -> A.cmc_params:
         return A.cmc_params(self.seed, self.step, self.precision, self.gamma, self.target,
-                            self.bound_factor, self.trial_cap, self.dt_iters)
+                            self.bound_factor, self.trial_cap, self.dt_iters,
+                            self.energy_corr, 0)
 
 
 def _stream(stream=None):
@@ -166,6 +168,10 @@ def cmc_step(cl: Cluster, p: Params, stream=None):
     A.check(A.lib().cmc_step(cl.c, C.byref(pc), _stream(stream)), "cmc_step")
 
 
+def cmc_energy_correction(cl: Cluster, stream=None):
+    A.check(A.lib().cmc_energy_correction(cl.c, _stream(stream)), "cmc_energy_correction")
+
+
 def cmc_diagnostics(cl: Cluster, stream=None) -> dict:
     out = torch.zeros(A.CMC_DIAG_N, dtype=torch.float64, device=cl.r.device)
     A.check(A.lib().cmc_diagnostics(cl.c, C.c_void_p(out.data_ptr()), _stream(stream)),
@@ -236,6 +242,10 @@ class Ensemble:
     def potential(self, precision: int = A.CMC_FP64, stream=None):
         A.check(A.lib().cmc_batch_potential(C.byref(self.handle), precision, _stream(stream)),
                 "cmc_batch_potential")
+
+    def energy_correction(self, stream=None):
+        A.check(A.lib().cmc_batch_energy_correction(C.byref(self.handle), _stream(stream)),
+                "cmc_batch_energy_correction")
 
     def diagnostics(self, stream=None) -> list:
         out = torch.zeros(A.CMC_DIAG_N * len(self), dtype=torch.float64,

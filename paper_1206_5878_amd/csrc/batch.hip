@@ -202,6 +202,7 @@ int cmc_batch_step(const cmc_batch *b, const cmc_params *p, void *stream) {
   if (!p || (p->precision != CMC_FP64 && p->precision != CMC_MIXED)) return CMC_EINVAL;
   if (!(p->target > 0.0 && p->target < 1.0)) return CMC_EINVAL;
   if (p->bound_factor < 0.0 || p->trial_cap < 0 || p->dt_iters < 0) return CMC_EINVAL;
+  if (p->energy_corr != 0 && p->energy_corr != 1) return CMC_EINVAL;
   const cmc::BatchDev d = cmc::batch_dev(*b);
   return cmc::status_of(cmc::launch_step(cmc::Target{nullptr, &d}, b->m_f32 != 0, *p, nullptr,
                                          static_cast<hipStream_t>(stream)));
@@ -214,6 +215,14 @@ int cmc_batch_potential(const cmc_batch *b, int32_t precision, void *stream) {
   const cmc::BatchDev d = cmc::batch_dev(*b);
   return cmc::status_of(cmc::launch_potential(cmc::Target{nullptr, &d}, b->m_f32 != 0,
                                               precision, true, static_cast<hipStream_t>(stream)));
+}
+
+int cmc_batch_energy_correction(const cmc_batch *b, void *stream) {
+  int rc = cmc::check_batch(b);
+  if (rc) return rc;
+  const cmc::BatchDev d = cmc::batch_dev(*b);
+  return cmc::status_of(cmc::launch_energy_correction(cmc::Target{nullptr, &d}, true,
+                                                      static_cast<hipStream_t>(stream)));
 }
 
 int cmc_batch_diagnostics(const cmc_batch *b, double *out_dev, void *stream) {

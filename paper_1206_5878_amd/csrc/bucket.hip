@@ -115,9 +115,10 @@ __global__ __launch_bounds__(HT) void k_bkt_colscan(Ctx ctx) {
 }
 
 // One block per cluster: bucket starts; the escapers' bin comes last, so the
-// kept stars are the first start[nb].  The state's n becomes that count.
+// kept stars are the first start[nb].  The state's n becomes that count, and
+// the energy correction of the staged stars is left pending (corr) or none.
 template <class Ctx>
-__global__ __launch_bounds__(HT) void k_bkt_start(Ctx ctx) {
+__global__ __launch_bounds__(HT) void k_bkt_start(Ctx ctx, int corr) {
   __shared__ uint32_t sh[HT / 64];
   const ClusterArgs &A = ctx.args();
   cmc_scalars *__restrict__ sc = A.s.sc;
@@ -140,6 +141,7 @@ __global__ __launch_bounds__(HT) void k_bkt_start(Ctx ctx) {
     A.w.bkt_info[0] = n;
     A.w.bkt_info[1] = kept;
     sc->n = kept;
+    sc->corr_n = corr ? n : 0;
   }
 }
 
@@ -256,23 +258,31 @@ __device__ void merge_step(const uint64_t *sk, const uint32_t *sv, uint64_t *dk,
 }
 
 // The staged records in the order of V's staged indices, into the state at
-// out .. out + count.
+// out .. out + count (and, with corr, each star's staged index into perm).
 template <typename MT>
 __device__ __forceinline__ void gather(const ClusterArgs &A, const uint32_t *V, int64_t out,
-                                       int64_t count) {
+                                       int64_t count, int corr) {
   const StageRec<MT> *__restrict__ stage = static_cast<const StageRec<MT> *>(A.w.stage);
   constexpr int B = 8;  // records in flight per thread
   for (int64_t p0 = 0; p0 < count; p0 += B * BT) {
     StageRec<MT> rec[B];
+    uint32_t src[B];
 #pragma unroll
     for (int q = 0; q < B; ++q) {
       const int64_t p = p0 + q * BT + threadIdx.x;
-      if (p < count) rec[q] = stage[V[p]];
+      src[q] = 0u;
+      if (p < count) {
+        src[q] = V[p];
+        rec[q] = stage[src[q]];
+      }
     }
 #pragma unroll
     for (int q = 0; q < B; ++q) {
       const int64_t p = p0 + q * BT + threadIdx.x;
-      if (p < count) put_star<MT>(A, out + p, rec[q]);
+      if (p < count) {
+        put_star<MT>(A, out + p, rec[q]);
+        if (corr) A.w.perm[out + p] = src[q];
+      }
     }
   }
 }
@@ -282,7 +292,7 @@ __device__ __forceinline__ void gather(const ClusterArgs &A, const uint32_t *V, 
 // buckets never overlap), then gathers the staged records in order.
 template <typename MT>
 __device__ void sort_large(const ClusterArgs &A, uint32_t base, int64_t count, uint64_t *K,
-                           uint32_t *V) {
+                           uint32_t *V, int corr) {
   uint64_t *kb[2] = {A.w.keys[0] + base, A.w.keys[1] + base};
   uint32_t *vb[2] = {A.w.vals[0] + base, A.w.vals[1] + base};
   const BktEnt *__restrict__ bent = A.w.bent + base;
@@ -307,14 +317,14 @@ __device__ void sort_large(const ClusterArgs &A, uint32_t base, int64_t count, u
     __syncthreads();
     src ^= 1;
   }
-  gather<MT>(A, vb[src], base, count);
+  gather<MT>(A, vb[src], base, count, corr);
 }
 
 // One block per bucket.  sub: 16-bit counts, then starts, of each value of
 // c mod 2048 (two to a word); entries (K radius key, V staged index) are
 // placed by c, then each run of equal c is put in (K, V) order.
 template <class Ctx, typename MT>
-__global__ __launch_bounds__(BT) void k_bkt_sort(Ctx ctx) {
+__global__ __launch_bounds__(BT) void k_bkt_sort(Ctx ctx, int corr) {
   __shared__ uint32_t sub[kBucketSpan / 2];
   __shared__ uint64_t K[kBucketSortCap];
   __shared__ uint32_t V[kBucketSortCap];
@@ -328,7 +338,7 @@ __global__ __launch_bounds__(BT) void k_bkt_sort(Ctx ctx) {
   const int64_t count = static_cast<int64_t>(A.w.bkt_start[b + 1]) - base;
   if (count <= 0) return;
   if (count > kBucketSortCap) {
-    sort_large<MT>(A, base, count, K, V);
+    sort_large<MT>(A, base, count, K, V, corr);
     return;
   }
   const int cnt = static_cast<int>(count);
@@ -413,26 +423,27 @@ __global__ __launch_bounds__(BT) void k_bkt_sort(Ctx ctx) {
   } else {
     bitonic_lds(K, V, cnt);
   }
-  gather<MT>(A, V, base, cnt);
+  gather<MT>(A, V, base, cnt, corr);
 }
 
 template <class L, typename MT>
-hipError_t run(const L &l, hipStream_t st) {
+hipError_t run(const L &l, int corr, hipStream_t st) {
   k_bkt_hist<<<l.grid(kShBktTile), HT, 0, st>>>(l.ctx(kShBktTile));
   k_bkt_colscan<<<l.grid(kShBktGroup), HT, 0, st>>>(l.ctx(kShBktGroup));
-  k_bkt_start<<<l.grid(kShOne), HT, 0, st>>>(l.ctx(kShOne));
+  k_bkt_start<<<l.grid(kShOne), HT, 0, st>>>(l.ctx(kShOne), corr);
   k_bkt_scatter<<<l.grid(kShBktTile), HT, 0, st>>>(l.ctx(kShBktTile));
   k_bkt_sort<decltype(l.ctx(kShBktSort)), MT>
-      <<<l.grid(kShBktSort), BT, 0, st>>>(l.ctx(kShBktSort));
+      <<<l.grid(kShBktSort), BT, 0, st>>>(l.ctx(kShBktSort), corr);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_bucket_sort(const Target &t, bool m_f32, hipStream_t st) {
+hipError_t launch_bucket_sort(const Target &t, bool m_f32, bool corr, hipStream_t st) {
+  const int c = corr ? 1 : 0;
   return dispatch(t, [&](const auto &l) {
-    return m_f32 ? run<std::decay_t<decltype(l)>, float>(l, st)
-                 : run<std::decay_t<decltype(l)>, double>(l, st);
+    return m_f32 ? run<std::decay_t<decltype(l)>, float>(l, c, st)
+                 : run<std::decay_t<decltype(l)>, double>(l, c, st);
   });
 }
 

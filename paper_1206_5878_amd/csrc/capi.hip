@@ -23,24 +23,29 @@ ClusterArgs cluster_args(const cmc_state &s, uint64_t seed, double gamma) {
   return a;
 }
 
-// potential, timestep, relax, orbit, sort; events (if given) between them
+// potential (then the pending energy correction), timestep, relax, orbit,
+// sort; events (if given) between them
 hipError_t launch_step(const Target &t, bool m_f32, const cmc_params &p, void *const *events,
                        hipStream_t st) {
   auto mark = [&](int i) -> hipError_t {
     return events ? hipEventRecord(static_cast<hipEvent_t>(events[i]), st) : hipSuccess;
   };
+  const bool corr = p.energy_corr != 0;
   hipError_t e = mark(0);
   if (e == hipSuccess) e = launch_potential(t, m_f32, p.precision, false, st);
+  // the correction needs the radial index of the new radii, which the orbit
+  // pass then reuses
+  if (e == hipSuccess && corr) e = launch_energy_correction(t, false, st);
   if (e == hipSuccess) e = mark(1);
   if (e == hipSuccess) e = launch_timestep(t, m_f32, p, st);
   if (e == hipSuccess) e = mark(2);
   if (e == hipSuccess) e = launch_relax(t, m_f32, p, st);
   if (e == hipSuccess) e = mark(3);
-  if (e == hipSuccess) e = launch_orbit(t, m_f32, p, true, st);
+  if (e == hipSuccess) e = launch_orbit(t, m_f32, p, true, corr, corr, st);
   if (e == hipSuccess) e = mark(4);
   if (e == hipSuccess) {
-    e = bucket_sort_of(t) ? launch_bucket_sort(t, m_f32, st)
-                          : launch_sort_stage(t, m_f32, false, true, st);
+    e = bucket_sort_of(t) ? launch_bucket_sort(t, m_f32, corr, st)
+                          : launch_sort_stage(t, m_f32, false, true, corr, st);
   }
   if (e == hipSuccess && p.step == CMC_STEP_DEVICE) e = launch_step_advance(t, st);
   if (e == hipSuccess) e = mark(5);
@@ -71,6 +76,7 @@ int check_params(const cmc_params *p) {
   if (p->precision != CMC_FP64 && p->precision != CMC_MIXED) return CMC_EINVAL;
   if (!(p->gamma > 0.0) || !(p->target > 0.0 && p->target < 1.0)) return CMC_EINVAL;
   if (p->bound_factor < 0.0 || p->trial_cap < 0 || p->dt_iters < 0) return CMC_EINVAL;
+  if (p->energy_corr != 0 && p->energy_corr != 1) return CMC_EINVAL;
   return CMC_OK;
 }
 
@@ -146,7 +152,7 @@ int cmc_sort(cmc_state *s, void *stream) {
   hipError_t e = cmc::launch_stage_from_state(one.t(), s->m_f32 != 0, as_stream(stream));
   if (e != hipSuccess) return CMC_EHIP;
   return status_of(
-      cmc::launch_sort_stage(one.t(), s->m_f32 != 0, false, false, as_stream(stream)));
+      cmc::launch_sort_stage(one.t(), s->m_f32 != 0, false, false, false, as_stream(stream)));
 }
 
 int cmc_potential(cmc_state *s, int32_t precision, void *stream) {
@@ -184,7 +190,8 @@ int cmc_orbit(cmc_state *s, const cmc_params *p, void *stream) {
   if ((rc = check_params(p))) return rc;
   const Single one = single(*s, p->seed, p->gamma);
   hipError_t e = cmc::launch_table_pack(one.t(), as_stream(stream));
-  if (e == hipSuccess) e = cmc::launch_orbit(one.t(), s->m_f32 != 0, *p, false, as_stream(stream));
+  if (e == hipSuccess)
+    e = cmc::launch_orbit(one.t(), s->m_f32 != 0, *p, false, false, false, as_stream(stream));
   return status_of(e);
 }
 
@@ -207,6 +214,14 @@ int cmc_step_timed(cmc_state *s, const cmc_params *p, void *const *events, void 
   for (int i = 0; i < 6; ++i)
     if (!events[i]) return CMC_EINVAL;
   return run_step(s, p, events, as_stream(stream));
+}
+
+int cmc_energy_correction(cmc_state *s, void *stream) {
+  Workspace w;
+  int rc = check_state(s, &w);
+  if (rc) return rc;
+  const Single one = single(*s, 0, 1.0);
+  return status_of(cmc::launch_energy_correction(one.t(), true, as_stream(stream)));
 }
 
 int cmc_diagnostics(const cmc_state *s, double *out_dev, void *stream) {

@@ -304,6 +304,9 @@ struct Workspace {
   uint32_t *bkt_tot;        // [bkt_bins] stars per bucket
   uint32_t *bkt_start;      // [bkt_bins + 1] first position of each bucket
   int64_t *bkt_info;        // [2]: staged stars, kept stars
+  RPhi *cor;                // [cap] energy correction, old order: (r_old, Phi_old(r_old))
+  double *pn;               // [cap] Phi_old(r_new), then the summed work terms
+  uint32_t *perm;           // [cap] staged (old) index of each sorted star
   int64_t bkt_bins, bkt_tiles;  // bkt_bins = 0: capacity above kBucketCapMax
   int64_t rx_nb;
   int rx_lg_nb;
@@ -366,6 +369,9 @@ inline Workspace layout(int64_t cap, void *base) {
   w.phib = reinterpret_cast<double *>(take(8 * (kPhiBins + 1)));
   w.phib_ctl = reinterpret_cast<uint64_t *>(take(8 * 2));
   w.bkey = reinterpret_cast<uint32_t *>(take(4 * c));
+  w.cor = reinterpret_cast<RPhi *>(take(sizeof(RPhi) * c));
+  w.pn = reinterpret_cast<double *>(take(8 * c));
+  w.perm = reinterpret_cast<uint32_t *>(take(4 * c));
   w.bent = reinterpret_cast<BktEnt *>(w.orec);  // orec is dead once the orbit pass ends
   static_assert(sizeof(BktEnt) <= sizeof(OrbitRec), "bent fits in orec");
   if (c <= kBucketCapMax) {
@@ -545,15 +551,18 @@ hipError_t launch_potential(const Target &t, bool m_f32, int precision, bool pub
                             hipStream_t st);
 hipError_t launch_timestep(const Target &t, bool m_f32, const cmc_params &p, hipStream_t st);
 hipError_t launch_relax(const Target &t, bool m_f32, const cmc_params &p, hipStream_t st);
+// corr: also record each star's energy-correction terms (cor, pn);
+// rindex_ready: the radial index of the sorted radii is already built.
 hipError_t launch_orbit(const Target &t, bool m_f32, const cmc_params &p, bool to_stage,
-                        hipStream_t st);
+                        bool corr, bool rindex_ready, hipStream_t st);
 hipError_t launch_table_pack(const Target &t, hipStream_t st);
 hipError_t launch_rindex(const Target &t, hipStream_t st);
 hipError_t launch_stage_from_state(const Target &t, bool m_f32, hipStream_t st);
 // Radix sort of the staged records by keys[0]: the step's records
-// (StageRec<mass type>) or WideRec.
+// (StageRec<mass type>) or WideRec.  corr: write perm and leave the energy
+// correction pending (sc->corr_n = staged stars); else clear it.
 hipError_t launch_sort_stage(const Target &t, bool m_f32, bool normalise_mass, bool step_records,
-                             hipStream_t st);
+                             bool corr, hipStream_t st);
 hipError_t launch_init(const Target &t, bool m_f32, hipStream_t st);
 hipError_t launch_diagnostics(const Target &t, bool m_f32, double *out, hipStream_t st);
 hipError_t launch_philox(uint64_t key, const uint32_t *ctr, uint32_t *out, int64_t n,
@@ -563,7 +572,11 @@ hipError_t launch_step(const Target &t, bool m_f32, const cmc_params &p, void *c
 hipError_t launch_step_advance(const Target &t, hipStream_t st);
 // The step's sort of the orbit pass's staged records (stage, bkey) into the
 // state; capacities above kBucketCapMax take the radix sort instead.
-hipError_t launch_bucket_sort(const Target &t, bool m_f32, hipStream_t st);
+hipError_t launch_bucket_sort(const Target &t, bool m_f32, bool corr, hipStream_t st);
+// The pending energy correction (energy.hip), after the potential of the
+// state the step left: builds the radial index, applies it, and with
+// `finish` clears sc->corr_n.
+hipError_t launch_energy_correction(const Target &t, bool finish, hipStream_t st);
 // Whether the target's step sorts by buckets.
 inline bool bucket_sort_of(const Target &t) {
   return t.many ? t.many->bucket_sort != 0 : t.one->w.bkt_bins > 0;

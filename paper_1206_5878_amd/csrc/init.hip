@@ -51,7 +51,9 @@ __global__ void k_clear_scalars(Ctx ctx) {
   sc->e_esc = 0.0;
   sc->mass_norm = 1.0;
   sc->step = 0;
-  for (int q = 0; q < 6; ++q) sc->reserved[q] = 0;
+  sc->corr_n = 0;
+  sc->corr_skipped = 0;
+  for (int q = 0; q < 4; ++q) sc->reserved[q] = 0;
 }
 
 // King density up to a constant; the series for small W avoids the
@@ -273,7 +275,7 @@ hipError_t launch_init(const Target &t, bool m_f32, hipStream_t st) {
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;
-  return launch_sort_stage(t, m_f32, true, false, st);
+  return launch_sort_stage(t, m_f32, true, false, false, st);
 }
 
 }  // namespace cmc

@@ -10,6 +10,10 @@
 // The mixed form draws the trial angle and takes the accept test in FP32;
 // brackets, roots, the table and Q stay in FP64.
 //
+// For the energy correction of Sec. 2.1 item 6 (energy.hip) a step can also
+// record, per star in this pass's order, (r_old, Phi_old(r_old)) and the old
+// potential at the new radius, Phi_old(r_new).
+//
 // Two kernels.  k_orbit_bracket: brackets, roots and the rejection bound F
 // of every star, written as a 48-byte orbit record (escapers and degenerate
 // orbits are finished there); its blocks stay resident and loop over tiles
@@ -316,7 +320,7 @@ __device__ __forceinline__ void or_status(cmc_scalars *sc, uint32_t fl) {
 
 template <class Ctx, typename MT, bool TO_STAGE>
 __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4)))
-void k_orbit_bracket(Ctx ctx, uint32_t step_arg, double bound_factor) {
+void k_orbit_bracket(Ctx ctx, uint32_t step_arg, double bound_factor, int corr) {
   extern __shared__ RPhi top[];
   __shared__ double shd[BT / 64];
   __shared__ GParams prm[2 * BT];
@@ -335,6 +339,8 @@ void k_orbit_bracket(Ctx ctx, uint32_t step_arg, double bound_factor) {
   uint64_t *__restrict__ keys = A.w.keys[0];
   uint32_t *__restrict__ bkey = A.w.bkey;
   OrbitRec *__restrict__ orec = A.w.orec;
+  RPhi *__restrict__ cor = A.w.cor;
+  double *__restrict__ pn = A.w.pn;
   cmc_scalars *__restrict__ sc = A.s.sc;
   double *__restrict__ part = A.w.red_part;
   const uint64_t seed = A.seed;
@@ -355,6 +361,7 @@ void k_orbit_bracket(Ctx ctx, uint32_t step_arg, double bound_factor) {
     double E = 0.0, J = 0.0, J2 = 0.0, vri = 0.0, vti = 0.0;
     if (i < n) {
       const RPhi me = tab[i];
+      if (corr) cor[i] = me;  // r_old and Phi_old(r_old)
       vri = vr[i];
       vti = vt[i];
       E = me.phi + 0.5 * (vri * vri + vti * vti);
@@ -434,8 +441,9 @@ void k_orbit_bracket(Ctx ctx, uint32_t step_arg, double bound_factor) {
         } else {
           const double rn = rdone + 0.0;
           const int64_t kn = interval_in(ix, ictl, rn, kmin, kmax);
-          const double qn = 2.0 * E - 2.0 * phi_in(lv, ms, kn, rn) -
-                            (J2 == 0.0 ? 0.0 : J2 / (rn * rn));
+          const double phn = phi_in(lv, ms, kn, rn);
+          const double qn = 2.0 * E - 2.0 * phn - (J2 == 0.0 ? 0.0 : J2 / (rn * rn));
+          if (corr) pn[i] = phn;
           double vrn, vtn;
           finish(rn, qn, J, J2, id[i], step, seed, vrn, vtn, fl);
           emit<TO_STAGE>(i, rn, vrn, vtn, m[i], id[i], rindex_last_le(ix, ictl, rn) + 1, r_new,
@@ -456,7 +464,7 @@ void k_orbit_bracket(Ctx ctx, uint32_t step_arg, double bound_factor) {
 
 template <class Ctx, typename MT, bool TO_STAGE, bool MIXED>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5)))
-void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap) {
+void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap, int corr) {
   __shared__ double shd[NT / 64];
   const ClusterArgs &A = ctx.args();
   const uint32_t step = step_of(A, step_arg);
@@ -472,6 +480,7 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap) {
   uint64_t *__restrict__ keys = A.w.keys[0];
   uint32_t *__restrict__ bkey = A.w.bkey;
   const OrbitRec *__restrict__ orec = A.w.orec;
+  double *__restrict__ pn = A.w.pn;
   cmc_scalars *__restrict__ sc = A.s.sc;
   double *__restrict__ part = A.w.red_part + 2 * A.w.star_blocks;
   const uint64_t seed = A.seed;
@@ -563,7 +572,8 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap) {
     if (busy && !settled) {
       kg = rindex_last_le(ix, ictl, r0);
       const int64_t k0 = kg < kmin ? kmin : (kg > kmax ? kmax : kg);
-      const double q0 = 2.0 * E - 2.0 * phi_in(lv, ms, k0, r0) - J2 / (r0 * r0);
+      double phn = phi_in(lv, ms, k0, r0);
+      const double q0 = 2.0 * E - 2.0 * phn - J2 / (r0 * r0);
       bool done = false;
       double qn = 0.0;
       if (q0 > 0.0) {
@@ -593,10 +603,12 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap) {
         fl |= CMC_ST_TRIAL_CAP;
         const double rn = r0 + 0.0;
         const int64_t kn = interval_in(ix, ictl, rn, kmin, kmax);
-        qn = 2.0 * E - 2.0 * phi_in(lv, ms, kn, rn) - (J2 == 0.0 ? 0.0 : J2 / (rn * rn));
+        phn = phi_in(lv, ms, kn, rn);
+        qn = 2.0 * E - 2.0 * phn - (J2 == 0.0 ? 0.0 : J2 / (rn * rn));
       }
       if (done) {
         const double rn = r0 + 0.0;
+        if (corr) pn[i] = phn;  // Phi_old(r_new)
         double vrn, vtn;
         finish(rn, qn, J, J2, sid, step, seed, vrn, vtn, fl);
         emit<TO_STAGE>(i, rn, vrn, vtn, m[i], sid, kg + 1, r_new, vr, vt, stage, keys, bkey);
@@ -681,7 +693,7 @@ __global__ __launch_bounds__(NT) void k_table_pack(Ctx ctx) {
 }
 
 template <class L, typename MT, bool TO_STAGE>
-hipError_t run2(const L &l, const cmc_params &p, hipStream_t st) {
+hipError_t run2(const L &l, const cmc_params &p, int corr, hipStream_t st) {
   const int32_t cap = p.trial_cap > 0 ? p.trial_cap : 10000;
   const double bf = p.bound_factor > 0.0 ? p.bound_factor : 1.2;
   using Cb = decltype(l.ctx(kShBracket));
@@ -689,13 +701,13 @@ hipError_t run2(const L &l, const cmc_params &p, hipStream_t st) {
   k_phi_bounds<<<l.grid(kShDiag), NT, 0, st>>>(l.ctx(kShDiag));
   k_orbit_bracket<Cb, MT, TO_STAGE>
       <<<l.grid(kShBracket), BT, sizeof(RPhi) * l.top_entries(), st>>>(l.ctx(kShBracket), p.step,
-                                                                       bf);
+                                                                       bf, corr);
   if (p.precision == CMC_MIXED)
     k_orbit_trials<Ct, MT, TO_STAGE, true><<<l.grid(kShTrials), NT, 0, st>>>(l.ctx(kShTrials),
-                                                                             p.step, cap);
+                                                                             p.step, cap, corr);
   else
     k_orbit_trials<Ct, MT, TO_STAGE, false><<<l.grid(kShTrials), NT, 0, st>>>(
-        l.ctx(kShTrials), p.step, cap);
+        l.ctx(kShTrials), p.step, cap, corr);
   k_orbit_sum<<<l.grid(kShOne), FT, 0, st>>>(l.ctx(kShOne));
   return hipGetLastError();
 }
@@ -731,14 +743,17 @@ hipError_t launch_table_pack(const Target &t, hipStream_t st) {
 }
 
 hipError_t launch_orbit(const Target &t, bool m_f32, const cmc_params &p, bool to_stage,
-                        hipStream_t st) {
-  hipError_t e = launch_rindex(t, st);
-  if (e != hipSuccess) return e;
+                        bool corr, bool rindex_ready, hipStream_t st) {
+  if (!rindex_ready) {
+    const hipError_t e = launch_rindex(t, st);
+    if (e != hipSuccess) return e;
+  }
+  const int c = (to_stage && corr) ? 1 : 0;  // correction terms only for a staged step
   return dispatch(t, [&](const auto &l) {
     using L = std::decay_t<decltype(l)>;
     if (m_f32)
-      return to_stage ? run2<L, float, true>(l, p, st) : run2<L, float, false>(l, p, st);
-    return to_stage ? run2<L, double, true>(l, p, st) : run2<L, double, false>(l, p, st);
+      return to_stage ? run2<L, float, true>(l, p, c, st) : run2<L, float, false>(l, p, c, st);
+    return to_stage ? run2<L, double, true>(l, p, c, st) : run2<L, double, false>(l, p, c, st);
   });
 }
 

@@ -107,9 +107,10 @@ __global__ __launch_bounds__(NT) void k_key_range(Ctx ctx) {
   }
 }
 
-// One block per cluster.
+// One block per cluster.  Also leaves the staged stars' energy correction
+// pending (corr) or none.
 template <class Ctx>
-__global__ __launch_bounds__(NT) void k_plan(Ctx ctx) {
+__global__ __launch_bounds__(NT) void k_plan(Ctx ctx, int corr) {
   __shared__ uint64_t smin[NT / 64], smax[NT / 64], snf[NT / 64];
   const ClusterArgs &A = ctx.args();
   const uint64_t *__restrict__ part = reinterpret_cast<const uint64_t *>(A.w.red_part);
@@ -156,6 +157,7 @@ __global__ __launch_bounds__(NT) void k_plan(Ctx ctx) {
   pi[kMaxKey] = hi;
   pi[kNonFin] = nf;
   sc->n = static_cast<int64_t>(kept);
+  sc->corr_n = corr ? static_cast<int64_t>(n) : 0;
 }
 
 // key of item k for pass 0 (compression applied) or a later pass
@@ -335,7 +337,7 @@ __global__ __launch_bounds__(DT) void k_downsweep(Ctx ctx, int pass) {
 }
 
 template <class Ctx, class Rec>
-__global__ __launch_bounds__(NT) void k_gather(Ctx ctx, int normalise) {
+__global__ __launch_bounds__(NT) void k_gather(Ctx ctx, int normalise, int corr) {
   const ClusterArgs &A = ctx.args();
   const Rec *__restrict__ stage = static_cast<const Rec *>(A.w.stage);
   const uint32_t *__restrict__ vals0 = A.w.vals[0];
@@ -364,6 +366,7 @@ __global__ __launch_bounds__(NT) void k_gather(Ctx ctx, int normalise) {
   else
     static_cast<double *>(m)[p] = mm;
   id[p] = rec.id;
+  if (corr) A.w.perm[p] = src;
 }
 
 // One thread per cluster: the device step counter moves on.
@@ -390,11 +393,12 @@ hipError_t launch_stage_from_state(const Target &t, bool, hipStream_t st) {
 
 // Sort the staged records by keys[0] (n = sc->n on entry) into the state.
 hipError_t launch_sort_stage(const Target &t, bool m_f32, bool normalise_mass, bool step_records,
-                             hipStream_t st) {
+                             bool corr, hipStream_t st) {
+  const int c = corr ? 1 : 0;
   return dispatch(t, [&](const auto &l) {
     k_sort_prep<<<l.grid(kShOne), 1, 0, st>>>(l.ctx(kShOne));
     k_key_range<<<l.grid(kShKeyRange), NT, 0, st>>>(l.ctx(kShKeyRange));
-    k_plan<<<l.grid(kShOne), NT, 0, st>>>(l.ctx(kShOne));
+    k_plan<<<l.grid(kShOne), NT, 0, st>>>(l.ctx(kShOne), c);
     for (int pass = 0; pass < 8; ++pass) {
       k_upsweep<<<l.grid(kShSortTile), NT, 0, st>>>(l.ctx(kShSortTile), pass);
       k_scan_digits<<<l.grid(kShDigit), NT, 0, st>>>(l.ctx(kShDigit), pass);
@@ -402,10 +406,10 @@ hipError_t launch_sort_stage(const Target &t, bool m_f32, bool normalise_mass, b
     }
     if (step_records && m_f32)
       k_gather<decltype(l.ctx(kShStar)), StageRec<float>>
-          <<<l.grid(kShStar), NT, 0, st>>>(l.ctx(kShStar), normalise_mass ? 1 : 0);
+          <<<l.grid(kShStar), NT, 0, st>>>(l.ctx(kShStar), normalise_mass ? 1 : 0, c);
     else
       k_gather<decltype(l.ctx(kShStar)), WideRec>
-          <<<l.grid(kShStar), NT, 0, st>>>(l.ctx(kShStar), normalise_mass ? 1 : 0);
+          <<<l.grid(kShStar), NT, 0, st>>>(l.ctx(kShStar), normalise_mass ? 1 : 0, c);
     return hipGetLastError();
   });
 }

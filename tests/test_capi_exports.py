@@ -23,7 +23,7 @@ def test_library_exports_every_declared_call():
     for n in names:
         assert hasattr(L, n), n
     assert set(A.EXPORTS) == set(names)
-    assert L.cmc_abi_version() == 2
+    assert L.cmc_abi_version() == 3
 
 
 def test_host_side_checks_without_gpu():
@@ -38,6 +38,7 @@ def test_host_side_checks_without_gpu():
     assert L.cmc_step(C.byref(s), C.byref(p), None) == A.CMC_EINVAL
     assert L.cmc_sort(C.byref(s), None) == A.CMC_EINVAL
     assert L.cmc_potential(C.byref(s), 0, None) == A.CMC_EINVAL
+    assert L.cmc_energy_correction(C.byref(s), None) == A.CMC_EINVAL
     assert L.cmc_init_plummer(None, 10, 1, 0, None) == A.CMC_EINVAL
     assert L.cmc_philox(1, None, None, 5, None) == A.CMC_EINVAL
     assert L.cmc_philox(1, None, None, 0, None) == A.CMC_OK
