@@ -86,7 +86,14 @@ def lib():
         L.ora_step.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _up, _dp, _dp,
                                C.POINTER(Params), C.POINTER(StepOut)]
         L.ora_step_ex.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _up, _dp, _dp,
-                                  C.POINTER(Params), C.POINTER(StepOut), _vp]
+                                  C.POINTER(Params), C.POINTER(StepOut), _vp, _vp]
+        L.ora_lfsr113_next.argtypes = [_up]
+        L.ora_lfsr113_next.restype = C.c_uint32
+        L.ora_lfsr113_block.argtypes = [_up, _up]
+        L.ora_lfsr113_jump_pow2.argtypes = [_up, C.c_int]
+        L.ora_lfsr113_stream.argtypes = [_up, C.c_uint64, _up]
+        L.ora_lfsr113_component_period.argtypes = [C.c_int, C.c_uint32, C.c_int64]
+        L.ora_lfsr113_component_period.restype = C.c_int64
         L.ora_energy_correction.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp]
         L.ora_energy_correction.restype = C.c_int64
         L.ora_diagnostics.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
@@ -119,23 +126,59 @@ def u01f(hi) -> float:
     return lib().ora_u01f(int(hi))
 
 
+def lfsr113_blocks(z, nblocks: int):
+    """(state after, words (nblocks, 4)) of the LFSR113 generator from state z."""
+    z = _u32(z).copy()
+    out = np.empty((nblocks, 4), np.uint32)
+    w = np.empty(4, np.uint32)
+    for b in range(nblocks):
+        lib().ora_lfsr113_block(z, w)
+        out[b] = w
+    return z, out
+
+
+def lfsr113_jump_pow2(z, e: int):
+    z = _u32(z).copy()
+    lib().ora_lfsr113_jump_pow2(z, int(e))
+    return z
+
+
+def lfsr113_stream(z0, sid: int):
+    """State of stream ``sid``: z0 advanced by sid * 2^80 steps."""
+    out = np.empty(4, np.uint32)
+    lib().ora_lfsr113_stream(_u32(z0).copy(), int(sid), out)
+    return out
+
+
+def lfsr113_component_period(c: int, z: int, limit: int) -> int:
+    return lib().ora_lfsr113_component_period(int(c), int(z), int(limit))
+
+
+def lfsr113_seed_states(z0, ids):
+    """Every star's stream state (one stream per star id)."""
+    return np.stack([lfsr113_stream(z0, int(i)) for i in ids]) if len(ids) else \
+        np.zeros((0, 4), np.uint32)
+
+
 # ---------------------------------------------------------------- state helpers
 class State:
-    """Sorted SoA star state (host, FP64)."""
+    """Sorted SoA star state (host, FP64); rng: optional LFSR113 states,
+    shape (n, 4) uint32, that move with the stars."""
 
-    def __init__(self, r, vr, vt, m, id_):
+    def __init__(self, r, vr, vt, m, id_, rng=None):
         self.r = _f64(r).copy()
         self.vr = _f64(vr).copy()
         self.vt = _f64(vt).copy()
         self.m = _f64(m).copy()
         self.id = _u32(id_).copy()
+        self.rng = None if rng is None else _u32(rng).reshape(-1, 4).copy()
 
     @property
     def n(self) -> int:
         return self.r.shape[0]
 
     def copy(self) -> "State":
-        return State(self.r, self.vr, self.vt, self.m, self.id)
+        return State(self.r, self.vr, self.vt, self.m, self.id, self.rng)
 
 
 def plummer_unsorted(n: int, seed: int, mass_spectrum: int = 0):
@@ -257,19 +300,25 @@ def orbit(st: State, table, seed: int, step: int, trial_cap: int = 10000,
 
 def step(st: State, seed: int, step_idx: int, gamma: float, target: float = 0.03,
          dt_fixed: float = 0.0, trial_cap: int = 10000, bound_factor: float = 1.2,
-         moves: bool = False):
+         moves: bool = False, lfsr: bool = False):
     """One whole step on a copy of ``st``.  Returns (new_state, info dict).
     moves: also info["moves"], shape (n_after, 3): each new star's
-    (r_old, Phi_old(r_old), Phi_old(r_new)) for ``energy_correction``."""
+    (r_old, Phi_old(r_old), Phi_old(r_new)) for ``energy_correction``.
+    lfsr: draw from the stars' LFSR113 streams (st.rng) instead of Philox."""
     s = st.copy()
+    if lfsr and (s.rng is None or s.rng.shape[0] != s.n):
+        raise ValueError("lfsr needs st.rng with one state per star")
+    rng = s.rng.reshape(-1) if lfsr and s.n else None
     phi = np.empty(max(s.n, 1)); mcum = np.empty(max(s.n, 1))
     mv = np.empty(3 * max(s.n, 1)) if moves else None
     p = Params(seed, step_idx, gamma, target, dt_fixed, trial_cap, bound_factor)
     o = StepOut()
     lib().ora_step_ex(s.n, s.r, s.vr, s.vt, s.m, s.id, phi, mcum, C.byref(p), C.byref(o),
-                      mv.ctypes.data if moves else None)
+                      mv.ctypes.data if moves else None,
+                      rng.ctypes.data if rng is not None else None)
     k = o.n_after
-    new = State(s.r[:k], s.vr[:k], s.vt[:k], s.m[:k], s.id[:k])
+    new = State(s.r[:k], s.vr[:k], s.vt[:k], s.m[:k], s.id[:k],
+                s.rng[:k] if lfsr else None)
     info = dict(dt=o.dt, n_after=k, status=o.status,
                 orbit={f: getattr(o.orbit, f) for f, _ in OrbitStats._fields_},
                 phi=phi[:st.n], mcum=mcum[:st.n])

@@ -83,6 +83,106 @@ static void draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t 
 }
 
 /* ------------------------------------------------------------------------- */
+/* The generator of Sec. 3.6: L'Ecuyer's combined Tausworthe LFSR113 (Math.
+ * Comp. 68, 1999).  Four component LFSRs of degrees k = 31, 29, 28, 25 with
+ * (q, s) = (6, 18), (2, 2), (13, 7), (3, 13); a component's state is the top
+ * k bits of its word, one step is
+ *   b = ((z << q) ^ z) >> (k - s);   z = ((z & top k bits) << s) ^ b,
+ * and each output is the XOR of the four words.  Period about 2^113.  A step
+ * is linear over GF(2) in the word, so D steps are the D-th power of a 32x32
+ * bit matrix, kept as its 32 columns (the image of each bit). */
+static const int lfsr_k[4] = {31, 29, 28, 25};
+static const int lfsr_q[4] = {6, 2, 13, 3};
+static const int lfsr_s[4] = {18, 2, 7, 13};
+
+static uint32_t lfsr_comp(uint32_t z, int c) {
+  const uint32_t top = ~0u << (32 - lfsr_k[c]);
+  const uint32_t b = ((z << lfsr_q[c]) ^ z) >> (lfsr_k[c] - lfsr_s[c]);
+  return ((z & top) << lfsr_s[c]) ^ b;
+}
+
+uint32_t ora_lfsr113_next(uint32_t z[4]) {
+  for (int c = 0; c < 4; ++c) z[c] = lfsr_comp(z[c], c);
+  return z[0] ^ z[1] ^ z[2] ^ z[3];
+}
+
+void ora_lfsr113_block(uint32_t z[4], uint32_t w[4]) {
+  for (int i = 0; i < 4; ++i) w[i] = ora_lfsr113_next(z);
+}
+
+static void lfsr_matrix(int c, uint32_t col[32]) {
+  for (int i = 0; i < 32; ++i) col[i] = lfsr_comp(1u << i, c);
+}
+
+static uint32_t mat_apply(const uint32_t col[32], uint32_t v) {
+  uint32_t r = 0;
+  for (int i = 0; i < 32; ++i)
+    if ((v >> i) & 1u) r ^= col[i];
+  return r;
+}
+
+static void mat_square(uint32_t col[32]) {
+  uint32_t t[32];
+  for (int i = 0; i < 32; ++i) t[i] = mat_apply(col, col[i]);
+  memcpy(col, t, sizeof t);
+}
+
+void ora_lfsr113_jump_pow2(uint32_t z[4], int e) {
+  for (int c = 0; c < 4; ++c) {
+    uint32_t col[32];
+    lfsr_matrix(c, col);
+    for (int t = 0; t < e; ++t) mat_square(col);
+    z[c] = mat_apply(col, z[c]);
+  }
+}
+
+void ora_lfsr113_stream(const uint32_t z0[4], uint64_t id, uint32_t z[4]) {
+  for (int c = 0; c < 4; ++c) {
+    uint32_t col[32];
+    lfsr_matrix(c, col);
+    for (int t = 0; t < 80; ++t) mat_square(col); /* one stream: 2^80 steps */
+    uint32_t v = z0[c];
+    for (uint64_t x = id; x; x >>= 1) {
+      if (x & 1u) v = mat_apply(col, v);
+      mat_square(col);
+    }
+    z[c] = v;
+  }
+}
+
+int64_t ora_lfsr113_component_period(int c, uint32_t z, int64_t limit) {
+  const uint32_t top = ~0u << (32 - lfsr_k[c]);
+  const uint32_t start = z & top;
+  for (int64_t t = 1; t <= limit; ++t) {
+    z = lfsr_comp(z, c);
+    if ((z & top) == start) return t;
+  }
+  return -1;
+}
+
+/* Where a step's random blocks come from: Philox keyed by the seed with
+ * counter (star id, step, purpose, trial), or, with lfsr set, the next block
+ * of the star's own LFSR113 stream (4 state words per star, in the order of
+ * the arrays).  consume = 0 reads a block without advancing the stream. */
+typedef struct {
+  uint64_t seed;
+  uint32_t step;
+  uint32_t *lfsr;
+} draws;
+
+static void star_draw(const draws *d, const uint32_t *id, int64_t k, uint32_t purpose,
+                      uint32_t trial, int consume, uint32_t w[4]) {
+  if (!d->lfsr) {
+    draw(d->seed, id[k], d->step, purpose, trial, w);
+    return;
+  }
+  uint32_t z[4];
+  memcpy(z, d->lfsr + 4 * k, sizeof z);
+  ora_lfsr113_block(z, w);
+  if (consume) memcpy(d->lfsr + 4 * k, z, sizeof z);
+}
+
+/* ------------------------------------------------------------------------- */
 /* Initial Plummer model.  The paper samples (m, r, vr, vt) from a
  * distribution function and keeps only |r|, vr and vt (Sec. 2.1, opening
  * paragraph).  Plummer sphere with scale radius 1: r = (X1^(-2/3) - 1)^(-1/2);
@@ -408,7 +508,7 @@ typedef struct {
 
 static void pair_geometry(int64_t n, int64_t p, const double *r, const double *m,
                           const double *vr, const double *vt, const uint32_t *id,
-                          uint64_t seed, uint32_t step, double lnL, pair_geo *g) {
+                          const draws *d, int consume, double lnL, pair_geo *g) {
   int64_t nbins = n / 20;
   if (nbins < 1) nbins = 1;
   int64_t a = 2 * p, b = 2 * p + 1;
@@ -421,7 +521,7 @@ static void pair_geometry(int64_t n, int64_t p, const double *r, const double *m
   double nb = (vol > 0.0) ? (double)(hi - lo) / vol : INFINITY;
 
   uint32_t w4[4];
-  draw(seed, id[a], step, ORA_P_RELAX, 0u, w4);
+  star_draw(d, id, a, ORA_P_RELAX, 0u, consume, w4); /* the pair's first star */
   double u1 = ora_u01(w4[1], w4[0]);
   double u2 = ora_u01(w4[3], w4[2]);
   double psi = 2.0 * PI * u1;
@@ -466,19 +566,26 @@ static double beta_of(double tp, double dt) {
   return (b < PI) ? b : PI;
 }
 
-int64_t ora_pair_terms(int64_t n, const double *r, const double *m, const double *vr,
-                       const double *vt, const uint32_t *id, uint64_t seed, uint32_t step,
-                       double gamma, double *w, double *tp, double *nb) {
+static int64_t pair_terms_d(int64_t n, const double *r, const double *m, const double *vr,
+                            const double *vt, const uint32_t *id, const draws *src,
+                            double gamma, double *w, double *tp, double *nb) {
   int64_t np = n / 2;
   double lnL = coulomb_log(gamma, n);
   for (int64_t p = 0; p < np; ++p) {
     pair_geo g;
-    pair_geometry(n, p, r, m, vr, vt, id, seed, step, lnL, &g);
+    pair_geometry(n, p, r, m, vr, vt, id, src, 0, lnL, &g);
     if (w) w[p] = g.wm;
     if (tp) tp[p] = g.tp;
     if (nb) nb[p] = g.nb;
   }
   return np;
+}
+
+int64_t ora_pair_terms(int64_t n, const double *r, const double *m, const double *vr,
+                       const double *vt, const uint32_t *id, uint64_t seed, uint32_t step,
+                       double gamma, double *w, double *tp, double *nb) {
+  const draws d = {seed, step, NULL};
+  return pair_terms_d(n, r, m, vr, vt, id, &d, gamma, w, tp, nb);
 }
 
 double ora_mean_sin2(int64_t np, const double *w, const double *tp, double dt) {
@@ -544,13 +651,13 @@ double ora_solve_dt(int64_t np, const double *w, const double *tp, double target
  * The frame is e1 = w/|w|, e2 = unit(e1 x a) with a the coordinate axis of the
  * smallest |w| component (lowest index on ties), e3 = e1 x e2.  Pair momentum
  * and kinetic energy are conserved exactly in real arithmetic. */
-void ora_relax(int64_t n, const double *r, const double *m, double *vr, double *vt,
-               const uint32_t *id, uint64_t seed, uint32_t step, double gamma, double dt) {
+static void relax_d(int64_t n, const double *r, const double *m, double *vr, double *vt,
+                    const uint32_t *id, const draws *src, double gamma, double dt) {
   int64_t np = n / 2;
   double lnL = coulomb_log(gamma, n);
   for (int64_t p = 0; p < np; ++p) {
     pair_geo g;
-    pair_geometry(n, p, r, m, vr, vt, id, seed, step, lnL, &g);
+    pair_geometry(n, p, r, m, vr, vt, id, src, 1, lnL, &g);
     double beta = beta_of(g.tp, dt);
     if (!(g.wm > 0.0) || beta == 0.0) continue;
     int64_t a = g.a, b = g.b;
@@ -597,6 +704,12 @@ void ora_relax(int64_t n, const double *r, const double *m, double *vr, double *
   }
 }
 
+void ora_relax(int64_t n, const double *r, const double *m, double *vr, double *vt,
+               const uint32_t *id, uint64_t seed, uint32_t step, double gamma, double dt) {
+  const draws src = {seed, step, NULL};
+  relax_d(n, r, m, vr, vt, id, &src, gamma, dt);
+}
+
 /* ------------------------------------------------------------------------- */
 /* New orbits (Sec. 2.1 step 5).  Q(r) = 2E - 2Phi(r) - J^2/r^2; the paper
  * brackets each turning point between table radii by bisection, solves it
@@ -626,12 +739,13 @@ static double dq_in(const double *mcum, int64_t k, double x, double J2) {
   return grav + 2.0 * J2 / (x * x * x);
 }
 
-void ora_orbit(int64_t n, const double *r, const double *phi, const double *mcum,
-               const double *ssuf, const double *m, double *vr, double *vt, const uint32_t *id, uint64_t seed,
-               uint32_t step, int32_t trial_cap, double bound_factor, double *r_new,
-               double *E_out, double *J_out, int64_t *kmin_out, int64_t *kmax_out,
-               double *rmin_out, double *rmax_out, int32_t *trials_out,
-               uint32_t *flags_out, ora_orbit_stats *st) {
+static void orbit_d(int64_t n, const double *r, const double *phi, const double *mcum,
+                    const double *ssuf, const double *m, double *vr, double *vt,
+                    const uint32_t *id, const draws *src, int32_t trial_cap,
+                    double bound_factor, double *r_new, double *E_out, double *J_out,
+                    int64_t *kmin_out, int64_t *kmax_out, double *rmin_out,
+                    double *rmax_out, int32_t *trials_out, uint32_t *flags_out,
+                    ora_orbit_stats *st) {
   ora_orbit_stats s;
   memset(&s, 0, sizeof s);
   ksum eesc = {0.0, 0.0};
@@ -730,7 +844,7 @@ void ora_orbit(int64_t n, const double *r, const double *phi, const double *mcum
         int accepted = 0;
         for (int32_t j = 0; j < trial_cap; ++j) {
           uint32_t w[4];
-          draw(seed, id[i], step, ORA_P_ORBIT, (uint32_t)j, w);
+          star_draw(src, id, i, ORA_P_ORBIT, (uint32_t)j, 1, w);
           double X = ora_u01(w[1], w[0]);
           double X2 = ora_u01(w[3], w[2]);
           double s0 = PI * (X - 0.5);
@@ -767,7 +881,7 @@ void ora_orbit(int64_t n, const double *r, const double *phi, const double *mcum
     int64_t kn = interval_of(r, kmin, kmax, rn);
     double qn = 2.0 * E - 2.0 * phi_in(phi, mcum, ssuf, kn, rn) - (J2 == 0.0 ? 0.0 : J2 / (rn * rn));
     uint32_t w[4];
-    draw(seed, id[i], step, ORA_P_SIGN, 0u, w);
+    star_draw(src, id, i, ORA_P_SIGN, 0u, 1, w);
     double vmag = sqrt(qn > 0.0 ? qn : 0.0);
     r_new[i] = rn;
     vr[i] = (w[0] >> 31) ? -vmag : vmag;
@@ -780,15 +894,27 @@ void ora_orbit(int64_t n, const double *r, const double *phi, const double *mcum
   if (st) *st = s;
 }
 
+void ora_orbit(int64_t n, const double *r, const double *phi, const double *mcum,
+               const double *ssuf, const double *m, double *vr, double *vt, const uint32_t *id,
+               uint64_t seed, uint32_t step, int32_t trial_cap, double bound_factor,
+               double *r_new, double *E_out, double *J_out, int64_t *kmin_out,
+               int64_t *kmax_out, double *rmin_out, double *rmax_out, int32_t *trials_out,
+               uint32_t *flags_out, ora_orbit_stats *st) {
+  const draws src = {seed, step, NULL};
+  orbit_d(n, r, phi, mcum, ssuf, m, vr, vt, id, &src, trial_cap, bound_factor, r_new, E_out,
+          J_out, kmin_out, kmax_out, rmin_out, rmax_out, trials_out, flags_out, st);
+}
+
 /* ------------------------------------------------------------------------- */
 void ora_step(int64_t n, double *r, double *vr, double *vt, double *m, uint32_t *id,
               double *phi, double *mcum, const ora_params *p, ora_step_out *out) {
-  ora_step_ex(n, r, vr, vt, m, id, phi, mcum, p, out, NULL);
+  ora_step_ex(n, r, vr, vt, m, id, phi, mcum, p, out, NULL, NULL);
 }
 
 void ora_step_ex(int64_t n, double *r, double *vr, double *vt, double *m, uint32_t *id,
                  double *phi, double *mcum, const ora_params *p, ora_step_out *out,
-                 double *moves) {
+                 double *moves, uint32_t *lfsr) {
+  const draws src = {p->seed, p->step, lfsr};
   size_t nn = (size_t)(n > 0 ? n : 1);
   uint32_t status = 0;
   double *ssuf = (double *)malloc(nn * sizeof(double));
@@ -797,17 +923,17 @@ void ora_step_ex(int64_t n, double *r, double *vr, double *vt, double *m, uint32
   int64_t np = n / 2;
   double *w = (double *)malloc((np > 0 ? (size_t)np : 1) * sizeof(double));
   double *tp = (double *)malloc((np > 0 ? (size_t)np : 1) * sizeof(double));
-  ora_pair_terms(n, r, m, vr, vt, id, p->seed, p->step, p->gamma, w, tp, NULL);
+  pair_terms_d(n, r, m, vr, vt, id, &src, p->gamma, w, tp, NULL);
   double dt = (p->dt_fixed > 0.0) ? p->dt_fixed : ora_solve_dt(np, w, tp, p->target, &status);
   free(w);
   free(tp);
 
-  ora_relax(n, r, m, vr, vt, id, p->seed, p->step, p->gamma, dt);
+  relax_d(n, r, m, vr, vt, id, &src, p->gamma, dt);
 
   double *rn = (double *)malloc(nn * sizeof(double));
   ora_orbit_stats st;
-  ora_orbit(n, r, phi, mcum, ssuf, m, vr, vt, id, p->seed, p->step, p->trial_cap,
-            p->bound_factor, rn, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, &st);
+  orbit_d(n, r, phi, mcum, ssuf, m, vr, vt, id, &src, p->trial_cap, p->bound_factor, rn,
+          NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, &st);
   status |= st.status;
 
   /* The old potential at each star's old and new radius (for the energy
@@ -826,6 +952,7 @@ void ora_step_ex(int64_t n, double *r, double *vr, double *vt, double *m, uint32
   double *t_vt = (double *)malloc(nn * sizeof(double));
   double *t_m = (double *)malloc(nn * sizeof(double));
   uint32_t *t_id = (uint32_t *)malloc(nn * sizeof(uint32_t));
+  uint32_t *t_lfsr = lfsr ? (uint32_t *)malloc(4 * nn * sizeof(uint32_t)) : NULL;
   int64_t kept = 0;
   for (int64_t q = 0; q < n; ++q) {
     int64_t o = perm[q];
@@ -834,6 +961,7 @@ void ora_step_ex(int64_t n, double *r, double *vr, double *vt, double *m, uint32
     t_vt[q] = vt[o];
     t_m[q] = m[o];
     t_id[q] = id[o];
+    if (lfsr) memcpy(t_lfsr + 4 * q, lfsr + 4 * o, 4 * sizeof(uint32_t));
     if (rn[o] < INFINITY) {
       ++kept;
       if (moves) {
@@ -849,6 +977,8 @@ void ora_step_ex(int64_t n, double *r, double *vr, double *vt, double *m, uint32
   memcpy(vt, t_vt, nn * sizeof(double));
   memcpy(m, t_m, nn * sizeof(double));
   memcpy(id, t_id, nn * sizeof(uint32_t));
+  if (lfsr) memcpy(lfsr, t_lfsr, 4 * nn * sizeof(uint32_t));
+  free(t_lfsr);
   free(t_r);
   free(t_vr);
   free(t_vt);

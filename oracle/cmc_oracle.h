@@ -51,6 +51,22 @@ void ora_philox_many(int64_t n, uint64_t key, const uint32_t *ctr, uint32_t *out
 double ora_u01(uint32_t hi, uint32_t lo); /* (2x+1) 2^-53, x = top 52 bits   */
 float ora_u01f(uint32_t hi);              /* (2x+1) 2^-24, x = top 23 bits   */
 
+/* The generator of Sec. 3.6: L'Ecuyer's combined Tausworthe LFSR113 (four
+ * component LFSRs, degrees 31, 29, 28, 25; state z[0..3], component c keeps
+ * the top k_c bits of z[c]; a usable state has each of those parts nonzero).
+ * next: one 32-bit output; block: 4 consecutive outputs (one draw of the
+ * step, in place of one Philox block). */
+uint32_t ora_lfsr113_next(uint32_t z[4]);
+void ora_lfsr113_block(uint32_t z[4], uint32_t w[4]);
+/* z advanced by 2^e steps (the e-fold squared step matrix of each component). */
+void ora_lfsr113_jump_pow2(uint32_t z[4], int e);
+/* Stream `id` of the seed state z0: z0 advanced by id * 2^80 steps, the jump
+ * displacement of Sec. 3.6. */
+void ora_lfsr113_stream(const uint32_t z0[4], uint64_t id, uint32_t z[4]);
+/* Pin helper: steps until component c's state (its top k bits) returns to
+ * that of z, or -1 after `limit` steps. */
+int64_t ora_lfsr113_component_period(int c, uint32_t z, int64_t limit);
+
 /* ---- initial model (Sec. 2.1 opening paragraph) ------------------------- */
 /* Plummer model, unsorted, star i gets id i.  mass_spectrum: 0 = equal
  * masses 1/n, 1 = broken power law (slope -1.3 on [0.1,0.5], -2.3 on
@@ -149,10 +165,13 @@ void ora_step(int64_t n, double *r, double *vr, double *vt, double *m, uint32_t 
 /* ora_step that also reports, for the star at each position q < n_after of
  * the new state, moves[3q..3q+2] = (r_old, Phi_old(r_old), Phi_old(r_new)):
  * its radius before the step and the old potential there and at its new
- * radius.  moves may be NULL. */
+ * radius.  moves may be NULL.  lfsr (4 words per star, or NULL for Philox):
+ * every draw of the step is the next block of the drawing star's own LFSR113
+ * stream -- the pair's first star for a relaxation, the star itself for each
+ * rejection trial and then its sign -- and the states move with the stars. */
 void ora_step_ex(int64_t n, double *r, double *vr, double *vt, double *m, uint32_t *id,
                  double *phi, double *mcum, const ora_params *p, ora_step_out *out,
-                 double *moves);
+                 double *moves, uint32_t *lfsr);
 
 /* ---- energy correction (Sec. 2.1 item 6) ----------------------------------- */
 /* For the state a step produced (n stars, its potential phi) and that step's
