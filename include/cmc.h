@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define CMC_ABI_VERSION 3
+#define CMC_ABI_VERSION 4
 
 /* ---- return codes --------------------------------------------------------- */
 #define CMC_OK 0
@@ -60,6 +60,16 @@ extern "C" {
                        from CMC_FP64 at ~1e-7 relative, and an accept/reject
                        decision within that of its threshold may flip.          */
 
+/* Random numbers of a step (cmc_params.rng).  Every draw is one block of four
+ * 32-bit words: the pair's first star draws one per relaxation, a star one per
+ * rejection trial and one for the sign of its new v_r. */
+#define CMC_RNG_PHILOX 0  /* Philox4x32-10 (Salmon et al. 2011), counter
+                             (star id, step, purpose, trial): stateless       */
+#define CMC_RNG_LFSR113 1 /* the generator of Sec. 3.6: L'Ecuyer's combined
+                             Tausworthe LFSR113, one stream per star, the next
+                             four outputs of the drawing star's stream; the
+                             state (cmc_state.rng) moves with the star       */
+
 /* Initial models of cmc_init_model (and of the ensemble) */
 #define CMC_MODEL_PLUMMER 0 /* Plummer sphere (Sec. 2.1 opening paragraph)      */
 #define CMC_MODEL_KING 1    /* King (1966) model with central potential W0     */
@@ -83,7 +93,8 @@ typedef struct cmc_scalars {
   int64_t reserved[4];
 } cmc_scalars;
 
-/* One cluster.  Every array has `cap` entries of device memory.
+/* One cluster.  Every array has `cap` entries of device memory (rng: 4 cap
+ * words).
  *  r, vr, vt, m, id : the stars, sorted by r on entry to cmc_potential,
  *                     cmc_timestep, cmc_relax and cmc_orbit (SoA).
  *  m                : double, or float when m_f32 != 0.
@@ -94,6 +105,10 @@ typedef struct cmc_scalars {
  *  r_new            : new radius from cmc_orbit, +inf for an escaper; the key
  *                     that cmc_sort orders by.
  *  sc               : device scalars (see cmc_scalars).
+ *  rng              : NULL, or each star's LFSR113 state (4 words, the
+ *                     component words z1..z4) in the order of the stars; when
+ *                     present it moves with its star in every sort.  Needed by
+ *                     steps with CMC_RNG_LFSR113.
  *  work, work_bytes : scratch of at least cmc_workspace_bytes(cap) bytes,
  *                     256-byte aligned; calls leave nothing in it that a later
  *                     call relies on, except the potential table a cmc_step
@@ -110,6 +125,7 @@ typedef struct cmc_state {
   cmc_scalars *sc;
   void *work;
   size_t work_bytes;
+  uint32_t *rng;
 } cmc_state;
 
 /* Parameters of one step. */
@@ -127,7 +143,7 @@ typedef struct cmc_params {
   int32_t trial_cap;   /* rejection trials per star before giving up (10000)      */
   int32_t dt_iters;    /* Newton iterations enqueued for dt; 0 = default (10)     */
   int32_t energy_corr; /* 1: potential-change energy correction (cmc_step)        */
-  int32_t reserved;
+  int32_t rng;         /* CMC_RNG_PHILOX or CMC_RNG_LFSR113 (needs s->rng)        */
 } cmc_params;
 
 /* Bytes of scratch a state of capacity `cap` needs. */
@@ -243,9 +259,25 @@ int cmc_energy_correction(cmc_state *s, void *stream);
 int cmc_diagnostics(const cmc_state *s, double *out_dev, void *stream);
 
 /* Raw Philox4x32-10 blocks: out_dev[4i..4i+3] = Philox(key, ctr_dev[4i..4i+3])
- * for i < n.  The generator every random draw above goes through. */
+ * for i < n.  The generator every random draw above goes through by default. */
 int cmc_philox(uint64_t key, const uint32_t *ctr_dev, uint32_t *out_dev, int64_t n,
                void *stream);
+
+/* LFSR113 streams (Sec. 3.6): s->rng[j] = the seed state z0 (4 words, host
+ * memory, read during the call) advanced by (stream_base + id_j) * 2^80
+ * steps, for j < sc->n.  The paper jumps by D = 2^80 to give each processor
+ * its own stream; here each star has one.  Stream indices must stay below
+ * 2^33 (= 2^113 / 2^80) for streams not to overlap: give the clusters of an
+ * ensemble disjoint ranges through stream_base.  CMC_EINVAL when s->rng is
+ * NULL, a component of z0 has its top k bits all zero (k = 31, 29, 28, 25:
+ * z1 < 2, z2 < 8, z3 < 16, z4 < 128), or stream_base >= 2^33. */
+int cmc_rng_seed_lfsr113(cmc_state *s, const uint32_t *z0, uint64_t stream_base, void *stream);
+
+/* Raw LFSR113 words: for each of the n states state_dev[4i..4i+3],
+ * out_dev[4(i blocks + b) .. +3] = its block b < blocks (4 consecutive
+ * outputs).  The states are not changed. */
+int cmc_lfsr113(const uint32_t *state_dev, uint32_t *out_dev, int64_t n, int32_t blocks,
+                void *stream);
 
 /* ---- ensembles ----------------------------------------------------------------
  * Independent clusters of uneven N advanced together: every kernel of a step
@@ -280,7 +312,8 @@ typedef struct cmc_batch {
   int32_t top_entries;          /* LDS entries of the orbit table's top levels   */
   int32_t bucket_sort;          /* 1: the step sorts by buckets (every capacity  */
                                 /*    <= CMC_BUCKET_CAP_MAX), 0: radix sort      */
-  int32_t reserved[2];
+  int32_t lfsr_ready;           /* 1: every cluster has an rng array             */
+  int32_t reserved;
 } cmc_batch;
 
 /* Device bytes of the ensemble tables for these states (0 if invalid). */
@@ -298,7 +331,7 @@ int cmc_batch_prepare(cmc_batch *b, const cmc_state *states, const cmc_cluster_s
 int cmc_batch_init(const cmc_batch *b, void *stream);
 
 /* One step of every cluster (as cmc_step); p->seed and p->gamma are ignored
- * (each cluster has its own).  With p->step == CMC_STEP_DEVICE the step index
+ * (each cluster has its own); CMC_RNG_LFSR113 needs b->lfsr_ready.  With p->step == CMC_STEP_DEVICE the step index
  * is each cluster's sc->step, advanced at the end: a call captured once in a
  * hipGraph then advances the ensemble each time the graph is replayed. */
 int cmc_batch_step(const cmc_batch *b, const cmc_params *p, void *stream);

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libcmc.so")
 CMC_OK, CMC_EINVAL, CMC_EWORKSPACE, CMC_EHIP, CMC_ERANGE = 0, -1, -2, -3, -4
 CMC_FP64, CMC_MIXED = 0, 1
 CMC_MODEL_PLUMMER, CMC_MODEL_KING = 0, 1
+CMC_RNG_PHILOX, CMC_RNG_LFSR113 = 0, 1
 CMC_STEP_DEVICE = 0xFFFFFFFF
 CMC_BUCKET_CAP_MAX = 16383 * 2048 - 1
 CMC_DIAG_N = 11
@@ -23,7 +24,8 @@ ST_DT_DEGEN, ST_NUMERIC, ST_DT_NOCONV = 0x10, 0x20, 0x40
 
 EXPORTS = ("cmc_workspace_bytes", "cmc_init_plummer", "cmc_init_model", "cmc_sort", "cmc_potential",
            "cmc_timestep", "cmc_relax", "cmc_orbit", "cmc_step", "cmc_step_timed",
-           "cmc_energy_correction", "cmc_diagnostics", "cmc_philox", "cmc_strerror",
+           "cmc_energy_correction", "cmc_diagnostics", "cmc_philox", "cmc_rng_seed_lfsr113",
+           "cmc_lfsr113", "cmc_strerror",
            "cmc_abi_version", "cmc_batch_device_bytes", "cmc_batch_prepare", "cmc_batch_init",
            "cmc_batch_step", "cmc_batch_potential", "cmc_batch_energy_correction",
            "cmc_batch_diagnostics")
@@ -43,14 +45,15 @@ class cmc_state(C.Structure):
                 ("vt", C.c_void_p), ("m", C.c_void_p), ("m_f32", C.c_int32),
                 ("reserved0", C.c_int32), ("id", C.c_void_p), ("phi", C.c_void_p),
                 ("mcum", C.c_void_p), ("ssuf", C.c_void_p), ("r_new", C.c_void_p),
-                ("sc", C.c_void_p), ("work", C.c_void_p), ("work_bytes", C.c_size_t)]
+                ("sc", C.c_void_p), ("work", C.c_void_p), ("work_bytes", C.c_size_t),
+                ("rng", C.c_void_p)]
 
 
 class cmc_params(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("step", C.c_uint32), ("precision", C.c_int32),
                 ("gamma", C.c_double), ("target", C.c_double), ("bound_factor", C.c_double),
                 ("trial_cap", C.c_int32), ("dt_iters", C.c_int32),
-                ("energy_corr", C.c_int32), ("reserved", C.c_int32)]
+                ("energy_corr", C.c_int32), ("rng", C.c_int32)]
 
 
 class cmc_cluster_spec(C.Structure):
@@ -62,7 +65,7 @@ class cmc_batch(C.Structure):
     _fields_ = [("clusters", C.c_int32), ("m_f32", C.c_int32), ("dev", C.c_void_p),
                 ("dev_bytes", C.c_size_t), ("total", C.c_int64 * CMC_SHAPES),
                 ("top_entries", C.c_int32), ("bucket_sort", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("lfsr_ready", C.c_int32), ("reserved", C.c_int32)]
 
 
 assert C.sizeof(cmc_scalars) == 128
@@ -108,6 +111,8 @@ def lib() -> C.CDLL:
         L.cmc_batch_energy_correction.argtypes = [bp, vp]
         L.cmc_diagnostics.argtypes = [sp, vp, vp]
         L.cmc_philox.argtypes = [C.c_uint64, vp, vp, C.c_int64, vp]
+        L.cmc_rng_seed_lfsr113.argtypes = [sp, C.POINTER(C.c_uint32), C.c_uint64, vp]
+        L.cmc_lfsr113.argtypes = [vp, vp, C.c_int64, C.c_int32, vp]
         L.cmc_strerror.argtypes = [C.c_int]
         L.cmc_strerror.restype = C.c_char_p
         L.cmc_abi_version.restype = C.c_int  # every other call returns int too

@@ -27,11 +27,12 @@ class Params:
     trial_cap: int = 10000
     dt_iters: int = 0
     energy_corr: int = 0
+    rng: int = A.CMC_RNG_PHILOX
 
     def c(self) -> A.cmc_params:
         return A.cmc_params(self.seed, self.step, self.precision, self.gamma, self.target,
                             self.bound_factor, self.trial_cap, self.dt_iters,
-                            self.energy_corr, 0)
+                            self.energy_corr, self.rng)
 
 
 def _stream(stream=None):
@@ -40,9 +41,10 @@ def _stream(stream=None):
 
 
 class Cluster:
-    """Device arrays of one cluster of capacity ``cap`` (see cmc_state)."""
+    """Device arrays of one cluster of capacity ``cap`` (see cmc_state).
+    rng: also allocate the per-star LFSR113 stream states."""
 
-    def __init__(self, cap: int, m_f32: bool = False, device: str = "cuda"):
+    def __init__(self, cap: int, m_f32: bool = False, device: str = "cuda", rng: bool = False):
         if cap <= 0:
             raise ValueError("cap must be positive")
         L = A.lib()
@@ -60,6 +62,7 @@ class Cluster:
         self.ssuf = torch.zeros(cap, **f64)
         self.r_new = torch.zeros(cap, **f64)
         self.sc = torch.zeros(16, dtype=torch.int64, device=dev)
+        self.rng = torch.zeros(4 * cap, dtype=torch.int32, device=dev) if rng else None
         nbytes = int(L.cmc_workspace_bytes(cap))
         if nbytes == 0:
             raise A.CmcError("capacity out of range")
@@ -69,7 +72,8 @@ class Cluster:
         self._c = A.cmc_state(cap, self.r.data_ptr(), self.vr.data_ptr(), self.vt.data_ptr(),
                               self.m.data_ptr(), 1 if m_f32 else 0, 0, self.id.data_ptr(),
                               self.phi.data_ptr(), self.mcum.data_ptr(), self.ssuf.data_ptr(),
-                              self.r_new.data_ptr(), self.sc.data_ptr(), base + off, nbytes)
+                              self.r_new.data_ptr(), self.sc.data_ptr(), base + off, nbytes,
+                              self.rng.data_ptr() if rng else None)
 
     # ------------------------------------------------------------ host views
     def scalars(self) -> dict:
@@ -87,8 +91,9 @@ class Cluster:
         buf = np.frombuffer(bytes(s), dtype=np.int64).copy()
         self.sc.copy_(torch.from_numpy(buf))
 
-    def load(self, r, vr, vt, m, id_) -> None:
-        """Upload a host state (first len(r) entries) and set n."""
+    def load(self, r, vr, vt, m, id_, rng=None) -> None:
+        """Upload a host state (first len(r) entries; rng: (n, 4) LFSR113
+        states) and set n."""
         n = len(r)
         if n > self.cap:
             raise A.CmcError("n > cap")
@@ -99,6 +104,9 @@ class Cluster:
         mt = np.float32 if self.m_f32 else np.float64
         self.m[:n] = torch.as_tensor(np.asarray(m, mt), device=dev)
         self.id[:n] = torch.as_tensor(np.asarray(id_, np.uint32).view(np.int32), device=dev)
+        if rng is not None:
+            z = np.ascontiguousarray(rng, np.uint32).reshape(-1)
+            self.rng[:4 * n] = torch.as_tensor(z.view(np.int32), device=dev)
         self.set_scalar("n", n)
 
     def capture(self, p: Params) -> torch.cuda.CUDAGraph:
@@ -121,6 +129,8 @@ class Cluster:
                ("r", "vr", "vt", "phi", "mcum", "ssuf", "r_new")}
         out["m"] = self.m[:n].cpu().numpy().astype(np.float64)
         out["id"] = self.id[:n].cpu().numpy().view(np.uint32)
+        if self.rng is not None:
+            out["rng"] = self.rng[:4 * n].cpu().numpy().view(np.uint32).reshape(n, 4)
         return out
 
     @property
@@ -189,6 +199,25 @@ def cmc_philox(key: int, ctr: np.ndarray, device: str = "cuda", stream=None) -> 
     return do.cpu().numpy().view(np.uint32)
 
 
+def cmc_rng_seed_lfsr113(cl: Cluster, z0, stream_base: int = 0, stream=None):
+    """Every star's LFSR113 state: z0 advanced by (stream_base + id) * 2^80."""
+    z = (C.c_uint32 * 4)(*[int(x) for x in z0])
+    A.check(A.lib().cmc_rng_seed_lfsr113(cl.c, z, int(stream_base), _stream(stream)),
+            "cmc_rng_seed_lfsr113")
+
+
+def cmc_lfsr113(states: np.ndarray, blocks: int, device: str = "cuda",
+                stream=None) -> np.ndarray:
+    """Raw LFSR113 words: (n, blocks, 4) from n states (n, 4)."""
+    z = np.ascontiguousarray(states, dtype=np.uint32).reshape(-1, 4)
+    n = z.shape[0]
+    dz = torch.as_tensor(z.view(np.int32), device=device)
+    do = torch.zeros(n * blocks * 4, dtype=torch.int32, device=device)
+    A.check(A.lib().cmc_lfsr113(C.c_void_p(dz.data_ptr()), C.c_void_p(do.data_ptr()), n,
+                                blocks, _stream(stream)), "cmc_lfsr113")
+    return do.cpu().numpy().view(np.uint32).reshape(n, blocks, 4)
+
+
 def cmc_step_timed(cl: Cluster, p: Params, events, stream=None):
     """cmc_step recording the six HIP events ``events`` (raw hipEvent_t
     handles, see hipevents.EventSet) around its five phases."""
@@ -207,10 +236,10 @@ class Ensemble:
     specs: one dict per cluster with keys n, seed, gamma, model, and
     optionally mass_spectrum, w0, cap (default n)."""
 
-    def __init__(self, specs, m_f32: bool = False, device: str = "cuda"):
+    def __init__(self, specs, m_f32: bool = False, device: str = "cuda", rng: bool = False):
         L = A.lib()
         self.specs = [dict(s) for s in specs]
-        self.clusters = [Cluster(int(s.get("cap", s["n"])), m_f32=m_f32, device=device)
+        self.clusters = [Cluster(int(s.get("cap", s["n"])), m_f32=m_f32, device=device, rng=rng)
                          for s in self.specs]
         k = len(self.clusters)
         self._states = (A.cmc_state * k)(*[cl._c for cl in self.clusters])
@@ -233,6 +262,14 @@ class Ensemble:
 
     def init(self, stream=None):
         A.check(A.lib().cmc_batch_init(C.byref(self.handle), _stream(stream)), "cmc_batch_init")
+
+    def seed_lfsr113(self, z0, stream=None):
+        """Each cluster's stars get LFSR113 streams; cluster c's stream indices
+        start after the capacities of the clusters before it."""
+        base = 0
+        for cl in self.clusters:
+            cmc_rng_seed_lfsr113(cl, z0, base, stream)
+            base += cl.cap
 
     def step(self, p: Params, stream=None):
         pc = p.c()

@@ -141,7 +141,7 @@ int cmc_batch_prepare(cmc_batch *b, const cmc_state *states, const cmc_cluster_s
   if (rc) return rc;
   const cmc::BatchLayout L = cmc::batch_layout(clusters, total);
   if (dev_bytes < L.bytes) return CMC_EWORKSPACE;
-  int32_t top = 0, bucket = 1;
+  int32_t top = 0, bucket = 1, lfsr = 1;
   for (int c = 0; c < clusters; ++c) {
     const cmc_cluster_spec &sp = specs[c];
     if (sp.n < 0) return CMC_EINVAL;
@@ -160,6 +160,7 @@ int cmc_batch_prepare(cmc_batch *b, const cmc_state *states, const cmc_cluster_s
     a.bracket_blocks = blocks[cmc::kShBracket][c];
     top = std::max(top, a.top.entries);
     if (a.w.bkt_bins == 0) bucket = 0;
+    if (!states[c].rng) lfsr = 0;
   }
   // tables: arguments, first block of each cluster per shape, block maps
   std::vector<char> host(L.bytes, 0);
@@ -184,7 +185,8 @@ int cmc_batch_prepare(cmc_batch *b, const cmc_state *states, const cmc_cluster_s
   for (int sh = 0; sh < CMC_SHAPES; ++sh) b->total[sh] = sh < cmc::kShapes ? total[sh] : 0;
   b->top_entries = top;
   b->bucket_sort = bucket;
-  b->reserved[0] = b->reserved[1] = 0;
+  b->lfsr_ready = lfsr;
+  b->reserved = 0;
   return CMC_OK;
 }
 
@@ -203,6 +205,8 @@ int cmc_batch_step(const cmc_batch *b, const cmc_params *p, void *stream) {
   if (!(p->target > 0.0 && p->target < 1.0)) return CMC_EINVAL;
   if (p->bound_factor < 0.0 || p->trial_cap < 0 || p->dt_iters < 0) return CMC_EINVAL;
   if (p->energy_corr != 0 && p->energy_corr != 1) return CMC_EINVAL;
+  if (p->rng != CMC_RNG_PHILOX && p->rng != CMC_RNG_LFSR113) return CMC_EINVAL;
+  if (p->rng == CMC_RNG_LFSR113 && !b->lfsr_ready) return CMC_EINVAL;
   const cmc::BatchDev d = cmc::batch_dev(*b);
   return cmc::status_of(cmc::launch_step(cmc::Target{nullptr, &d}, b->m_f32 != 0, *p, nullptr,
                                          static_cast<hipStream_t>(stream)));

@@ -258,7 +258,8 @@ __device__ void merge_step(const uint64_t *sk, const uint32_t *sv, uint64_t *dk,
 }
 
 // The staged records in the order of V's staged indices, into the state at
-// out .. out + count (and, with corr, each star's staged index into perm).
+// out .. out + count (and, with corr, each star's staged index into perm; a
+// state with LFSR113 streams takes each star's staged stream state along).
 template <typename MT>
 __device__ __forceinline__ void gather(const ClusterArgs &A, const uint32_t *V, int64_t out,
                                        int64_t count, int corr) {
@@ -282,6 +283,7 @@ __device__ __forceinline__ void gather(const ClusterArgs &A, const uint32_t *V, 
       if (p < count) {
         put_star<MT>(A, out + p, rec[q]);
         if (corr) A.w.perm[out + p] = src[q];
+        if (A.s.rng) store_lfsr(A.s.rng, out + p, A.w.rng_stage[src[q]]);
       }
     }
   }

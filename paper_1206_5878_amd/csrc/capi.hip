@@ -45,7 +45,7 @@ hipError_t launch_step(const Target &t, bool m_f32, const cmc_params &p, void *c
   if (e == hipSuccess) e = mark(4);
   if (e == hipSuccess) {
     e = bucket_sort_of(t) ? launch_bucket_sort(t, m_f32, corr, st)
-                          : launch_sort_stage(t, m_f32, false, true, corr, st);
+                          : launch_sort_stage(t, m_f32, false, true, corr, true, st);
   }
   if (e == hipSuccess && p.step == CMC_STEP_DEVICE) e = launch_step_advance(t, st);
   if (e == hipSuccess) e = mark(5);
@@ -77,7 +77,14 @@ int check_params(const cmc_params *p) {
   if (!(p->gamma > 0.0) || !(p->target > 0.0 && p->target < 1.0)) return CMC_EINVAL;
   if (p->bound_factor < 0.0 || p->trial_cap < 0 || p->dt_iters < 0) return CMC_EINVAL;
   if (p->energy_corr != 0 && p->energy_corr != 1) return CMC_EINVAL;
+  if (p->rng != CMC_RNG_PHILOX && p->rng != CMC_RNG_LFSR113) return CMC_EINVAL;
   return CMC_OK;
+}
+
+// A step, timestep, relaxation or orbit call that draws from LFSR113 streams
+// needs the state's stream array.
+int check_rng(const cmc_state *s, const cmc_params *p) {
+  return (p->rng == CMC_RNG_LFSR113 && !s->rng) ? CMC_EINVAL : CMC_OK;
 }
 
 int status_of(hipError_t e) { return e == hipSuccess ? CMC_OK : CMC_EHIP; }
@@ -152,7 +159,8 @@ int cmc_sort(cmc_state *s, void *stream) {
   hipError_t e = cmc::launch_stage_from_state(one.t(), s->m_f32 != 0, as_stream(stream));
   if (e != hipSuccess) return CMC_EHIP;
   return status_of(
-      cmc::launch_sort_stage(one.t(), s->m_f32 != 0, false, false, false, as_stream(stream)));
+      cmc::launch_sort_stage(one.t(), s->m_f32 != 0, false, false, false, true,
+                             as_stream(stream)));
 }
 
 int cmc_potential(cmc_state *s, int32_t precision, void *stream) {
@@ -170,6 +178,7 @@ int cmc_timestep(cmc_state *s, const cmc_params *p, void *stream) {
   int rc = check_state(s, &w);
   if (rc) return rc;
   if ((rc = check_params(p))) return rc;
+  if ((rc = check_rng(s, p))) return rc;
   const Single one = single(*s, p->seed, p->gamma);
   return status_of(cmc::launch_timestep(one.t(), s->m_f32 != 0, *p, as_stream(stream)));
 }
@@ -179,6 +188,7 @@ int cmc_relax(cmc_state *s, const cmc_params *p, void *stream) {
   int rc = check_state(s, &w);
   if (rc) return rc;
   if ((rc = check_params(p))) return rc;
+  if ((rc = check_rng(s, p))) return rc;
   const Single one = single(*s, p->seed, p->gamma);
   return status_of(cmc::launch_relax(one.t(), s->m_f32 != 0, *p, as_stream(stream)));
 }
@@ -188,6 +198,7 @@ int cmc_orbit(cmc_state *s, const cmc_params *p, void *stream) {
   int rc = check_state(s, &w);
   if (rc) return rc;
   if ((rc = check_params(p))) return rc;
+  if ((rc = check_rng(s, p))) return rc;
   const Single one = single(*s, p->seed, p->gamma);
   hipError_t e = cmc::launch_table_pack(one.t(), as_stream(stream));
   if (e == hipSuccess)
@@ -201,6 +212,7 @@ static int run_step(cmc_state *s, const cmc_params *p, void *const *events, hipS
   int rc = check_state(s, &w);
   if (rc) return rc;
   if ((rc = check_params(p))) return rc;
+  if ((rc = check_rng(s, p))) return rc;
   const Single one = single(*s, p->seed, p->gamma);
   return status_of(cmc::launch_step(one.t(), s->m_f32 != 0, *p, events, st));
 }
@@ -237,6 +249,25 @@ int cmc_philox(uint64_t key, const uint32_t *ctr_dev, uint32_t *out_dev, int64_t
                void *stream) {
   if (n < 0 || (n > 0 && (!ctr_dev || !out_dev))) return CMC_EINVAL;
   return status_of(cmc::launch_philox(key, ctr_dev, out_dev, n, as_stream(stream)));
+}
+
+int cmc_rng_seed_lfsr113(cmc_state *s, const uint32_t *z0, uint64_t stream_base, void *stream) {
+  Workspace w;
+  int rc = check_state(s, &w);
+  if (rc) return rc;
+  if (!s->rng || !z0 || stream_base >= (uint64_t(1) << 33)) return CMC_EINVAL;
+  // each component needs a nonzero state in its top k bits (k = 31, 29, 28, 25)
+  if (z0[0] < 2u || z0[1] < 8u || z0[2] < 16u || z0[3] < 128u) return CMC_EINVAL;
+  const uint32_t z[4] = {z0[0], z0[1], z0[2], z0[3]};
+  const Single one = single(*s, 0, 1.0);
+  return status_of(cmc::launch_lfsr_seed(one.t(), z, stream_base, as_stream(stream)));
+}
+
+int cmc_lfsr113(const uint32_t *state_dev, uint32_t *out_dev, int64_t n, int32_t blocks,
+                void *stream) {
+  if (n < 0 || blocks < 0 || (n > 0 && blocks > 0 && (!state_dev || !out_dev)))
+    return CMC_EINVAL;
+  return status_of(cmc::launch_lfsr_words(state_dev, out_dev, n, blocks, as_stream(stream)));
 }
 
 }  // extern "C"

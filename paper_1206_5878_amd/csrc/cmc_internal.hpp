@@ -60,6 +60,48 @@ __device__ __forceinline__ float u01f(uint32_t hi) {
   return static_cast<float>(2 * (hi >> 9) + 1) * 0x1.0p-24f;
 }
 
+// ---------------------------------------------------------------- LFSR113
+// The generator of Sec. 3.6: L'Ecuyer's combined Tausworthe LFSR113.  Four
+// component LFSRs of degrees k = 31, 29, 28, 25 with (q, s) = (6, 18),
+// (2, 2), (13, 7), (3, 13); component c keeps the top k bits of its word and
+// steps as b = ((z << q) ^ z) >> (k - s), z = ((z & top k bits) << s) ^ b;
+// an output is the XOR of the four words.  A draw is one block of four
+// consecutive outputs, in place of one Philox block.
+struct alignas(16) Lfsr {
+  uint32_t z[4];
+};
+
+template <int K, int Q, int S>
+__device__ __forceinline__ uint32_t taus_step(uint32_t z) {
+  const uint32_t b = ((z << Q) ^ z) >> (K - S);
+  return ((z & (~0u << (32 - K))) << S) ^ b;
+}
+
+__device__ __forceinline__ uint32_t lfsr_next(Lfsr &g) {
+  g.z[0] = taus_step<31, 6, 18>(g.z[0]);
+  g.z[1] = taus_step<29, 2, 2>(g.z[1]);
+  g.z[2] = taus_step<28, 13, 7>(g.z[2]);
+  g.z[3] = taus_step<25, 3, 13>(g.z[3]);
+  return g.z[0] ^ g.z[1] ^ g.z[2] ^ g.z[3];
+}
+
+__device__ __forceinline__ U4 lfsr_block(Lfsr &g) {
+  U4 w;
+  w.x = lfsr_next(g);
+  w.y = lfsr_next(g);
+  w.z = lfsr_next(g);
+  w.w = lfsr_next(g);
+  return w;
+}
+
+// A star's LFSR113 state in cmc_state.rng (4 words per star).
+__device__ __forceinline__ Lfsr load_lfsr(const uint32_t *rng, int64_t k) {
+  return reinterpret_cast<const Lfsr *>(rng)[k];
+}
+__device__ __forceinline__ void store_lfsr(uint32_t *rng, int64_t k, const Lfsr &g) {
+  reinterpret_cast<Lfsr *>(rng)[k] = g;
+}
+
 // ---------------------------------------------------------------- reductions
 // Deterministic: fixed butterfly inside a wave, fixed order across waves.
 template <typename T>
@@ -273,6 +315,11 @@ constexpr int kBucketSortCap = 4096;    // stars a bucket sorts in LDS
 constexpr uint32_t kBucketEsc = 0xFFFFFFFFu;  // bkey of a star that leaves the cluster
 constexpr int kKingTab = 3 * kKingNodes + 8;
 constexpr int kPhiBins = 16384;  // bins of the potential-bound table (orbit.hip)
+// LFSR113 stream seeding (rng.hip): for each component, the 32x32 bit matrix
+// of 2^(80+b) steps for every bit b of a stream index (a base below 2^33
+// plus a 32-bit star id), as 32 columns.
+constexpr int kLfsrStreamBits = 34;
+constexpr int kLfsrJumpWords = 4 * kLfsrStreamBits * 32;
 
 struct Workspace {
   RPhi *lev[kMaxLevels];    // level L: [ceil(cap / 8^L)]
@@ -307,6 +354,8 @@ struct Workspace {
   RPhi *cor;                // [cap] energy correction, old order: (r_old, Phi_old(r_old))
   double *pn;               // [cap] Phi_old(r_new), then the summed work terms
   uint32_t *perm;           // [cap] staged (old) index of each sorted star
+  Lfsr *rng_stage;          // [cap] LFSR113 states after the orbit pass, staged order
+  uint32_t *lfsr_jump;      // [kLfsrJumpWords] jump matrices of the stream seeding
   int64_t bkt_bins, bkt_tiles;  // bkt_bins = 0: capacity above kBucketCapMax
   int64_t rx_nb;
   int rx_lg_nb;
@@ -372,6 +421,8 @@ inline Workspace layout(int64_t cap, void *base) {
   w.cor = reinterpret_cast<RPhi *>(take(sizeof(RPhi) * c));
   w.pn = reinterpret_cast<double *>(take(8 * c));
   w.perm = reinterpret_cast<uint32_t *>(take(4 * c));
+  w.rng_stage = reinterpret_cast<Lfsr *>(take(sizeof(Lfsr) * c));
+  w.lfsr_jump = reinterpret_cast<uint32_t *>(take(4 * kLfsrJumpWords));
   w.bent = reinterpret_cast<BktEnt *>(w.orec);  // orec is dead once the orbit pass ends
   static_assert(sizeof(BktEnt) <= sizeof(OrbitRec), "bent fits in orec");
   if (c <= kBucketCapMax) {
@@ -562,11 +613,16 @@ hipError_t launch_stage_from_state(const Target &t, bool m_f32, hipStream_t st);
 // (StageRec<mass type>) or WideRec.  corr: write perm and leave the energy
 // correction pending (sc->corr_n = staged stars); else clear it.
 hipError_t launch_sort_stage(const Target &t, bool m_f32, bool normalise_mass, bool step_records,
-                             bool corr, hipStream_t st);
+                             bool corr, bool move_rng, hipStream_t st);
 hipError_t launch_init(const Target &t, bool m_f32, hipStream_t st);
 hipError_t launch_diagnostics(const Target &t, bool m_f32, double *out, hipStream_t st);
 hipError_t launch_philox(uint64_t key, const uint32_t *ctr, uint32_t *out, int64_t n,
                          hipStream_t st);
+// LFSR113 (rng.hip): every star's stream state, and raw words.
+hipError_t launch_lfsr_seed(const Target &t, const uint32_t z0[4], uint64_t stream_base,
+                            hipStream_t st);
+hipError_t launch_lfsr_words(const uint32_t *state, uint32_t *out, int64_t n, int32_t blocks,
+                             hipStream_t st);
 hipError_t launch_step(const Target &t, bool m_f32, const cmc_params &p, void *const *events,
                        hipStream_t st);
 hipError_t launch_step_advance(const Target &t, hipStream_t st);

@@ -275,7 +275,7 @@ hipError_t launch_init(const Target &t, bool m_f32, hipStream_t st) {
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;
-  return launch_sort_stage(t, m_f32, true, false, false, st);
+  return launch_sort_stage(t, m_f32, true, false, false, false, st);
 }
 
 }  // namespace cmc

@@ -12,7 +12,9 @@
 //
 // For the energy correction of Sec. 2.1 item 6 (energy.hip) a step can also
 // record, per star in this pass's order, (r_old, Phi_old(r_old)) and the old
-// potential at the new radius, Phi_old(r_new).
+// potential at the new radius, Phi_old(r_new).  Draws come from Philox or,
+// with the LFSR113 generator of Sec. 3.6, from the star's own stream, whose
+// state then leaves with the staged star.
 //
 // Two kernels.  k_orbit_bracket: brackets, roots and the rejection bound F
 // of every star, written as a 48-byte orbit record (escapers and degenerate
@@ -298,13 +300,12 @@ __device__ __forceinline__ void emit(int64_t i, double rn, double vrn, double vt
 }
 
 // New velocity from Q at the new radius: J conserved, E conserved in the old
-// potential, random sign of v_r.
-__device__ __forceinline__ void finish(double rn, double qn, double J, double J2, uint32_t sid,
-                                       uint32_t step, uint64_t seed, double &vrn, double &vtn,
+// potential, the sign of v_r from the top bit of the sign draw's first word.
+__device__ __forceinline__ void finish(double rn, double qn, double J, double J2,
+                                       uint32_t sign_word, double &vrn, double &vtn,
                                        uint32_t &fl) {
-  const U4 w = philox(sid, step, kSign, 0u, seed);
   const double vmag = sqrt(qn > 0.0 ? qn : 0.0);
-  vrn = (w.x >> 31) ? -vmag : vmag;
+  vrn = (sign_word >> 31) ? -vmag : vmag;
   vtn = (J2 == 0.0) ? 0.0 : J / rn;
   if (!isfinite(rn) || !isfinite(vrn) || !isfinite(vtn)) fl |= CMC_ST_NONFINITE;
 }
@@ -318,7 +319,16 @@ __device__ __forceinline__ void or_status(cmc_scalars *sc, uint32_t fl) {
   }
 }
 
-template <class Ctx, typename MT, bool TO_STAGE>
+// The star's LFSR113 state after its draws: staged for the sort, or in place.
+template <bool TO_STAGE>
+__device__ __forceinline__ void put_lfsr(const ClusterArgs &A, int64_t i, const Lfsr &g) {
+  if (TO_STAGE)
+    A.w.rng_stage[i] = g;
+  else
+    store_lfsr(A.s.rng, i, g);
+}
+
+template <class Ctx, typename MT, bool TO_STAGE, bool LF>
 __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4)))
 void k_orbit_bracket(Ctx ctx, uint32_t step_arg, double bound_factor, int corr) {
   extern __shared__ RPhi top[];
@@ -362,6 +372,9 @@ void k_orbit_bracket(Ctx ctx, uint32_t step_arg, double bound_factor, int corr) 
     if (i < n) {
       const RPhi me = tab[i];
       if (corr) cor[i] = me;  // r_old and Phi_old(r_old)
+      // an LFSR113 state moves with its star: staged here, replaced below by
+      // the stars that draw
+      if (TO_STAGE && A.s.rng) A.w.rng_stage[i] = load_lfsr(A.s.rng, i);
       vri = vr[i];
       vti = vt[i];
       E = me.phi + 0.5 * (vri * vri + vti * vti);
@@ -444,8 +457,16 @@ void k_orbit_bracket(Ctx ctx, uint32_t step_arg, double bound_factor, int corr) 
           const double phn = phi_in(lv, ms, kn, rn);
           const double qn = 2.0 * E - 2.0 * phn - (J2 == 0.0 ? 0.0 : J2 / (rn * rn));
           if (corr) pn[i] = phn;
+          U4 ws;
+          if (LF) {
+            Lfsr g = load_lfsr(A.s.rng, i);
+            ws = lfsr_block(g);
+            put_lfsr<TO_STAGE>(A, i, g);
+          } else {
+            ws = philox(id[i], step, kSign, 0u, seed);
+          }
           double vrn, vtn;
-          finish(rn, qn, J, J2, id[i], step, seed, vrn, vtn, fl);
+          finish(rn, qn, J, J2, ws.x, vrn, vtn, fl);
           emit<TO_STAGE>(i, rn, vrn, vtn, m[i], id[i], rindex_last_le(ix, ictl, rn) + 1, r_new,
                          vr, vt, stage, keys, bkey);
         }
@@ -462,7 +483,7 @@ void k_orbit_bracket(Ctx ctx, uint32_t step_arg, double bound_factor, int corr) 
   }
 }
 
-template <class Ctx, typename MT, bool TO_STAGE, bool MIXED>
+template <class Ctx, typename MT, bool TO_STAGE, bool MIXED, bool LF>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5)))
 void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap, int corr) {
   __shared__ double shd[NT / 64];
@@ -506,6 +527,7 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap, int corr) {
   uint32_t sid = 0;
   int32_t j = 0;
   double r0 = 0.0;
+  Lfsr lg{};  // the star's LFSR113 stream (LF)
 
   for (;;) {
     // idle lanes take the chunk's next stars that still need trials
@@ -529,6 +551,7 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap, int corr) {
           kmax = o.kmax;
           sid = id[mine];
           j = 0;
+          if (LF) lg = load_lfsr(A.s.rng, mine);
         }
       }
     }
@@ -536,7 +559,7 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap, int corr) {
     // one rejection trial per busy lane; the interval search runs in groups
     double X2 = 0.0, cs = 0.0;
     if (busy) {
-      const U4 w = philox(sid, step, kOrbit, static_cast<uint32_t>(j), seed);
+      const U4 w = LF ? lfsr_block(lg) : philox(sid, step, kOrbit, static_cast<uint32_t>(j), seed);
       if (MIXED) {
         // Trial angle and acceptance in FP32.  With s = pi (X - 1/2), the
         // offset of r from the nearer turning point is r_a (1 - |sin s|) =
@@ -609,8 +632,10 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap, int corr) {
       if (done) {
         const double rn = r0 + 0.0;
         if (corr) pn[i] = phn;  // Phi_old(r_new)
+        const U4 ws = LF ? lfsr_block(lg) : philox(sid, step, kSign, 0u, seed);
+        if (LF) put_lfsr<TO_STAGE>(A, i, lg);
         double vrn, vtn;
-        finish(rn, qn, J, J2, sid, step, seed, vrn, vtn, fl);
+        finish(rn, qn, J, J2, ws.x, vrn, vtn, fl);
         emit<TO_STAGE>(i, rn, vrn, vtn, m[i], sid, kg + 1, r_new, vr, vt, stage, keys, bkey);
         busy = false;
       }
@@ -692,21 +717,21 @@ __global__ __launch_bounds__(NT) void k_table_pack(Ctx ctx) {
   put_table(levels_of(A.w), A.w.ms, k, A.s.r[k], A.s.phi[k], A.s.mcum[k], A.s.ssuf[k]);
 }
 
-template <class L, typename MT, bool TO_STAGE>
+template <class L, typename MT, bool TO_STAGE, bool LF>
 hipError_t run2(const L &l, const cmc_params &p, int corr, hipStream_t st) {
   const int32_t cap = p.trial_cap > 0 ? p.trial_cap : 10000;
   const double bf = p.bound_factor > 0.0 ? p.bound_factor : 1.2;
   using Cb = decltype(l.ctx(kShBracket));
   using Ct = decltype(l.ctx(kShTrials));
   k_phi_bounds<<<l.grid(kShDiag), NT, 0, st>>>(l.ctx(kShDiag));
-  k_orbit_bracket<Cb, MT, TO_STAGE>
+  k_orbit_bracket<Cb, MT, TO_STAGE, LF>
       <<<l.grid(kShBracket), BT, sizeof(RPhi) * l.top_entries(), st>>>(l.ctx(kShBracket), p.step,
                                                                        bf, corr);
   if (p.precision == CMC_MIXED)
-    k_orbit_trials<Ct, MT, TO_STAGE, true><<<l.grid(kShTrials), NT, 0, st>>>(l.ctx(kShTrials),
-                                                                             p.step, cap, corr);
+    k_orbit_trials<Ct, MT, TO_STAGE, true, LF><<<l.grid(kShTrials), NT, 0, st>>>(
+        l.ctx(kShTrials), p.step, cap, corr);
   else
-    k_orbit_trials<Ct, MT, TO_STAGE, false><<<l.grid(kShTrials), NT, 0, st>>>(
+    k_orbit_trials<Ct, MT, TO_STAGE, false, LF><<<l.grid(kShTrials), NT, 0, st>>>(
         l.ctx(kShTrials), p.step, cap, corr);
   k_orbit_sum<<<l.grid(kShOne), FT, 0, st>>>(l.ctx(kShOne));
   return hipGetLastError();
@@ -749,11 +774,21 @@ hipError_t launch_orbit(const Target &t, bool m_f32, const cmc_params &p, bool t
     if (e != hipSuccess) return e;
   }
   const int c = (to_stage && corr) ? 1 : 0;  // correction terms only for a staged step
+  const bool lf = p.rng == CMC_RNG_LFSR113;
   return dispatch(t, [&](const auto &l) {
     using L = std::decay_t<decltype(l)>;
+    if (lf) {
+      if (m_f32)
+        return to_stage ? run2<L, float, true, true>(l, p, c, st)
+                        : run2<L, float, false, true>(l, p, c, st);
+      return to_stage ? run2<L, double, true, true>(l, p, c, st)
+                      : run2<L, double, false, true>(l, p, c, st);
+    }
     if (m_f32)
-      return to_stage ? run2<L, float, true>(l, p, c, st) : run2<L, float, false>(l, p, c, st);
-    return to_stage ? run2<L, double, true>(l, p, c, st) : run2<L, double, false>(l, p, c, st);
+      return to_stage ? run2<L, float, true, false>(l, p, c, st)
+                      : run2<L, float, false, false>(l, p, c, st);
+    return to_stage ? run2<L, double, true, false>(l, p, c, st)
+                    : run2<L, double, false, false>(l, p, c, st);
   });
 }
 

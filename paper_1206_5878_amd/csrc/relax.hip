@@ -4,7 +4,9 @@
 // time t_p = (pi/32) w^3 / (lnL n_b (m1+m2)^2); deflection
 // beta = min(pi, (pi/2) sqrt(dt/t_p)).  dt solves mean_p sin^2(beta_p/2) =
 // target by safeguarded Newton on x = ln dt: per iteration one grid-wide
-// evaluation and a one-block update.  One thread per pair otherwise.  The
+// evaluation and a one-block update.  One thread per pair otherwise.  A
+// pair's random block comes from Philox or from its first star's LFSR113
+// stream (Sec. 3.6), which only the kick advances.  The
 // mixed form computes the pair terms and the kick in FP32 and keeps the
 // centre-of-mass velocity, the sums and the Newton solve in FP64.
 #include <type_traits>
@@ -20,14 +22,26 @@ struct PairGeo {
   double v1x, v1y, v2x, v2y, v2z, wx, wy, wz, wm, tp, u2, ma, mb;
 };
 
+// The pair's random block: Philox at counter (id of its first star, step,
+// kRelax, 0), or the next block of the first star's LFSR113 stream (consume:
+// advance the stream; the timestep's pass only reads it).
+template <bool LF>
+__device__ __forceinline__ U4 pair_block(const ClusterArgs &A, int64_t a, uint32_t step,
+                                         bool consume) {
+  if (!LF) return philox(A.s.id[a], step, kRelax, 0u, A.seed);
+  Lfsr g = load_lfsr(A.s.rng, a);
+  const U4 w = lfsr_block(g);
+  if (consume) store_lfsr(A.s.rng, a, g);
+  return w;
+}
+
 template <typename MT, bool MIXED>
 __device__ __forceinline__ PairGeo pair_geometry(int64_t p, int64_t n,
                                                  const double *__restrict__ r,
                                                  const MT *__restrict__ m,
                                                  const double *__restrict__ vr,
                                                  const double *__restrict__ vt,
-                                                 const uint32_t *__restrict__ id,
-                                                 uint64_t seed, uint32_t step, double lnL) {
+                                                 const U4 &w, double lnL) {
   PairGeo g;
   int64_t nbins = n / 20;
   if (nbins < 1) nbins = 1;
@@ -40,7 +54,6 @@ __device__ __forceinline__ PairGeo pair_geometry(int64_t p, int64_t n,
   const double vol = (4.0 * kPi / 3.0) * (rh - rl) * (rh * rh + rh * rl + rl * rl);
   const double nb = vol > 0.0 ? static_cast<double>(hi - lo) / vol : kInf;
 
-  const U4 w = philox(id[a], step, kRelax, 0u, seed);
   g.v1x = vr[a];
   g.v1y = vt[a];
   g.v2x = vr[b];
@@ -110,7 +123,7 @@ __device__ __forceinline__ double beta_of(double tp, double dt) {
 // dt_state slots
 enum { kX = 0, kLo, kHi, kDone, kIt, kCnt, kZero, kInfN, kLogSum };
 
-template <class Ctx, typename MT, bool MIXED>
+template <class Ctx, typename MT, bool MIXED, bool LF>
 __global__ __launch_bounds__(NT) void k_pair_tp(Ctx ctx, uint32_t step_arg) {
   __shared__ double sh[4 * (NT / 64)];
   const ClusterArgs &A = ctx.args();
@@ -119,10 +132,8 @@ __global__ __launch_bounds__(NT) void k_pair_tp(Ctx ctx, uint32_t step_arg) {
   const MT *__restrict__ m = static_cast<const MT *>(A.s.m);
   const double *__restrict__ vr = A.s.vr;
   const double *__restrict__ vt = A.s.vt;
-  const uint32_t *__restrict__ id = A.s.id;
   double *__restrict__ tp_out = A.w.pair_tp;
   double *__restrict__ part = A.w.pair_part;
-  const uint64_t seed = A.seed;
   const double gamma = A.gamma;
   const int64_t n = A.s.sc->n;
   const int64_t np = n / 2;
@@ -132,8 +143,8 @@ __global__ __launch_bounds__(NT) void k_pair_tp(Ctx ctx, uint32_t step_arg) {
   const int64_t p = blk * NT + threadIdx.x;
   double v[4] = {0.0, 0.0, 0.0, 0.0};  // counted, t_p = 0, t_p = inf, sum ln t_p
   if (p < np) {
-    const PairGeo g =
-        pair_geometry<MT, MIXED>(p, n, r, m, vr, vt, id, seed, step, coulomb_log(gamma, n));
+    const U4 w = pair_block<LF>(A, 2 * p, step, false);
+    const PairGeo g = pair_geometry<MT, MIXED>(p, n, r, m, vr, vt, w, coulomb_log(gamma, n));
     if (g.wm > 0.0) {
       tp_out[p] = g.tp;
       v[0] = 1.0;
@@ -312,7 +323,7 @@ __global__ __launch_bounds__(NT) void k_dt_update(Ctx ctx, double target, double
 }
 
 // ---------------------------------------------------------------- kicks
-template <class Ctx, typename MT, bool MIXED>
+template <class Ctx, typename MT, bool MIXED, bool LF>
 __global__ __launch_bounds__(NT) void k_relax(Ctx ctx, uint32_t step_arg) {
   const ClusterArgs &A = ctx.args();
   const uint32_t step = step_of(A, step_arg);
@@ -320,16 +331,14 @@ __global__ __launch_bounds__(NT) void k_relax(Ctx ctx, uint32_t step_arg) {
   const MT *__restrict__ m = static_cast<const MT *>(A.s.m);
   double *__restrict__ vr = A.s.vr;
   double *__restrict__ vt = A.s.vt;
-  const uint32_t *__restrict__ id = A.s.id;
-  const uint64_t seed = A.seed;
   const double gamma = A.gamma;
   const int64_t n = A.s.sc->n;
   const int64_t np = n / 2;
   const int64_t p = ctx.block() * NT + threadIdx.x;
   if (p >= np) return;
   const double dt = A.s.sc->dt;
-  const PairGeo g =
-      pair_geometry<MT, MIXED>(p, n, r, m, vr, vt, id, seed, step, coulomb_log(gamma, n));
+  const U4 w = pair_block<LF>(A, 2 * p, step, true);  // every pair draws, kicked or not
+  const PairGeo g = pair_geometry<MT, MIXED>(p, n, r, m, vr, vt, w, coulomb_log(gamma, n));
   const double beta = beta_of(g.tp, dt);
   if (!(g.wm > 0.0) || beta == 0.0) return;
   const int64_t a = 2 * p, b = a + 1;
@@ -423,8 +432,12 @@ hipError_t run_timestep(const L &l, const cmc_params &p, hipStream_t st) {
   // Newton stops once its step in ln dt is below what the terms resolve:
   // FP64 terms to ~1e-16, FP32 terms (mixed) to ~1e-7 each
   const double kXTol = MIXED ? 1e-7 : 1e-14;
-  k_pair_tp<decltype(l.ctx(kShPair)), MT, MIXED><<<l.grid(kShPair), NT, 0, st>>>(
-      l.ctx(kShPair), p.step);
+  if (p.rng == CMC_RNG_LFSR113)
+    k_pair_tp<decltype(l.ctx(kShPair)), MT, MIXED, true><<<l.grid(kShPair), NT, 0, st>>>(
+        l.ctx(kShPair), p.step);
+  else
+    k_pair_tp<decltype(l.ctx(kShPair)), MT, MIXED, false><<<l.grid(kShPair), NT, 0, st>>>(
+        l.ctx(kShPair), p.step);
   k_dt_init<<<l.grid(kShOne), IT, 0, st>>>(l.ctx(kShOne), p.target);
   const int iters = p.dt_iters > 0 ? p.dt_iters : 10;
   for (int i = 0; i < iters; ++i) {
@@ -438,8 +451,12 @@ hipError_t run_timestep(const L &l, const cmc_params &p, hipStream_t st) {
 
 template <class L, typename MT, bool MIXED>
 hipError_t run_relax(const L &l, const cmc_params &p, hipStream_t st) {
-  k_relax<decltype(l.ctx(kShPair)), MT, MIXED><<<l.grid(kShPair), NT, 0, st>>>(
-      l.ctx(kShPair), p.step);
+  if (p.rng == CMC_RNG_LFSR113)
+    k_relax<decltype(l.ctx(kShPair)), MT, MIXED, true><<<l.grid(kShPair), NT, 0, st>>>(
+        l.ctx(kShPair), p.step);
+  else
+    k_relax<decltype(l.ctx(kShPair)), MT, MIXED, false><<<l.grid(kShPair), NT, 0, st>>>(
+        l.ctx(kShPair), p.step);
   return hipGetLastError();
 }
 

@@ -56,6 +56,7 @@ __global__ __launch_bounds__(NT) void k_stage_from_state(Ctx ctx) {
   rec.pad = 0u;
   static_cast<WideRec *>(A.w.stage)[i] = rec;
   A.w.keys[0][i] = radius_key(rec.r);
+  if (A.s.rng) A.w.rng_stage[i] = load_lfsr(A.s.rng, i);  // moves with its star
 }
 
 // Per-block min and max of the finite keys and count of non-finite ones;
@@ -337,7 +338,7 @@ __global__ __launch_bounds__(DT) void k_downsweep(Ctx ctx, int pass) {
 }
 
 template <class Ctx, class Rec>
-__global__ __launch_bounds__(NT) void k_gather(Ctx ctx, int normalise, int corr) {
+__global__ __launch_bounds__(NT) void k_gather(Ctx ctx, int normalise, int corr, int move_rng) {
   const ClusterArgs &A = ctx.args();
   const Rec *__restrict__ stage = static_cast<const Rec *>(A.w.stage);
   const uint32_t *__restrict__ vals0 = A.w.vals[0];
@@ -367,6 +368,7 @@ __global__ __launch_bounds__(NT) void k_gather(Ctx ctx, int normalise, int corr)
     static_cast<double *>(m)[p] = mm;
   id[p] = rec.id;
   if (corr) A.w.perm[p] = src;
+  if (move_rng && A.s.rng) store_lfsr(A.s.rng, p, A.w.rng_stage[src]);
 }
 
 // One thread per cluster: the device step counter moves on.
@@ -393,8 +395,8 @@ hipError_t launch_stage_from_state(const Target &t, bool, hipStream_t st) {
 
 // Sort the staged records by keys[0] (n = sc->n on entry) into the state.
 hipError_t launch_sort_stage(const Target &t, bool m_f32, bool normalise_mass, bool step_records,
-                             bool corr, hipStream_t st) {
-  const int c = corr ? 1 : 0;
+                             bool corr, bool move_rng, hipStream_t st) {
+  const int c = corr ? 1 : 0, mv = move_rng ? 1 : 0;
   return dispatch(t, [&](const auto &l) {
     k_sort_prep<<<l.grid(kShOne), 1, 0, st>>>(l.ctx(kShOne));
     k_key_range<<<l.grid(kShKeyRange), NT, 0, st>>>(l.ctx(kShKeyRange));
@@ -406,10 +408,10 @@ hipError_t launch_sort_stage(const Target &t, bool m_f32, bool normalise_mass, b
     }
     if (step_records && m_f32)
       k_gather<decltype(l.ctx(kShStar)), StageRec<float>>
-          <<<l.grid(kShStar), NT, 0, st>>>(l.ctx(kShStar), normalise_mass ? 1 : 0, c);
+          <<<l.grid(kShStar), NT, 0, st>>>(l.ctx(kShStar), normalise_mass ? 1 : 0, c, mv);
     else
       k_gather<decltype(l.ctx(kShStar)), WideRec>
-          <<<l.grid(kShStar), NT, 0, st>>>(l.ctx(kShStar), normalise_mass ? 1 : 0, c);
+          <<<l.grid(kShStar), NT, 0, st>>>(l.ctx(kShStar), normalise_mass ? 1 : 0, c, mv);
     return hipGetLastError();
   });
 }

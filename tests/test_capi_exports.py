@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared():
     text = open(os.path.join(ROOT, "include", "cmc.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(cmc_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(cmc_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_call():
@@ -23,7 +23,7 @@ def test_library_exports_every_declared_call():
     for n in names:
         assert hasattr(L, n), n
     assert set(A.EXPORTS) == set(names)
-    assert L.cmc_abi_version() == 3
+    assert L.cmc_abi_version() == 4
 
 
 def test_host_side_checks_without_gpu():
@@ -39,6 +39,10 @@ def test_host_side_checks_without_gpu():
     assert L.cmc_sort(C.byref(s), None) == A.CMC_EINVAL
     assert L.cmc_potential(C.byref(s), 0, None) == A.CMC_EINVAL
     assert L.cmc_energy_correction(C.byref(s), None) == A.CMC_EINVAL
+    z = (C.c_uint32 * 4)(12345, 12345, 12345, 12345)
+    assert L.cmc_rng_seed_lfsr113(C.byref(s), z, 0, None) == A.CMC_EINVAL
+    assert L.cmc_lfsr113(None, None, -1, 1, None) == A.CMC_EINVAL
+    assert L.cmc_lfsr113(None, None, 0, 4, None) == A.CMC_OK  # nothing to do
     assert L.cmc_init_plummer(None, 10, 1, 0, None) == A.CMC_EINVAL
     assert L.cmc_philox(1, None, None, 5, None) == A.CMC_EINVAL
     assert L.cmc_philox(1, None, None, 0, None) == A.CMC_OK
