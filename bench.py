@@ -92,6 +92,8 @@ def main() -> int:
                     help="skip the run of the other precision form")
     ap.add_argument("--uncorrected", action="store_true",
                     help="core-collapse workload: run without the energy correction")
+    ap.add_argument("--energy-corr", action="store_true",
+                    help="with --plain: steps with the potential-change energy correction")
     ap.add_argument("--plain", action="store_true",
                     help="time plain cmc_step calls only (no per-phase events); for profilers")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -137,6 +139,7 @@ def main() -> int:
     if args.plain:
         prec = P.CMC_FP64 if precision == "fp64" else P.CMC_MIXED
         cl, params = setup(P, wl, prec, args.warmup)
+        params.energy_corr = 1 if args.energy_corr else 0
         n_start = cl.n
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -148,7 +151,8 @@ def main() -> int:
         print(json.dumps({"metric": METRIC, "value": n_start * K / el, "unit": "star-updates/s",
                           "n_gpus": 1, "steps": K, "warmup": args.warmup,
                           "ms_per_step": el / K * 1e3, "mode": "plain", "n_start": n_start,
-                          "n_end": cl.n, "workload": args.workload, "precision": precision}),
+                          "n_end": cl.n, "workload": args.workload, "precision": precision,
+                          "energy_corr": bool(args.energy_corr)}),
               flush=True)
         return 0
 
@@ -202,6 +206,8 @@ def main() -> int:
         # the same step with the potential-change energy correction (Sec. 2.1
         # item 6), which the headline metric's step list leaves out
         "with_energy_correction": run["with_energy_correction"],
+        # the same step drawing from per-star LFSR113 streams (Sec. 3.6)
+        "with_lfsr113": lfsr_rate(P, wl, precision, K, args.warmup),
         "final": run["final"],
     }
     if run_o is not None:
@@ -395,6 +401,35 @@ def timed_run(P, EventSet, wl, precision, K, warmup, corr_too=False) -> dict:
             "final": {"n": sc["n"], "dt": sc["dt"], "status": sc["status"],
                       "trials_per_star": sc["trials"] / max(n_mean, 1),
                       "dt_iters": sc["dt_iters"]}}
+
+
+def lfsr_rate(P, wl, precision, K, warmup) -> dict:
+    """The same workload with every draw from the stars' LFSR113 streams (the
+    generator of Sec. 3.6), timed as K replays of one captured step."""
+    import torch
+    prec = P.CMC_FP64 if precision == "fp64" else P.CMC_MIXED
+    n0 = wl["n"]
+    cl = P.Cluster(n0, m_f32=wl["m_f32"], rng=True)
+    P.cmc_init_plummer(cl, n0, wl["seed"], wl["mass_spectrum"])
+    P.cmc_rng_seed_lfsr113(cl, [0x12345678, 0x9ABCDEF0, 0x0FEDCBA9, 0x87654321], 0)
+    params = P.Params(seed=wl["seed"], gamma=wl["gamma"], precision=prec, rng=P.CMC_RNG_LFSR113)
+    for k in range(warmup):
+        params.step = k
+        P.cmc_step(cl, params)
+    cl.set_scalar("step", warmup)
+    g = cl.capture(params)
+    glog = torch.zeros(K + 1, dtype=torch.int64, device="cuda")
+    glog[0].copy_(cl.sc[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        g.replay()
+        glog[k + 1].copy_(cl.sc[0])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    print(f"# {precision}: {el / K * 1e3:.3f} ms/step (graph replays, LFSR113 streams)",
+          file=sys.stderr, flush=True)
+    return {"value": float(sum(glog.cpu().tolist()[:K])) / el, "ms_per_step": el / K * 1e3}
 
 
 def core_collapse_bench(P, args, wl, precision) -> int:
