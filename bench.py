@@ -94,6 +94,8 @@ def main() -> int:
                     help="core-collapse workload: run without the energy correction")
     ap.add_argument("--energy-corr", action="store_true",
                     help="with --plain: steps with the potential-change energy correction")
+    ap.add_argument("--lfsr113", action="store_true",
+                    help="with --plain: steps drawing from per-star LFSR113 streams")
     ap.add_argument("--plain", action="store_true",
                     help="time plain cmc_step calls only (no per-phase events); for profilers")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -138,7 +140,7 @@ def main() -> int:
         return core_collapse_bench(P, args, wl, precision)
     if args.plain:
         prec = P.CMC_FP64 if precision == "fp64" else P.CMC_MIXED
-        cl, params = setup(P, wl, prec, args.warmup)
+        cl, params = setup(P, wl, prec, args.warmup, lfsr=args.lfsr113)
         params.energy_corr = 1 if args.energy_corr else 0
         n_start = cl.n
         torch.cuda.synchronize()
@@ -152,7 +154,7 @@ def main() -> int:
                           "n_gpus": 1, "steps": K, "warmup": args.warmup,
                           "ms_per_step": el / K * 1e3, "mode": "plain", "n_start": n_start,
                           "n_end": cl.n, "workload": args.workload, "precision": precision,
-                          "energy_corr": bool(args.energy_corr)}),
+                          "energy_corr": bool(args.energy_corr), "lfsr113": bool(args.lfsr113)}),
               flush=True)
         return 0
 
@@ -311,12 +313,18 @@ def ensemble_bench(P, args, wl, precision) -> int:
     return 0
 
 
-def setup(P, wl, prec, warmup):
+LFSR_SEED = [0x12345678, 0x9ABCDEF0, 0x0FEDCBA9, 0x87654321]
+
+
+def setup(P, wl, prec, warmup, lfsr=False):
     import torch
     n0 = wl["n"]
-    cl = P.Cluster(n0, m_f32=wl["m_f32"])
+    cl = P.Cluster(n0, m_f32=wl["m_f32"], rng=lfsr)
     P.cmc_init_plummer(cl, n0, wl["seed"], wl["mass_spectrum"])
     params = P.Params(seed=wl["seed"], gamma=wl["gamma"], precision=prec)
+    if lfsr:
+        P.cmc_rng_seed_lfsr113(cl, LFSR_SEED, 0)
+        params.rng = P.CMC_RNG_LFSR113
     for k in range(warmup):
         params.step = k
         P.cmc_step(cl, params)
@@ -408,14 +416,7 @@ def lfsr_rate(P, wl, precision, K, warmup) -> dict:
     generator of Sec. 3.6), timed as K replays of one captured step."""
     import torch
     prec = P.CMC_FP64 if precision == "fp64" else P.CMC_MIXED
-    n0 = wl["n"]
-    cl = P.Cluster(n0, m_f32=wl["m_f32"], rng=True)
-    P.cmc_init_plummer(cl, n0, wl["seed"], wl["mass_spectrum"])
-    P.cmc_rng_seed_lfsr113(cl, [0x12345678, 0x9ABCDEF0, 0x0FEDCBA9, 0x87654321], 0)
-    params = P.Params(seed=wl["seed"], gamma=wl["gamma"], precision=prec, rng=P.CMC_RNG_LFSR113)
-    for k in range(warmup):
-        params.step = k
-        P.cmc_step(cl, params)
+    cl, params = setup(P, wl, prec, warmup, lfsr=True)
     cl.set_scalar("step", warmup)
     g = cl.capture(params)
     glog = torch.zeros(K + 1, dtype=torch.int64, device="cuda")

@@ -372,9 +372,10 @@ void k_orbit_bracket(Ctx ctx, uint32_t step_arg, double bound_factor, int corr) 
     if (i < n) {
       const RPhi me = tab[i];
       if (corr) cor[i] = me;  // r_old and Phi_old(r_old)
-      // an LFSR113 state moves with its star: staged here, replaced below by
-      // the stars that draw
-      if (TO_STAGE && A.s.rng) A.w.rng_stage[i] = load_lfsr(A.s.rng, i);
+      // an LFSR113 state moves with its star; a Philox step stages it as it
+      // is (an LFSR step stages it after the star's draws, and every kept
+      // star draws at least its sign)
+      if (TO_STAGE && !LF && A.s.rng) A.w.rng_stage[i] = load_lfsr(A.s.rng, i);
       vri = vr[i];
       vti = vt[i];
       E = me.phi + 0.5 * (vri * vri + vti * vti);

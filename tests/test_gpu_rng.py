@@ -213,3 +213,43 @@ def test_lfsr_graph_replay(cmc):
     ha, hb = eager.host(), graphed.host()
     for key in ("r", "vr", "vt", "m", "id", "rng"):
         assert np.array_equal(ha[key], hb[key]), key
+
+
+def test_lfsr_step_full_size_sampled(cmc, ora):
+    """At the benchmark's size (N = 1e7, f32 masses from the mass spectrum,
+    mixed precision), sampled stars' streams after a step are their seeded
+    streams advanced by the blocks they drew: one per relaxation as a pair's
+    first star, one per trial, one for the sign."""
+    n = 10_000_000
+    cl = cmc.Cluster(n, m_f32=True, rng=True)
+    cmc.cmc_init_plummer(cl, n, 1, 1)
+    cmc.cmc_rng_seed_lfsr113(cl, Z0, 0)
+    ids0 = cl.id[:n].cpu().numpy().view(np.uint32)
+    first = np.zeros(n, bool)
+    first[0:n - n % 2:2] = True
+    was_first = dict(zip(ids0[::9973].tolist(), first[::9973].tolist()))
+    cmc.cmc_step(cl, cmc.Params(seed=1, step=0, gamma=0.01, precision=1,
+                                rng=cmc.CMC_RNG_LFSR113))
+    s = cl.scalars()
+    k = s["n"]
+    ids = cl.id[:k].cpu().numpy().view(np.uint32)
+    rng = cl.rng[:4 * k].cpu().numpy().view(np.uint32).reshape(k, 4)
+    pos = {int(i): j for j, i in enumerate(ids)}
+    drawn = []
+    for i, f in list(was_first.items())[:600]:
+        if i not in pos:
+            continue  # escaped
+        z = ora.lfsr113_stream(Z0, i)
+        got = rng[pos[i]]
+        for nb in range(0, 200):
+            if np.array_equal(z, got):
+                break
+            z, _ = ora.lfsr113_blocks(z, 1)
+        else:
+            raise AssertionError(f"star {i}: state not on its stream")
+        drawn.append(nb - (1 if f else 0))
+    drawn = np.array(drawn)
+    assert len(drawn) > 500 and drawn.min() >= 1
+    # trials per star: about 1.75, as the step reports
+    assert abs((drawn - 1).mean() - s["trials"] / n) < 0.15
+    del cl
