@@ -263,3 +263,25 @@ def test_energy_budget_at_scale(cmc, n, precision):
     assert skipped < 1e-3 * n
     assert err < 1e-6
     assert raw > 10 * err
+
+
+def test_corrected_energy_per_step_mixed_vs_oracle(cmc, ora):
+    """Precision's share of the corrected step's energy: from the same sorted
+    state, one mixed corrected step on the GPU and one oracle corrected step
+    end at total energies within 1e-6 of |E|.  The oracle's own change is the
+    escapers' and skipped stars' share only."""
+    n = 20_000
+    st = ora.plummer(n, 5)
+    cl = cmc.Cluster(n)
+    for k in range(3):
+        cl.load(st.r, st.vr, st.vt, st.m, st.id)
+        cl.set_scalar("dt", 0.0)
+        cmc.cmc_step(cl, cmc.Params(seed=5, step=k, precision=cmc.CMC_MIXED, energy_corr=1))
+        cmc.cmc_potential(cl)
+        cmc.cmc_energy_correction(cl)
+        eg = float(cmc.cmc_diagnostics(cl)["E"])
+        cor, skipped, info = oracle_corrected_step(ora, st, 5, k, 0.11)
+        eo = ora.diagnostics(cor)["E"]
+        assert cl.n == cor.n
+        assert abs(eg - eo) / abs(eo) < 1e-6, (k, eg, eo)
+        st = cor
