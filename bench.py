@@ -201,8 +201,11 @@ def main() -> int:
                           "achieved_GBs": value * step_bytes / 1e9,
                           "frac": value * step_bytes / 1e9 / HBM_PEAK_GBS},
         "phases_ms": phase_ms,
-        "timing": "hipGraph replays of one captured step; 'calls' times the same number of "
-                  "plain cmc_step_timed calls first, which also give the per-phase split",
+        "timing": "hipGraph replays of one captured step (dt_iters = %d: warm-started dt "
+                  "solves converge in 2-3 Newton iterations, checked through "
+                  "CMC_ST_DT_NOCONV); 'calls' times the same number of plain cmc_step_timed "
+                  "calls first (default 10 iterations), which also give the per-phase split"
+                  % GRAPH_DT_ITERS,
         "gpu_ms_per_step": run["gpu_ms_per_step"],
         "calls": run["calls"],
         # the same step with the potential-change energy correction (Sec. 2.1
@@ -314,6 +317,22 @@ def ensemble_bench(P, args, wl, precision) -> int:
 
 
 LFSR_SEED = [0x12345678, 0x9ABCDEF0, 0x0FEDCBA9, 0x87654321]
+# Newton iterations enqueued in a captured step.  Every captured step here
+# follows eager warm-up steps, so its dt solve starts from the last dt and
+# converges in 2-3 iterations; an iteration after convergence is a no-op
+# launch pair (~9 us).  A solve that ran out would raise CMC_ST_DT_NOCONV,
+# which the runs below check.
+GRAPH_DT_ITERS = 5
+
+
+def graph_params(P, params):
+    return P.Params(**{**params.__dict__, "dt_iters": GRAPH_DT_ITERS})
+
+
+def check_dt(P, cl, what):
+    st = int(cl.scalars()["status"])
+    if st & P.ST_DT_NOCONV:
+        raise RuntimeError(f"{what}: the dt solve ran out of iterations (status {st:#x})")
 
 
 def setup(P, wl, prec, warmup, lfsr=False):
@@ -366,7 +385,7 @@ def timed_run(P, EventSet, wl, precision, K, warmup, corr_too=False) -> dict:
     # The same cluster continues with K replays of one captured step (the step
     # index comes from the device counter, set to carry on from the calls).
     cl.set_scalar("step", warmup + K)
-    g = cl.capture(params)
+    g = cl.capture(graph_params(P, params))
     g.replay()  # steps warmup + K: not timed
     glog = torch.zeros(K + 1, dtype=torch.int64, device="cuda")
     glog[0].copy_(cl.sc[0])
@@ -381,12 +400,13 @@ def timed_run(P, EventSet, wl, precision, K, warmup, corr_too=False) -> dict:
     torch.cuda.synchronize()
     gel = time.perf_counter() - t0
     gupdates = float(sum(glog.cpu().tolist()[:K]))
+    check_dt(P, cl, "graph replays")
     print(f"# {precision}: {gel / K * 1e3:.3f} ms/step (graph replays)", file=sys.stderr,
           flush=True)
     corr = None
     if corr_too:
         del g
-        q = P.Params(**{**params.__dict__, "energy_corr": 1})
+        q = P.Params(**{**graph_params(P, params).__dict__, "energy_corr": 1})
         gc = cl.capture(q)
         gc.replay()  # leaves the first correction pending: not timed
         glog[0].copy_(cl.sc[0])
@@ -397,6 +417,7 @@ def timed_run(P, EventSet, wl, precision, K, warmup, corr_too=False) -> dict:
             glog[k + 1].copy_(cl.sc[0])
         torch.cuda.synchronize()
         cel = time.perf_counter() - t0
+        check_dt(P, cl, "graph replays with the energy correction")
         corr = {"value": float(sum(glog.cpu().tolist()[:K])) / cel, "ms_per_step": cel / K * 1e3,
                 "corr_skipped_last": int(cl.scalars()["corr_skipped"])}
         print(f"# {precision}: {cel / K * 1e3:.3f} ms/step (graph replays, energy correction)",
@@ -418,7 +439,7 @@ def lfsr_rate(P, wl, precision, K, warmup) -> dict:
     prec = P.CMC_FP64 if precision == "fp64" else P.CMC_MIXED
     cl, params = setup(P, wl, prec, warmup, lfsr=True)
     cl.set_scalar("step", warmup)
-    g = cl.capture(params)
+    g = cl.capture(graph_params(P, params))
     glog = torch.zeros(K + 1, dtype=torch.int64, device="cuda")
     glog[0].copy_(cl.sc[0])
     torch.cuda.synchronize()
@@ -428,6 +449,7 @@ def lfsr_rate(P, wl, precision, K, warmup) -> dict:
         glog[k + 1].copy_(cl.sc[0])
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    check_dt(P, cl, "LFSR113 graph replays")
     print(f"# {precision}: {el / K * 1e3:.3f} ms/step (graph replays, LFSR113 streams)",
           file=sys.stderr, flush=True)
     return {"value": float(sum(glog.cpu().tolist()[:K])) / el, "ms_per_step": el / K * 1e3}
