@@ -96,6 +96,9 @@ def lib():
         L.ora_lfsr113_component_period.restype = C.c_int64
         L.ora_energy_correction.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp]
         L.ora_energy_correction.restype = C.c_int64
+        L.ora_orbit_subset.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _up,
+                                       C.c_uint64, C.c_uint32, C.c_int32, C.c_double, C.c_int64,
+                                       _ip, _dp]
         L.ora_diagnostics.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
         _lib = L
     return _lib
@@ -296,6 +299,19 @@ def orbit(st: State, table, seed: int, step: int, trial_cap: int = 10000,
     if details:
         return r_new[:n], vr, vt, stats, d
     return r_new[:n], vr, vt, stats
+
+
+def orbit_subset(st: State, table, seed: int, step: int, idx, trial_cap: int = 10000,
+                 bound_factor: float = 1.2):
+    """``orbit`` for the stars at positions idx only: (r_new, vr, vt) of those
+    stars (r_new = inf for an escaper)."""
+    phi, mcum, ssuf = table
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    vr = st.vr.copy(); vt = st.vt.copy()
+    r_new = np.full(max(st.n, 1), np.nan)
+    lib().ora_orbit_subset(st.n, st.r, _f64(phi), _f64(mcum), _f64(ssuf), st.m, vr, vt, st.id,
+                           seed, step, trial_cap, bound_factor, idx.shape[0], idx, r_new)
+    return r_new[idx], vr[idx], vt[idx]
 
 
 def step(st: State, seed: int, step_idx: int, gamma: float, target: float = 0.03,

@@ -745,12 +745,16 @@ static void orbit_d(int64_t n, const double *r, const double *phi, const double 
                     double bound_factor, double *r_new, double *E_out, double *J_out,
                     int64_t *kmin_out, int64_t *kmax_out, double *rmin_out,
                     double *rmax_out, int32_t *trials_out, uint32_t *flags_out,
-                    ora_orbit_stats *st) {
+                    ora_orbit_stats *st, const int64_t *only, int64_t count) {
   ora_orbit_stats s;
   memset(&s, 0, sizeof s);
   ksum eesc = {0.0, 0.0};
 
-  for (int64_t i = 0; i < n; ++i) {
+  /* every star, or only the listed ones (each star's orbit depends on the
+   * table and its own state alone) */
+  const int64_t todo = only ? count : n;
+  for (int64_t q = 0; q < todo; ++q) {
+    const int64_t i = only ? only[q] : q;
     uint32_t fl = 0;
     double E = phi[i] + 0.5 * (vr[i] * vr[i] + vt[i] * vt[i]);
     double J = r[i] * vt[i];
@@ -902,7 +906,16 @@ void ora_orbit(int64_t n, const double *r, const double *phi, const double *mcum
                uint32_t *flags_out, ora_orbit_stats *st) {
   const draws src = {seed, step, NULL};
   orbit_d(n, r, phi, mcum, ssuf, m, vr, vt, id, &src, trial_cap, bound_factor, r_new, E_out,
-          J_out, kmin_out, kmax_out, rmin_out, rmax_out, trials_out, flags_out, st);
+          J_out, kmin_out, kmax_out, rmin_out, rmax_out, trials_out, flags_out, st, NULL, 0);
+}
+
+void ora_orbit_subset(int64_t n, const double *r, const double *phi, const double *mcum,
+                      const double *ssuf, const double *m, double *vr, double *vt,
+                      const uint32_t *id, uint64_t seed, uint32_t step, int32_t trial_cap,
+                      double bound_factor, int64_t count, const int64_t *idx, double *r_new) {
+  const draws src = {seed, step, NULL};
+  orbit_d(n, r, phi, mcum, ssuf, m, vr, vt, id, &src, trial_cap, bound_factor, r_new, NULL,
+          NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, idx, count);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -933,7 +946,7 @@ void ora_step_ex(int64_t n, double *r, double *vr, double *vt, double *m, uint32
   double *rn = (double *)malloc(nn * sizeof(double));
   ora_orbit_stats st;
   orbit_d(n, r, phi, mcum, ssuf, m, vr, vt, id, &src, p->trial_cap, p->bound_factor, rn,
-          NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, &st);
+          NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, &st, NULL, 0);
   status |= st.status;
 
   /* The old potential at each star's old and new radius (for the energy

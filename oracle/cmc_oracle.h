@@ -134,6 +134,15 @@ void ora_orbit(int64_t n, const double *r, const double *phi, const double *mcum
                double *rmin_out, double *rmax_out, int32_t *trials_out,
                uint32_t *flags_out, ora_orbit_stats *st);
 
+/* ora_orbit for the listed stars only (idx[0..count-1]): writes r_new, vr,
+ * vt at those indices; every other entry is left alone.  Each star's new
+ * orbit depends on the table and its own state only, so this is ora_orbit
+ * restricted to a sample (for checks at sizes where the whole pass is slow). */
+void ora_orbit_subset(int64_t n, const double *r, const double *phi, const double *mcum,
+                      const double *ssuf, const double *m, double *vr, double *vt,
+                      const uint32_t *id, uint64_t seed, uint32_t step, int32_t trial_cap,
+                      double bound_factor, int64_t count, const int64_t *idx, double *r_new);
+
 /* Potential at an arbitrary radius from the table. */
 double ora_phi_at(int64_t n, const double *r, const double *phi, const double *mcum,
                   const double *ssuf, double x);

@@ -630,3 +630,16 @@ def test_core_degenerate(ora):
     st = _core_state(ora, np.full(50, 0.7), np.full(50, 0.02))
     d = ora.diagnostics(st)
     assert np.isnan(d["rc"]) and np.isnan(d["rho_c"])  # every window has zero volume
+
+
+def test_orbit_subset_is_the_orbit_pass_restricted():
+    """The sampled orbit entry gives, at each listed star, exactly what the
+    whole pass gives there (each orbit depends on the table and the star)."""
+    import numpy as np
+    import oracle as O
+    st = O.plummer(4000, 8)
+    tab = O.potential(st.r, st.m)
+    rn, vr, vt, _ = O.orbit(st, tab, 8, 2)
+    idx = np.array([0, 1, 17, 2048, 3998, 3999])
+    a, b, c = O.orbit_subset(st, tab, 8, 2, idx)
+    assert np.array_equal(a, rn[idx]) and np.array_equal(b, vr[idx]) and np.array_equal(c, vt[idx])
