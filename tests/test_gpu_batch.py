@@ -208,3 +208,43 @@ def test_batch_diagnostics(cmc, ora):
         ref = ora.diagnostics(oracle_init(ora, s))
         for key in ("T", "W", "E", "virial", "M", "rc", "rho_c"):
             assert rel(d[key], ref[key]) < 1e-11, key
+
+
+def test_batch_full_workload(cmc):
+    """The benchmark's ensemble at its real size: 64 clusters, N log-uniform in
+    [1e4, 1e6] (about 1.4e7 stars), half Plummer and half King W0 = 6, one
+    captured mixed step.  The largest, the smallest and two more clusters come
+    out bit for bit as their own single-cluster calls."""
+    import os
+    import sys
+    import torch
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    wl = bench.WORKLOADS["ensemble_64_plummer_king_w6"]
+    specs = bench.ensemble_specs(cmc, wl)
+    ns = [s["n"] for s in specs]
+    assert len(specs) == 64 and 1.0e7 < sum(ns) < 2.0e7
+    ens = cmc.Ensemble(specs)
+    ens.init()
+    p = cmc.Params(precision=cmc.CMC_MIXED)
+    for k in range(2):
+        p.step = k
+        ens.step(p)
+    g = ens.capture(cmc.Params(precision=cmc.CMC_MIXED))
+    for cl in ens.clusters:
+        cl.set_scalar("step", 2)
+    g.replay()
+    torch.cuda.synchronize()
+    pick = sorted({int(np.argmax(ns)), int(np.argmin(ns)), 1, 62})
+    for c in pick:
+        s = specs[c]
+        one = cmc.Cluster(s["n"])
+        cmc.cmc_init_model(one, s["n"], s["seed"], s["model"], 0, s["w0"])
+        for k in range(3):
+            cmc.cmc_step(one, cmc.Params(seed=s["seed"], gamma=s["gamma"], step=k,
+                                         precision=cmc.CMC_MIXED))
+        ha, hb = ens.clusters[c].host(), one.host()
+        for key in ("r", "vr", "vt", "m", "id"):
+            assert np.array_equal(ha[key], hb[key]), (c, key)
+        assert ens.clusters[c].scalars()["step"] == 3
+        del one
