@@ -42,6 +42,18 @@ def density_slope(r, m, r_lo: float, r_hi: float, bins: int = 12) -> float:
     return float(-slope)
 
 
+def core_density_slope(series, rho_c0: float, lo: float = 1e2, hi: float = 1e5) -> float:
+    """Power-law index of rho_c against r_c along the collapse: least squares in
+    log-log over the samples with lo <= rho_c / rho_c(0) <= hi (the paper fits
+    the same relation in its core-collapse runs, Sec. 4)."""
+    import numpy as np
+    rows = np.array([(r[2], r[7]) for r in series])
+    sel = (rows[:, 0] >= lo * rho_c0) & (rows[:, 0] <= hi * rho_c0)
+    if sel.sum() < 4:
+        return float("nan")
+    return float(np.polyfit(np.log(rows[sel, 1]), np.log(rows[sel, 0]), 1)[0])
+
+
 def core_collapse_run(n: int, seed: int = 1, *, gamma: float = 0.11,
                       precision: int = A.CMC_MIXED, energy_corr: bool = True,
                       t_end: float = 30.0, every: int = 10, collapse: float = 1e4,
@@ -51,8 +63,9 @@ def core_collapse_run(n: int, seed: int = 1, *, gamma: float = 0.11,
     energy_corr: each step applies the potential-change energy correction of
     Sec. 2.1 item 6, which the paper's code applies.  Every `every` steps,
     the potential, the pending correction and the diagnostics are taken:
-    t / t_rh, r_c / r_h (r_h the current half-mass radius), rho_c, E, N, and
-    the energy budget (E - E0 + the energy escapers took) / |E0|.  The
+    t / t_rh, r_c / r_h (r_h the current half-mass radius), rho_c, E, N, the
+    step count, the energy budget (E - E0 + the energy escapers took) / |E0|,
+    and r_c (in units of the virial radius, 1 in Henon units).  The
     collapse
     time t_cc is the first sample with rho_c >= collapse * rho_c(0), where the
     density profile's power-law index between 10 r_c and r_h / 2 is also
@@ -73,7 +86,7 @@ def core_collapse_run(n: int, seed: int = 1, *, gamma: float = 0.11,
     pick = torch.tensor([1, 7, 11], dtype=torch.int64, device=dev)
     rec = torch.zeros((every, 3), dtype=torch.int64, device=dev)
     E0 = float(d0["E"])
-    rows = [(0.0, float(d0["rc"] / d0["r50"]), rho0, E0, int(cl.n), 0, 0.0)]
+    rows = [(0.0, float(d0["rc"] / d0["r50"]), rho0, E0, int(cl.n), 0, 0.0, float(d0["rc"]))]
     t = 0.0
     e_esc = 0.0
     skipped = 0
@@ -96,7 +109,7 @@ def core_collapse_run(n: int, seed: int = 1, *, gamma: float = 0.11,
         d = cmc_diagnostics(cl)
         E = float(d["E"])
         rows.append((t / trh, float(d["rc"] / d["r50"]), float(d["rho_c"]), E,
-                     int(cl.n), steps, (E - E0 + e_esc) / abs(E0)))
+                     int(cl.n), steps, (E - E0 + e_esc) / abs(E0), float(d["rc"])))
         if cc is None and rows[-1][2] >= collapse * rho0:
             wall = time.perf_counter() - wall0
             h = cl.host()
@@ -112,6 +125,7 @@ def core_collapse_run(n: int, seed: int = 1, *, gamma: float = 0.11,
             break
     torch.cuda.synchronize()
     return {"n": n, "seed": seed, "precision": "mixed" if precision == A.CMC_MIXED else "fp64",
-            "energy_corr": bool(energy_corr), "t_rh": trh, "rho_c0": rho0, "collapse": cc, "steps": steps,
+            "energy_corr": bool(energy_corr), "t_rh": trh,
+            "core_slope": core_density_slope(rows, rho0), "rho_c0": rho0, "collapse": cc, "steps": steps,
             "wall_s": time.perf_counter() - wall0, "status": int(cl.scalars()["status"]),
             "series": rows}
