@@ -53,55 +53,62 @@ def lib():
         if not os.path.exists(_LIB_PATH):
             from . import build as _b
             _b.build()
-        L = C.CDLL(_LIB_PATH)
-        L.ora_philox_many.argtypes = [C.c_int64, C.c_uint64, _up, _up]
-        L.ora_u01.argtypes = [C.c_uint32, C.c_uint32]
-        L.ora_u01.restype = C.c_double
-        L.ora_u01f.argtypes = [C.c_uint32]
-        L.ora_u01f.restype = C.c_float
-        L.ora_plummer.argtypes = [C.c_int64, C.c_uint64, C.c_int, _dp, _dp, _dp, _dp, _up]
-        L.ora_king.argtypes = [C.c_int64, C.c_uint64, C.c_double, C.c_int, _dp, _dp, _dp, _dp,
-                               _up]
-        L.ora_king_profile.argtypes = [C.c_double, _dp, _dp, _dp, C.c_int, _dp]
-        L.ora_king_profile.restype = C.c_int
-        L.ora_king_density.argtypes = [C.c_double]
-        L.ora_king_density.restype = C.c_double
-        L.ora_sort_perm.argtypes = [C.c_int64, _dp, _ip]
-        L.ora_potential.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp]
-        L.ora_phi_at.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, C.c_double]
-        L.ora_phi_at.restype = C.c_double
-        L.ora_pair_terms.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _up, C.c_uint64,
-                                     C.c_uint32, C.c_double, _dp, _dp, _dp]
-        L.ora_pair_terms.restype = C.c_int64
-        L.ora_mean_sin2.argtypes = [C.c_int64, _dp, _dp, C.c_double]
-        L.ora_mean_sin2.restype = C.c_double
-        L.ora_solve_dt.argtypes = [C.c_int64, _dp, _dp, C.c_double, C.POINTER(C.c_uint32)]
-        L.ora_solve_dt.restype = C.c_double
-        L.ora_relax.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _up, C.c_uint64, C.c_uint32,
-                                C.c_double, C.c_double]
-        L.ora_orbit.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _up, C.c_uint64,
-                                C.c_uint32, C.c_int32, C.c_double, _dp,
-                                _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-                                C.POINTER(OrbitStats)]
-        L.ora_step.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _up, _dp, _dp,
-                               C.POINTER(Params), C.POINTER(StepOut)]
-        L.ora_step_ex.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _up, _dp, _dp,
-                                  C.POINTER(Params), C.POINTER(StepOut), _vp, _vp]
-        L.ora_lfsr113_next.argtypes = [_up]
-        L.ora_lfsr113_next.restype = C.c_uint32
-        L.ora_lfsr113_block.argtypes = [_up, _up]
-        L.ora_lfsr113_jump_pow2.argtypes = [_up, C.c_int]
-        L.ora_lfsr113_stream.argtypes = [_up, C.c_uint64, _up]
-        L.ora_lfsr113_component_period.argtypes = [C.c_int, C.c_uint32, C.c_int64]
-        L.ora_lfsr113_component_period.restype = C.c_int64
-        L.ora_energy_correction.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp]
-        L.ora_energy_correction.restype = C.c_int64
-        L.ora_orbit_subset.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _up,
-                                       C.c_uint64, C.c_uint32, C.c_int32, C.c_double, C.c_int64,
-                                       _ip, _dp]
-        L.ora_diagnostics.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
-        _lib = L
+        _lib = load(_LIB_PATH)
     return _lib
+
+
+def load(path: str):
+    """A build of the oracle's C source at ``path`` with every entry point's
+    argument types declared (the tests also load deliberately broken builds
+    to show that the pins catch them)."""
+    L = C.CDLL(path)
+    L.ora_philox_many.argtypes = [C.c_int64, C.c_uint64, _up, _up]
+    L.ora_u01.argtypes = [C.c_uint32, C.c_uint32]
+    L.ora_u01.restype = C.c_double
+    L.ora_u01f.argtypes = [C.c_uint32]
+    L.ora_u01f.restype = C.c_float
+    L.ora_plummer.argtypes = [C.c_int64, C.c_uint64, C.c_int, _dp, _dp, _dp, _dp, _up]
+    L.ora_king.argtypes = [C.c_int64, C.c_uint64, C.c_double, C.c_int, _dp, _dp, _dp, _dp,
+                           _up]
+    L.ora_king_profile.argtypes = [C.c_double, _dp, _dp, _dp, C.c_int, _dp]
+    L.ora_king_profile.restype = C.c_int
+    L.ora_king_density.argtypes = [C.c_double]
+    L.ora_king_density.restype = C.c_double
+    L.ora_sort_perm.argtypes = [C.c_int64, _dp, _ip]
+    L.ora_potential.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp]
+    L.ora_phi_at.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, C.c_double]
+    L.ora_phi_at.restype = C.c_double
+    L.ora_pair_terms.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _up, C.c_uint64,
+                                 C.c_uint32, C.c_double, _dp, _dp, _dp]
+    L.ora_pair_terms.restype = C.c_int64
+    L.ora_mean_sin2.argtypes = [C.c_int64, _dp, _dp, C.c_double]
+    L.ora_mean_sin2.restype = C.c_double
+    L.ora_solve_dt.argtypes = [C.c_int64, _dp, _dp, C.c_double, C.POINTER(C.c_uint32)]
+    L.ora_solve_dt.restype = C.c_double
+    L.ora_relax.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _up, C.c_uint64, C.c_uint32,
+                            C.c_double, C.c_double]
+    L.ora_orbit.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _up, C.c_uint64,
+                            C.c_uint32, C.c_int32, C.c_double, _dp,
+                            _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                            C.POINTER(OrbitStats)]
+    L.ora_step.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _up, _dp, _dp,
+                           C.POINTER(Params), C.POINTER(StepOut)]
+    L.ora_step_ex.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _up, _dp, _dp,
+                              C.POINTER(Params), C.POINTER(StepOut), _vp, _vp]
+    L.ora_lfsr113_next.argtypes = [_up]
+    L.ora_lfsr113_next.restype = C.c_uint32
+    L.ora_lfsr113_block.argtypes = [_up, _up]
+    L.ora_lfsr113_jump_pow2.argtypes = [_up, C.c_int]
+    L.ora_lfsr113_stream.argtypes = [_up, C.c_uint64, _up]
+    L.ora_lfsr113_component_period.argtypes = [C.c_int, C.c_uint32, C.c_int64]
+    L.ora_lfsr113_component_period.restype = C.c_int64
+    L.ora_energy_correction.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.ora_energy_correction.restype = C.c_int64
+    L.ora_orbit_subset.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _up,
+                                   C.c_uint64, C.c_uint32, C.c_int32, C.c_double, C.c_int64,
+                                   _ip, _dp]
+    L.ora_diagnostics.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    return L
 
 
 def _f64(x):
