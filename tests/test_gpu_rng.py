@@ -253,3 +253,33 @@ def test_lfsr_step_full_size_sampled(cmc, ora):
     # trials per star: about 1.75, as the step reports
     assert abs((drawn - 1).mean() - s["trials"] / n) < 0.15
     del cl
+
+
+def test_lfsr_with_energy_correction_lockstep(cmc, ora):
+    """Both options in one step: the sort carries the permutation and the
+    streams together; the corrected state and every stream match the oracle."""
+    n = 8_000
+    st = ora.plummer(n, 4)
+    st.rng = ora.lfsr113_seed_states(Z0, st.id)
+    cl = cmc.Cluster(n, rng=True)
+    for k in range(2):
+        cl.load(st.r, st.vr, st.vt, st.m, st.id, st.rng)
+        cl.set_scalar("dt", 0.0)
+        cmc.cmc_step(cl, cmc.Params(seed=4, step=k, gamma=0.11, rng=cmc.CMC_RNG_LFSR113,
+                                    energy_corr=1))
+        cmc.cmc_potential(cl)
+        cmc.cmc_energy_correction(cl)
+        new, info = ora.step(st, 4, k, 0.11, moves=True, lfsr=True)
+        phi, _, _ = ora.potential(new.r, new.m)
+        cor, skipped = ora.energy_correction(new, phi, info["moves"])
+        s = cl.scalars()
+        h = cl.host()
+        assert rel(s["dt"], info["dt"]) < TOL
+        assert s["n"] == cor.n and s["corr_skipped"] == skipped
+        assert np.array_equal(h["id"], cor.id)
+        assert np.array_equal(h["rng"], cor.rng)
+        assert rel(h["r"], cor.r) < TOL
+        vs = np.hypot(cor.vr, cor.vt).max()
+        for key in ("vr", "vt"):
+            assert np.max(np.abs(h[key] ** 2 - getattr(cor, key) ** 2)) < TOL * 4 * vs ** 2
+        st = cor
