@@ -108,11 +108,14 @@ typedef struct cmc_scalars {
  *  rng              : NULL, or each star's LFSR113 state (4 words, the
  *                     component words z1..z4) in the order of the stars; when
  *                     present it moves with its star in every sort.  Needed by
- *                     steps with CMC_RNG_LFSR113.
+ *                     steps with CMC_RNG_LFSR113.  cmc_init_* do not set it:
+ *                     seed it with cmc_rng_seed_lfsr113 after the model.
  *  work, work_bytes : scratch of at least cmc_workspace_bytes(cap) bytes,
  *                     256-byte aligned; calls leave nothing in it that a later
  *                     call relies on, except the potential table a cmc_step
- *                     or cmc_potential builds for the same step's orbit pass. */
+ *                     or cmc_potential builds for the same step's orbit pass,
+ *                     and the data of a pending energy correction (see
+ *                     cmc_energy_correction). */
 typedef struct cmc_state {
   int64_t cap;
   double *r, *vr, *vt;
