@@ -93,7 +93,8 @@ class Cluster:
 
     def load(self, r, vr, vt, m, id_, rng=None) -> None:
         """Upload a host state (first len(r) entries; rng: (n, 4) LFSR113
-        states) and set n."""
+        states), set n and drop any pending energy correction (it belonged to
+        the stars this replaces)."""
         n = len(r)
         if n > self.cap:
             raise A.CmcError("n > cap")
@@ -107,7 +108,10 @@ class Cluster:
         if rng is not None:
             z = np.ascontiguousarray(rng, np.uint32).reshape(-1)
             self.rng[:4 * n] = torch.as_tensor(z.view(np.int32), device=dev)
-        self.set_scalar("n", n)
+        sc = A.cmc_scalars.from_buffer_copy(self.sc.cpu().numpy().tobytes())
+        sc.n = n
+        sc.corr_n = 0
+        self.sc.copy_(torch.from_numpy(np.frombuffer(bytes(sc), dtype=np.int64).copy()))
 
     def capture(self, p: Params) -> torch.cuda.CUDAGraph:
         """A graph of one cmc_step that takes its step index from the device
