@@ -21,6 +21,20 @@ def test_half_mass_relaxation_time():
     assert half_mass_relaxation_time(10**6, 4.0) == pytest.approx(8 * 0.138e6 / np.log(1e5))
 
 
+def test_collapse_fits():
+    """The two fits of the collapse runs recover known power laws: a sample
+    with rho ~ r^-2 (mass uniform in r), and a core track rho_c ~ r_c^-2.23."""
+    from paper_1206_5878_amd.evolve import core_density_slope, density_slope
+    rng = np.random.default_rng(3)
+    r = rng.uniform(0.0, 10.0, 400_000)            # dM/dr constant: rho ~ r^-2
+    beta = density_slope(r, np.full(r.size, 1.0 / r.size), 0.5, 5.0)
+    assert beta == pytest.approx(2.0, abs=0.03)
+    rows = [(0.0, 0.0, 10.0 ** (0.1 * k), 0.0, 0, 0, 0.0, 10.0 ** (-0.1 * k / 2.23))
+            for k in range(70)]
+    assert core_density_slope(rows, 1.0) == pytest.approx(-2.23, abs=1e-9)
+    assert np.isnan(core_density_slope(rows[:3], 1.0))   # too few samples in range
+
+
 @pytest.mark.gpu
 def test_core_collapse_n1e5(P):
     from paper_1206_5878_amd.evolve import core_collapse_run
