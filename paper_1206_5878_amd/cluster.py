@@ -113,6 +113,52 @@ class Cluster:
         sc.corr_n = 0
         self.sc.copy_(torch.from_numpy(np.frombuffer(bytes(sc), dtype=np.int64).copy()))
 
+    def checkpoint(self) -> dict:
+        """Host copy of everything a later step reads: the active stars'
+        arrays (and LFSR113 states), and the scalars block with n, the dt
+        the next solve starts from and the device step counter.  Random
+        draws are keyed by (id, step), so a run resumed from it repeats the
+        uninterrupted run bit for bit.  A pending energy correction lives in
+        the workspace: apply it first (cmc_potential, cmc_energy_correction)."""
+        sc = self.scalars()
+        if sc["corr_n"]:
+            raise A.CmcError("a correction is pending: call cmc_potential and "
+                             "cmc_energy_correction before the checkpoint")
+        h = self.host()
+        ck = {k: h[k] for k in ("r", "vr", "vt", "id")}
+        ck["m"] = self.m[:self.n].cpu().numpy()
+        if self.rng is not None:
+            ck["rng"] = h["rng"]
+        ck["scalars"] = self.sc.cpu().numpy().copy()
+        return ck
+
+    def save(self, path: str) -> None:
+        """checkpoint() as a numpy .npz file (plain arrays, no pickles)."""
+        np.savez(path, **self.checkpoint())
+
+    def restore(self, ck) -> None:
+        """Load a checkpoint (the dict, or a path to a saved one) into this
+        cluster: same mass storage, capacity at least its n."""
+        if isinstance(ck, str):
+            with np.load(ck, allow_pickle=False) as f:
+                ck = {k: f[k] for k in f.files}
+        n = int(ck["r"].shape[0])
+        if n > self.cap:
+            raise A.CmcError("checkpoint larger than the capacity")
+        if (ck["m"].dtype == np.float32) != self.m_f32:
+            raise A.CmcError("checkpoint mass storage differs from the cluster's")
+        if ("rng" in ck) and self.rng is None:
+            raise A.CmcError("checkpoint has LFSR113 states: make the cluster with rng=True")
+        dev = self.r.device
+        for k in ("r", "vr", "vt"):
+            getattr(self, k)[:n] = torch.as_tensor(ck[k], device=dev)
+        self.m[:n] = torch.as_tensor(ck["m"], device=dev)
+        self.id[:n] = torch.as_tensor(np.asarray(ck["id"], np.uint32).view(np.int32), device=dev)
+        if "rng" in ck:
+            z = np.ascontiguousarray(ck["rng"], np.uint32).reshape(-1)
+            self.rng[:4 * n] = torch.as_tensor(z.view(np.int32), device=dev)
+        self.sc.copy_(torch.as_tensor(np.asarray(ck["scalars"], np.int64), device=dev))
+
     def capture(self, p: Params) -> torch.cuda.CUDAGraph:
         """A graph of one cmc_step that takes its step index from the device
         counter and advances it (CMC_STEP_DEVICE): replay it once per step."""
