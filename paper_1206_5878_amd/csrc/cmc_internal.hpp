@@ -408,8 +408,11 @@ inline Workspace layout(int64_t cap, void *base) {
   w.pair_part = reinterpret_cast<double *>(take(8 * 4 * w.pair_blocks));
   w.dt_state = reinterpret_cast<double *>(take(8 * 32));
   w.red_part = reinterpret_cast<double *>(take(8 * 8 * w.star_blocks));
+  // at least one bucket per star: a trial radius's scan then stays within a
+  // line of the radii where stars crowd; halving the buckets makes the
+  // trials slower by more than the smaller index saves in building it
   w.rx_lg_nb = 0;
-  while ((int64_t(1) << w.rx_lg_nb) < (c + 1) / 2) ++w.rx_lg_nb;
+  while ((int64_t(1) << w.rx_lg_nb) < c + 1) ++w.rx_lg_nb;
   w.rx_nb = int64_t(1) << w.rx_lg_nb;
   w.rx_start = reinterpret_cast<uint32_t *>(take(4 * (w.rx_nb + 1)));
   w.rx_tile = reinterpret_cast<uint32_t *>(take(4 * cdiv(w.rx_nb + 1, 4096)));
