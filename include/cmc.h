@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define CMC_ABI_VERSION 4
+#define CMC_ABI_VERSION 5
 
 /* ---- return codes --------------------------------------------------------- */
 #define CMC_OK 0
@@ -89,7 +89,8 @@ typedef struct cmc_scalars {
   int64_t step;       /* steps taken with cmc_params.step == CMC_STEP_DEVICE    */
   int64_t corr_n;     /* stars of the last step's orbit pass whose energy
                          correction is pending (0: none; see cmc_energy_correction) */
-  int64_t corr_skipped; /* stars the last applied correction left unchanged     */
+  int64_t corr_skipped; /* stars the last correction call left unchanged (0 when
+                           it found no correction pending)                      */
   int64_t reserved[4];
 } cmc_scalars;
 
@@ -338,6 +339,23 @@ int cmc_batch_init(const cmc_batch *b, void *stream);
  * is each cluster's sc->step, advanced at the end: a call captured once in a
  * hipGraph then advances the ensemble each time the graph is replayed. */
 int cmc_batch_step(const cmc_batch *b, const cmc_params *p, void *stream);
+
+/* The step's phases one at a time over every cluster, each as its
+ * single-cluster call on each cluster (Sec. 2.1 applied per cluster); the
+ * cluster's own seed and gamma are used, p->seed and p->gamma are ignored;
+ * CMC_RNG_LFSR113 needs b->lfsr_ready.  Called in the order potential,
+ * timestep, relax, orbit, sort they give the result of one cmc_batch_step
+ * (without energy_corr) bit for bit.
+ *  cmc_batch_sort     : as cmc_sort (step 6): order by r_new, drop escapers.
+ *  cmc_batch_potential: as cmc_potential (step 1); below.
+ *  cmc_batch_timestep : as cmc_timestep (step 2): each cluster's sc->dt.
+ *  cmc_batch_relax    : as cmc_relax (step 3(i)) with each cluster's sc->dt.
+ *  cmc_batch_orbit    : as cmc_orbit (step 5): needs cmc_batch_potential's
+ *                       public table; writes r_new, vr, vt. */
+int cmc_batch_sort(const cmc_batch *b, void *stream);
+int cmc_batch_timestep(const cmc_batch *b, const cmc_params *p, void *stream);
+int cmc_batch_relax(const cmc_batch *b, const cmc_params *p, void *stream);
+int cmc_batch_orbit(const cmc_batch *b, const cmc_params *p, void *stream);
 
 /* cmc_potential of every cluster (public phi, mcum, ssuf). */
 int cmc_batch_potential(const cmc_batch *b, int32_t precision, void *stream);

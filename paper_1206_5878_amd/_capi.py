@@ -27,7 +27,8 @@ EXPORTS = ("cmc_workspace_bytes", "cmc_init_plummer", "cmc_init_model", "cmc_sor
            "cmc_energy_correction", "cmc_diagnostics", "cmc_philox", "cmc_rng_seed_lfsr113",
            "cmc_lfsr113", "cmc_strerror",
            "cmc_abi_version", "cmc_batch_device_bytes", "cmc_batch_prepare", "cmc_batch_init",
-           "cmc_batch_step", "cmc_batch_potential", "cmc_batch_energy_correction",
+           "cmc_batch_step", "cmc_batch_sort", "cmc_batch_potential", "cmc_batch_timestep",
+           "cmc_batch_relax", "cmc_batch_orbit", "cmc_batch_energy_correction",
            "cmc_batch_diagnostics")
 CMC_SHAPES = 16
 
@@ -105,6 +106,9 @@ def lib() -> C.CDLL:
                                         C.c_size_t]
         L.cmc_batch_init.argtypes = [bp, vp]
         L.cmc_batch_step.argtypes = [bp, pp, vp]
+        L.cmc_batch_sort.argtypes = [bp, vp]
+        for f in ("cmc_batch_timestep", "cmc_batch_relax", "cmc_batch_orbit"):
+            getattr(L, f).argtypes = [bp, pp, vp]
         L.cmc_batch_potential.argtypes = [bp, C.c_int32, vp]
         L.cmc_batch_diagnostics.argtypes = [bp, vp, vp]
         L.cmc_energy_correction.argtypes = [sp, vp]

@@ -330,6 +330,24 @@ class Ensemble:
         A.check(A.lib().cmc_batch_potential(C.byref(self.handle), precision, _stream(stream)),
                 "cmc_batch_potential")
 
+    def sort(self, stream=None):
+        A.check(A.lib().cmc_batch_sort(C.byref(self.handle), _stream(stream)), "cmc_batch_sort")
+
+    def timestep(self, p: Params, stream=None):
+        pc = p.c()
+        A.check(A.lib().cmc_batch_timestep(C.byref(self.handle), C.byref(pc), _stream(stream)),
+                "cmc_batch_timestep")
+
+    def relax(self, p: Params, stream=None):
+        pc = p.c()
+        A.check(A.lib().cmc_batch_relax(C.byref(self.handle), C.byref(pc), _stream(stream)),
+                "cmc_batch_relax")
+
+    def orbit(self, p: Params, stream=None):
+        pc = p.c()
+        A.check(A.lib().cmc_batch_orbit(C.byref(self.handle), C.byref(pc), _stream(stream)),
+                "cmc_batch_orbit")
+
     def energy_correction(self, stream=None):
         A.check(A.lib().cmc_batch_energy_correction(C.byref(self.handle), _stream(stream)),
                 "cmc_batch_energy_correction")

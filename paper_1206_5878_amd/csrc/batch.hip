@@ -116,6 +116,18 @@ int check_batch(const cmc_batch *b) {
   return CMC_OK;
 }
 
+// The step parameters an ensemble call reads (seed and gamma come from each
+// cluster's spec instead).
+int check_batch_params(const cmc_batch *b, const cmc_params *p) {
+  if (!p || (p->precision != CMC_FP64 && p->precision != CMC_MIXED)) return CMC_EINVAL;
+  if (!(p->target > 0.0 && p->target < 1.0)) return CMC_EINVAL;
+  if (p->bound_factor < 0.0 || p->trial_cap < 0 || p->dt_iters < 0) return CMC_EINVAL;
+  if (p->energy_corr != 0 && p->energy_corr != 1) return CMC_EINVAL;
+  if (p->rng != CMC_RNG_PHILOX && p->rng != CMC_RNG_LFSR113) return CMC_EINVAL;
+  if (p->rng == CMC_RNG_LFSR113 && !b->lfsr_ready) return CMC_EINVAL;
+  return CMC_OK;
+}
+
 int status_of(hipError_t e) { return e == hipSuccess ? CMC_OK : CMC_EHIP; }
 
 }  // namespace
@@ -201,15 +213,51 @@ int cmc_batch_init(const cmc_batch *b, void *stream) {
 int cmc_batch_step(const cmc_batch *b, const cmc_params *p, void *stream) {
   int rc = cmc::check_batch(b);
   if (rc) return rc;
-  if (!p || (p->precision != CMC_FP64 && p->precision != CMC_MIXED)) return CMC_EINVAL;
-  if (!(p->target > 0.0 && p->target < 1.0)) return CMC_EINVAL;
-  if (p->bound_factor < 0.0 || p->trial_cap < 0 || p->dt_iters < 0) return CMC_EINVAL;
-  if (p->energy_corr != 0 && p->energy_corr != 1) return CMC_EINVAL;
-  if (p->rng != CMC_RNG_PHILOX && p->rng != CMC_RNG_LFSR113) return CMC_EINVAL;
-  if (p->rng == CMC_RNG_LFSR113 && !b->lfsr_ready) return CMC_EINVAL;
+  if ((rc = cmc::check_batch_params(b, p))) return rc;
   const cmc::BatchDev d = cmc::batch_dev(*b);
   return cmc::status_of(cmc::launch_step(cmc::Target{nullptr, &d}, b->m_f32 != 0, *p, nullptr,
                                          static_cast<hipStream_t>(stream)));
+}
+
+int cmc_batch_sort(const cmc_batch *b, void *stream) {
+  int rc = cmc::check_batch(b);
+  if (rc) return rc;
+  const cmc::BatchDev d = cmc::batch_dev(*b);
+  const cmc::Target t{nullptr, &d};
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = cmc::launch_stage_from_state(t, b->m_f32 != 0, st);
+  if (e == hipSuccess) e = cmc::launch_sort_stage(t, b->m_f32 != 0, false, false, false, true, st);
+  return cmc::status_of(e);
+}
+
+int cmc_batch_timestep(const cmc_batch *b, const cmc_params *p, void *stream) {
+  int rc = cmc::check_batch(b);
+  if (rc) return rc;
+  if ((rc = cmc::check_batch_params(b, p))) return rc;
+  const cmc::BatchDev d = cmc::batch_dev(*b);
+  return cmc::status_of(cmc::launch_timestep(cmc::Target{nullptr, &d}, b->m_f32 != 0, *p,
+                                             static_cast<hipStream_t>(stream)));
+}
+
+int cmc_batch_relax(const cmc_batch *b, const cmc_params *p, void *stream) {
+  int rc = cmc::check_batch(b);
+  if (rc) return rc;
+  if ((rc = cmc::check_batch_params(b, p))) return rc;
+  const cmc::BatchDev d = cmc::batch_dev(*b);
+  return cmc::status_of(cmc::launch_relax(cmc::Target{nullptr, &d}, b->m_f32 != 0, *p,
+                                          static_cast<hipStream_t>(stream)));
+}
+
+int cmc_batch_orbit(const cmc_batch *b, const cmc_params *p, void *stream) {
+  int rc = cmc::check_batch(b);
+  if (rc) return rc;
+  if ((rc = cmc::check_batch_params(b, p))) return rc;
+  const cmc::BatchDev d = cmc::batch_dev(*b);
+  const cmc::Target t{nullptr, &d};
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = cmc::launch_table_pack(t, st);
+  if (e == hipSuccess) e = cmc::launch_orbit(t, b->m_f32 != 0, *p, false, false, false, st);
+  return cmc::status_of(e);
 }
 
 int cmc_batch_potential(const cmc_batch *b, int32_t precision, void *stream) {

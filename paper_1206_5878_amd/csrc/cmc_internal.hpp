@@ -603,6 +603,10 @@ ClusterArgs cluster_args(const cmc_state &s, uint64_t seed, double gamma);
 // reads only the workspace table)
 hipError_t launch_potential(const Target &t, bool m_f32, int precision, bool public_arrays,
                             hipStream_t st);
+// phi, mcum, ssuf of the state without the orbit table: the workspace need
+// only hold pot_tsum and pot_carry (pot_tiles of them).
+hipError_t launch_potential_public_only(const Target &t, bool m_f32, int precision,
+                                        hipStream_t st);
 hipError_t launch_timestep(const Target &t, bool m_f32, const cmc_params &p, hipStream_t st);
 hipError_t launch_relax(const Target &t, bool m_f32, const cmc_params &p, hipStream_t st);
 // corr: also record each star's energy-correction terms (cor, pn);

@@ -32,8 +32,9 @@ __global__ __launch_bounds__(NT) void k_corr_old(Ctx ctx) {
   const ClusterArgs &A = ctx.args();
   cmc_scalars *__restrict__ sc = A.s.sc;
   const int64_t np = sc->corr_n < A.s.cap ? sc->corr_n : A.s.cap;
-  if (np <= 0) return;
+  // every correction call reports its own skips, none when nothing is pending
   if (ctx.block() == 0 && threadIdx.x == 0) sc->corr_skipped = 0;
+  if (np <= 0) return;
   const int64_t i = ctx.block() * NT + threadIdx.x;
   const RIndexCtl c = *A.w.rx_ctl;
   if (i >= np || c.n == 0) return;  // no star left: no new potential

@@ -155,7 +155,9 @@ __global__ __launch_bounds__(ST) void k_pot_tile_scan(Ctx ctx) {
   }
 }
 
-template <class Ctx, typename MT, bool PUBLIC, bool MIXED>
+// PUBLIC: write the state's phi, mcum, ssuf; TABLE: write the orbit table in
+// the workspace.
+template <class Ctx, typename MT, bool PUBLIC, bool MIXED, bool TABLE = true>
 __global__ __launch_bounds__(PT) void k_pot_apply(Ctx ctx) {
   __shared__ double sh[2 * (PT / 64)];
   const ClusterArgs &A = ctx.args();
@@ -203,7 +205,7 @@ __global__ __launch_bounds__(PT) void k_pot_apply(Ctx ctx) {
         A.s.ssuf[k] = S[j];
         A.s.phi[k] = ph;
       }
-      put_table(lv, A.w.ms, k, rr[j], ph, M[j], S[j]);
+      if (TABLE) put_table(lv, A.w.ms, k, rr[j], ph, M[j], S[j]);
     }
   }
 }
@@ -222,7 +224,30 @@ hipError_t run(const L &l, bool pub, hipStream_t st) {
   return hipGetLastError();
 }
 
+// The state's phi, mcum, ssuf only, with no orbit table (a workspace holding
+// just the scan's tile sums and carries).
+template <class L, typename MT, bool MIXED>
+hipError_t run_public_only(const L &l, hipStream_t st) {
+  k_pot_tile_sums<decltype(l.ctx(kShPotTile)), MT, MIXED>
+      <<<l.grid(kShPotTile), PT, 0, st>>>(l.ctx(kShPotTile));
+  k_pot_tile_scan<<<l.grid(kShOne), ST, 0, st>>>(l.ctx(kShOne));
+  k_pot_apply<decltype(l.ctx(kShPotTile)), MT, true, MIXED, false>
+      <<<l.grid(kShPotTile), PT, 0, st>>>(l.ctx(kShPotTile));
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_potential_public_only(const Target &t, bool m_f32, int precision,
+                                        hipStream_t st) {
+  return dispatch(t, [&](const auto &l) {
+    using L = std::decay_t<decltype(l)>;
+    const bool mx = precision == CMC_MIXED;
+    if (m_f32)
+      return mx ? run_public_only<L, float, true>(l, st) : run_public_only<L, float, false>(l, st);
+    return mx ? run_public_only<L, double, true>(l, st) : run_public_only<L, double, false>(l, st);
+  });
+}
 
 hipError_t launch_potential(const Target &t, bool m_f32, int precision, bool public_arrays,
                             hipStream_t st) {

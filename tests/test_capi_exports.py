@@ -23,7 +23,7 @@ def test_library_exports_every_declared_call():
     for n in names:
         assert hasattr(L, n), n
     assert set(A.EXPORTS) == set(names)
-    assert L.cmc_abi_version() == 4
+    assert L.cmc_abi_version() == 5
 
 
 def test_host_side_checks_without_gpu():

@@ -1,0 +1,138 @@
+"""The mixed-precision form over 100 steps at N = 1e6 against the FP64
+oracle (equal-mass Plummer, seed 1, ln(0.11 N)).
+
+The GPU runs 100 mixed steps from its own initial model.  At steps 0, 10,
+..., 90 the state it has reached is copied to the host, and from that same
+state both sides take the step's phases: the potential (Sec. 2.1 step 1),
+Delta t and the relaxation (steps 2-3), and then a whole step (steps 1-6),
+the GPU in mixed precision and the oracle in FP64.  Per star, matched by id:
+
+  Phi  the potential at the star, relative to |Phi_i|;
+  E    the orbit energy Phi_i + (vr^2 + vt^2)/2 after the relaxation, the
+       quantity the orbit step conserves, relative to |Phi_i| (a bound star
+       has Phi_i <= E < 0, so this is the scale of the terms E is made of;
+       relative to |E| itself the error of a star with E near 0 measures the
+       cancellation, not the arithmetic);
+  J    r vt after the relaxation, relative to r |v| (the largest J the star's
+       speed allows; J of a nearly radial orbit is a small difference of
+       kicked components);
+  r    the new radius after the whole step, relative to max(r_new, r_old);
+       stars beyond 1e-5 are accept/reject decisions that FP32 took the
+       other way ("flips") and are counted, not compared;
+  Etot the total energy T + W of the stepped states (each side's own
+       potential of its own result), relative.
+
+The max, p99 and median of each are printed (run with -s to see them) and
+the maxima held to the mixed tolerance of 1e-5; the total energy to 1e-6
+of |E| per step, so 1e-4 over 100 steps even if every step's error added
+up."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+N = 1_000_000
+SEED, GAMMA = 1, 0.11
+MTOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def cmc():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1206_5878_amd as P
+    P.lib()
+    return P
+
+
+def stats(e):
+    e = np.asarray(e, np.float64)
+    return dict(max=float(e.max()), p99=float(np.percentile(e, 99)),
+                median=float(np.median(e)))
+
+
+def by_id(ids, want):
+    order = np.argsort(ids)
+    pos = np.searchsorted(ids[order], want)
+    pos = np.minimum(pos, ids.size - 1)
+    assert np.array_equal(ids[order][pos], want)
+    return order[pos]
+
+
+def probe_step(cmc, ora, probe, st, k):
+    """One step's phases from state st on both sides; the error table."""
+    mixed = cmc.Params(seed=SEED, step=k, gamma=GAMMA, precision=cmc.CMC_MIXED)
+    row = {"step": k}
+    # Sec. 2.1 step 1
+    probe.load(st.r, st.vr, st.vt, st.m, st.id)
+    probe.set_scalar("dt", 0.0)
+    cmc.cmc_potential(probe, cmc.CMC_MIXED)
+    phi_o, _, _ = ora.potential(st.r, st.m)
+    h = probe.host()
+    row["phi"] = stats(np.abs(h["phi"] - phi_o) / np.abs(phi_o))
+    # steps 2 and 3(i), each side with its own Delta t
+    cmc.cmc_timestep(probe, mixed)
+    dt_g = probe.scalars()["dt"]
+    dt_o, _ = ora.timestep(st, SEED, k, GAMMA, 0.03)
+    row["dt"] = abs(dt_g / dt_o - 1.0)
+    cmc.cmc_relax(probe, mixed)
+    g = probe.host()
+    rl = ora.relax(st, SEED, k, GAMMA, dt_o)
+    e_g = h["phi"] + 0.5 * (g["vr"] ** 2 + g["vt"] ** 2)
+    e_o = phi_o + 0.5 * (rl.vr ** 2 + rl.vt ** 2)
+    row["E"] = stats(np.abs(e_g - e_o) / np.abs(phi_o))
+    sp = np.hypot(rl.vr, rl.vt)
+    jsc = st.r * np.where(sp > 0, sp, 1.0)
+    row["J"] = stats(np.abs(st.r * g["vt"] - st.r * rl.vt) / jsc)
+    # the whole step
+    probe.load(st.r, st.vr, st.vt, st.m, st.id)
+    probe.set_scalar("dt", 0.0)
+    cmc.cmc_step(probe, mixed)
+    new, _ = ora.step(st, SEED, k, GAMMA)
+    ng = probe.host()
+    row["n"] = (probe.n, new.n)
+    common = np.intersect1d(ng["id"], new.id)
+    ig, io = by_id(ng["id"], common), by_id(new.id, common)
+    i_old = by_id(st.id, common)
+    e = np.abs(ng["r"][ig] - new.r[io]) / np.maximum(new.r[io], st.r[i_old])
+    row["flips"] = int(np.sum(e > MTOL))
+    row["r"] = stats(e[e <= MTOL])
+    cmc.cmc_potential(probe, cmc.CMC_FP64)
+    etot_g = float(cmc.cmc_diagnostics(probe)["E"])
+    etot_o = float(ora.diagnostics(new)["E"])
+    row["Etot"] = abs(etot_g - etot_o) / abs(etot_o)
+    return row
+
+
+def test_mixed_100_steps_1e6_against_fp64_oracle(cmc, ora):
+    run = cmc.Cluster(N)
+    cmc.cmc_init_plummer(run, N, SEED, 0)
+    probe = cmc.Cluster(N)
+    rows = []
+    for k in range(100):
+        if k % 10 == 0:
+            h = run.host()
+            st = ora.State(h["r"], h["vr"], h["vt"], h["m"], h["id"])
+            rows.append(probe_step(cmc, ora, probe, st, k))
+            r = rows[-1]
+            print(f"step {k:3d}: n {r['n']}  dt {r['dt']:.1e}  flips {r['flips']}  "
+                  f"Etot {r['Etot']:.1e}  " +
+                  "  ".join(f"{q} max {r[q]['max']:.1e} p99 {r[q]['p99']:.1e} "
+                            f"med {r[q]['median']:.1e}" for q in ("phi", "E", "J", "r")),
+                  flush=True)
+        cmc.cmc_step(run, cmc.Params(seed=SEED, step=k, gamma=GAMMA, precision=cmc.CMC_MIXED))
+        assert not (run.scalars()["status"] & (cmc.ST_NONFINITE | cmc.ST_TRIAL_CAP))
+    for q in ("phi", "E", "J", "r"):
+        worst = max(r[q]["max"] for r in rows)
+        print(f"over the 10 probes: {q} max {worst:.2e}, p99 "
+              f"{max(r[q]['p99'] for r in rows):.2e}, median "
+              f"{np.median([r[q]['median'] for r in rows]):.2e}")
+        assert worst < MTOL, (q, worst)
+        assert worst > 0.0, q  # FP32 arithmetic really ran
+    print(f"total energy: max {max(r['Etot'] for r in rows):.2e}; dt: max "
+          f"{max(r['dt'] for r in rows):.2e}; flips: {[r['flips'] for r in rows]}")
+    assert max(r["dt"] for r in rows) < MTOL
+    assert max(r["Etot"] for r in rows) < 1e-6
+    for r in rows:
+        assert abs(r["n"][0] - r["n"][1]) <= 3  # FP32 kicks may move a star across E = 0
+        assert r["flips"] <= max(3, 2e-5 * N), r["flips"]
