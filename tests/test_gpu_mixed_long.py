@@ -19,6 +19,14 @@ the GPU in mixed precision and the oracle in FP64.  Per star, matched by id:
   r    the new radius after the whole step, relative to max(r_new, r_old);
        stars beyond 1e-5 are accept/reject decisions that FP32 took the
        other way ("flips") and are counted, not compared;
+       the kick has a discrete decision too: the reference axis of the
+       rotation basis is the one of the smallest |w| component, and where two
+       components tie to within FP32 rounding the mixed form may take the
+       other axis, which turns the same random azimuth into another, equally
+       valid kick.  A pair whose E or J is off by more than 1e-5 is such a
+       flip: both of its stars, counted, not compared, and each such pair
+       must still conserve its kinetic energy and radial momentum to 1e-5
+       (the kick stays exact);
   Etot the total energy T + W of the stepped states (each side's own
        potential of its own result), relative.
 
@@ -80,10 +88,30 @@ def probe_step(cmc, ora, probe, st, k):
     rl = ora.relax(st, SEED, k, GAMMA, dt_o)
     e_g = h["phi"] + 0.5 * (g["vr"] ** 2 + g["vt"] ** 2)
     e_o = phi_o + 0.5 * (rl.vr ** 2 + rl.vt ** 2)
-    row["E"] = stats(np.abs(e_g - e_o) / np.abs(phi_o))
+    err_e = np.abs(e_g - e_o) / np.abs(phi_o)
     sp = np.hypot(rl.vr, rl.vt)
     jsc = st.r * np.where(sp > 0, sp, 1.0)
-    row["J"] = stats(np.abs(st.r * g["vt"] - st.r * rl.vt) / jsc)
+    err_j = np.abs(st.r * g["vt"] - st.r * rl.vt) / jsc
+    # kick-basis flips, by pair (2j, 2j+1); an odd last star is never kicked
+    npair = st.r.size // 2
+    bad = (err_e > MTOL) | (err_j > MTOL)
+    assert not bad[2 * npair:].any()
+    pb = bad[:2 * npair].reshape(npair, 2).any(axis=1)
+    flipped = np.repeat(pb, 2)
+    row["kick_flips"] = int(pb.sum())
+    m = np.asarray(st.m, np.float64)[:2 * npair].reshape(npair, 2)[pb]
+    v0r = st.vr[:2 * npair].reshape(npair, 2)[pb]
+    v0t = st.vt[:2 * npair].reshape(npair, 2)[pb]
+    v1r = g["vr"][:2 * npair].reshape(npair, 2)[pb]
+    v1t = g["vt"][:2 * npair].reshape(npair, 2)[pb]
+    ke0 = (m * (v0r ** 2 + v0t ** 2)).sum(axis=1)
+    ke1 = (m * (v1r ** 2 + v1t ** 2)).sum(axis=1)
+    assert np.all(np.abs(ke1 - ke0) <= MTOL * ke0), (ke0, ke1)
+    p0, p1 = (m * v0r).sum(axis=1), (m * v1r).sum(axis=1)
+    assert np.all(np.abs(p1 - p0) <= MTOL * np.sqrt(ke0 * m.sum(axis=1))), (p0, p1)
+    keep = np.concatenate([~flipped, np.ones(st.r.size - 2 * npair, bool)])
+    row["E"] = stats(err_e[keep])
+    row["J"] = stats(err_j[keep])
     # the whole step
     probe.load(st.r, st.vr, st.vt, st.m, st.id)
     probe.set_scalar("dt", 0.0)
@@ -116,6 +144,7 @@ def test_mixed_100_steps_1e6_against_fp64_oracle(cmc, ora):
             rows.append(probe_step(cmc, ora, probe, st, k))
             r = rows[-1]
             print(f"step {k:3d}: n {r['n']}  dt {r['dt']:.1e}  flips {r['flips']}  "
+                  f"kick flips {r['kick_flips']}  "
                   f"Etot {r['Etot']:.1e}  " +
                   "  ".join(f"{q} max {r[q]['max']:.1e} p99 {r[q]['p99']:.1e} "
                             f"med {r[q]['median']:.1e}" for q in ("phi", "E", "J", "r")),
@@ -130,9 +159,11 @@ def test_mixed_100_steps_1e6_against_fp64_oracle(cmc, ora):
         assert worst < MTOL, (q, worst)
         assert worst > 0.0, q  # FP32 arithmetic really ran
     print(f"total energy: max {max(r['Etot'] for r in rows):.2e}; dt: max "
-          f"{max(r['dt'] for r in rows):.2e}; flips: {[r['flips'] for r in rows]}")
+          f"{max(r['dt'] for r in rows):.2e}; flips: {[r['flips'] for r in rows]}; "
+          f"kick flips: {[r['kick_flips'] for r in rows]}")
     assert max(r["dt"] for r in rows) < MTOL
     assert max(r["Etot"] for r in rows) < 1e-6
     for r in rows:
         assert abs(r["n"][0] - r["n"][1]) <= 3  # FP32 kicks may move a star across E = 0
         assert r["flips"] <= max(3, 2e-5 * N), r["flips"]
+        assert r["kick_flips"] <= max(3, 1e-5 * N), r["kick_flips"]
