@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define CMC_ABI_VERSION 5
+#define CMC_ABI_VERSION 6
 
 /* ---- return codes --------------------------------------------------------- */
 #define CMC_OK 0
@@ -42,6 +42,8 @@ extern "C" {
 #define CMC_EWORKSPACE (-2) /* work_bytes < cmc_workspace_bytes(cap)            */
 #define CMC_EHIP (-3)       /* a kernel launch failed (hipGetLastError)         */
 #define CMC_ERANGE (-4)     /* n > cap                                          */
+#define CMC_ESCRATCH (-5)   /* cmc_step_noalloc: cmc_workspace_bytes(cap) is
+                               larger than CMC_SCRATCH_BYTES                    */
 
 /* ---- sticky device status bits (cmc_scalars.status) ----------------------- */
 #define CMC_ST_NONFINITE 0x01u /* a non-finite radius or velocity was produced  */
@@ -232,6 +234,31 @@ int cmc_step(cmc_state *s, const cmc_params *p, void *stream);
  * index of the orbit pass count to the potential phase).  events: 6
  * hipEvent_t created by the caller. */
 int cmc_step_timed(cmc_state *s, const cmc_params *p, void *const *events, void *stream);
+
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): cmc_step
+ * with the library's own scratch in place of s->work.  s->work and
+ * s->work_bytes are ignored (they may be NULL and 0); every other array of
+ * the state is the caller's, as for cmc_step, and the result is cmc_step's
+ * bit for bit.
+ *  - The scratch is one static device array of CMC_SCRATCH_BYTES per GPU
+ *    (64 MiB), held from the first call on that GPU until the process ends;
+ *    its device address is looked up once per GPU, on the first call made
+ *    while that GPU is current.  `stream` must belong to the current device.
+ *  - Capacity limit: cmc_workspace_bytes(s->cap) <= CMC_SCRATCH_BYTES, about
+ *    320,000 stars (about 208 bytes per star); a larger cap returns
+ *    CMC_ESCRATCH and enqueues nothing.
+ *  - p->energy_corr must be 0 (CMC_EINVAL otherwise): a pending correction's
+ *    data would have to outlive the call in scratch that the next call on the
+ *    GPU overwrites.  Like cmc_step with energy_corr = 0, the step drops a
+ *    correction the state had pending.
+ *  - Every call on one GPU shares that GPU's array, and each call leaves its
+ *    contents behind; no call relies on what an earlier one left.  Calls that
+ *    overlap in time on one GPU (different streams, or threads) race on it
+ *    and give undefined results: order them on one stream.
+ *  - Allocates nothing: no hipMalloc, hipFree or allocating library call. */
+#define CMC_SCRATCH_BYTES ((size_t)64 << 20)
+int cmc_step_noalloc(cmc_state *s, const cmc_params *p, void *stream);
 
 /* Energy correction (Sec. 2.1 item 6): the orbits of a step are drawn in the
  * old potential Phi_old; once the stars have moved, the potential is

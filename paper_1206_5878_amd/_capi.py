@@ -12,7 +12,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcmc.so")
 
-CMC_OK, CMC_EINVAL, CMC_EWORKSPACE, CMC_EHIP, CMC_ERANGE = 0, -1, -2, -3, -4
+CMC_OK, CMC_EINVAL, CMC_EWORKSPACE, CMC_EHIP, CMC_ERANGE, CMC_ESCRATCH = 0, -1, -2, -3, -4, -5
+CMC_SCRATCH_BYTES = 64 << 20
 CMC_FP64, CMC_MIXED = 0, 1
 CMC_MODEL_PLUMMER, CMC_MODEL_KING = 0, 1
 CMC_RNG_PHILOX, CMC_RNG_LFSR113 = 0, 1
@@ -23,7 +24,7 @@ ST_NONFINITE, ST_TRIAL_CAP, ST_BOUND, ST_ESCAPER = 0x01, 0x02, 0x04, 0x08
 ST_DT_DEGEN, ST_NUMERIC, ST_DT_NOCONV = 0x10, 0x20, 0x40
 
 EXPORTS = ("cmc_workspace_bytes", "cmc_init_plummer", "cmc_init_model", "cmc_sort", "cmc_potential",
-           "cmc_timestep", "cmc_relax", "cmc_orbit", "cmc_step", "cmc_step_timed",
+           "cmc_timestep", "cmc_relax", "cmc_orbit", "cmc_step", "cmc_step_timed", "cmc_step_noalloc",
            "cmc_energy_correction", "cmc_diagnostics", "cmc_philox", "cmc_rng_seed_lfsr113",
            "cmc_lfsr113", "cmc_strerror",
            "cmc_abi_version", "cmc_batch_device_bytes", "cmc_batch_prepare", "cmc_batch_init",
@@ -96,7 +97,7 @@ def lib() -> C.CDLL:
                                      C.c_double, vp]
         L.cmc_sort.argtypes = [sp, vp]
         L.cmc_potential.argtypes = [sp, C.c_int32, vp]
-        for f in ("cmc_timestep", "cmc_relax", "cmc_orbit", "cmc_step"):
+        for f in ("cmc_timestep", "cmc_relax", "cmc_orbit", "cmc_step", "cmc_step_noalloc"):
             getattr(L, f).argtypes = [sp, pp, vp]
         L.cmc_step_timed.argtypes = [sp, pp, C.POINTER(C.c_void_p), vp]
         bp = C.POINTER(cmc_batch)

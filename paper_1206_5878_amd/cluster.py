@@ -228,6 +228,14 @@ def cmc_step(cl: Cluster, p: Params, stream=None):
     A.check(A.lib().cmc_step(cl.c, C.byref(pc), _stream(stream)), "cmc_step")
 
 
+def cmc_step_noalloc(cl: Cluster, p: Params, stream=None):
+    """cmc_step on the library's static per-GPU scratch instead of the
+    cluster's workspace (for callers that cannot allocate); caps up to
+    cmc_workspace_bytes(cap) <= CMC_SCRATCH_BYTES, energy_corr = 0."""
+    pc = p.c()
+    A.check(A.lib().cmc_step_noalloc(cl.c, C.byref(pc), _stream(stream)), "cmc_step_noalloc")
+
+
 def cmc_energy_correction(cl: Cluster, stream=None):
     A.check(A.lib().cmc_energy_correction(cl.c, _stream(stream)), "cmc_energy_correction")
 

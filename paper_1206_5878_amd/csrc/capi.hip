@@ -2,6 +2,8 @@
 // include/cmc.h): host-side argument checks, workspace carving, and the
 // launch sequence of each step of arXiv:1206.5878 Sec. 2.1.  Nothing here
 // allocates, frees or synchronises.
+#include <mutex>
+
 #include "cmc_internal.hpp"
 
 using cmc::Workspace;
@@ -100,6 +102,33 @@ Single single(const cmc_state &s, uint64_t seed, double gamma) {
 
 hipStream_t as_stream(void *stream) { return static_cast<hipStream_t>(stream); }
 
+// ---------------------------------------------------------------- static scratch
+// The workspace of cmc_step_noalloc: one copy per GPU, for the whole process.
+// In host code `scratch` names a host-side stand-in, not device memory: only
+// the address hipGetSymbolAddress returns for the current device is passed on.
+__device__ __align__(256) unsigned char scratch[CMC_SCRATCH_BYTES];
+
+constexpr int kScratchDevices = 64;
+std::mutex scratch_mu;
+void *scratch_addr[kScratchDevices];  // device address of `scratch`, per device
+
+// The current device's scratch address, looked up on the first call made
+// while that device is current.
+int scratch_of_current_device(void **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return CMC_EHIP;
+  if (dev < 0 || dev >= kScratchDevices) return CMC_EINVAL;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_addr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CMC_EHIP;
+    if (reinterpret_cast<uintptr_t>(p) % 256 != 0) return CMC_EHIP;
+    scratch_addr[dev] = p;
+  }
+  *out = scratch_addr[dev];
+  return CMC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -123,6 +152,8 @@ const char *cmc_strerror(int code) {
       return "HIP kernel launch failed";
     case CMC_ERANGE:
       return "star count larger than the state capacity";
+    case CMC_ESCRATCH:
+      return "capacity too large for the library's static scratch (CMC_SCRATCH_BYTES)";
     default:
       return "unknown cmc error code";
   }
@@ -219,6 +250,20 @@ static int run_step(cmc_state *s, const cmc_params *p, void *const *events, hipS
 
 int cmc_step(cmc_state *s, const cmc_params *p, void *stream) {
   return run_step(s, p, nullptr, as_stream(stream));
+}
+
+int cmc_step_noalloc(cmc_state *s, const cmc_params *p, void *stream) {
+  if (!s || s->cap <= 0 || s->cap > kMaxCap) return CMC_EINVAL;
+  if (cmc::layout(s->cap, nullptr).bytes > CMC_SCRATCH_BYTES) return CMC_ESCRATCH;
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (p->energy_corr != 0) return CMC_EINVAL;
+  void *ptr = nullptr;
+  if ((rc = scratch_of_current_device(&ptr))) return rc;
+  cmc_state t = *s;
+  t.work = ptr;
+  t.work_bytes = CMC_SCRATCH_BYTES;
+  return run_step(&t, p, nullptr, as_stream(stream));
 }
 
 int cmc_step_timed(cmc_state *s, const cmc_params *p, void *const *events, void *stream) {

@@ -23,7 +23,7 @@ def test_library_exports_every_declared_call():
     for n in names:
         assert hasattr(L, n), n
     assert set(A.EXPORTS) == set(names)
-    assert L.cmc_abi_version() == 5
+    assert L.cmc_abi_version() == 6
 
 
 def test_host_side_checks_without_gpu():
@@ -62,6 +62,20 @@ def test_host_side_checks_without_gpu():
     assert L.cmc_init_plummer(C.byref(s), 101, 1, 0, None) == A.CMC_ERANGE
     assert L.cmc_init_plummer(C.byref(s), 10, 1, 3, None) == A.CMC_EINVAL
     assert b"workspace" in L.cmc_strerror(A.CMC_EWORKSPACE)
+    # the static-scratch step: a capacity beyond the scratch, and a pending
+    # correction it could not keep, are refused before anything runs
+    big = 1
+    while L.cmc_workspace_bytes(big) <= A.CMC_SCRATCH_BYTES:
+        big *= 2
+    assert big > 200_000
+    s.cap = big
+    good = A.cmc_params(1, 0, 0, 0.11, 0.03, 1.2, 10000, 0)
+    assert L.cmc_step_noalloc(C.byref(s), C.byref(good), None) == A.CMC_ESCRATCH
+    assert b"scratch" in L.cmc_strerror(A.CMC_ESCRATCH)
+    s.cap = 100
+    corr = A.cmc_params(1, 0, 0, 0.11, 0.03, 1.2, 10000, 0, 1)
+    assert L.cmc_step_noalloc(C.byref(s), C.byref(corr), None) == A.CMC_EINVAL
+    assert L.cmc_step_noalloc(None, C.byref(good), None) == A.CMC_EINVAL
 
 
 def test_product_does_not_import_oracle():
