@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define CMC_ABI_VERSION 6
+#define CMC_ABI_VERSION 7
 
 /* ---- return codes --------------------------------------------------------- */
 #define CMC_OK 0
@@ -246,7 +246,7 @@ int cmc_step_timed(cmc_state *s, const cmc_params *p, void *const *events, void 
  *    its device address is looked up once per GPU, on the first call made
  *    while that GPU is current.  `stream` must belong to the current device.
  *  - Capacity limit: cmc_workspace_bytes(s->cap) <= CMC_SCRATCH_BYTES, about
- *    320,000 stars (about 208 bytes per star); a larger cap returns
+ *    250,000 stars (about 270 bytes per star); a larger cap returns
  *    CMC_ESCRATCH and enqueues nothing.
  *  - p->energy_corr must be 0 (CMC_EINVAL otherwise): a pending correction's
  *    data would have to outlive the call in scratch that the next call on the
@@ -329,7 +329,7 @@ typedef struct cmc_cluster_spec {
   double w0;             /* King central potential                               */
 } cmc_cluster_spec;
 
-#define CMC_SHAPES 16
+#define CMC_SHAPES 24
 
 /* Host handle of an ensemble, filled by cmc_batch_prepare.  `dev` is device
  * memory of cmc_batch_device_bytes() bytes, 256-byte aligned, owned by the
@@ -344,7 +344,7 @@ typedef struct cmc_batch {
   int32_t bucket_sort;          /* 1: the step sorts by buckets (every capacity  */
                                 /*    <= CMC_BUCKET_CAP_MAX), 0: radix sort      */
   int32_t lfsr_ready;           /* 1: every cluster has an rng array             */
-  int32_t reserved;
+  int32_t sorted_searches;      /* the launch table's choice for the ensemble    */
 } cmc_batch;
 
 /* Device bytes of the ensemble tables for these states (0 if invalid). */
@@ -393,6 +393,41 @@ int cmc_batch_energy_correction(const cmc_batch *b, void *stream);
 /* cmc_diagnostics of every cluster: out_dev[CMC_DIAG_N c .. CMC_DIAG_N c +
  * CMC_DIAG_N - 1] for cluster c. */
 int cmc_batch_diagnostics(const cmc_batch *b, double *out_dev, void *stream);
+
+/* ---- launch table ------------------------------------------------------------
+ * How the orbit pass (Sec. 2.1 item 5) is launched, by capacity: a read-only
+ * table that the library consults when it sets up a call (each single-cluster
+ * call, and cmc_batch_prepare for an ensemble, with the sum of the clusters'
+ * capacities).  Every entry gives the same results bit for bit; only the
+ * speed differs.  The built-in table holds measured defaults; an autotuner
+ * (the package's tune.py, after the paper's own launch-configuration study,
+ * Appendix A) times candidates on the GPU and installs its table here.
+ *  sorted         : 1: the turning-point searches are grouped by the sample
+ *                   of the LDS-resident top levels they reach, so that the
+ *                   searches sharing a subtree run together; 0: each star's
+ *                   wavefront searches its own brackets to the bottom.
+ *  bracket_blocks : resident blocks of the direct search kernel for a single
+ *                   cluster (an ensemble shares them out by capacity), 8..65535.
+ *  trial_chunk    : stars per wavefront chunk of the rejection-trial kernel,
+ *                   a multiple of 64 in [64, 1024]. */
+typedef struct cmc_tuning {
+  int64_t min_cap;        /* the entry serves capacities >= min_cap          */
+  int32_t sorted;
+  int32_t bracket_blocks;
+  int32_t trial_chunk;
+  int32_t reserved[3];
+} cmc_tuning;
+#define CMC_TUNING_MAX 32
+
+/* Install a launch table of n entries (n <= CMC_TUNING_MAX, min_cap strictly
+ * increasing, the first 0); n = 0 restores the built-in table.  The table is
+ * copied.  A setup call: not to be made while other calls of the library run
+ * or are being set up in other threads.  CMC_EINVAL for a bad table (the
+ * table in use is then unchanged). */
+int cmc_set_tuning(const cmc_tuning *entries, int32_t n);
+
+/* The entry of the table in use that serves capacity cap (*out). */
+int cmc_get_tuning(int64_t cap, cmc_tuning *out);
 
 /* Text for a CMC_E* code. */
 const char *cmc_strerror(int code);

@@ -30,8 +30,9 @@ EXPORTS = ("cmc_workspace_bytes", "cmc_init_plummer", "cmc_init_model", "cmc_sor
            "cmc_abi_version", "cmc_batch_device_bytes", "cmc_batch_prepare", "cmc_batch_init",
            "cmc_batch_step", "cmc_batch_sort", "cmc_batch_potential", "cmc_batch_timestep",
            "cmc_batch_relax", "cmc_batch_orbit", "cmc_batch_energy_correction",
-           "cmc_batch_diagnostics")
-CMC_SHAPES = 16
+           "cmc_batch_diagnostics", "cmc_set_tuning", "cmc_get_tuning")
+CMC_TUNING_MAX = 32
+CMC_SHAPES = 24
 
 
 class cmc_scalars(C.Structure):
@@ -67,7 +68,12 @@ class cmc_batch(C.Structure):
     _fields_ = [("clusters", C.c_int32), ("m_f32", C.c_int32), ("dev", C.c_void_p),
                 ("dev_bytes", C.c_size_t), ("total", C.c_int64 * CMC_SHAPES),
                 ("top_entries", C.c_int32), ("bucket_sort", C.c_int32),
-                ("lfsr_ready", C.c_int32), ("reserved", C.c_int32)]
+                ("lfsr_ready", C.c_int32), ("sorted_searches", C.c_int32)]
+
+
+class cmc_tuning(C.Structure):
+    _fields_ = [("min_cap", C.c_int64), ("sorted", C.c_int32), ("bracket_blocks", C.c_int32),
+                ("trial_chunk", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 assert C.sizeof(cmc_scalars) == 128
@@ -118,11 +124,36 @@ def lib() -> C.CDLL:
         L.cmc_philox.argtypes = [C.c_uint64, vp, vp, C.c_int64, vp]
         L.cmc_rng_seed_lfsr113.argtypes = [sp, C.POINTER(C.c_uint32), C.c_uint64, vp]
         L.cmc_lfsr113.argtypes = [vp, vp, C.c_int64, C.c_int32, vp]
+        L.cmc_set_tuning.argtypes = [C.POINTER(cmc_tuning), C.c_int32]
+        L.cmc_get_tuning.argtypes = [C.c_int64, C.POINTER(cmc_tuning)]
         L.cmc_strerror.argtypes = [C.c_int]
         L.cmc_strerror.restype = C.c_char_p
         L.cmc_abi_version.restype = C.c_int  # every other call returns int too
         _lib = L
+        _install_tuning(L)
     return _lib
+
+
+TUNING_PATH = os.path.join(HERE, "tuning.json")
+
+
+def _install_tuning(L) -> None:
+    """Install the autotuner's launch table (tune.py) when the package holds
+    one; the library's built-in table serves otherwise."""
+    if not os.path.exists(TUNING_PATH):
+        return
+    import json
+    with open(TUNING_PATH) as f:
+        table = json.load(f)["table"]
+    arr = (cmc_tuning * len(table))()
+    for k, e in enumerate(table):
+        arr[k].min_cap = int(e["min_cap"])
+        arr[k].sorted = int(e["sorted"])
+        arr[k].bracket_blocks = int(e["bracket_blocks"])
+        arr[k].trial_chunk = int(e["trial_chunk"])
+    rc = L.cmc_set_tuning(arr, len(table))
+    if rc != CMC_OK:
+        raise CmcError(f"{TUNING_PATH}: the library refused the launch table (code {rc})")
 
 
 def check(rc: int, what: str) -> None:

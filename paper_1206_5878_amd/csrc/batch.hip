@@ -38,11 +38,13 @@ BatchLayout batch_layout(int32_t clusters, const int64_t *total) {
 }
 
 // Blocks of each cluster in each launch shape.  The bracket kernel's
-// resident blocks are shared out in proportion to the clusters' capacities.
+// resident blocks (the launch table's for the summed capacity) are shared
+// out in proportion to the clusters' capacities.
 void shape_blocks(const std::vector<ClusterArgs> &a, std::vector<int64_t> *blocks) {
   const int C = static_cast<int>(a.size());
   double cap_sum = 0.0;
   for (const auto &x : a) cap_sum += static_cast<double>(x.s.cap);
+  const int64_t resident = a.empty() ? 1 : a[0].w.bracket_blocks;
   for (int sh = 0; sh < kShapes; ++sh) {
     blocks[sh].assign(C, 0);
     for (int c = 0; c < C; ++c) {
@@ -50,7 +52,7 @@ void shape_blocks(const std::vector<ClusterArgs> &a, std::vector<int64_t> *block
       int64_t b = blocks_of(static_cast<Shape>(sh), w, a[c].s.cap);
       if (sh == kShBracket) {
         const int64_t share = static_cast<int64_t>(
-            std::llround(kBracketBlocks * static_cast<double>(a[c].s.cap) / cap_sum));
+            std::llround(resident * static_cast<double>(a[c].s.cap) / cap_sum));
         b = std::max<int64_t>(1, std::min<int64_t>(share, b));
       }
       blocks[sh][c] = b;
@@ -72,12 +74,17 @@ int totals(const cmc_state *states, int32_t clusters, std::vector<ClusterArgs> *
            std::vector<int64_t> *blocks, int64_t *total) {
   if (!states || clusters < 1 || clusters > kMaxClusters) return CMC_EINVAL;
   args->clear();
+  int64_t cap_sum = 0;
   for (int c = 0; c < clusters; ++c) {
     const int rc = check_state(states[c]);
     if (rc) return rc;
     if ((states[c].m_f32 != 0) != (states[0].m_f32 != 0)) return CMC_EINVAL;
     args->push_back(cluster_args(states[c], 0, 1.0));
+    cap_sum += states[c].cap;
   }
+  // one launch table entry for the whole ensemble: its summed capacity
+  const cmc_tuning tun = tuning_for(cap_sum);
+  for (auto &a : *args) apply_tuning(a.w, tun);
   shape_blocks(*args, blocks);
   for (int sh = 0; sh < kShapes; ++sh) {
     int64_t t = 0;
@@ -105,6 +112,7 @@ BatchDev batch_dev(const cmc_batch &b) {
   d.any_f32 = b.m_f32;
   d.any_f64 = !b.m_f32;
   d.bucket_sort = b.bucket_sort;
+  d.sorted = b.sorted_searches;
   return d;
 }
 
@@ -198,7 +206,7 @@ int cmc_batch_prepare(cmc_batch *b, const cmc_state *states, const cmc_cluster_s
   b->top_entries = top;
   b->bucket_sort = bucket;
   b->lfsr_ready = lfsr;
-  b->reserved = 0;
+  b->sorted_searches = args[0].w.sorted;
   return CMC_OK;
 }
 

@@ -10,10 +10,40 @@ using cmc::Workspace;
 
 namespace cmc {
 
+// ---------------------------------------------------------------- launch table
+// Read-only while calls run (cmc_set_tuning is a setup call).  Built in:
+// measured defaults (see the package's tuning notes).
+namespace {
+constexpr cmc_tuning kBuiltinTuning[] = {
+    {0, 0, kDefaultBracketBlocks, kDefaultTrialChunk, {0, 0, 0}},
+};
+cmc_tuning g_tuning[CMC_TUNING_MAX];
+int32_t g_tuning_n = 0;  // 0: the built-in table
+std::mutex g_tuning_mu;
+}  // namespace
+
+cmc_tuning tuning_for(int64_t cap) {
+  const cmc_tuning *t = g_tuning_n ? g_tuning : kBuiltinTuning;
+  const int32_t n = g_tuning_n ? g_tuning_n
+                               : static_cast<int32_t>(sizeof(kBuiltinTuning) /
+                                                      sizeof(kBuiltinTuning[0]));
+  int32_t k = 0;
+  while (k + 1 < n && t[k + 1].min_cap <= cap) ++k;
+  return t[k];
+}
+
+// A capacity's launch settings into its workspace view.
+void apply_tuning(Workspace &w, const cmc_tuning &t) {
+  w.sorted = t.sorted;
+  w.bracket_blocks = t.bracket_blocks;
+  w.trial_chunk = t.trial_chunk;
+}
+
 ClusterArgs cluster_args(const cmc_state &s, uint64_t seed, double gamma) {
   ClusterArgs a{};
   a.s = s;
   a.w = layout(s.cap, s.work);
+  apply_tuning(a.w, tuning_for(s.cap));
   a.top = orbit_top(a.w, s.cap);
   a.seed = seed;
   a.gamma = gamma;
@@ -134,6 +164,27 @@ int scratch_of_current_device(void **out) {
 extern "C" {
 
 int cmc_abi_version(void) { return CMC_ABI_VERSION; }
+
+int cmc_set_tuning(const cmc_tuning *entries, int32_t n) {
+  if (n < 0 || n > CMC_TUNING_MAX || (n > 0 && !entries)) return CMC_EINVAL;
+  for (int32_t k = 0; k < n; ++k) {
+    const cmc_tuning &t = entries[k];
+    if (k == 0 ? t.min_cap != 0 : t.min_cap <= entries[k - 1].min_cap) return CMC_EINVAL;
+    if (t.sorted != 0 && t.sorted != 1) return CMC_EINVAL;
+    if (t.bracket_blocks < 8 || t.bracket_blocks > 65535) return CMC_EINVAL;
+    if (t.trial_chunk < 64 || t.trial_chunk > 1024 || t.trial_chunk % 64 != 0) return CMC_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(cmc::g_tuning_mu);
+  for (int32_t k = 0; k < n; ++k) cmc::g_tuning[k] = entries[k];
+  cmc::g_tuning_n = n;
+  return CMC_OK;
+}
+
+int cmc_get_tuning(int64_t cap, cmc_tuning *out) {
+  if (!out || cap < 0) return CMC_EINVAL;
+  *out = cmc::tuning_for(cap);
+  return CMC_OK;
+}
 
 size_t cmc_workspace_bytes(int64_t cap) {
   if (cap <= 0 || cap > kMaxCap) return 0;

@@ -240,11 +240,35 @@ struct alignas(16) RPhi {
 struct alignas(16) MS {
   double M, S;
 };
-// Orbit of one star between the bracket and trial kernels (F < 0: done).
-struct alignas(16) OrbitRec {
-  double E, J, rmin, rmax, F;
-  int32_t kmin, kmax;
+// Orbit of one star between the orbit pass's kernels, as two 32-byte halves:
+// each turning point is found by one kernel, which writes its half whole
+// (one aligned sector, no partial write).  lo: E, the lower turning point
+// rmin in interval kmin (-1: inside the innermost star) and dQ/dr there;
+// hi: J, rmax in interval kmax and dQ/dr there.  E >= 0 (or NaN) marks a
+// star already sent out as an escaper.
+struct alignas(32) OrbitLo {
+  double E, rmin, dq;
+  int32_t kmin;
+  uint32_t pad;
 };
+struct alignas(32) OrbitHi {
+  double J, rmax, dq;
+  int32_t kmax;
+  uint32_t pad;
+};
+struct alignas(64) OrbitRec {
+  OrbitLo lo;
+  OrbitHi hi;
+};
+// One turning-point search left below the LDS-resident top levels: the
+// star's E, J and index, and the sample of the level ltop the search reached
+// (bit 31: the upper turning point).  Searches are grouped by that sample, so
+// the ones that share a subtree of the table run together.
+struct alignas(8) OrbQuery {
+  double E, J;
+  uint32_t i, node;
+};
+constexpr uint32_t kQueryHi = 0x80000000u;
 constexpr int kMaxLevels = 12;  // 8^11 > 2^32 stars
 struct Levels {
   RPhi *const *lev;  // the workspace's level pointers, [kMaxLevels]
@@ -314,6 +338,11 @@ constexpr int kBucketTile = 16384;      // stars per histogram and scatter tile
 constexpr int kBucketSortCap = 4096;    // stars a bucket sorts in LDS
 constexpr uint32_t kBucketEsc = 0xFFFFFFFFu;  // bkey of a star that leaves the cluster
 constexpr int kKingTab = 3 * kKingNodes + 8;
+// The orbit table's top levels held in LDS by the orbit pass's kernels, and
+// the sorted turning-point searches below them (orbit.hip).
+constexpr int kTopBytes = 48 * 1024;
+constexpr int kTopEntries = kTopBytes / 16;  // (r, Phi) entries
+constexpr int kQueryTile = 8192;             // stars per tile of the search sort
 constexpr int kPhiBins = 16384;  // bins of the potential-bound table (orbit.hip)
 // LFSR113 stream seeding (rng.hip): for each component, the 32x32 bit matrix
 // of 2^(80+b) steps for every bit b of a stream index (a base below 2^33
@@ -356,7 +385,17 @@ struct Workspace {
   uint32_t *perm;           // [cap] staged (old) index of each sorted star
   Lfsr *rng_stage;          // [cap] LFSR113 states after the orbit pass, staged order
   uint32_t *lfsr_jump;      // [kLfsrJumpWords] jump matrices of the stream seeding
+  OrbQuery *oq;             // [2 cap] turning-point searches grouped by top sample
+  uint32_t *oq_cnt;         // [oq_tiles * oq_bins] per-tile counts, then tile offsets
+  uint32_t *oq_tot;         // [oq_bins] searches per top sample
+  uint32_t *oq_start;       // [oq_bins + 1] first search of each top sample
+  uint32_t *oq_chunk;       // [oq_bins + 1] first search block of each top sample
+  uint32_t *oq_node;        // [cap] each star's two top samples
   int64_t bkt_bins, bkt_tiles;  // bkt_bins = 0: capacity above kBucketCapMax
+  int64_t oq_bins, oq_tiles;    // samples of the level the LDS top ends at; tiles
+  // launch settings from the launch table (cluster_args; layout() leaves the
+  // built-in defaults)
+  int32_t sorted, bracket_blocks, trial_chunk;
   int64_t rx_nb;
   int rx_lg_nb;
   int64_t sort_tiles, pot_tiles, pair_blocks, star_blocks;
@@ -364,6 +403,33 @@ struct Workspace {
 };
 
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Top levels of the orbit table kept in LDS: levels from the top down while
+// they fit kTopBytes (at the capacity).  ltop = the lowest of them.
+struct OrbitTop {             // top levels of the orbit table kept in LDS
+  int32_t off[kMaxLevels];    // LDS entry offset of level L, for L >= ltop
+  int32_t len[kMaxLevels];    // entries of level L at the capacity
+  int32_t ltop, entries;
+};
+inline OrbitTop top_levels(int nlev, int64_t cap) {
+  OrbitTop tl{};
+  int64_t tot = 0;
+  tl.ltop = nlev;
+  for (int L = nlev - 1; L >= 0; --L) {
+    const int64_t stride = int64_t(1) << (3 * L);
+    const int64_t len = (cap + stride - 1) / stride;
+    if ((tot + len) * 16 > kTopBytes) break;
+    tl.off[L] = static_cast<int32_t>(tot);
+    tl.len[L] = static_cast<int32_t>(len);
+    tot += len;
+    tl.ltop = L;
+  }
+  tl.entries = static_cast<int32_t>(tot);
+  return tl;
+}
+
+constexpr int kDefaultBracketBlocks = 1024;  // resident bracket blocks of one cluster
+constexpr int kDefaultTrialChunk = 128;      // stars per wavefront chunk of the trial kernel
 
 inline Workspace layout(int64_t cap, void *base) {
   Workspace w{};
@@ -426,6 +492,17 @@ inline Workspace layout(int64_t cap, void *base) {
   w.perm = reinterpret_cast<uint32_t *>(take(4 * c));
   w.rng_stage = reinterpret_cast<Lfsr *>(take(sizeof(Lfsr) * c));
   w.lfsr_jump = reinterpret_cast<uint32_t *>(take(4 * kLfsrJumpWords));
+  {
+    const OrbitTop tl = top_levels(w.nlev, c);
+    w.oq_bins = tl.ltop > 0 ? tl.len[tl.ltop] : 1;
+    w.oq_tiles = cdiv(c, kQueryTile);
+    w.oq = reinterpret_cast<OrbQuery *>(take(sizeof(OrbQuery) * 2 * c));
+    w.oq_cnt = reinterpret_cast<uint32_t *>(take(4 * w.oq_tiles * w.oq_bins));
+    w.oq_tot = reinterpret_cast<uint32_t *>(take(4 * w.oq_bins));
+    w.oq_start = reinterpret_cast<uint32_t *>(take(4 * (w.oq_bins + 1)));
+    w.oq_chunk = reinterpret_cast<uint32_t *>(take(4 * (w.oq_bins + 1)));
+    w.oq_node = reinterpret_cast<uint32_t *>(take(4 * c));
+  }
   w.bent = reinterpret_cast<BktEnt *>(w.orec);  // orec is dead once the orbit pass ends
   static_assert(sizeof(BktEnt) <= sizeof(OrbitRec), "bent fits in orec");
   if (c <= kBucketCapMax) {
@@ -436,6 +513,9 @@ inline Workspace layout(int64_t cap, void *base) {
     w.bkt_start = reinterpret_cast<uint32_t *>(take(4 * (w.bkt_bins + 1)));
     w.bkt_info = reinterpret_cast<int64_t *>(take(8 * 2));
   }
+  w.sorted = 0;
+  w.bracket_blocks = kDefaultBracketBlocks;
+  w.trial_chunk = kDefaultTrialChunk;
   w.bytes = (off + 255) & ~size_t(255);
   return w;
 }
@@ -464,11 +544,6 @@ __device__ __forceinline__ void put_table(const Levels &lv, MS *ms, int64_t k, d
 // cluster.  An ensemble: one launch covers every cluster, each cluster owns
 // its own arrays and workspace, and a per-shape map names the cluster of
 // each block and the cluster's first block.
-struct OrbitTop {             // top levels of the orbit table kept in LDS
-  int32_t off[kMaxLevels];    // LDS entry offset of level L, for L >= ltop
-  int32_t len[kMaxLevels];    // entries of level L at the capacity
-  int32_t ltop, entries;
-};
 struct ClusterArgs {
   cmc_state s;                // the cluster's arrays (device pointers)
   Workspace w;                // its workspace
@@ -527,12 +602,15 @@ enum Shape : int {
   kShBktTile,   // histogram and scatter tiles of the step's sort
   kShBktGroup,  // groups of 64 buckets
   kShBktSort,   // one block per bucket of kept stars
+  kShQTile,     // tiles of the orbit pass's search sort
+  kShQGroup,    // groups of 64 top samples
+  kShQSearch,   // blocks of sorted turning-point searches
   kShapes
 };
 constexpr int kBracketThreads = 512;
-constexpr int kBracketBlocks = 1024;  // resident bracket blocks of one cluster
-constexpr int kTrialChunk = 128;      // stars per wavefront chunk of the trial kernel
 constexpr int kRxTile = 4096;         // bucket-index entries per prefix-maximum tile
+constexpr int kQuerySearchBlock = 256; // threads of the sorted-search kernel
+constexpr int kQuerySearchChunk = 1024; // searches of one group per block of it
 __host__ __device__ inline int64_t blocks_of(Shape sh, const Workspace &w, int64_t cap) {
   const int64_t c = cap > 0 ? cap : 1;
   switch (sh) {
@@ -546,9 +624,9 @@ __host__ __device__ inline int64_t blocks_of(Shape sh, const Workspace &w, int64
     case kShDigit: return 256;
     case kShBracket: {
       const int64_t b = cdiv(c, kBracketThreads);
-      return b < kBracketBlocks ? b : kBracketBlocks;
+      return b < w.bracket_blocks ? b : w.bracket_blocks;
     }
-    case kShTrials: return cdiv(c, int64_t(kTrialChunk) * (kBlock / 64));
+    case kShTrials: return cdiv(c, int64_t(w.trial_chunk) * (kBlock / 64));
     case kShRxClear: {
       const int64_t b = cdiv(w.rx_nb + 1, kBlock);
       return b < 4096 ? b : 4096;
@@ -558,6 +636,9 @@ __host__ __device__ inline int64_t blocks_of(Shape sh, const Workspace &w, int64
     case kShBktTile: return w.bkt_bins ? w.bkt_tiles : 1;
     case kShBktGroup: return w.bkt_bins ? cdiv(w.bkt_bins, 64) : 1;
     case kShBktSort: return w.bkt_bins ? w.bkt_bins - 1 : 1;
+    case kShQTile: return w.oq_tiles;
+    case kShQGroup: return cdiv(w.oq_bins, 64);
+    case kShQSearch: return w.oq_bins + cdiv(2 * c, kQuerySearchChunk);
     default: return 1;
   }
 }
@@ -573,6 +654,7 @@ struct BatchDev {
   int32_t top_entries;                  // largest OrbitTop::entries
   int32_t any_f32, any_f64;             // mass storage kinds present
   int32_t bucket_sort;                  // every cluster's capacity <= kBucketCapMax
+  int32_t sorted;                       // the orbit pass groups its searches
 };
 struct Target {
   const ClusterArgs *one;               // host struct, or null
@@ -583,12 +665,16 @@ struct OneL {
   One ctx(Shape) const { return One{a}; }
   unsigned grid(Shape sh) const { return static_cast<unsigned>(blocks_of(sh, a.w, a.s.cap)); }
   int top_entries() const { return a.top.entries; }
+  // whether some cluster's table fits the LDS whole (its star pass then
+  // searches with the LDS levels alone)
+  bool flat_top() const { return a.top.ltop == 0; }
 };
 struct ManyL {
   const BatchDev &d;
   Many ctx(Shape sh) const { return Many{d.args, d.map[sh], d.first[sh]}; }
   unsigned grid(Shape sh) const { return static_cast<unsigned>(d.total[sh]); }
   int top_entries() const { return d.top_entries; }
+  bool flat_top() const { return true; }
 };
 
 // The orbit table's LDS-resident top levels for a capacity.
@@ -640,6 +726,16 @@ hipError_t launch_bucket_sort(const Target &t, bool m_f32, bool corr, hipStream_
 // state the step left: builds the radial index, applies it, and with
 // `finish` clears sc->corr_n.
 hipError_t launch_energy_correction(const Target &t, bool finish, hipStream_t st);
+// Whether the orbit pass groups its turning-point searches (orbit.hip), as
+// the launch table chose for the cluster or the ensemble.
+inline bool sorted_searches(const Target &t) {
+  if (t.many) return t.many->sorted != 0;
+  return t.one->w.sorted != 0;
+}
+// The launch table (capi.hip): the entry serving a capacity, and its
+// settings into a workspace view.
+cmc_tuning tuning_for(int64_t cap);
+void apply_tuning(Workspace &w, const cmc_tuning &t);
 // Whether the target's step sorts by buckets.
 inline bool bucket_sort_of(const Target &t) {
   return t.many ? t.many->bucket_sort != 0 : t.one->w.bkt_bins > 0;

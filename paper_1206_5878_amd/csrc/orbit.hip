@@ -16,15 +16,7 @@
 // with the LFSR113 generator of Sec. 3.6, from the star's own stream, whose
 // state then leaves with the staged star.
 //
-// Two kernels.  k_orbit_bracket: brackets, roots and the rejection bound F
-// of every star, written as a 48-byte orbit record (escapers and degenerate
-// orbits are finished there); its blocks stay resident and loop over tiles
-// of stars.  k_orbit_trials: each wavefront owns a chunk of stars and every
-// lane draws trials for one star at a time, taking the chunk's next star as
-// soon as its own is accepted, so the loop does not wait for the unluckiest
-// lane of the wavefront.
-//
-// Searches.  The lower and the upper bracket are each "the last index k
+// Brackets.  The lower and the upper bracket are each "the last index k
 // where a predicate monotone in k holds".  They descend the sampled levels of
 // the table (level L = every 8^L-th (r, Phi)): per level, the 8 children of
 // the current sample are one aligned cache line, and the count of children
@@ -32,9 +24,22 @@
 // thousand entries) sit in LDS and each lane descends them alone; below
 // them, lanes work in groups of 8 so that every node is one coalesced load.
 // Brackets are unique, so this finds the index a bisection over the whole
-// table finds.  The interval of a trial radius comes from the radial bucket
-// index (rindex.hip); a trial that the potential-bound table proves rejected
-// skips that lookup (see surely_rejected).
+// table finds.  Two forms, with the same result:
+//  - direct (k_orbit_bracket): each star's wavefront searches its own two
+//    brackets to the bottom; below the LDS top every level is a random line
+//    of a table far larger than the L2.
+//  - sorted (k_oq_*): the searches are first grouped by the LDS-level sample
+//    they reached (a counting sort of 2 N small records), so that the
+//    searches sharing a subtree run together and find it in the L2; each
+//    writes its half of the star's orbit record.
+// Either way the roots inside the brackets and the rejection bound F follow.
+// k_orbit_trials then draws the radii: each wavefront owns a chunk of stars
+// and every lane draws trials for one star at a time, taking the chunk's
+// next star as soon as its own is accepted, so the loop does not wait for
+// the unluckiest lane of the wavefront.  The interval of a trial radius
+// comes from the radial bucket index (rindex.hip); a trial that the
+// potential-bound table proves rejected skips that lookup (see
+// surely_rejected).
 #include <algorithm>
 #include <type_traits>
 
@@ -45,7 +50,6 @@ namespace {
 
 constexpr int NT = kBlock;
 constexpr int BT = 512;         // threads per block of the bracket kernel
-constexpr int kChunk = 128;     // stars per wavefront in the trial kernel
 // group searches whose loads are in flight together: 4 keeps the bracket
 // kernel at 86 VGPRs without spills (8 needs 118); its occupancy is set by
 // the LDS-resident top levels either way, and 4 measured ~1 % faster
@@ -64,23 +68,6 @@ __device__ __forceinline__ bool q_nonneg(double twoE, double J2, const RPhi &e) 
   if (e.r == 0.0) return J2 == 0.0 && twoE - 2.0 * e.phi >= 0.0;
   return (twoE - 2.0 * e.phi) * (e.r * e.r) >= J2;
 }
-// Q_k < 0 and k < below.
-struct QNeg {
-  double twoE, J2;
-  int64_t below;
-  __device__ bool operator()(int64_t k, const RPhi &e) const {
-    return k < below && q_neg(twoE, J2, e);
-  }
-};
-// Q_k >= 0 or k <= upto.
-struct QNonNeg {
-  double twoE, J2;
-  int64_t upto;
-  __device__ bool operator()(int64_t k, const RPhi &e) const {
-    return k <= upto || q_nonneg(twoE, J2, e);
-  }
-};
-
 // Potential inside interval k from the defining sum: -(M_k / x + S_k); flat
 // at Phi_0 inside the innermost star.
 __device__ __forceinline__ double phi_in(const Levels &lv, const MS *__restrict__ ms, int64_t k,
@@ -156,122 +143,173 @@ __device__ __forceinline__ bool surely_rejected(const PhiBounds &pb, double x, d
 }
 
 // ---------------------------------------------------------------- group search
-// The same search, cooperative: lanes form groups of 8 (group g = lanes
+// The searches run cooperatively: lanes form groups of 8 (group g = lanes
 // 8g..8g+7), and each group runs the searches of its 8 lanes together.  Per
-// level, lane q of the group loads child q of each of the 8 current samples,
-// so every node is one coalesced 128-byte load instead of 7 loads per lane,
-// and a ballot counts the children that satisfy the predicate.  Predicate
-// parameters travel through LDS.  Every lane of the wavefront must call it.
+// level, lane q loads child q of each of the 8 current samples, so every
+// node is one aligned 128-byte block -- one coalesced line in global memory,
+// 8 consecutive entries (no bank conflict inside the group) in LDS -- and a
+// ballot counts the children that satisfy each predicate.  The 8 loads of a
+// level are in flight together.  Predicate parameters travel through LDS.
+// Every lane of the wavefront must call it.
 struct GParams {
-  double a, b;  // QNeg/QNonNeg: 2E, J^2
-  int32_t c;    // QNeg: below; QNonNeg: upto
-  int32_t s0;   // sample reached at level ltop (-1: no index holds)
+  double a, b;  // 2E, J^2
+  int32_t c;    // the star's index: below (lower bracket) or upto (upper)
+  int32_t s0;   // the sample the search starts below (-1: no index holds)
 };
-struct GQNeg {
+struct GQNeg {  // lower bracket: Q_k < 0 and k < below
   __device__ static bool eval(const GParams &p, int64_t k, const RPhi &e) {
     return k < p.c && q_neg(p.a, p.b, e);
   }
 };
-struct GQNonNeg {
+struct GQNonNeg {  // upper bracket: Q_k >= 0 or k <= upto
   __device__ static bool eval(const GParams &p, int64_t k, const RPhi &e) {
     return k <= p.c || q_nonneg(p.a, p.b, e);
   }
 };
 
-// Descent of the levels below ltop for two searches per lane (predicates PA
-// and PB, e.g. the lower and the upper bracket).  Each lane brings the
-// samples its own searches reached at level ltop (see top_descend; -1: no
-// index holds).  All 16 searches of a group have their loads in flight
-// together, so a level costs one memory round trip.
-template <class PA, class PB>
-__device__ __forceinline__ void group_descend2(const Levels &lv, int ltop, int64_t n,
-                                               const GParams &ma, const GParams &mb,
-                                               GParams *prm_a, GParams *prm_b, int64_t &ka,
-                                               int64_t &kb) {
+// Level entries: from the LDS copy of the top levels (L >= ltop) or from
+// global memory.
+struct TopSrc {
+  const RPhi *top;
+  const OrbitTop *tl;
+  const Levels *lv;
+  __device__ __forceinline__ RPhi operator()(int L, int64_t child) const {
+    return L >= tl->ltop ? top[tl->off[L] + child] : lv->lev[L][child];
+  }
+};
+
+// Descent of levels lhi down to llo for the 8 searches of each group, each
+// starting below sample mine.s0 of level lhi + 1 (lhi = nlev - 1: below the
+// root, s0 = 0).  Returns the sample of level llo the lane's own search
+// reaches (-1: no index holds).  wprm: the wavefront's 64 LDS slots.
+template <class Pred, class Src>
+__device__ __forceinline__ int32_t group_descend(const Src &src, int lhi, int llo, int64_t n,
+                                                 const GParams &mine, GParams *wprm) {
   const int lane = threadIdx.x & 63, g = lane >> 3, q = lane & 7;
-  prm_a[lane] = ma;
-  prm_b[lane] = mb;
+  wprm[lane] = mine;
   __builtin_amdgcn_wave_barrier();
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  int32_t s[16];
+  int32_t s[8];
 #pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    s[t] = prm_a[(g << 3) + t].s0;
-    s[8 + t] = prm_b[(g << 3) + t].s0;
-  }
+  for (int u = 0; u < 8; ++u) s[u] = wprm[(g << 3) + u].s0;
 #pragma unroll
   for (int L = kMaxLevels - 1; L >= 0; --L) {
-    if (L < ltop) {
-      // re-read the parameters from LDS at every level rather than keep
-      // 16 sets of them live in registers
+    if (L <= lhi && L >= llo) {
+      // re-read the parameters from LDS at every level rather than keep 8
+      // sets of them live in registers
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
       const int64_t stride = int64_t(1) << (3 * L);
       const int64_t cnt = (n + stride - 1) / stride;
-      const RPhi *lev = lv.lev[L];
+      RPhi e[8];
 #pragma unroll
-      for (int h = 0; h < 16; h += kGroupBatch) {
-        RPhi e[kGroupBatch];
+      for (int u = 0; u < 8; ++u) {
+        const int64_t child = static_cast<int64_t>(s[u]) * 8 + q;
+        e[u] = (s[u] >= 0 && child < cnt) ? src(L, child) : RPhi{0.0, 0.0};
+      }
 #pragma unroll
-        for (int v = 0; v < kGroupBatch; ++v) {
-          const int u = h + v;
-          const int64_t child = static_cast<int64_t>(s[u]) * 8 + q;
-          e[v] = (s[u] >= 0 && child < cnt) ? lev[child] : RPhi{0.0, 0.0};
-        }
-#pragma unroll
-        for (int v = 0; v < kGroupBatch; ++v) {
-          const int u = h + v;
-          const GParams p = (u < 8) ? prm_a[(g << 3) + u] : prm_b[(g << 3) + u - 8];
-          const int64_t child = static_cast<int64_t>(s[u]) * 8 + q;
-          const bool in = s[u] >= 0 && child < cnt;
-          const bool ok = in && ((u < 8) ? PA::eval(p, child * stride, e[v])
-                                         : PB::eval(p, child * stride, e[v]));
-          const uint64_t m = __ballot(ok);
-          const int c = __popcll((m >> (g << 3)) & 0xFFull);
-          if (s[u] >= 0) s[u] = s[u] * 8 + c - 1;
-        }
+      for (int u = 0; u < 8; ++u) {
+        const GParams p = wprm[(g << 3) + u];
+        const int64_t child = static_cast<int64_t>(s[u]) * 8 + q;
+        const bool ok = s[u] >= 0 && child < cnt && Pred::eval(p, child * stride, e[u]);
+        const uint64_t m = __ballot(ok);
+        const int c = __popcll((m >> (g << 3)) & 0xFFull);
+        if (s[u] >= 0) s[u] = s[u] * 8 + c - 1;
       }
     }
   }
   __builtin_amdgcn_wave_barrier();
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  int32_t ra = s[0], rb = s[8];
+  int32_t r = s[0];
 #pragma unroll
-  for (int t = 1; t < 8; ++t) {
-    if (q == t) {
-      ra = s[t];
-      rb = s[8 + t];
-    }
-  }
-  ka = ra;
-  kb = rb;
+  for (int u = 1; u < 8; ++u)
+    if (q == u) r = s[u];
+  return r;
 }
 
 // ---------------------------------------------------------------- LDS top
-// The levels [ltop, nlev) -- a few thousand entries, see orbit_top() -- are
-// copied into LDS by every block of the bracket kernel; each lane descends
-// them on its own.
-constexpr int kTopBytes = 48 * 1024;
+// The levels [ltop, nlev) -- at most kTopEntries entries, see top_levels() --
+// are copied into LDS by every block of the kernels that start the searches.
+__device__ __forceinline__ void load_top(RPhi *top, const Levels &lv, const OrbitTop &tl,
+                                         int nthreads) {
+  for (int L = tl.ltop; L < lv.nlev; ++L)
+    for (int e = threadIdx.x; e < tl.len[L]; e += nthreads) top[tl.off[L] + e] = lv.lev[L][e];
+}
 
-template <class Pred>
-__device__ __forceinline__ int32_t top_descend(const RPhi *top, const OrbitTop &tl, int nlev,
-                                               int64_t n, const Pred &pred) {
-  if (!pred(0, top[tl.off[nlev - 1]])) return -1;
-  int64_t s = 0;
-#pragma unroll
-  for (int L = kMaxLevels - 1; L >= 0; --L) {
-    if (L < nlev && L >= tl.ltop) {
-      const int64_t stride = int64_t(1) << (3 * L);
-      const int64_t cnt = (n + stride - 1) / stride;
-      const int64_t base = s * 8;
-      const RPhi *blk = top + tl.off[L] + base;
-      int c = 0;
-#pragma unroll
-      for (int q = 1; q < 8; ++q)
-        if (base + q < cnt && pred((base + q) * stride, blk[q])) c = q;
-      s = base + c;
-    }
+// Both brackets of a lane's star from the root down to level llo: the
+// samples of level llo (llo = 0: the brackets).  bound = false: no search
+// (the lane still takes part).  Every lane of the wavefront must call it.
+__device__ __forceinline__ void bracket_samples(const TopSrc &src, int nlev, int llo, int64_t n,
+                                                bool bound, double E, double J2, int64_t i,
+                                                GParams *wprm, int32_t &t0, int32_t &t1) {
+  const RPhi e0 = src.top[src.tl->off[nlev - 1]];  // table entry 0
+  const int32_t ii = static_cast<int32_t>(i);
+  GParams lo{2.0 * E, J2, ii, -1}, hi{2.0 * E, J2, ii, -1};
+  if (bound) {
+    lo.s0 = GQNeg::eval(lo, 0, e0) ? 0 : -1;
+    hi.s0 = 0;  // k = 0 <= upto always holds
   }
-  return static_cast<int32_t>(s);
+  t0 = group_descend<GQNeg>(src, nlev - 1, llo, n, lo, wprm);
+  t1 = group_descend<GQNonNeg>(src, nlev - 1, llo, n, hi, wprm);
+}
+
+// ---------------------------------------------------------------- turning points
+// The lower turning point in interval kmin (-1: inside the innermost star,
+// where the potential is flat), from r^2 Q = 2(E + S_k) r^2 + 2 M_k r - J^2
+// in the cancellation-free form, kept inside the interval; with dQ/dr there.
+__device__ __forceinline__ OrbitLo finalize_lo(const RPhi *__restrict__ tab,
+                                               const MS *__restrict__ ms, int64_t kmin, double E,
+                                               double J, double J2) {
+  double rmin;
+  if (J2 == 0.0) {
+    rmin = 0.0;
+  } else if (kmin < 0) {
+    rmin = J / sqrt(2.0 * (E - tab[0].phi));
+  } else {
+    const MS t = ms[kmin];
+    const double a = 2.0 * (E + t.S);
+    const double b = 2.0 * t.M;
+    const double disc = b * b + 4.0 * a * J2;
+    const double den = b + sqrt(disc > 0.0 ? disc : 0.0);
+    rmin = den > 0.0 ? 2.0 * J2 / den : tab[kmin].r;
+  }
+  const double rl = kmin >= 0 ? tab[kmin].r : 0.0, rh = tab[kmin + 1].r;
+  rmin = rmin < rl ? rl : (rmin > rh ? rh : rmin);
+  OrbitLo o{};
+  o.E = E;
+  o.rmin = rmin;
+  o.dq = (J2 != 0.0) ? dq_in(ms, kmin, rmin, J2) : 0.0;
+  o.kmin = static_cast<int32_t>(kmin);
+  return o;
+}
+
+// The upper turning point in interval kmax (n - 1: beyond the last star).
+__device__ __forceinline__ OrbitHi finalize_hi(const RPhi *__restrict__ tab,
+                                               const MS *__restrict__ ms, int64_t n, int64_t kmax,
+                                               double E, double J, double J2) {
+  const MS t = ms[kmax];
+  const double a = 2.0 * (E + t.S);
+  const double b = 2.0 * t.M;
+  const double disc = b * b + 4.0 * a * J2;
+  const double sq = sqrt(disc > 0.0 ? disc : 0.0);
+  const double rl = tab[kmax].r;
+  const double rh = (kmax + 1 < n) ? tab[kmax + 1].r : kInf;
+  double rmax = a < 0.0 ? (b + sq) / (-2.0 * a) : rh;
+  rmax = rmax < rl ? rl : (rmax > rh ? rh : rmax);
+  OrbitHi o{};
+  o.J = J;
+  o.rmax = rmax;
+  o.dq = dq_in(ms, kmax, rmax, J2);
+  o.kmax = static_cast<int32_t>(kmax);
+  return o;
+}
+
+// The record of a star that leaves the cluster (E >= 0 or NaN): the trial
+// kernel skips it.
+__device__ __forceinline__ OrbitLo escaper_lo(double E) {
+  OrbitLo o{};
+  o.E = E;
+  o.kmin = -1;
+  return o;
 }
 
 // Star outputs: the staged record, its radix key and c = the number of old
@@ -331,165 +369,415 @@ __device__ __forceinline__ void put_lfsr(const ClusterArgs &A, int64_t i, const 
     store_lfsr(A.s.rng, i, g);
 }
 
-template <class Ctx, typename MT, bool TO_STAGE, bool LF>
-__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4)))
-void k_orbit_bracket(Ctx ctx, uint32_t step_arg, double bound_factor, int corr) {
-  extern __shared__ RPhi top[];
-  __shared__ double shd[BT / 64];
-  __shared__ GParams prm[2 * BT];
-  const ClusterArgs &A = ctx.args();
-  const uint32_t step = step_of(A, step_arg);
-  const Levels lv = levels_of(A.w);
-  const OrbitTop &tl = A.top;
-  const RIndex ix{A.s.r, A.w.rx_start, A.w.rx_ctl};
-  const MS *__restrict__ ms = A.w.ms;
+
+// Per-star work of the pass before the searches: the energy-correction
+// record, the staged RNG state, E and J, and the escapers (sent out here,
+// their masses and energies summed).  Returns whether the star is bound.
+template <typename MT, bool TO_STAGE, bool LF>
+__device__ __forceinline__ bool star_start(const ClusterArgs &A, int64_t i, int corr, double &E,
+                                           double &J, double &J2, double &c_esc, double &e_esc,
+                                           uint32_t &fl) {
+  const RPhi me = A.w.lev[0][i];
+  if (corr) A.w.cor[i] = me;  // r_old and Phi_old(r_old)
+  // an LFSR113 state moves with its star; a Philox step stages it as it is
+  // (an LFSR step stages it after the star's draws, and every kept star
+  // draws at least its sign)
+  if (TO_STAGE && !LF && A.s.rng) A.w.rng_stage[i] = load_lfsr(A.s.rng, i);
+  const double vri = A.s.vr[i], vti = A.s.vt[i];
+  E = me.phi + 0.5 * (vri * vri + vti * vti);
+  J = me.r * vti;
+  J2 = J * J;
+  if (E < 0.0) return true;
+  // unbound: leaves the cluster
   const MT *__restrict__ m = static_cast<const MT *>(A.s.m);
-  double *__restrict__ vr = A.s.vr;
-  double *__restrict__ vt = A.s.vt;
-  const uint32_t *__restrict__ id = A.s.id;
-  double *__restrict__ r_new = A.s.r_new;
-  StageRec<MT> *__restrict__ stage = static_cast<StageRec<MT> *>(A.w.stage);
-  uint64_t *__restrict__ keys = A.w.keys[0];
-  uint32_t *__restrict__ bkey = A.w.bkey;
-  OrbitRec *__restrict__ orec = A.w.orec;
-  RPhi *__restrict__ cor = A.w.cor;
-  double *__restrict__ pn = A.w.pn;
-  cmc_scalars *__restrict__ sc = A.s.sc;
-  double *__restrict__ part = A.w.red_part;
-  const uint64_t seed = A.seed;
-  const RIndexCtl ictl = *ix.ctl;
-  const int64_t n = ictl.n;
-  const RPhi *tab = lv.lev[0];
-  GParams *wprm = prm + (threadIdx.x & ~63);
-  for (int L = tl.ltop; L < lv.nlev; ++L)
-    for (int e = threadIdx.x; e < tl.len[L]; e += BT) top[tl.off[L] + e] = lv.lev[L][e];
-  __syncthreads();
+  c_esc += 1.0;
+  e_esc += load_mass(m, i) * E;
+  fl |= CMC_ST_ESCAPER;
+  if (E != E) fl |= CMC_ST_NONFINITE;
+  emit<TO_STAGE>(i, kInf, vri, vti, m[i], A.s.id[i], 0, A.s.r_new, A.s.vr, A.s.vt,
+                 static_cast<StageRec<MT> *>(A.w.stage), A.w.keys[0], A.w.bkey);
+  A.w.orec[i].lo = escaper_lo(E);
+  return false;
+}
 
-  double c_esc = 0.0, e_esc = 0.0;
-  uint32_t fl = 0;
-  const int64_t tiles = (n + BT - 1) / BT;
-  const int64_t blk = ctx.block(), nblk = ctx.nblocks();
-  for (int64_t tile = blk; tile < tiles; tile += nblk) {  // block-uniform
-    const int64_t i = tile * BT + threadIdx.x;
-    double E = 0.0, J = 0.0, J2 = 0.0, vri = 0.0, vti = 0.0;
-    if (i < n) {
-      const RPhi me = tab[i];
-      if (corr) cor[i] = me;  // r_old and Phi_old(r_old)
-      // an LFSR113 state moves with its star; a Philox step stages it as it
-      // is (an LFSR step stages it after the star's draws, and every kept
-      // star draws at least its sign)
-      if (TO_STAGE && !LF && A.s.rng) A.w.rng_stage[i] = load_lfsr(A.s.rng, i);
-      vri = vr[i];
-      vti = vt[i];
-      E = me.phi + 0.5 * (vri * vri + vti * vti);
-      J = me.r * vti;
-      J2 = J * J;
-    }
-    const bool bound = i < n && E < 0.0;
-    const int32_t ii = static_cast<int32_t>(i);
-    // brackets: the LDS levels per lane, the rest by groups of 8 lanes
-    int32_t t0 = -1, t1 = -1;
-    if (bound) {
-      t0 = top_descend(top, tl, lv.nlev, n, QNeg{2.0 * E, J2, ii});
-      t1 = top_descend(top, tl, lv.nlev, n, QNonNeg{2.0 * E, J2, ii});
-    }
-    int64_t kmin_g, kmax_g;
-    group_descend2<GQNeg, GQNonNeg>(lv, tl.ltop, n, GParams{2.0 * E, J2, ii, t0},
-                                    GParams{2.0 * E, J2, ii, t1}, wprm, wprm + BT, kmin_g,
-                                    kmax_g);
-
-    if (i < n) {
-      OrbitRec rec{E, J, 0.0, 0.0, -1.0, 0, 0};
-      if (!(E < 0.0)) {  // unbound: leaves the cluster
-        c_esc += 1.0;
-        e_esc += load_mass(m, i) * E;
-        fl |= CMC_ST_ESCAPER;
-        if (E != E) fl |= CMC_ST_NONFINITE;
-        emit<TO_STAGE>(i, kInf, vri, vti, m[i], id[i], 0, r_new, vr, vt, stage, keys, bkey);
-      } else {
-        const int64_t kmin = kmin_g, kmax = kmax_g;
-        double rmin, rmax;
-        if (J2 == 0.0) {
-          rmin = 0.0;
-        } else if (kmin < 0) {
-          rmin = J / sqrt(2.0 * (E - tab[0].phi));
-        } else {
-          const MS t = ms[kmin];
-          const double a = 2.0 * (E + t.S);
-          const double b = 2.0 * t.M;
-          const double disc = b * b + 4.0 * a * J2;
-          const double den = b + sqrt(disc > 0.0 ? disc : 0.0);
-          rmin = den > 0.0 ? 2.0 * J2 / den : tab[kmin].r;
-        }
-        {
-          const double rl = kmin >= 0 ? tab[kmin].r : 0.0, rh = tab[kmin + 1].r;
-          rmin = rmin < rl ? rl : (rmin > rh ? rh : rmin);
-        }
-        {
-          const MS t = ms[kmax];
-          const double a = 2.0 * (E + t.S);
-          const double b = 2.0 * t.M;
-          const double disc = b * b + 4.0 * a * J2;
-          const double sq = sqrt(disc > 0.0 ? disc : 0.0);
-          const double rl = tab[kmax].r;
-          const double rh = (kmax + 1 < n) ? tab[kmax + 1].r : kInf;
-          rmax = a < 0.0 ? (b + sq) / (-2.0 * a) : rh;
-          rmax = rmax < rl ? rl : (rmax > rh ? rh : rmax);
-        }
-        const double rc = 0.5 * (rmax + rmin), ra = 0.5 * (rmax - rmin);
-        double F = -1.0;
-        double rdone = rmin;  // radius of an orbit finished without trials
-        if (ra > 0.0) {
-          const double glo = (J2 != 0.0) ? sqrt(2.0 * ra / fabs(dq_in(ms, kmin, rmin, J2))) : 0.0;
-          const double ghi = sqrt(2.0 * ra / fabs(dq_in(ms, kmax, rmax, J2)));
-          F = bound_factor * (glo > ghi ? glo : ghi);
-          if (!(F > 0.0 && F < kInf)) {
-            F = -1.0;
-            rdone = rc;
-            fl |= CMC_ST_NUMERIC;
-          }
-        }
-        if (F > 0.0) {
-          rec.rmin = rmin;
-          rec.rmax = rmax;
-          rec.F = F;
-          rec.kmin = static_cast<int32_t>(kmin);
-          rec.kmax = static_cast<int32_t>(kmax);
-        } else {
-          const double rn = rdone + 0.0;
-          const int64_t kn = interval_in(ix, ictl, rn, kmin, kmax);
-          const double phn = phi_in(lv, ms, kn, rn);
-          const double qn = 2.0 * E - 2.0 * phn - (J2 == 0.0 ? 0.0 : J2 / (rn * rn));
-          if (corr) pn[i] = phn;
-          U4 ws;
-          if (LF) {
-            Lfsr g = load_lfsr(A.s.rng, i);
-            ws = lfsr_block(g);
-            put_lfsr<TO_STAGE>(A, i, g);
-          } else {
-            ws = philox(id[i], step, kSign, 0u, seed);
-          }
-          double vrn, vtn;
-          finish(rn, qn, J, J2, ws.x, vrn, vtn, fl);
-          emit<TO_STAGE>(i, rn, vrn, vtn, m[i], id[i], rindex_last_le(ix, ictl, rn) + 1, r_new,
-                         vr, vt, stage, keys, bkey);
-        }
-      }
-      orec[i] = rec;
-    }
-  }
-  or_status(sc, fl);
-  c_esc = block_sum<BT>(c_esc, shd);
-  e_esc = block_sum<BT>(e_esc, shd);
+// The escaper partials (count, sum of m E) of 512 stars at part[2 tile]:
+// both forms of the pass write them per 512 consecutive stars, so the sum
+// does not depend on the form or its launch settings.
+template <int NTH>
+__device__ __forceinline__ void esc_partials(double c_esc, double e_esc, double *shd,
+                                             double *part, int64_t blk) {
+  c_esc = block_sum<NTH>(c_esc, shd);
+  e_esc = block_sum<NTH>(e_esc, shd);
   if (threadIdx.x == 0) {
     part[2 * blk] = c_esc;
     part[2 * blk + 1] = e_esc;
   }
 }
 
+// Direct form: every bracket searched to the bottom by the star's own
+// wavefront (the LDS levels per lane, the rest by groups of 8 lanes); its
+// blocks stay resident and loop over tiles of stars.  For tables whose levels
+// below the LDS top are few or small.
+template <class Ctx, typename MT, bool TO_STAGE, bool LF>
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4)))
+void k_orbit_bracket(Ctx ctx, int corr) {
+  extern __shared__ RPhi top[];
+  __shared__ double shd[BT / 64];
+  __shared__ GParams prm[BT];
+  const ClusterArgs &A = ctx.args();
+  const Levels lv = levels_of(A.w);
+  const OrbitTop &tl = A.top;
+  const MS *__restrict__ ms = A.w.ms;
+  OrbitRec *__restrict__ orec = A.w.orec;
+  const RIndexCtl ictl = *A.w.rx_ctl;
+  const int64_t n = ictl.n;
+  const RPhi *tab = lv.lev[0];
+  GParams *wprm = prm + (threadIdx.x & ~63);
+  load_top(top, lv, tl, BT);
+  __syncthreads();
+  const TopSrc src{top, &tl, &lv};
+
+  uint32_t fl = 0;
+  const int64_t tiles = (n + BT - 1) / BT;
+  const int64_t blk = ctx.block(), nblk = ctx.nblocks();
+  for (int64_t tile = blk; tile < tiles; tile += nblk) {  // block-uniform
+    const int64_t i = tile * BT + threadIdx.x;
+    double c_esc = 0.0, e_esc = 0.0;
+    double E = 0.0, J = 0.0, J2 = 0.0;
+    const bool bound =
+        i < n && star_start<MT, TO_STAGE, LF>(A, i, corr, E, J, J2, c_esc, e_esc, fl);
+    int32_t kmin, kmax;
+    bracket_samples(src, lv.nlev, 0, n, bound, E, J2, i, wprm, kmin, kmax);
+    if (bound) {
+      orec[i].lo = finalize_lo(tab, ms, kmin, E, J, J2);
+      orec[i].hi = finalize_hi(tab, ms, n, kmax, E, J, J2);
+    }
+    esc_partials<BT>(c_esc, e_esc, shd, A.w.red_part, tile);
+  }
+  or_status(A.s.sc, fl);
+}
+
+// ---------------------------------------------------------------- sorted searches
+// The sorted form.  Below the LDS top every search costs a few random lines
+// of a table far larger than the L2; grouped by the top-level sample it
+// reached, the searches that share a subtree run together and find it in
+// the L2.  k_oq_hist counts each tile's searches per sample, k_oq_colscan
+// and k_oq_start turn the counts into offsets, k_oq_scatter sends every
+// star's searches (E, J, index, sample) to their groups and finishes what
+// needs no search, and k_oq_search runs the grouped searches and writes
+// each star's half-records.  Brackets are unique, so the result is the one
+// of the direct form.
+constexpr int QT = 512;   // threads of the tile kernels
+constexpr int QS = kQuerySearchBlock;
+constexpr int kSubEntries = 1024;  // LDS entries of a group's subtree in the search
+
+// Samples of level ltop over the n stars (the groups of this pass).
+__device__ __forceinline__ int64_t query_bins(const OrbitTop &tl, int64_t n) {
+  return tl.ltop > 0 ? cdiv(n, int64_t(1) << (3 * tl.ltop)) : 0;
+}
+
+// Consecutive tiles (and search blocks) on one XCD: blocks go round-robin
+// over the 8 XCDs, so logical tile (b mod 8) q + b / 8 puts each XCD on a
+// contiguous eighth.
+__device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t nb) {
+  const int64_t q = nb / 8;
+  return b < 8 * q ? (b % 8) * q + b / 8 : b;
+}
+
+template <class Ctx>
+__global__ __launch_bounds__(QT) void k_oq_hist(Ctx ctx) {
+  extern __shared__ RPhi top[];
+  __shared__ uint32_t hist[kTopEntries];
+  __shared__ GParams prm[QT];
+  const ClusterArgs &A = ctx.args();
+  const OrbitTop &tl = A.top;
+  const RIndexCtl ictl = *A.w.rx_ctl;
+  const int64_t n = ictl.n;
+  const int64_t bins = query_bins(tl, n);
+  const int64_t t = ctx.block();
+  const int64_t k0 = t * kQueryTile;
+  if (bins == 0 || k0 >= n) return;  // block-uniform
+  const Levels lv = levels_of(A.w);
+  const RPhi *__restrict__ tab = lv.lev[0];
+  uint32_t *__restrict__ node = A.w.oq_node;
+  GParams *wprm = prm + (threadIdx.x & ~63);
+  load_top(top, lv, tl, QT);
+  for (int b = threadIdx.x; b < bins; b += QT) hist[b] = 0u;
+  __syncthreads();
+  const TopSrc src{top, &tl, &lv};
+  const int64_t k1 = k0 + kQueryTile < n ? k0 + kQueryTile : n;
+  for (int j = 0; j < kQueryTile / QT; ++j) {  // block-uniform
+    const int64_t i = k0 + j * QT + threadIdx.x;
+    double E = 0.0, J2 = 0.0;
+    bool bound = false;
+    if (i < k1) {
+      const RPhi me = tab[i];
+      const double vri = A.s.vr[i], vti = A.s.vt[i];
+      E = me.phi + 0.5 * (vri * vri + vti * vti);
+      const double J = me.r * vti;
+      J2 = J * J;
+      bound = E < 0.0;
+    }
+    int32_t t0, t1;
+    bracket_samples(src, lv.nlev, tl.ltop, n, bound, E, J2, i, wprm, t0, t1);
+    if (i < k1) {
+      // the two samples for the scatter: (t0 + 1) | t1 << 16, or none
+      uint32_t code = 0xFFFFFFFFu;
+      if (bound) {
+        if (t0 >= 0) atomicAdd(&hist[t0], 1u);
+        atomicAdd(&hist[t1], 1u);
+        code = static_cast<uint32_t>(t0 + 1) | (static_cast<uint32_t>(t1) << 16);
+      }
+      node[i] = code;
+    }
+  }
+  __syncthreads();
+  uint32_t *__restrict__ row = A.w.oq_cnt + t * A.w.oq_bins;
+  for (int b = threadIdx.x; b < bins; b += QT) row[b] = hist[b];
+}
+
+// Block g: samples 64 g .. 64 g + 63, one lane each; the 16 waves split the
+// tiles.  Counts become tile offsets inside the sample's group; oq_tot gets
+// the group sizes.
+template <class Ctx>
+__global__ __launch_bounds__(QT) void k_oq_colscan(Ctx ctx) {
+  __shared__ uint32_t part[QT / 64][64];
+  const ClusterArgs &A = ctx.args();
+  const int64_t n = A.w.rx_ctl->n;
+  const int64_t bins = query_bins(A.top, n);
+  const int64_t b = ctx.block() * 64 + (threadIdx.x & 63);
+  if (ctx.block() * 64 >= bins) return;
+  const int w = threadIdx.x >> 6;
+  const bool own = b < bins;
+  const int64_t tiles = cdiv(n, kQueryTile);
+  const int64_t per = cdiv(tiles, QT / 64);
+  const int64_t t0 = w * per;
+  const int64_t t1 = t0 + per < tiles ? t0 + per : tiles;
+  const int64_t stride = A.w.oq_bins;
+  uint32_t *__restrict__ cnt = A.w.oq_cnt;
+  uint32_t s = 0u;
+  if (own) {
+#pragma unroll 4
+    for (int64_t t = t0; t < t1; ++t) s += cnt[t * stride + b];
+  }
+  part[w][threadIdx.x & 63] = s;
+  __syncthreads();
+  uint32_t pre = 0u, tot = 0u;
+#pragma unroll
+  for (int q = 0; q < QT / 64; ++q) {
+    const uint32_t v = part[q][threadIdx.x & 63];
+    if (q < w) pre += v;
+    tot += v;
+  }
+  if (!own) return;
+  if (w == 0) A.w.oq_tot[b] = tot;
+  for (int64_t t = t0; t < t1; ++t) {
+    const uint32_t v = cnt[t * stride + b];
+    cnt[t * stride + b] = pre;
+    pre += v;
+  }
+}
+
+// One block per cluster: the first search of each group (oq_start[bins] is
+// the number of searches), and the first block of the search kernel that
+// works on each group, kQuerySearchChunk searches per block (oq_chunk[bins]
+// is the number of blocks with work).
+template <class Ctx>
+__global__ __launch_bounds__(QT) void k_oq_start(Ctx ctx) {
+  __shared__ uint32_t sh[QT / 64];
+  const ClusterArgs &A = ctx.args();
+  const int64_t bins = query_bins(A.top, A.w.rx_ctl->n);
+  const uint32_t *__restrict__ tot = A.w.oq_tot;
+  uint32_t *__restrict__ start = A.w.oq_start;
+  uint32_t *__restrict__ chunk = A.w.oq_chunk;
+  uint32_t carry = 0u, ccarry = 0u;
+  for (int64_t b0 = 0; b0 < bins; b0 += QT) {
+    const int64_t b = b0 + threadIdx.x;
+    const uint32_t v = b < bins ? tot[b] : 0u;
+    const uint32_t cv = (v + kQuerySearchChunk - 1) / kQuerySearchChunk;
+    uint32_t all, call;
+    const uint32_t ex = block_excl_scan<QT>(v, sh, &all);
+    const uint32_t cex = block_excl_scan<QT>(cv, sh, &call);
+    if (b < bins) {
+      start[b] = carry + ex;
+      chunk[b] = ccarry + cex;
+    }
+    carry += all;
+    ccarry += call;
+  }
+  if (threadIdx.x == 0) {
+    start[bins] = carry;
+    chunk[bins] = ccarry;
+  }
+}
+
+// The star pass: what star_start does, then each search to its group at an
+// LDS-atomic slot (the order inside a group does not matter: every search
+// writes its own star's half-record); a search the LDS levels already
+// finish (no index below) is finished here.  A table that fits the LDS
+// whole (no level below the top) has no groups: its stars are searched
+// here to the bottom.
+template <class Ctx, typename MT, bool TO_STAGE, bool LF>
+__global__ __launch_bounds__(QT) void k_oq_scatter(Ctx ctx, int corr) {
+  extern __shared__ RPhi top[];
+  __shared__ uint32_t cur[kTopEntries];
+  __shared__ GParams prm[QT];
+  __shared__ double shd[QT / 64];
+  const ClusterArgs &A = ctx.args();
+  const OrbitTop &tl = A.top;
+  const RIndexCtl ictl = *A.w.rx_ctl;
+  const int64_t n = ictl.n;
+  const int64_t bins = query_bins(tl, n);
+  const int64_t blk = ctx.block();
+  const int64_t t = xcd_order(blk, ctx.nblocks());
+  const int64_t k0 = t * kQueryTile;
+  const Levels lv = levels_of(A.w);
+  const RPhi *__restrict__ tab = lv.lev[0];
+  const MS *__restrict__ ms = A.w.ms;
+  OrbitRec *__restrict__ orec = A.w.orec;
+  OrbQuery *__restrict__ oq = A.w.oq;
+  GParams *wprm = prm + (threadIdx.x & ~63);
+  uint32_t fl = 0;
+  if (k0 < n) {  // block-uniform
+    if (bins == 0) {
+      load_top(top, lv, tl, QT);
+    } else {
+      const uint32_t *__restrict__ row = A.w.oq_cnt + t * A.w.oq_bins;
+      for (int b = threadIdx.x; b < bins; b += QT) cur[b] = A.w.oq_start[b] + row[b];
+    }
+    __syncthreads();
+    const TopSrc src{top, &tl, &lv};
+    const int64_t k1 = k0 + kQueryTile < n ? k0 + kQueryTile : n;
+    for (int j = 0; j < kQueryTile / QT && k0 + j * QT < n; ++j) {  // block-uniform
+      const int64_t i = k0 + j * QT + threadIdx.x;
+      double c_esc = 0.0, e_esc = 0.0;
+      double E = 0.0, J = 0.0, J2 = 0.0;
+      const bool bound =
+          i < k1 && star_start<MT, TO_STAGE, LF>(A, i, corr, E, J, J2, c_esc, e_esc, fl);
+      if (bins == 0) {
+        int32_t kmin, kmax;
+        bracket_samples(src, lv.nlev, 0, n, bound, E, J2, i, wprm, kmin, kmax);
+        if (bound) {
+          orec[i].lo = finalize_lo(tab, ms, kmin, E, J, J2);
+          orec[i].hi = finalize_hi(tab, ms, n, kmax, E, J, J2);
+        }
+      } else if (bound) {
+        const uint32_t code = A.w.oq_node[i];
+        const int32_t t0 = static_cast<int32_t>(code & 0xFFFFu) - 1;
+        const uint32_t t1 = code >> 16;
+        const uint32_t ui = static_cast<uint32_t>(i);
+        if (t0 < 0) {
+          orec[i].lo = finalize_lo(tab, ms, -1, E, J, J2);
+        } else {
+          const uint32_t pos = atomicAdd(&cur[t0], 1u);
+          oq[pos] = OrbQuery{E, J, ui, static_cast<uint32_t>(t0)};
+        }
+        const uint32_t pos = atomicAdd(&cur[t1], 1u);
+        oq[pos] = OrbQuery{E, J, ui, t1 | kQueryHi};
+      }
+      // escaper partials per 512 stars, as the direct form writes them
+      esc_partials<QT>(c_esc, e_esc, shd, A.w.red_part, (k0 / QT) + j);
+    }
+  }
+  or_status(A.s.sc, fl);
+}
+
+// A grouped search of either bracket: c >= 0 is the lower bracket below star
+// c, c < 0 the upper bracket of star -c - 1.
+struct GQAny {
+  __device__ static bool eval(const GParams &p, int64_t k, const RPhi &e) {
+    return p.c >= 0 ? (k < p.c && q_neg(p.a, p.b, e))
+                    : (k <= -static_cast<int64_t>(p.c) - 1 || q_nonneg(p.a, p.b, e));
+  }
+};
+
+// Level entries of the grouped search: the levels lsub .. ltop - 1 under one
+// top sample, staged in LDS (level L's span of 8^(ltop - L) entries at offset
+// (8^(ltop - L) - 8) / 7), the levels below from global memory.
+struct NodeSrc {
+  const RPhi *sub;
+  const Levels *lv;
+  int64_t node;
+  int ltop, lsub;
+  __device__ __forceinline__ RPhi operator()(int L, int64_t child) const {
+    if (L >= lsub) {
+      const int64_t span = int64_t(1) << (3 * (ltop - L));
+      return sub[(span - 8) / 7 + (child - node * span)];
+    }
+    return lv->lev[L][child];
+  }
+};
+
+// The grouped searches.  Block b works on kQuerySearchChunk searches of one
+// group (the first blocks of the group at oq_chunk): it stages the levels of
+// the group's subtree that fit kSubEntries in LDS (one coalesced copy, shared
+// by all its searches), then runs the searches a wavefront at a time, the
+// levels below from global memory, and each lane finishes its own search.
+template <class Ctx>
+__global__ __launch_bounds__(QS) void k_oq_search(Ctx ctx) {
+  __shared__ RPhi sub[kSubEntries];
+  __shared__ GParams prm[QS];
+  const ClusterArgs &A = ctx.args();
+  const OrbitTop &tl = A.top;
+  const RIndexCtl ictl = *A.w.rx_ctl;
+  const int64_t n = ictl.n;
+  const int64_t bins = query_bins(tl, n);
+  if (bins == 0) return;
+  const uint32_t *__restrict__ chunk = A.w.oq_chunk;
+  const int64_t b = xcd_order(ctx.block(), ctx.nblocks());
+  if (b >= static_cast<int64_t>(chunk[bins])) return;  // block-uniform
+  // the group of block b: the last s with chunk[s] <= b
+  int64_t lo = 0, hi = bins;
+  while (hi - lo > 1) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if (static_cast<int64_t>(chunk[mid]) <= b) lo = mid; else hi = mid;
+  }
+  const int64_t node = lo;
+  const int64_t q0 = A.w.oq_start[node] + (b - chunk[node]) * int64_t(kQuerySearchChunk);
+  const int64_t qe = A.w.oq_start[node + 1];
+  const int64_t q1 = q0 + kQuerySearchChunk < qe ? q0 + kQuerySearchChunk : qe;
+  const Levels lv = levels_of(A.w);
+  const int ltop = tl.ltop;
+  // the subtree's levels ltop - 1 down to lsub, while they fit
+  int lsub = ltop;
+  while (lsub > 1 && ((int64_t(1) << (3 * (ltop - lsub + 1))) * 8 - 8) / 7 <= kSubEntries) --lsub;
+  for (int L = ltop - 1; L >= lsub; --L) {
+    const int64_t span = int64_t(1) << (3 * (ltop - L));
+    const int64_t stride = int64_t(1) << (3 * L);
+    const int64_t cnt = (n + stride - 1) / stride;
+    const int64_t base = node * span;
+    for (int64_t e = threadIdx.x; e < span; e += QS)
+      if (base + e < cnt) sub[(span - 8) / 7 + e] = lv.lev[L][base + e];
+  }
+  __syncthreads();
+  const NodeSrc src{sub, &lv, node, ltop, lsub};
+  GParams *wprm = prm + (threadIdx.x & ~63);
+  const RPhi *__restrict__ tab = lv.lev[0];
+  OrbitRec *__restrict__ orec = A.w.orec;
+  for (int64_t qb = q0; qb < q1; qb += QS) {  // block-uniform
+    const int64_t qi = qb + threadIdx.x;
+    const bool act = qi < q1;
+    OrbQuery qr{0.0, 0.0, 0u, 0u};
+    if (act) qr = A.w.oq[qi];
+    const bool hi_b = (qr.node & kQueryHi) != 0u;
+    const double J2 = qr.J * qr.J;
+    const int32_t ci = static_cast<int32_t>(qr.i);
+    const GParams mine{2.0 * qr.E, J2, hi_b ? -ci - 1 : ci,
+                       act ? static_cast<int32_t>(node) : -1};
+    const int32_t k = group_descend<GQAny>(src, ltop - 1, 0, n, mine, wprm);
+    if (act) {
+      if (hi_b)
+        orec[qr.i].hi = finalize_hi(tab, A.w.ms, n, k, qr.E, qr.J, J2);
+      else
+        orec[qr.i].lo = finalize_lo(tab, A.w.ms, k, qr.E, qr.J, J2);
+    }
+  }
+}
+
 template <class Ctx, typename MT, bool TO_STAGE, bool MIXED, bool LF>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5)))
-void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap, int corr) {
+void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap, int corr,
+                    double bound_factor) {
   __shared__ double shd[NT / 64];
   const ClusterArgs &A = ctx.args();
   const uint32_t step = step_of(A, step_arg);
@@ -517,9 +805,10 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap, int corr) {
   const int lane = threadIdx.x & 63;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t wave = blk * (NT / 64) + (threadIdx.x >> 6);
-  const int64_t c_end0 = (wave + 1) * kChunk;
+  const int64_t chunk = A.w.trial_chunk;  // stars per wavefront
+  const int64_t c_end0 = (wave + 1) * chunk;
   const int64_t c_end = c_end0 < n ? c_end0 : n;
-  int64_t cursor = wave * kChunk;  // wave-uniform
+  int64_t cursor = wave * chunk;  // wave-uniform
   uint32_t c_tr = 0, c_viol = 0, c_cap = 0;
   uint32_t fl = 0;
 
@@ -542,20 +831,60 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap, int corr) {
       cursor += __popcll(need);
       if (!busy && mine < c_end) {
         const OrbitRec o = orec[mine];
-        if (o.F > 0.0) {
-          busy = true;
-          i = mine;
-          E = o.E;
-          J = o.J;
-          J2 = J * J;
-          rc = 0.5 * (o.rmax + o.rmin);
-          ra = 0.5 * (o.rmax - o.rmin);
-          F = o.F;
-          kmin = o.kmin;
-          kmax = o.kmax;
-          sid = id[mine];
-          j = 0;
-          if (LF) lg = load_lfsr(A.s.rng, mine);
+        if (o.lo.E < 0.0) {  // else an escaper, already sent out
+          // the rejection bound: F = bound_factor * the larger endpoint
+          // value of g(s), 2 r_a / |dQ/dr| under the square root
+          const double oJ = o.hi.J, oJ2 = oJ * oJ;
+          const double orc = 0.5 * (o.hi.rmax + o.lo.rmin);
+          const double ora = 0.5 * (o.hi.rmax - o.lo.rmin);
+          double oF = -1.0;
+          double rdone = o.lo.rmin;  // radius of an orbit finished without trials
+          if (ora > 0.0) {
+            const double glo = (oJ2 != 0.0) ? sqrt(2.0 * ora / fabs(o.lo.dq)) : 0.0;
+            const double ghi = sqrt(2.0 * ora / fabs(o.hi.dq));
+            oF = bound_factor * (glo > ghi ? glo : ghi);
+            if (!(oF > 0.0 && oF < kInf)) {
+              oF = -1.0;
+              rdone = orc;
+              fl |= CMC_ST_NUMERIC;
+            }
+          }
+          if (oF > 0.0) {
+            busy = true;
+            i = mine;
+            E = o.lo.E;
+            J = oJ;
+            J2 = oJ2;
+            rc = orc;
+            ra = ora;
+            F = oF;
+            kmin = o.lo.kmin;
+            kmax = o.hi.kmax;
+            sid = id[mine];
+            j = 0;
+            if (LF) lg = load_lfsr(A.s.rng, mine);
+          } else {
+            // a point orbit (or no usable bound): the new radius is rdone,
+            // with no trial
+            const double rn = rdone + 0.0;
+            const int64_t kn = interval_in(ix, ictl, rn, o.lo.kmin, o.hi.kmax);
+            const double phn = phi_in(lv, ms, kn, rn);
+            const double qn =
+                2.0 * o.lo.E - 2.0 * phn - (oJ2 == 0.0 ? 0.0 : oJ2 / (rn * rn));
+            if (corr) pn[mine] = phn;
+            U4 ws;
+            if (LF) {
+              Lfsr g = load_lfsr(A.s.rng, mine);
+              ws = lfsr_block(g);
+              put_lfsr<TO_STAGE>(A, mine, g);
+            } else {
+              ws = philox(id[mine], step, kSign, 0u, seed);
+            }
+            double vrn, vtn;
+            finish(rn, qn, oJ, oJ2, ws.x, vrn, vtn, fl);
+            emit<TO_STAGE>(mine, rn, vrn, vtn, m[mine], id[mine],
+                           rindex_last_le(ix, ictl, rn) + 1, r_new, vr, vt, stage, keys, bkey);
+          }
         }
       }
     }
@@ -657,6 +986,7 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap, int corr) {
   }
 }
 
+
 // The potential at the bound table's edges (after the radial index is built),
 // grid-stride over the edges.
 template <class Ctx>
@@ -680,16 +1010,17 @@ __global__ __launch_bounds__(NT) void k_phi_bounds(Ctx ctx) {
   }
 }
 
+
 constexpr int FT = 1024;
 
-// One block per cluster: the cluster's bracket and trial partials.
+// One block per cluster: the cluster's escaper and trial partials.
 template <class Ctx>
 __global__ __launch_bounds__(FT) void k_orbit_sum(Ctx ctx) {
   __shared__ double sh[FT / 64];
   const ClusterArgs &A = ctx.args();
   const double *__restrict__ pa = A.w.red_part;
   const double *__restrict__ pb = A.w.red_part + 2 * A.w.star_blocks;
-  const int64_t na = A.bracket_blocks;
+  const int64_t na = cdiv(A.w.rx_ctl->n, 512);  // escaper partials, per 512 stars
   const int64_t nb = blocks_of(kShTrials, A.w, A.s.cap);
   cmc_scalars *__restrict__ sc = A.s.sc;
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -722,47 +1053,43 @@ __global__ __launch_bounds__(NT) void k_table_pack(Ctx ctx) {
 }
 
 template <class L, typename MT, bool TO_STAGE, bool LF>
-hipError_t run2(const L &l, const cmc_params &p, int corr, hipStream_t st) {
+hipError_t run2(const L &l, const cmc_params &p, int corr, bool sorted, hipStream_t st) {
   const int32_t cap = p.trial_cap > 0 ? p.trial_cap : 10000;
   const double bf = p.bound_factor > 0.0 ? p.bound_factor : 1.2;
-  using Cb = decltype(l.ctx(kShBracket));
   using Ct = decltype(l.ctx(kShTrials));
+  const size_t top_bytes = sizeof(RPhi) * l.top_entries();
   k_phi_bounds<<<l.grid(kShDiag), NT, 0, st>>>(l.ctx(kShDiag));
-  k_orbit_bracket<Cb, MT, TO_STAGE, LF>
-      <<<l.grid(kShBracket), BT, sizeof(RPhi) * l.top_entries(), st>>>(l.ctx(kShBracket), p.step,
-                                                                       bf, corr);
+  if (sorted) {
+    using Cq = decltype(l.ctx(kShQTile));
+    k_oq_hist<<<l.grid(kShQTile), QT, top_bytes, st>>>(l.ctx(kShQTile));
+    k_oq_colscan<<<l.grid(kShQGroup), QT, 0, st>>>(l.ctx(kShQGroup));
+    k_oq_start<<<l.grid(kShOne), QT, 0, st>>>(l.ctx(kShOne));
+    k_oq_scatter<Cq, MT, TO_STAGE, LF>
+        <<<l.grid(kShQTile), QT, l.flat_top() ? top_bytes : 0, st>>>(l.ctx(kShQTile), corr);
+    k_oq_search<<<l.grid(kShQSearch), QS, 0, st>>>(l.ctx(kShQSearch));
+  } else {
+    using Cb = decltype(l.ctx(kShBracket));
+    k_orbit_bracket<Cb, MT, TO_STAGE, LF><<<l.grid(kShBracket), BT, top_bytes, st>>>(
+        l.ctx(kShBracket), corr);
+  }
   if (p.precision == CMC_MIXED)
     k_orbit_trials<Ct, MT, TO_STAGE, true, LF><<<l.grid(kShTrials), NT, 0, st>>>(
-        l.ctx(kShTrials), p.step, cap, corr);
+        l.ctx(kShTrials), p.step, cap, corr, bf);
   else
     k_orbit_trials<Ct, MT, TO_STAGE, false, LF><<<l.grid(kShTrials), NT, 0, st>>>(
-        l.ctx(kShTrials), p.step, cap, corr);
+        l.ctx(kShTrials), p.step, cap, corr, bf);
   k_orbit_sum<<<l.grid(kShOne), FT, 0, st>>>(l.ctx(kShOne));
   return hipGetLastError();
 }
 
 }  // namespace
 
-static_assert(sizeof(OrbitRec) == 48, "orbit record layout");
-static_assert(BT == kBracketThreads && kChunk == kTrialChunk, "launch shapes");
+static_assert(sizeof(OrbitRec) == 64 && sizeof(OrbitLo) == 32 && sizeof(OrbitHi) == 32,
+              "orbit record layout");
+static_assert(sizeof(OrbQuery) == 24, "search record layout");
+static_assert(BT == kBracketThreads && QT == BT, "launch shapes: escaper partials per 512 stars");
 
-// Levels from the top down while they fit kTopBytes of LDS.
-OrbitTop orbit_top(const Workspace &w, int64_t cap) {
-  OrbitTop tl{};
-  int64_t tot = 0;
-  tl.ltop = w.nlev;
-  for (int L = w.nlev - 1; L >= 0; --L) {
-    const int64_t stride = int64_t(1) << (3 * L);
-    const int64_t len = (cap + stride - 1) / stride;
-    if ((tot + len) * static_cast<int64_t>(sizeof(RPhi)) > kTopBytes) break;
-    tl.off[L] = static_cast<int32_t>(tot);
-    tl.len[L] = static_cast<int32_t>(len);
-    tot += len;
-    tl.ltop = L;
-  }
-  tl.entries = static_cast<int32_t>(tot);
-  return tl;
-}
+OrbitTop orbit_top(const Workspace &w, int64_t cap) { return top_levels(w.nlev, cap); }
 
 hipError_t launch_table_pack(const Target &t, hipStream_t st) {
   return dispatch(t, [&](const auto &l) {
@@ -779,20 +1106,21 @@ hipError_t launch_orbit(const Target &t, bool m_f32, const cmc_params &p, bool t
   }
   const int c = (to_stage && corr) ? 1 : 0;  // correction terms only for a staged step
   const bool lf = p.rng == CMC_RNG_LFSR113;
+  const bool sorted = sorted_searches(t);
   return dispatch(t, [&](const auto &l) {
     using L = std::decay_t<decltype(l)>;
     if (lf) {
       if (m_f32)
-        return to_stage ? run2<L, float, true, true>(l, p, c, st)
-                        : run2<L, float, false, true>(l, p, c, st);
-      return to_stage ? run2<L, double, true, true>(l, p, c, st)
-                      : run2<L, double, false, true>(l, p, c, st);
+        return to_stage ? run2<L, float, true, true>(l, p, c, sorted, st)
+                        : run2<L, float, false, true>(l, p, c, sorted, st);
+      return to_stage ? run2<L, double, true, true>(l, p, c, sorted, st)
+                      : run2<L, double, false, true>(l, p, c, sorted, st);
     }
     if (m_f32)
-      return to_stage ? run2<L, float, true, false>(l, p, c, st)
-                      : run2<L, float, false, false>(l, p, c, st);
-    return to_stage ? run2<L, double, true, false>(l, p, c, st)
-                    : run2<L, double, false, false>(l, p, c, st);
+      return to_stage ? run2<L, float, true, false>(l, p, c, sorted, st)
+                      : run2<L, float, false, false>(l, p, c, sorted, st);
+    return to_stage ? run2<L, double, true, false>(l, p, c, sorted, st)
+                    : run2<L, double, false, false>(l, p, c, sorted, st);
   });
 }
 

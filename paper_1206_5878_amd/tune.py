@@ -1,0 +1,143 @@
+"""Launch-table autotuner for the orbit pass (arXiv:1206.5878 Sec. 2.1 item 5;
+the paper's Appendix A studies the launch configuration of its GPU orbit
+kernels the same way: by timing them).
+
+The library consults a read-only launch table (cmc_set_tuning /
+cmc_get_tuning in include/cmc.h) when it sets up a call: per capacity band,
+whether the turning-point searches are grouped ("sorted") or direct, the
+resident blocks of the direct search kernel, and the stars per wavefront
+chunk of the rejection-trial kernel.  Every entry gives the same results bit
+for bit, so only the speed is at stake.  This module times the candidates on
+the GPU on each band's workload, with HIP events on the stream the kernels
+run on, and writes the winning table to tuning.json beside it; lib() installs
+that file at load.
+
+python -m paper_1206_5878_amd.tune [--steps K] [--out PATH]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import time
+
+from . import _capi as A
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TABLE_PATH = os.path.join(HERE, "tuning.json")
+
+FIELDS = ("min_cap", "sorted", "bracket_blocks", "trial_chunk")
+
+# Capacity bands and the workload each is timed on (seeded synthetic Plummer
+# models, as the benchmark's): below 2^17 stars, up to 2^22, and above.
+BANDS = [
+    dict(min_cap=0, n=100_000, mass_spectrum=0, m_f32=False, gamma=0.11, precision=0),
+    dict(min_cap=1 << 17, n=1_000_000, mass_spectrum=0, m_f32=False, gamma=0.11, precision=1),
+    dict(min_cap=1 << 22, n=10_000_000, mass_spectrum=1, m_f32=True, gamma=0.01, precision=1),
+]
+
+
+def candidates():
+    for chunk in (64, 128, 256):
+        for blocks in (512, 1024, 2048):
+            yield dict(sorted=0, bracket_blocks=blocks, trial_chunk=chunk)
+        yield dict(sorted=1, bracket_blocks=1024, trial_chunk=chunk)
+
+
+def to_c(entries) -> "C.Array":
+    arr = (A.cmc_tuning * len(entries))()
+    for k, e in enumerate(entries):
+        arr[k].min_cap = int(e["min_cap"])
+        arr[k].sorted = int(e["sorted"])
+        arr[k].bracket_blocks = int(e["bracket_blocks"])
+        arr[k].trial_chunk = int(e["trial_chunk"])
+    return arr
+
+
+def set_table(entries) -> None:
+    """Install a launch table (list of dicts with FIELDS); [] restores the
+    built-in one."""
+    arr = to_c(entries) if entries else None
+    A.check(A.lib().cmc_set_tuning(arr, len(entries)), "cmc_set_tuning")
+
+
+def get(cap: int) -> dict:
+    """The entry of the table in use that serves capacity cap."""
+    t = A.cmc_tuning()
+    A.check(A.lib().cmc_get_tuning(int(cap), C.byref(t)), "cmc_get_tuning")
+    return {f: int(getattr(t, f)) for f in FIELDS}
+
+
+def load(path: str = TABLE_PATH) -> list:
+    """The table stored in a tuning file (its "table" list)."""
+    with open(path) as f:
+        return json.load(f)["table"]
+
+
+def time_band(P, band: dict, steps: int, warmup: int) -> list:
+    """ms per step of every candidate on the band's workload."""
+    import torch
+    cl = P.Cluster(band["n"], m_f32=band["m_f32"])
+    P.cmc_init_plummer(cl, band["n"], 1, band["mass_spectrum"])
+    k = 0
+    rows = []
+    for cand in candidates():
+        set_table([dict(min_cap=0, **cand)])
+        for _ in range(warmup):
+            P.cmc_step(cl, P.Params(seed=1, step=k, gamma=band["gamma"],
+                                    precision=band["precision"]))
+            k += 1
+        # the calls enqueue on torch's current stream, where these events go
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            P.cmc_step(cl, P.Params(seed=1, step=k, gamma=band["gamma"],
+                                    precision=band["precision"]))
+            k += 1
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        rows.append(dict(cand, ms_per_step=ms))
+        print(f"# n={band['n']} {cand}: {ms:.3f} ms/step", flush=True)
+    return rows
+
+
+def tune(steps: int = 5, warmup: int = 1) -> dict:
+    import paper_1206_5878_amd as P
+    import torch
+    table, measured = [], []
+    try:
+        for band in BANDS:
+            rows = time_band(P, band, steps, warmup)
+            best = min(rows, key=lambda r: r["ms_per_step"])
+            table.append({"min_cap": band["min_cap"],
+                          **{f: best[f] for f in FIELDS if f != "min_cap"}})
+            measured.append({"workload": {k: band[k] for k in
+                                          ("n", "mass_spectrum", "m_f32", "gamma", "precision")},
+                             "candidates": rows})
+    finally:
+        set_table([])
+    return {"table": table, "measured": measured,
+            "device": torch.cuda.get_device_name(0),
+            "date": time.strftime("%Y-%m-%d %H:%M:%S"),
+            "steps": steps, "warmup": warmup}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--out", default=TABLE_PATH)
+    args = ap.parse_args()
+    res = tune(args.steps, args.warmup)
+    with open(args.out, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res["table"]), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

@@ -23,7 +23,7 @@ def test_library_exports_every_declared_call():
     for n in names:
         assert hasattr(L, n), n
     assert set(A.EXPORTS) == set(names)
-    assert L.cmc_abi_version() == 6
+    assert L.cmc_abi_version() == 7
 
 
 def test_host_side_checks_without_gpu():
@@ -76,6 +76,39 @@ def test_host_side_checks_without_gpu():
     corr = A.cmc_params(1, 0, 0, 0.11, 0.03, 1.2, 10000, 0, 1)
     assert L.cmc_step_noalloc(C.byref(s), C.byref(corr), None) == A.CMC_EINVAL
     assert L.cmc_step_noalloc(None, C.byref(good), None) == A.CMC_EINVAL
+
+
+def test_launch_table_host_side():
+    """The launch table: bad tables are refused and leave the one in use;
+    lookups pick the band of a capacity; n = 0 restores the built-in table."""
+    from paper_1206_5878_amd import _capi as A
+    from paper_1206_5878_amd import tune
+    L = A.lib()
+    before = [tune.get(c) for c in (1, 1 << 17, 1 << 24)]
+    good = [dict(min_cap=0, sorted=0, bracket_blocks=512, trial_chunk=64),
+            dict(min_cap=1000, sorted=1, bracket_blocks=1024, trial_chunk=256)]
+    bad = [
+        [dict(good[0], min_cap=5)],                               # first band not at 0
+        [good[1], good[0]],                                       # not increasing
+        [dict(good[0], trial_chunk=100)],                         # not a multiple of 64
+        [dict(good[0], trial_chunk=2048)],
+        [dict(good[0], bracket_blocks=4)],
+        [dict(good[0], sorted=2)],
+    ]
+    try:
+        for t in bad:
+            arr = tune.to_c(t)
+            assert L.cmc_set_tuning(arr, len(t)) == A.CMC_EINVAL
+        assert [tune.get(c) for c in (1, 1 << 17, 1 << 24)] == before
+        assert L.cmc_set_tuning(None, A.CMC_TUNING_MAX + 1) == A.CMC_EINVAL
+        tune.set_table(good)
+        assert tune.get(999) == good[0]
+        assert tune.get(1000) == good[1] and tune.get(10**9) == good[1]
+        assert L.cmc_get_tuning(5, None) == A.CMC_EINVAL
+    finally:
+        tune.set_table([])
+        A._install_tuning(L)
+    assert [tune.get(c) for c in (1, 1 << 17, 1 << 24)] == before
 
 
 def test_product_does_not_import_oracle():
