@@ -44,11 +44,18 @@ class StepOut(C.Structure):
                 ("status", C.c_uint32)]
 
 
+_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")
 _lib = None
+_omp = None
+_active = None  # the library the wrappers below call
 
 
 def lib():
+    """The library the wrappers call: the serial build, unless inside
+    ``threads()``."""
     global _lib
+    if _active is not None:
+        return _active
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             from . import build as _b
@@ -57,11 +64,39 @@ def lib():
     return _lib
 
 
+def omp_lib():
+    """The OpenMP build of the same source (same results bit for bit)."""
+    global _omp
+    if _omp is None:
+        if not os.path.exists(_OMP_PATH):
+            from . import build as _b
+            _b.build()
+        _omp = load(_OMP_PATH)
+    return _omp
+
+
+class threads:
+    """``with oracle.threads():`` makes the wrappers call the OpenMP build
+    (its team size: ``oracle.omp_lib().ora_threads()``)."""
+
+    def __enter__(self):
+        global _active
+        self._prev = _active
+        _active = omp_lib()
+        return _active
+
+    def __exit__(self, *exc):
+        global _active
+        _active = self._prev
+        return False
+
+
 def load(path: str):
     """A build of the oracle's C source at ``path`` with every entry point's
     argument types declared (the tests also load deliberately broken builds
     to show that the pins catch them)."""
     L = C.CDLL(path)
+    L.ora_threads.restype = C.c_int
     L.ora_philox_many.argtypes = [C.c_int64, C.c_uint64, _up, _up]
     L.ora_u01.argtypes = [C.c_uint32, C.c_uint32]
     L.ora_u01.restype = C.c_double

@@ -4,13 +4,19 @@
  * TEST INFRASTRUCTURE ONLY (tests, smoke check, CPU baseline).  Shares no
  * code with the HIP library.  See cmc_oracle.h for the interface and the
  * paper reference.  Built with -ffp-contract=off so every line is the IEEE
- * operation it reads as.
+ * operation it reads as.  Built a second time with OpenMP for the CPU
+ * baseline's all-core timing: the per-star and per-pair loops are
+ * independent, and every sum runs serially in index order, so both builds
+ * give the same results bit for bit; the scan and the sort stay serial.
  */
 #include "cmc_oracle.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define PI 3.14159265358979323846
 
@@ -58,6 +64,15 @@ void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
   out[1] = x1;
   out[2] = x2;
   out[3] = x3;
+}
+
+/* Threads the library's parallel loops use: 1 unless built with OpenMP. */
+int ora_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }
 
 void ora_philox_many(int64_t n, uint64_t key, const uint32_t *ctr, uint32_t *out) {
@@ -571,6 +586,7 @@ static int64_t pair_terms_d(int64_t n, const double *r, const double *m, const d
                             double gamma, double *w, double *tp, double *nb) {
   int64_t np = n / 2;
   double lnL = coulomb_log(gamma, n);
+#pragma omp parallel for schedule(static)
   for (int64_t p = 0; p < np; ++p) {
     pair_geo g;
     pair_geometry(n, p, r, m, vr, vt, id, src, 0, lnL, &g);
@@ -591,12 +607,18 @@ int64_t ora_pair_terms(int64_t n, const double *r, const double *m, const double
 double ora_mean_sin2(int64_t np, const double *w, const double *tp, double dt) {
   ksum s = {0.0, 0.0};
   int64_t cnt = 0;
+  double *h2 = (double *)malloc((size_t)(np > 0 ? np : 1) * sizeof(double));
+#pragma omp parallel for schedule(static)
+  for (int64_t p = 0; p < np; ++p) {
+    double h = sin(0.5 * beta_of(tp[p], dt));
+    h2[p] = h * h;
+  }
   for (int64_t p = 0; p < np; ++p) {
     if (!(w[p] > 0.0)) continue;
-    double h = sin(0.5 * beta_of(tp[p], dt));
-    kadd(&s, h * h);
+    kadd(&s, h2[p]);
     ++cnt;
   }
+  free(h2);
   return cnt ? kval(&s) / (double)cnt : 0.0;
 }
 
@@ -655,6 +677,7 @@ static void relax_d(int64_t n, const double *r, const double *m, double *vr, dou
                     const uint32_t *id, const draws *src, double gamma, double dt) {
   int64_t np = n / 2;
   double lnL = coulomb_log(gamma, n);
+#pragma omp parallel for schedule(static)
   for (int64_t p = 0; p < np; ++p) {
     pair_geo g;
     pair_geometry(n, p, r, m, vr, vt, id, src, 1, lnL, &g);
@@ -739,6 +762,13 @@ static double dq_in(const double *mcum, int64_t k, double x, double J2) {
   return grav + 2.0 * J2 / (x * x * x);
 }
 
+/* One star's share of the pass's tallies. */
+typedef struct {
+  int32_t esc, capped, trials, violations;
+  uint32_t fl;
+  double m_e; /* m E of an escaper */
+} star_tally;
+
 static void orbit_d(int64_t n, const double *r, const double *phi, const double *mcum,
                     const double *ssuf, const double *m, double *vr, double *vt,
                     const uint32_t *id, const draws *src, int32_t trial_cap,
@@ -751,10 +781,15 @@ static void orbit_d(int64_t n, const double *r, const double *phi, const double 
   ksum eesc = {0.0, 0.0};
 
   /* every star, or only the listed ones (each star's orbit depends on the
-   * table and its own state alone) */
+   * table and its own state alone); each star's tallies are kept apart and
+   * summed in star order after the loop, so the result does not depend on
+   * whether the loop runs on one thread or many */
   const int64_t todo = only ? count : n;
+  star_tally *tally = (star_tally *)calloc((size_t)(todo > 0 ? todo : 1), sizeof(star_tally));
+#pragma omp parallel for schedule(dynamic, 4096)
   for (int64_t q = 0; q < todo; ++q) {
     const int64_t i = only ? only[q] : q;
+    star_tally *t = &tally[q];
     uint32_t fl = 0;
     double E = phi[i] + 0.5 * (vr[i] * vr[i] + vt[i] * vt[i]);
     double J = r[i] * vt[i];
@@ -763,11 +798,11 @@ static void orbit_d(int64_t n, const double *r, const double *phi, const double 
     if (J_out) J_out[i] = J;
     if (!(E < 0.0)) { /* unbound (or not a number): leaves the cluster */
       r_new[i] = INFINITY;
-      s.n_esc++;
-      kadd(&eesc, m[i] * E);
+      t->esc = 1;
+      t->m_e = m[i] * E;
       fl |= ORA_ST_ESCAPER;
       if (E != E) fl |= ORA_ST_NONFINITE;
-      s.status |= fl;
+      t->fl = fl;
       if (flags_out) flags_out[i] = fl;
       if (kmin_out) kmin_out[i] = -2;
       if (kmax_out) kmax_out[i] = -2;
@@ -859,7 +894,7 @@ static void orbit_d(int64_t n, const double *r, const double *phi, const double 
           if (!(q0 > 0.0)) continue;
           double g0 = ra * cos(s0) / sqrt(q0);
           if (g0 > F) {
-            s.violations++;
+            t->violations++;
             fl |= ORA_ST_BOUND;
           }
           if (F * X2 < g0) {
@@ -868,7 +903,7 @@ static void orbit_d(int64_t n, const double *r, const double *phi, const double 
           }
         }
         if (!accepted) {
-          s.capped++;
+          t->capped = 1;
           fl |= ORA_ST_TRIAL_CAP;
         }
       } else {
@@ -876,7 +911,7 @@ static void orbit_d(int64_t n, const double *r, const double *phi, const double 
         fl |= ORA_ST_NUMERIC;
       }
     }
-    s.trials += ntr;
+    t->trials = ntr;
     if (trials_out) trials_out[i] = ntr;
 
     /* New state: J conserved, E conserved in the old potential, random sign
@@ -891,9 +926,21 @@ static void orbit_d(int64_t n, const double *r, const double *phi, const double 
     vr[i] = (w[0] >> 31) ? -vmag : vmag;
     vt[i] = (J2 == 0.0) ? 0.0 : J / rn;
     if (!isfinite(rn) || !isfinite(vr[i]) || !isfinite(vt[i])) fl |= ORA_ST_NONFINITE;
-    s.status |= fl;
+    t->fl = fl;
     if (flags_out) flags_out[i] = fl;
   }
+  for (int64_t q = 0; q < todo; ++q) {
+    const star_tally *t = &tally[q];
+    if (t->esc) {
+      s.n_esc++;
+      kadd(&eesc, t->m_e);
+    }
+    s.violations += t->violations;
+    s.capped += t->capped;
+    s.trials += t->trials;
+    s.status |= t->fl;
+  }
+  free(tally);
   s.e_esc = kval(&eesc);
   if (st) *st = s;
 }
@@ -954,6 +1001,7 @@ void ora_step_ex(int64_t n, double *r, double *vr, double *vt, double *m, uint32
   double *phi_rn = NULL;
   if (moves) {
     phi_rn = (double *)malloc(nn * sizeof(double));
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i)
       phi_rn[i] = (rn[i] < INFINITY) ? ora_phi_at(n, r, phi, mcum, ssuf, rn[i]) : NAN;
   }

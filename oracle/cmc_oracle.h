@@ -199,6 +199,10 @@ int64_t ora_energy_correction(int64_t n, const double *r, const double *m, doubl
 void ora_diagnostics(int64_t n, const double *r, const double *vr, const double *vt,
                      const double *m, const double *phi, const double *mcum, double *out);
 
+/* Threads the parallel loops use: 1 for the plain build, the OpenMP team
+ * size for the OpenMP build (liboracle_omp.so). */
+int ora_threads(void);
+
 #ifdef __cplusplus
 }
 #endif
