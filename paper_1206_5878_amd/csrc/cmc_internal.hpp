@@ -340,8 +340,13 @@ constexpr uint32_t kBucketEsc = 0xFFFFFFFFu;  // bkey of a star that leaves the 
 constexpr int kKingTab = 3 * kKingNodes + 8;
 // The orbit table's top levels held in LDS by the orbit pass's kernels, and
 // the sorted turning-point searches below them (orbit.hip).
-constexpr int kTopBytes = 48 * 1024;
-constexpr int kTopEntries = kTopBytes / 16;  // (r, Phi) entries
+// In LDS each 8-entry node of a level is followed by one unused entry: node
+// s then starts on bank 36 s mod 64 of the 4-byte banks instead of all nodes
+// on the same two, so the lanes of a wavefront that read the children of
+// different nodes spread over the banks.
+constexpr int kTopBytes = 52 * 1024;
+constexpr int kTopEntries = kTopBytes / 16;  // LDS slots of 16 bytes, padding included
+__host__ __device__ inline int64_t top_padded(int64_t len) { return len + (len >> 3) + 1; }
 constexpr int kQueryTile = 8192;             // stars per tile of the search sort
 constexpr int kPhiBins = 16384;  // bins of the potential-bound table (orbit.hip)
 // LFSR113 stream seeding (rng.hip): for each component, the 32x32 bit matrix
@@ -407,7 +412,8 @@ __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 
 // Top levels of the orbit table kept in LDS: levels from the top down while
 // they fit kTopBytes (at the capacity).  ltop = the lowest of them.
 struct OrbitTop {             // top levels of the orbit table kept in LDS
-  int32_t off[kMaxLevels];    // LDS entry offset of level L, for L >= ltop
+  int32_t off[kMaxLevels];    // LDS slot of level L's entry 0, for L >= ltop (entry
+                              // e of the level at slot off + e + e / 8)
   int32_t len[kMaxLevels];    // entries of level L at the capacity
   int32_t ltop, entries;
 };
@@ -418,10 +424,10 @@ inline OrbitTop top_levels(int nlev, int64_t cap) {
   for (int L = nlev - 1; L >= 0; --L) {
     const int64_t stride = int64_t(1) << (3 * L);
     const int64_t len = (cap + stride - 1) / stride;
-    if ((tot + len) * 16 > kTopBytes) break;
+    if ((tot + top_padded(len)) * 16 > kTopBytes) break;
     tl.off[L] = static_cast<int32_t>(tot);
     tl.len[L] = static_cast<int32_t>(len);
-    tot += len;
+    tot += top_padded(len);
     tl.ltop = L;
   }
   tl.entries = static_cast<int32_t>(tot);
@@ -430,6 +436,7 @@ inline OrbitTop top_levels(int nlev, int64_t cap) {
 
 constexpr int kDefaultBracketBlocks = 1024;  // resident bracket blocks of one cluster
 constexpr int kDefaultTrialChunk = 128;      // stars per wavefront chunk of the trial kernel
+constexpr int kMaxTrialChunk = 1024;         // the launch table's largest chunk
 
 inline Workspace layout(int64_t cap, void *base) {
   Workspace w{};

@@ -142,49 +142,188 @@ __device__ __forceinline__ bool surely_rejected(const PhiBounds &pb, double x, d
   return F * X2 >= gmax * (1.0 + 1e-12);
 }
 
+// ---------------------------------------------------------------- LDS levels
+// Each lane descends the LDS-resident levels alone: per level, the 7 other
+// children of its sample, one 16-byte read each (the padded layout spreads
+// the lanes' nodes over the banks).  Q_k < 0 and k < below: the lower
+// bracket; Q_k >= 0 or k <= upto: the upper one.
+struct QNeg {
+  double twoE, J2;
+  int32_t below;
+  __device__ bool operator()(int32_t k, const RPhi &e) const {
+    return k < below && q_neg(twoE, J2, e);
+  }
+};
+struct QNonNeg {
+  double twoE, J2;
+  int32_t upto;
+  __device__ bool operator()(int32_t k, const RPhi &e) const {
+    return k <= upto || q_nonneg(twoE, J2, e);
+  }
+};
+// Either bracket for the search kernel: c >= 0 the lower bracket below star
+// c, c < 0 the upper bracket of star -c - 1.
+struct QAny {
+  double twoE, J2;
+  int32_t c;
+  __device__ bool operator()(int32_t k, const RPhi &e) const {
+    return c >= 0 ? (k < c && q_neg(twoE, J2, e)) : (k <= -c - 1 || q_nonneg(twoE, J2, e));
+  }
+};
+
+// LDS slot of entry e of a padded level that starts at slot off.
+__device__ __forceinline__ int64_t pad_slot(int64_t off, int64_t e) { return off + e + (e >> 3); }
+
+// The levels [ltop, nlev) -- at most kTopEntries slots, see top_levels() --
+// are copied into LDS by every block of the kernels that start the searches.
+__device__ __forceinline__ void load_top(RPhi *top, const Levels &lv, const OrbitTop &tl,
+                                         int nthreads) {
+  for (int L = tl.ltop; L < lv.nlev; ++L)
+    for (int e = threadIdx.x; e < tl.len[L]; e += nthreads)
+      top[pad_slot(tl.off[L], e)] = lv.lev[L][e];
+}
+
+// Descent of the LDS levels: the sample of level ltop below which the last
+// index satisfying pred lies (-1: no index does).  With ltop = 0 that is the
+// index itself.
+// The last child c in 0..7 of a node (entries blk[0..7], child 0 known to
+// hold) where pred holds, by bisection over the 8: the predicate is monotone
+// in the index, so 3 evaluations find it.  Children from `avail` on do not
+// exist (they count as not holding).  k0 + q * stride: child q's index.
+template <class Pred>
+__device__ __forceinline__ int node_last(const RPhi *blk, int avail, int32_t k0, int32_t stride,
+                                         const Pred &pred) {
+  int c = 0;
+#pragma unroll
+  for (int h = 4; h >= 1; h >>= 1) {
+    const int q = c + h;
+    if (q < avail && pred(k0 + q * stride, blk[q])) c = q;
+  }
+  return c;
+}
+
+template <class Pred>
+__device__ __forceinline__ int32_t top_descend(const RPhi *top, const OrbitTop &tl, int nlev,
+                                               int64_t n, const Pred &pred) {
+  if (!pred(0, top[tl.off[nlev - 1]])) return -1;
+  int32_t s = 0;
+#pragma unroll
+  for (int L = kMaxLevels - 1; L >= 0; --L) {
+    if (L < nlev && L >= tl.ltop) {
+      const int32_t stride = int32_t(1) << (3 * L);
+      const int32_t cnt = static_cast<int32_t>((n + stride - 1) / stride);
+      const int32_t base = s * 8;
+      const RPhi *blk = top + pad_slot(tl.off[L], base);
+      s = base + node_last(blk, cnt - base, base * stride, stride, pred);
+    }
+  }
+  return s;
+}
+
 // ---------------------------------------------------------------- group search
-// The searches run cooperatively: lanes form groups of 8 (group g = lanes
-// 8g..8g+7), and each group runs the searches of its 8 lanes together.  Per
-// level, lane q loads child q of each of the 8 current samples, so every
-// node is one aligned 128-byte block -- one coalesced line in global memory,
-// 8 consecutive entries (no bank conflict inside the group) in LDS -- and a
-// ballot counts the children that satisfy each predicate.  The 8 loads of a
-// level are in flight together.  Predicate parameters travel through LDS.
-// Every lane of the wavefront must call it.
+// Below the LDS levels the searches run cooperatively: lanes form groups of 8
+// (group g = lanes 8g..8g+7), and each group runs the searches of its 8
+// lanes together.  Per level, lane q loads child q of each current sample,
+// so every node is one coalesced 128-byte load instead of 8 loads per lane,
+// and a ballot counts the children that satisfy the predicate.  Predicate
+// parameters travel through LDS.  Every lane of the wavefront must call it.
 struct GParams {
   double a, b;  // 2E, J^2
-  int32_t c;    // the star's index: below (lower bracket) or upto (upper)
+  int32_t c;    // the star's index: below (lower bracket) or upto (upper); see GQAny
   int32_t s0;   // the sample the search starts below (-1: no index holds)
 };
-struct GQNeg {  // lower bracket: Q_k < 0 and k < below
+struct GQNeg {
   __device__ static bool eval(const GParams &p, int64_t k, const RPhi &e) {
     return k < p.c && q_neg(p.a, p.b, e);
   }
 };
-struct GQNonNeg {  // upper bracket: Q_k >= 0 or k <= upto
+struct GQNonNeg {
   __device__ static bool eval(const GParams &p, int64_t k, const RPhi &e) {
     return k <= p.c || q_nonneg(p.a, p.b, e);
   }
 };
-
-// Level entries: from the LDS copy of the top levels (L >= ltop) or from
-// global memory.
-struct TopSrc {
-  const RPhi *top;
-  const OrbitTop *tl;
-  const Levels *lv;
-  __device__ __forceinline__ RPhi operator()(int L, int64_t child) const {
-    return L >= tl->ltop ? top[tl->off[L] + child] : lv->lev[L][child];
+// Either bracket: c >= 0 is the lower bracket below star c, c < 0 the upper
+// bracket of star -c - 1.
+struct GQAny {
+  __device__ static bool eval(const GParams &p, int64_t k, const RPhi &e) {
+    return p.c >= 0 ? (k < p.c && q_neg(p.a, p.b, e))
+                    : (k <= -static_cast<int64_t>(p.c) - 1 || q_nonneg(p.a, p.b, e));
   }
 };
 
-// Descent of levels lhi down to llo for the 8 searches of each group, each
-// starting below sample mine.s0 of level lhi + 1 (lhi = nlev - 1: below the
-// root, s0 = 0).  Returns the sample of level llo the lane's own search
-// reaches (-1: no index holds).  wprm: the wavefront's 64 LDS slots.
-template <class Pred, class Src>
-__device__ __forceinline__ int32_t group_descend(const Src &src, int lhi, int llo, int64_t n,
-                                                 const GParams &mine, GParams *wprm) {
+// Descent of the levels below lhi + 1 down to level 0 for two searches per
+// lane (predicates PA and PB), each starting below the sample s0 of level
+// lhi + 1 that its lane brings (-1: no index holds).  The loads of
+// kGroupBatch searches are in flight together.
+template <class PA, class PB>
+__device__ __forceinline__ void group_descend2(const Levels &lv, int lhi, int64_t n,
+                                               const GParams &ma, const GParams &mb,
+                                               GParams *prm_a, GParams *prm_b, int32_t &ka,
+                                               int32_t &kb) {
+  const int lane = threadIdx.x & 63, g = lane >> 3, q = lane & 7;
+  prm_a[lane] = ma;
+  prm_b[lane] = mb;
+  __builtin_amdgcn_wave_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  int32_t s[16];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    s[t] = prm_a[(g << 3) + t].s0;
+    s[8 + t] = prm_b[(g << 3) + t].s0;
+  }
+#pragma unroll
+  for (int L = kMaxLevels - 1; L >= 0; --L) {
+    if (L <= lhi) {
+      // re-read the parameters from LDS at every level rather than keep
+      // 16 sets of them live in registers
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      const int64_t stride = int64_t(1) << (3 * L);
+      const int64_t cnt = (n + stride - 1) / stride;
+      const RPhi *lev = lv.lev[L];
+#pragma unroll
+      for (int h = 0; h < 16; h += kGroupBatch) {
+        RPhi e[kGroupBatch];
+#pragma unroll
+        for (int v = 0; v < kGroupBatch; ++v) {
+          const int u = h + v;
+          const int64_t child = static_cast<int64_t>(s[u]) * 8 + q;
+          e[v] = (s[u] >= 0 && child < cnt) ? lev[child] : RPhi{0.0, 0.0};
+        }
+#pragma unroll
+        for (int v = 0; v < kGroupBatch; ++v) {
+          const int u = h + v;
+          const GParams p = (u < 8) ? prm_a[(g << 3) + u] : prm_b[(g << 3) + u - 8];
+          const int64_t child = static_cast<int64_t>(s[u]) * 8 + q;
+          const bool in = s[u] >= 0 && child < cnt;
+          const bool ok = in && ((u < 8) ? PA::eval(p, child * stride, e[v])
+                                         : PB::eval(p, child * stride, e[v]));
+          const uint64_t m = __ballot(ok);
+          const int c = __popcll((m >> (g << 3)) & 0xFFull);
+          if (s[u] >= 0) s[u] = s[u] * 8 + c - 1;
+        }
+      }
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  int32_t ra = s[0], rb = s[8];
+#pragma unroll
+  for (int t = 1; t < 8; ++t) {
+    if (q == t) {
+      ra = s[t];
+      rb = s[8 + t];
+    }
+  }
+  ka = ra;
+  kb = rb;
+}
+
+// One search per lane, the same way (8 per group, all 8 loads of a level in
+// flight), from below sample mine.s0 of level lhi + 1 to level 0; returns
+// the lane's own result.
+template <class P>
+__device__ __forceinline__ int32_t group_descend1(const Levels &lv, int lhi, int64_t n,
+                                                  const GParams &mine, GParams *wprm) {
   const int lane = threadIdx.x & 63, g = lane >> 3, q = lane & 7;
   wprm[lane] = mine;
   __builtin_amdgcn_wave_barrier();
@@ -194,23 +333,22 @@ __device__ __forceinline__ int32_t group_descend(const Src &src, int lhi, int ll
   for (int u = 0; u < 8; ++u) s[u] = wprm[(g << 3) + u].s0;
 #pragma unroll
   for (int L = kMaxLevels - 1; L >= 0; --L) {
-    if (L <= lhi && L >= llo) {
-      // re-read the parameters from LDS at every level rather than keep 8
-      // sets of them live in registers
+    if (L <= lhi) {
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
       const int64_t stride = int64_t(1) << (3 * L);
       const int64_t cnt = (n + stride - 1) / stride;
+      const RPhi *lev = lv.lev[L];
       RPhi e[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int64_t child = static_cast<int64_t>(s[u]) * 8 + q;
-        e[u] = (s[u] >= 0 && child < cnt) ? src(L, child) : RPhi{0.0, 0.0};
+        e[u] = (s[u] >= 0 && child < cnt) ? lev[child] : RPhi{0.0, 0.0};
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const GParams p = wprm[(g << 3) + u];
         const int64_t child = static_cast<int64_t>(s[u]) * 8 + q;
-        const bool ok = s[u] >= 0 && child < cnt && Pred::eval(p, child * stride, e[u]);
+        const bool ok = s[u] >= 0 && child < cnt && P::eval(p, child * stride, e[u]);
         const uint64_t m = __ballot(ok);
         const int c = __popcll((m >> (g << 3)) & 0xFFull);
         if (s[u] >= 0) s[u] = s[u] * 8 + c - 1;
@@ -224,32 +362,6 @@ __device__ __forceinline__ int32_t group_descend(const Src &src, int lhi, int ll
   for (int u = 1; u < 8; ++u)
     if (q == u) r = s[u];
   return r;
-}
-
-// ---------------------------------------------------------------- LDS top
-// The levels [ltop, nlev) -- at most kTopEntries entries, see top_levels() --
-// are copied into LDS by every block of the kernels that start the searches.
-__device__ __forceinline__ void load_top(RPhi *top, const Levels &lv, const OrbitTop &tl,
-                                         int nthreads) {
-  for (int L = tl.ltop; L < lv.nlev; ++L)
-    for (int e = threadIdx.x; e < tl.len[L]; e += nthreads) top[tl.off[L] + e] = lv.lev[L][e];
-}
-
-// Both brackets of a lane's star from the root down to level llo: the
-// samples of level llo (llo = 0: the brackets).  bound = false: no search
-// (the lane still takes part).  Every lane of the wavefront must call it.
-__device__ __forceinline__ void bracket_samples(const TopSrc &src, int nlev, int llo, int64_t n,
-                                                bool bound, double E, double J2, int64_t i,
-                                                GParams *wprm, int32_t &t0, int32_t &t1) {
-  const RPhi e0 = src.top[src.tl->off[nlev - 1]];  // table entry 0
-  const int32_t ii = static_cast<int32_t>(i);
-  GParams lo{2.0 * E, J2, ii, -1}, hi{2.0 * E, J2, ii, -1};
-  if (bound) {
-    lo.s0 = GQNeg::eval(lo, 0, e0) ? 0 : -1;
-    hi.s0 = 0;  // k = 0 <= upto always holds
-  }
-  t0 = group_descend<GQNeg>(src, nlev - 1, llo, n, lo, wprm);
-  t1 = group_descend<GQNonNeg>(src, nlev - 1, llo, n, hi, wprm);
 }
 
 // ---------------------------------------------------------------- turning points
@@ -423,7 +535,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4)))
 void k_orbit_bracket(Ctx ctx, int corr) {
   extern __shared__ RPhi top[];
   __shared__ double shd[BT / 64];
-  __shared__ GParams prm[BT];
+  __shared__ GParams prm[2 * BT];
   const ClusterArgs &A = ctx.args();
   const Levels lv = levels_of(A.w);
   const OrbitTop &tl = A.top;
@@ -435,7 +547,6 @@ void k_orbit_bracket(Ctx ctx, int corr) {
   GParams *wprm = prm + (threadIdx.x & ~63);
   load_top(top, lv, tl, BT);
   __syncthreads();
-  const TopSrc src{top, &tl, &lv};
 
   uint32_t fl = 0;
   const int64_t tiles = (n + BT - 1) / BT;
@@ -446,8 +557,16 @@ void k_orbit_bracket(Ctx ctx, int corr) {
     double E = 0.0, J = 0.0, J2 = 0.0;
     const bool bound =
         i < n && star_start<MT, TO_STAGE, LF>(A, i, corr, E, J, J2, c_esc, e_esc, fl);
+    const int32_t ii = static_cast<int32_t>(i);
+    // brackets: the LDS levels per lane, the rest by groups of 8 lanes
+    int32_t t0 = -1, t1 = -1;
+    if (bound) {
+      t0 = top_descend(top, tl, lv.nlev, n, QNeg{2.0 * E, J2, ii});
+      t1 = top_descend(top, tl, lv.nlev, n, QNonNeg{2.0 * E, J2, ii});
+    }
     int32_t kmin, kmax;
-    bracket_samples(src, lv.nlev, 0, n, bound, E, J2, i, wprm, kmin, kmax);
+    group_descend2<GQNeg, GQNonNeg>(lv, tl.ltop - 1, n, GParams{2.0 * E, J2, ii, t0},
+                                    GParams{2.0 * E, J2, ii, t1}, wprm, wprm + BT, kmin, kmax);
     if (bound) {
       orec[i].lo = finalize_lo(tab, ms, kmin, E, J, J2);
       orec[i].hi = finalize_hi(tab, ms, n, kmax, E, J, J2);
@@ -469,7 +588,7 @@ void k_orbit_bracket(Ctx ctx, int corr) {
 // of the direct form.
 constexpr int QT = 512;   // threads of the tile kernels
 constexpr int QS = kQuerySearchBlock;
-constexpr int kSubEntries = 1024;  // LDS entries of a group's subtree in the search
+constexpr int kSubEntries = 704;  // LDS slots of a group's subtree in the search
 
 // Samples of level ltop over the n stars (the groups of this pass).
 __device__ __forceinline__ int64_t query_bins(const OrbitTop &tl, int64_t n) {
@@ -488,7 +607,6 @@ template <class Ctx>
 __global__ __launch_bounds__(QT) void k_oq_hist(Ctx ctx) {
   extern __shared__ RPhi top[];
   __shared__ uint32_t hist[kTopEntries];
-  __shared__ GParams prm[QT];
   const ClusterArgs &A = ctx.args();
   const OrbitTop &tl = A.top;
   const RIndexCtl ictl = *A.w.rx_ctl;
@@ -500,36 +618,27 @@ __global__ __launch_bounds__(QT) void k_oq_hist(Ctx ctx) {
   const Levels lv = levels_of(A.w);
   const RPhi *__restrict__ tab = lv.lev[0];
   uint32_t *__restrict__ node = A.w.oq_node;
-  GParams *wprm = prm + (threadIdx.x & ~63);
   load_top(top, lv, tl, QT);
   for (int b = threadIdx.x; b < bins; b += QT) hist[b] = 0u;
   __syncthreads();
-  const TopSrc src{top, &tl, &lv};
   const int64_t k1 = k0 + kQueryTile < n ? k0 + kQueryTile : n;
-  for (int j = 0; j < kQueryTile / QT; ++j) {  // block-uniform
-    const int64_t i = k0 + j * QT + threadIdx.x;
-    double E = 0.0, J2 = 0.0;
-    bool bound = false;
-    if (i < k1) {
-      const RPhi me = tab[i];
-      const double vri = A.s.vr[i], vti = A.s.vt[i];
-      E = me.phi + 0.5 * (vri * vri + vti * vti);
-      const double J = me.r * vti;
-      J2 = J * J;
-      bound = E < 0.0;
+  for (int64_t i = k0 + threadIdx.x; i < k1; i += QT) {
+    const RPhi me = tab[i];
+    const double vri = A.s.vr[i], vti = A.s.vt[i];
+    const double E = me.phi + 0.5 * (vri * vri + vti * vti);
+    const double J = me.r * vti;
+    const double J2 = J * J;
+    // the two samples for the scatter: (t0 + 1) | t1 << 16, or none
+    uint32_t code = 0xFFFFFFFFu;
+    if (E < 0.0) {
+      const int32_t ii = static_cast<int32_t>(i);
+      const int32_t t0 = top_descend(top, tl, lv.nlev, n, QNeg{2.0 * E, J2, ii});
+      const int32_t t1 = top_descend(top, tl, lv.nlev, n, QNonNeg{2.0 * E, J2, ii});
+      if (t0 >= 0) atomicAdd(&hist[t0], 1u);
+      atomicAdd(&hist[t1], 1u);
+      code = static_cast<uint32_t>(t0 + 1) | (static_cast<uint32_t>(t1) << 16);
     }
-    int32_t t0, t1;
-    bracket_samples(src, lv.nlev, tl.ltop, n, bound, E, J2, i, wprm, t0, t1);
-    if (i < k1) {
-      // the two samples for the scatter: (t0 + 1) | t1 << 16, or none
-      uint32_t code = 0xFFFFFFFFu;
-      if (bound) {
-        if (t0 >= 0) atomicAdd(&hist[t0], 1u);
-        atomicAdd(&hist[t1], 1u);
-        code = static_cast<uint32_t>(t0 + 1) | (static_cast<uint32_t>(t1) << 16);
-      }
-      node[i] = code;
-    }
+    node[i] = code;
   }
   __syncthreads();
   uint32_t *__restrict__ row = A.w.oq_cnt + t * A.w.oq_bins;
@@ -621,7 +730,6 @@ template <class Ctx, typename MT, bool TO_STAGE, bool LF>
 __global__ __launch_bounds__(QT) void k_oq_scatter(Ctx ctx, int corr) {
   extern __shared__ RPhi top[];
   __shared__ uint32_t cur[kTopEntries];
-  __shared__ GParams prm[QT];
   __shared__ double shd[QT / 64];
   const ClusterArgs &A = ctx.args();
   const OrbitTop &tl = A.top;
@@ -636,7 +744,6 @@ __global__ __launch_bounds__(QT) void k_oq_scatter(Ctx ctx, int corr) {
   const MS *__restrict__ ms = A.w.ms;
   OrbitRec *__restrict__ orec = A.w.orec;
   OrbQuery *__restrict__ oq = A.w.oq;
-  GParams *wprm = prm + (threadIdx.x & ~63);
   uint32_t fl = 0;
   if (k0 < n) {  // block-uniform
     if (bins == 0) {
@@ -646,7 +753,6 @@ __global__ __launch_bounds__(QT) void k_oq_scatter(Ctx ctx, int corr) {
       for (int b = threadIdx.x; b < bins; b += QT) cur[b] = A.w.oq_start[b] + row[b];
     }
     __syncthreads();
-    const TopSrc src{top, &tl, &lv};
     const int64_t k1 = k0 + kQueryTile < n ? k0 + kQueryTile : n;
     for (int j = 0; j < kQueryTile / QT && k0 + j * QT < n; ++j) {  // block-uniform
       const int64_t i = k0 + j * QT + threadIdx.x;
@@ -655,9 +761,10 @@ __global__ __launch_bounds__(QT) void k_oq_scatter(Ctx ctx, int corr) {
       const bool bound =
           i < k1 && star_start<MT, TO_STAGE, LF>(A, i, corr, E, J, J2, c_esc, e_esc, fl);
       if (bins == 0) {
-        int32_t kmin, kmax;
-        bracket_samples(src, lv.nlev, 0, n, bound, E, J2, i, wprm, kmin, kmax);
-        if (bound) {
+        if (bound) {  // the whole table in LDS: the samples are the brackets
+          const int32_t ii = static_cast<int32_t>(i);
+          const int32_t kmin = top_descend(top, tl, lv.nlev, n, QNeg{2.0 * E, J2, ii});
+          const int32_t kmax = top_descend(top, tl, lv.nlev, n, QNonNeg{2.0 * E, J2, ii});
           orec[i].lo = finalize_lo(tab, ms, kmin, E, J, J2);
           orec[i].hi = finalize_hi(tab, ms, n, kmax, E, J, J2);
         }
@@ -682,41 +789,17 @@ __global__ __launch_bounds__(QT) void k_oq_scatter(Ctx ctx, int corr) {
   or_status(A.s.sc, fl);
 }
 
-// A grouped search of either bracket: c >= 0 is the lower bracket below star
-// c, c < 0 the upper bracket of star -c - 1.
-struct GQAny {
-  __device__ static bool eval(const GParams &p, int64_t k, const RPhi &e) {
-    return p.c >= 0 ? (k < p.c && q_neg(p.a, p.b, e))
-                    : (k <= -static_cast<int64_t>(p.c) - 1 || q_nonneg(p.a, p.b, e));
-  }
-};
-
-// Level entries of the grouped search: the levels lsub .. ltop - 1 under one
-// top sample, staged in LDS (level L's span of 8^(ltop - L) entries at offset
-// (8^(ltop - L) - 8) / 7), the levels below from global memory.
-struct NodeSrc {
-  const RPhi *sub;
-  const Levels *lv;
-  int64_t node;
-  int ltop, lsub;
-  __device__ __forceinline__ RPhi operator()(int L, int64_t child) const {
-    if (L >= lsub) {
-      const int64_t span = int64_t(1) << (3 * (ltop - L));
-      return sub[(span - 8) / 7 + (child - node * span)];
-    }
-    return lv->lev[L][child];
-  }
-};
-
 // The grouped searches.  Block b works on kQuerySearchChunk searches of one
-// group (the first blocks of the group at oq_chunk): it stages the levels of
-// the group's subtree that fit kSubEntries in LDS (one coalesced copy, shared
-// by all its searches), then runs the searches a wavefront at a time, the
-// levels below from global memory, and each lane finishes its own search.
+// group (the first block of each group at oq_chunk): it stages the levels
+// of the group's subtree that fit kSubEntries slots in LDS (padded as the
+// top levels; one coalesced copy shared by all its searches), each lane
+// descends them alone, the levels below go by groups of 8 lanes from global
+// memory, and each lane finishes its own search.
 template <class Ctx>
 __global__ __launch_bounds__(QS) void k_oq_search(Ctx ctx) {
   __shared__ RPhi sub[kSubEntries];
   __shared__ GParams prm[QS];
+  __shared__ int32_t soff[kMaxLevels];
   const ClusterArgs &A = ctx.args();
   const OrbitTop &tl = A.top;
   const RIndexCtl ictl = *A.w.rx_ctl;
@@ -738,19 +821,34 @@ __global__ __launch_bounds__(QS) void k_oq_search(Ctx ctx) {
   const int64_t q1 = q0 + kQuerySearchChunk < qe ? q0 + kQuerySearchChunk : qe;
   const Levels lv = levels_of(A.w);
   const int ltop = tl.ltop;
-  // the subtree's levels ltop - 1 down to lsub, while they fit
+  // the subtree's levels ltop - 1 down to lsub, while they fit (padded)
   int lsub = ltop;
-  while (lsub > 1 && ((int64_t(1) << (3 * (ltop - lsub + 1))) * 8 - 8) / 7 <= kSubEntries) --lsub;
+  {
+    int64_t used = 0;
+    while (lsub > 1) {
+      const int64_t span = int64_t(1) << (3 * (ltop - lsub + 1));
+      if (used + top_padded(span) > kSubEntries) break;
+      used += top_padded(span);
+      --lsub;
+    }
+  }
+  if (threadIdx.x == 0) {
+    int64_t used = 0;
+    for (int L = ltop - 1; L >= lsub; --L) {
+      soff[L] = static_cast<int32_t>(used);
+      used += top_padded(int64_t(1) << (3 * (ltop - L)));
+    }
+  }
+  __syncthreads();
   for (int L = ltop - 1; L >= lsub; --L) {
     const int64_t span = int64_t(1) << (3 * (ltop - L));
     const int64_t stride = int64_t(1) << (3 * L);
     const int64_t cnt = (n + stride - 1) / stride;
     const int64_t base = node * span;
     for (int64_t e = threadIdx.x; e < span; e += QS)
-      if (base + e < cnt) sub[(span - 8) / 7 + e] = lv.lev[L][base + e];
+      if (base + e < cnt) sub[pad_slot(soff[L], e)] = lv.lev[L][base + e];
   }
   __syncthreads();
-  const NodeSrc src{sub, &lv, node, ltop, lsub};
   GParams *wprm = prm + (threadIdx.x & ~63);
   const RPhi *__restrict__ tab = lv.lev[0];
   OrbitRec *__restrict__ orec = A.w.orec;
@@ -761,10 +859,23 @@ __global__ __launch_bounds__(QS) void k_oq_search(Ctx ctx) {
     if (act) qr = A.w.oq[qi];
     const bool hi_b = (qr.node & kQueryHi) != 0u;
     const double J2 = qr.J * qr.J;
+    const double twoE = 2.0 * qr.E;
+    // the staged levels, per lane (the group's sample holds the predicate)
     const int32_t ci = static_cast<int32_t>(qr.i);
-    const GParams mine{2.0 * qr.E, J2, hi_b ? -ci - 1 : ci,
-                       act ? static_cast<int32_t>(node) : -1};
-    const int32_t k = group_descend<GQAny>(src, ltop - 1, 0, n, mine, wprm);
+    const QAny pred{twoE, J2, hi_b ? -ci - 1 : ci};
+    int32_t s = static_cast<int32_t>(node);
+    if (act) {
+      for (int L = ltop - 1; L >= lsub; --L) {
+        const int32_t stride = int32_t(1) << (3 * L);
+        const int32_t cnt = static_cast<int32_t>((n + stride - 1) / stride);
+        const int32_t base = s * 8;
+        const int32_t local = base - static_cast<int32_t>(node) * (int32_t(1) << (3 * (ltop - L)));
+        s = base + node_last(sub + pad_slot(soff[L], local), cnt - base, base * stride, stride,
+                             pred);
+      }
+    }
+    const GParams mine{twoE, J2, hi_b ? -ci - 1 : ci, act ? s : -1};
+    const int32_t k = group_descend1<GQAny>(lv, lsub - 1, n, mine, wprm);
     if (act) {
       if (hi_b)
         orec[qr.i].hi = finalize_hi(tab, A.w.ms, n, k, qr.E, qr.J, J2);
@@ -779,6 +890,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5)))
 void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap, int corr,
                     double bound_factor) {
   __shared__ double shd[NT / 64];
+  // stars of each wavefront's chunk finished without trials (kept apart so
+  // that their code does not hold registers in the trial loop)
+  __shared__ uint32_t deferred[NT / 64][kMaxTrialChunk];
+  __shared__ uint32_t n_deferred[NT / 64];
   const ClusterArgs &A = ctx.args();
   const uint32_t step = step_of(A, step_arg);
   const Levels lv = levels_of(A.w);
@@ -812,6 +927,11 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap, int corr,
   uint32_t c_tr = 0, c_viol = 0, c_cap = 0;
   uint32_t fl = 0;
 
+  const int wv = threadIdx.x >> 6;
+  if (lane == 0) n_deferred[wv] = 0u;
+  __builtin_amdgcn_wave_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+
   // lane state: current star and its orbit
   bool busy = false;
   int64_t i = 0;
@@ -838,15 +958,13 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap, int corr,
           const double orc = 0.5 * (o.hi.rmax + o.lo.rmin);
           const double ora = 0.5 * (o.hi.rmax - o.lo.rmin);
           double oF = -1.0;
-          double rdone = o.lo.rmin;  // radius of an orbit finished without trials
           if (ora > 0.0) {
             const double glo = (oJ2 != 0.0) ? sqrt(2.0 * ora / fabs(o.lo.dq)) : 0.0;
             const double ghi = sqrt(2.0 * ora / fabs(o.hi.dq));
             oF = bound_factor * (glo > ghi ? glo : ghi);
             if (!(oF > 0.0 && oF < kInf)) {
               oF = -1.0;
-              rdone = orc;
-              fl |= CMC_ST_NUMERIC;
+              fl |= CMC_ST_NUMERIC;  // finished at the orbit's centre, below
             }
           }
           if (oF > 0.0) {
@@ -864,26 +982,10 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap, int corr,
             j = 0;
             if (LF) lg = load_lfsr(A.s.rng, mine);
           } else {
-            // a point orbit (or no usable bound): the new radius is rdone,
-            // with no trial
-            const double rn = rdone + 0.0;
-            const int64_t kn = interval_in(ix, ictl, rn, o.lo.kmin, o.hi.kmax);
-            const double phn = phi_in(lv, ms, kn, rn);
-            const double qn =
-                2.0 * o.lo.E - 2.0 * phn - (oJ2 == 0.0 ? 0.0 : oJ2 / (rn * rn));
-            if (corr) pn[mine] = phn;
-            U4 ws;
-            if (LF) {
-              Lfsr g = load_lfsr(A.s.rng, mine);
-              ws = lfsr_block(g);
-              put_lfsr<TO_STAGE>(A, mine, g);
-            } else {
-              ws = philox(id[mine], step, kSign, 0u, seed);
-            }
-            double vrn, vtn;
-            finish(rn, qn, oJ, oJ2, ws.x, vrn, vtn, fl);
-            emit<TO_STAGE>(mine, rn, vrn, vtn, m[mine], id[mine],
-                           rindex_last_le(ix, ictl, rn) + 1, r_new, vr, vt, stage, keys, bkey);
+            // a point orbit (or no usable bound): finished without trials
+            // after the loop
+            const uint32_t slot = atomicAdd(&n_deferred[wv], 1u);
+            deferred[wv][slot] = static_cast<uint32_t>(mine - wave * chunk);
           }
         }
       }
@@ -973,6 +1075,35 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap, int corr,
         busy = false;
       }
     }
+  }
+  // the deferred stars: the new radius is rdone (r_min, or the orbit's
+  // centre when the bound is unusable), with no trial
+  __builtin_amdgcn_wave_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  const uint32_t nd = n_deferred[wv];
+  for (uint32_t d = lane; d < nd; d += 64) {
+    const int64_t mine = wave * chunk + deferred[wv][d];
+    const OrbitRec o = orec[mine];
+    const double oJ = o.hi.J, oJ2 = oJ * oJ;
+    const double ora = 0.5 * (o.hi.rmax - o.lo.rmin);
+    const double rdone = ora > 0.0 ? 0.5 * (o.hi.rmax + o.lo.rmin) : o.lo.rmin;
+    const double rn = rdone + 0.0;
+    const int64_t kn = interval_in(ix, ictl, rn, o.lo.kmin, o.hi.kmax);
+    const double phn = phi_in(lv, ms, kn, rn);
+    const double qn = 2.0 * o.lo.E - 2.0 * phn - (oJ2 == 0.0 ? 0.0 : oJ2 / (rn * rn));
+    if (corr) pn[mine] = phn;
+    U4 ws;
+    if (LF) {
+      Lfsr g = load_lfsr(A.s.rng, mine);
+      ws = lfsr_block(g);
+      put_lfsr<TO_STAGE>(A, mine, g);
+    } else {
+      ws = philox(id[mine], step, kSign, 0u, seed);
+    }
+    double vrn, vtn;
+    finish(rn, qn, oJ, oJ2, ws.x, vrn, vtn, fl);
+    emit<TO_STAGE>(mine, rn, vrn, vtn, m[mine], id[mine], rindex_last_le(ix, ictl, rn) + 1,
+                   r_new, vr, vt, stage, keys, bkey);
   }
   or_status(sc, fl);
   const double t_tr = block_sum<NT>(static_cast<double>(c_tr), shd);
