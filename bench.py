@@ -61,22 +61,51 @@ def alg_bytes(m_bytes: int) -> dict:
     }
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+CPU_SAMPLE_N = 3_000_000  # oracle sample: about 5 s per serial step on the GPU box's host
+
+
 def cpu_baseline(wl: dict) -> dict:
-    """The oracle as it stands, one step of a 10^6-star sample of the same
-    workload (same generator, mass spectrum and Coulomb logarithm), serial."""
+    """The oracle as it stands: one step of a sample of the same workload
+    (same generator, mass spectrum and Coulomb logarithm) timed on the host,
+    serial (the parity reference, one core) and in its OpenMP build on every
+    core (same results bit for bit: per-star and per-pair loops in parallel,
+    the scan, the sort and every sum serial)."""
+    import numpy as np
     import oracle
 
-    n = min(wl["n"], 1_000_000)
+    n = min(wl["n"], CPU_SAMPLE_N)
     st = oracle.plummer(n, wl["seed"], wl["mass_spectrum"])
     if wl["m_f32"]:
-        import numpy as np
         st.m = st.m.astype(np.float32).astype(np.float64)
     t0 = time.perf_counter()
-    new, info = oracle.step(st, wl["seed"], 0, wl["gamma"])
+    ser, _ = oracle.step(st, wl["seed"], 0, wl["gamma"])
     el = time.perf_counter() - t0
+    with oracle.threads() as L:
+        threads = int(L.ora_threads())
+        t0 = time.perf_counter()
+        par, _ = oracle.step(st, wl["seed"], 0, wl["gamma"])
+        el_p = time.perf_counter() - t0
+    same = bool(np.array_equal(ser.r, par.r) and np.array_equal(ser.id, par.id))
     return {"value": n / el, "unit": "star-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"1 step of a {n}-star sample of the workload, serial FP64 C oracle, "
-                      f"{el:.2f} s"}
+                      f"{el:.2f} s",
+            "cpu": cpu_model(),
+            "all_cores": {"value": n / el_p, "cores": threads, "seconds": el_p,
+                          "same_result_as_serial": same,
+                          "note": "OpenMP build of the oracle: the per-star and per-pair "
+                                  "loops on every core; potential scan, sort and sums serial"}}
 
 
 def main() -> int:
@@ -90,6 +119,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-other", action="store_true",
                     help="skip the run of the other precision form")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the N = 1e6 and ensemble legs of the default run")
     ap.add_argument("--uncorrected", action="store_true",
                     help="core-collapse workload: run without the energy correction")
     ap.add_argument("--energy-corr", action="store_true",
@@ -220,6 +251,16 @@ def main() -> int:
                                   "ms_per_step": run_o["ms_per_step"],
                                   "calls": run_o["calls"],
                                   "phases_ms": run_o["phases_ms"], "final": run_o["final"]}
+    out["launch_table"] = tune_entry(P, wl["n"])
+    if not args.no_legs:
+        # the other metric point (N = 1e6) and the batched ensemble
+        out["legs"] = {
+            "plummer_n1e6_equal_mass": point_leg(P, EventSet, "plummer_n1e6_equal_mass", K,
+                                                 args.warmup),
+            "ensemble_64_plummer_king_w6": ensemble_leg(
+                P, WORKLOADS["ensemble_64_plummer_king_w6"],
+                WORKLOADS["ensemble_64_plummer_king_w6"]["precision"], K, args.warmup),
+        }
     if not args.no_cpu_baseline:
         print("# timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)
@@ -244,10 +285,12 @@ def ensemble_specs(P, wl) -> list:
             for c in range(k)]
 
 
-def ensemble_bench(P, args, wl, precision) -> int:
+def ensemble_leg(P, wl, precision, K, warmup, drift_steps=50) -> dict:
     """The ensemble advanced by one captured graph per step (device step
     counter), against the same clusters stepped one by one with the
-    single-cluster call."""
+    single-cluster call in FP64; then drift_steps corrected steps of each
+    form from the same initial models, with each cluster's relative energy
+    change (T + W after the last pending correction) in both forms."""
     import numpy as np
     import torch
     prec = P.CMC_FP64 if precision == "fp64" else P.CMC_MIXED
@@ -256,11 +299,10 @@ def ensemble_bench(P, args, wl, precision) -> int:
     ens.init()
     params = P.Params(precision=prec)
     g = ens.capture(params)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         g.replay()
     torch.cuda.synchronize()
     n0 = sum(cl.n for cl in ens.clusters)
-    K = args.steps
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -274,46 +316,120 @@ def ensemble_bench(P, args, wl, precision) -> int:
     n1 = sum(cl.n for cl in ens.clusters)
     updates = K * 0.5 * (n0 + n1)  # escapers leave a few stars per step
     stats = [cl.scalars() for cl in ens.clusters]
-    # the same clusters, one single-cluster call each per step
+    del g
+    print(f"# ensemble {precision}: {el / K * 1e3:.3f} ms/step (graph replays)",
+          file=sys.stderr, flush=True)
+
+    def loop(prec_loop, steps, first, corr=0):
+        for k in range(first, first + steps):
+            for cl, sp in zip(ens.clusters, specs):
+                P.cmc_step(cl, P.Params(seed=sp["seed"], gamma=sp["gamma"], step=k,
+                                        precision=prec_loop, energy_corr=corr))
+
+    # the same clusters, one single-cluster FP64 call each per step
     ens.init()
-    for k in range(args.warmup):
-        for cl, sp in zip(ens.clusters, specs):
-            P.cmc_step(cl, P.Params(seed=sp["seed"], gamma=sp["gamma"], step=k, precision=prec))
+    loop(P.CMC_FP64, warmup, 0)
     torch.cuda.synchronize()
     m0 = sum(cl.n for cl in ens.clusters)
     t1 = time.perf_counter()
-    for k in range(K):
-        for cl, sp in zip(ens.clusters, specs):
-            P.cmc_step(cl, P.Params(seed=sp["seed"], gamma=sp["gamma"], step=args.warmup + k,
-                                    precision=prec))
+    loop(P.CMC_FP64, K, warmup)
     torch.cuda.synchronize()
     el_loop = time.perf_counter() - t1
     m1 = sum(cl.n for cl in ens.clusters)
-    loop_updates = K * 0.5 * (m0 + m1)
+    print(f"# per-cluster FP64 loop: {el_loop / K * 1e3:.3f} ms/step",
+          file=sys.stderr, flush=True)
+
+    def energies():
+        ens.potential(P.CMC_FP64)
+        ens.energy_correction()
+        return np.array([d["E"] for d in ens.diagnostics()])
+
+    # drift: the batched form in its precision against the FP64 loop
+    ens.init()
+    E0 = energies()
+    gc = ens.capture(P.Params(precision=prec, energy_corr=1))
+    for _ in range(drift_steps):
+        gc.replay()
+    torch.cuda.synchronize()
+    del gc
+    d_b = (energies() - E0) / np.abs(E0)
+    ens.init()
+    loop(P.CMC_FP64, drift_steps, 0, corr=1)
+    d_f = (energies() - E0) / np.abs(E0)
+    diff = np.abs(d_b - d_f)
+    return {
+        "value": updates / el,
+        "ms_per_step": el / K * 1e3,
+        "gpu_ms_per_step": gpu_ms,
+        "stars": n0,
+        "clusters": len(specs),
+        "n_min": min(sp["n"] for sp in specs), "n_max": max(sp["n"] for sp in specs),
+        "precision": precision,
+        "launch_table": tune_entry(P, sum(cl.cap for cl in ens.clusters)),
+        "per_cluster_fp64_calls": {"value": K * 0.5 * (m0 + m1) / el_loop,
+                                   "ms_per_step": el_loop / K * 1e3},
+        "drift": {"steps": drift_steps, "energy_corr": True,
+                  "batched_rel_dE_max": float(np.abs(d_b).max()),
+                  "fp64_loop_rel_dE_max": float(np.abs(d_f).max()),
+                  "abs_difference_max": float(diff.max()),
+                  "abs_difference_median": float(np.median(diff))},
+        "final": {"n": n1, "status_or": int(np.bitwise_or.reduce([s["status"] for s in stats])),
+                  "dt_min": min(s["dt"] for s in stats), "dt_max": max(s["dt"] for s in stats)},
+    }
+
+
+def ensemble_bench(P, args, wl, precision) -> int:
+    leg = ensemble_leg(P, wl, precision, args.steps, args.warmup)
     out = {
         "metric": METRIC,
-        "value": updates / el,
+        "value": leg["value"],
         "unit": "star-updates/s",
         "n_gpus": 1,
-        "steps": K,
+        "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": el / K * 1e3,
+        "ms_per_step": leg["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "clusters": wl["clusters"], "stars": n0,
-                   "n_min": min(s["n"] for s in specs), "n_max": max(s["n"] for s in specs),
-                   "precision": precision, "w0": wl["w0"], "gamma": wl["gamma"],
-                   "seed": wl["seed"], "graph": True},
-        "gpu_ms_per_step": gpu_ms,
-        "per_cluster_calls": {"value": loop_updates / el_loop, "ms_per_step": el_loop / K * 1e3},
-        "final": {"n": n1, "status_or": int(np.bitwise_or.reduce([s["status"] for s in stats])),
-                  "dt_min": min(s["dt"] for s in stats), "dt_max": max(s["dt"] for s in stats)},
+        "config": {"workload": args.workload, "clusters": wl["clusters"], "stars": leg["stars"],
+                   "n_min": leg["n_min"], "n_max": leg["n_max"], "precision": precision,
+                   "w0": wl["w0"], "gamma": wl["gamma"], "seed": wl["seed"], "graph": True},
+        **{k: leg[k] for k in ("gpu_ms_per_step", "launch_table", "per_cluster_fp64_calls",
+                               "drift", "final")},
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def tune_entry(P, cap: int) -> dict:
+    """The launch-table entry the library uses for a capacity."""
+    from paper_1206_5878_amd import tune
+    return tune.get(cap)
+
+
+def point_leg(P, EventSet, name: str, K: int, warmup: int) -> dict:
+    """One more single-cluster workload: its precision and the other, each as
+    plain calls (with phases) and graph replays, with the phase roofline."""
+    wl = WORKLOADS[name]
+    precision = wl["precision"]
+    other = "fp64" if precision == "mixed" else "mixed"
+    run = timed_run(P, EventSet, wl, precision, K, warmup)
+    run_o = timed_run(P, EventSet, wl, other, K, warmup)
+    ab = alg_bytes(4 if wl["m_f32"] else 8)
+    step_bytes = sum(ab.values())
+    return {"workload": name, "n": wl["n"], "precision": precision,
+            "value": run["value"], "ms_per_step": run["ms_per_step"],
+            "calls": run["calls"], "phases_ms": run["phases_ms"],
+            "launch_table": tune_entry(P, wl["n"]),
+            "step_roofline": {"alg_bytes_per_star": step_bytes,
+                              "achieved_GBs": run["value"] * step_bytes / 1e9,
+                              "frac": run["value"] * step_bytes / 1e9 / HBM_PEAK_GBS},
+            "other_precision": {"precision": other, "value": run_o["value"],
+                                "ms_per_step": run_o["ms_per_step"],
+                                "phases_ms": run_o["phases_ms"]},
+            "final": run["final"]}
 
 
 LFSR_SEED = [0x12345678, 0x9ABCDEF0, 0x0FEDCBA9, 0x87654321]
