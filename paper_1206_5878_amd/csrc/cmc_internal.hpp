@@ -348,6 +348,8 @@ constexpr int kTopBytes = 52 * 1024;
 constexpr int kTopEntries = kTopBytes / 16;  // LDS slots of 16 bytes, padding included
 __host__ __device__ inline int64_t top_padded(int64_t len) { return len + (len >> 3) + 1; }
 constexpr int kQueryTile = 8192;             // stars per tile of the search sort
+constexpr int kQuerySearchBlock = 256;       // threads of the sorted-search kernel
+constexpr int kQuerySearchChunk = 1024;      // searches of one group per block of it
 constexpr int kPhiBins = 16384;  // bins of the potential-bound table (orbit.hip)
 // LFSR113 stream seeding (rng.hip): for each component, the 32x32 bit matrix
 // of 2^(80+b) steps for every bit b of a stream index (a base below 2^33
@@ -395,6 +397,7 @@ struct Workspace {
   uint32_t *oq_tot;         // [oq_bins] searches per top sample
   uint32_t *oq_start;       // [oq_bins + 1] first search of each top sample
   uint32_t *oq_chunk;       // [oq_bins + 1] first search block of each top sample
+  uint32_t *oq_bmap;        // [search blocks] the top sample each search block works on
   uint32_t *oq_node;        // [cap] each star's two top samples
   int64_t bkt_bins, bkt_tiles;  // bkt_bins = 0: capacity above kBucketCapMax
   int64_t oq_bins, oq_tiles;    // samples of the level the LDS top ends at; tiles
@@ -508,6 +511,7 @@ inline Workspace layout(int64_t cap, void *base) {
     w.oq_tot = reinterpret_cast<uint32_t *>(take(4 * w.oq_bins));
     w.oq_start = reinterpret_cast<uint32_t *>(take(4 * (w.oq_bins + 1)));
     w.oq_chunk = reinterpret_cast<uint32_t *>(take(4 * (w.oq_bins + 1)));
+    w.oq_bmap = reinterpret_cast<uint32_t *>(take(4 * (w.oq_bins + cdiv(2 * c, kQuerySearchChunk))));
     w.oq_node = reinterpret_cast<uint32_t *>(take(4 * c));
   }
   w.bent = reinterpret_cast<BktEnt *>(w.orec);  // orec is dead once the orbit pass ends
@@ -616,8 +620,6 @@ enum Shape : int {
 };
 constexpr int kBracketThreads = 512;
 constexpr int kRxTile = 4096;         // bucket-index entries per prefix-maximum tile
-constexpr int kQuerySearchBlock = 256; // threads of the sorted-search kernel
-constexpr int kQuerySearchChunk = 1024; // searches of one group per block of it
 __host__ __device__ inline int64_t blocks_of(Shape sh, const Workspace &w, int64_t cap) {
   const int64_t c = cap > 0 ? cap : 1;
   switch (sh) {

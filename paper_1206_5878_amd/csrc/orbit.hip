@@ -718,6 +718,12 @@ __global__ __launch_bounds__(QT) void k_oq_start(Ctx ctx) {
     start[bins] = carry;
     chunk[bins] = ccarry;
   }
+  __syncthreads();
+  // the search blocks' map: block c works on the group s with
+  // chunk[s] <= c < chunk[s + 1]
+  uint32_t *__restrict__ bmap = A.w.oq_bmap;
+  for (int64_t b = threadIdx.x; b < bins; b += QT)
+    for (uint32_t c = chunk[b]; c < chunk[b + 1]; ++c) bmap[c] = static_cast<uint32_t>(b);
 }
 
 // The star pass: what star_start does, then each search to its group at an
@@ -809,13 +815,7 @@ __global__ __launch_bounds__(QS) void k_oq_search(Ctx ctx) {
   const uint32_t *__restrict__ chunk = A.w.oq_chunk;
   const int64_t b = xcd_order(ctx.block(), ctx.nblocks());
   if (b >= static_cast<int64_t>(chunk[bins])) return;  // block-uniform
-  // the group of block b: the last s with chunk[s] <= b
-  int64_t lo = 0, hi = bins;
-  while (hi - lo > 1) {
-    const int64_t mid = lo + ((hi - lo) >> 1);
-    if (static_cast<int64_t>(chunk[mid]) <= b) lo = mid; else hi = mid;
-  }
-  const int64_t node = lo;
+  const int64_t node = A.w.oq_bmap[b];  // the group of block b
   const int64_t q0 = A.w.oq_start[node] + (b - chunk[node]) * int64_t(kQuerySearchChunk);
   const int64_t qe = A.w.oq_start[node + 1];
   const int64_t q1 = q0 + kQuerySearchChunk < qe ? q0 + kQuerySearchChunk : qe;
