@@ -57,11 +57,13 @@ def core_density_slope(series, rho_c0: float, lo: float = 1e2, hi: float = 1e5) 
 def core_collapse_run(n: int, seed: int = 1, *, gamma: float = 0.11,
                       precision: int = A.CMC_MIXED, energy_corr: bool = True,
                       t_end: float = 30.0, every: int = 10, collapse: float = 1e4,
-                      stop: float = 1e6, max_steps: int = 50_000) -> dict:
+                      stop: float = 1e6, max_steps: int = 50_000,
+                      target: float = 0.03) -> dict:
     """Evolve an equal-mass Plummer sphere of n stars towards core collapse.
 
     energy_corr: each step applies the potential-change energy correction of
-    Sec. 2.1 item 6, which the paper's code applies.  Every `every` steps,
+    Sec. 2.1 item 6, which the paper's code applies.  target: the mean
+    sin^2(beta/2) over pairs that fixes each step's Delta t.  Every `every` steps,
     the potential, the pending correction and the diagnostics are taken:
     t / t_rh, r_c / r_h (r_h the current half-mass radius), rho_c, E, N, the
     step count, the energy budget (E - E0 + the energy escapers took) / |E0|,
@@ -79,7 +81,7 @@ def core_collapse_run(n: int, seed: int = 1, *, gamma: float = 0.11,
     d0 = cmc_diagnostics(cl)
     trh = half_mass_relaxation_time(n, float(d0["r50"]))
     rho0 = float(d0["rho_c"])
-    g = cl.capture(Params(seed=seed, gamma=gamma, precision=precision,
+    g = cl.capture(Params(seed=seed, gamma=gamma, precision=precision, target=target,
                           energy_corr=1 if energy_corr else 0))
     dev = cl.sc.device
     # scalars copied after each step: dt, e_esc (f64 bits), corr_skipped
