@@ -12,6 +12,7 @@ namespace cmc {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kInf = __builtin_inf();
+constexpr float kInfF = __builtin_inff();
 
 // Philox counter word 2: what a draw is for.
 enum : uint32_t {
@@ -286,6 +287,12 @@ struct RIndexCtl {
   uint64_t lo, hi;  // bits of r_0 and r_(n-1)
   uint32_t shift, n;
 };
+// Buckets [b0, b1) of the index that all take the value k.
+struct alignas(16) RxRange {
+  uint32_t b0, b1, k, pad;
+};
+constexpr int kRxShort = 32;     // bucket ranges one thread fills itself
+constexpr int kRxPiece = 16384;  // longest range one block of the long-range pass fills
 struct RIndex {
   const double *r;         // the sorted radii
   const uint32_t *start;   // [nb + 1]
@@ -302,7 +309,11 @@ __device__ __forceinline__ int64_t rindex_last_le(const RIndex &ix, const RIndex
   if (kx < c.lo) return -1;
   if (kx >= c.hi) return static_cast<int64_t>(c.n) - 1;
   const uint64_t b = (kx - c.lo) >> c.shift;
+  // (the bounds only matter for a table that was not sorted)
   int64_t lo = ix.start[b], hi = ix.start[b + 1];
+  const int64_t n = static_cast<int64_t>(c.n);
+  lo = lo < n ? lo : n;
+  hi = hi < n ? hi : n;
   // r_k <= x for k < lo, r_k > x for k >= hi: the answer is the last k in
   // [lo - 1, hi - 1] with r_k <= x; halve long ranges, then scan
   while (hi - lo > 16) {
@@ -376,7 +387,8 @@ struct Workspace {
   double *dt_state;         // [32]
   double *red_part;         // [8 * star_blocks]  generic per-block partials
   uint32_t *rx_start;       // [rx_nb + 1] radial index buckets
-  uint32_t *rx_tile;        // [cdiv(rx_nb + 1, 4096)] prefix-maximum tiles
+  RxRange *rx_long;         // [rx_long_cap] bucket ranges too long for one thread
+  uint32_t *rx_nlong;       // [1] ranges in rx_long
   RIndexCtl *rx_ctl;        // [1]
   double *king;             // [kKingTab] King model profile (initial model only)
   double *phib;             // [kPhiBins + 1] Phi at the bound table's edge radii
@@ -405,6 +417,7 @@ struct Workspace {
   // built-in defaults)
   int32_t sorted, bracket_blocks, trial_chunk;
   int64_t rx_nb;
+  int64_t rx_long_cap;
   int rx_lg_nb;
   int64_t sort_tiles, pot_tiles, pair_blocks, star_blocks;
   size_t bytes;
@@ -491,7 +504,11 @@ inline Workspace layout(int64_t cap, void *base) {
   while ((int64_t(1) << w.rx_lg_nb) < c + 1) ++w.rx_lg_nb;
   w.rx_nb = int64_t(1) << w.rx_lg_nb;
   w.rx_start = reinterpret_cast<uint32_t *>(take(4 * (w.rx_nb + 1)));
-  w.rx_tile = reinterpret_cast<uint32_t *>(take(4 * cdiv(w.rx_nb + 1, 4096)));
+  // ranges longer than kRxShort are disjoint, and none is longer than
+  // kRxPiece after the split: at most this many pieces
+  w.rx_long_cap = cdiv(w.rx_nb + 1, kRxShort + 1) + cdiv(w.rx_nb + 1, kRxPiece) + 1;
+  w.rx_long = reinterpret_cast<RxRange *>(take(sizeof(RxRange) * w.rx_long_cap));
+  w.rx_nlong = reinterpret_cast<uint32_t *>(take(4));
   w.rx_ctl = reinterpret_cast<RIndexCtl *>(take(sizeof(RIndexCtl)));
   w.king = reinterpret_cast<double *>(take(8 * kKingTab));
   w.phib = reinterpret_cast<double *>(take(8 * (kPhiBins + 1)));
@@ -607,8 +624,8 @@ enum Shape : int {
   kShDigit,     // one block per radix digit
   kShBracket,   // resident blocks of the bracket kernel
   kShTrials,    // wavefront chunks of the trial kernel
-  kShRxClear,   // grid-stride clear of the bucket index
-  kShRxTile,    // prefix-maximum tiles of the bucket index
+  kShRxFill,    // one thread per star (at least one), fills the bucket index
+  kShRxLong,    // grid-stride over the bucket index's long ranges
   kShDiag,      // grid-stride diagnostics partials
   kShBktTile,   // histogram and scatter tiles of the step's sort
   kShBktGroup,  // groups of 64 buckets
@@ -619,7 +636,6 @@ enum Shape : int {
   kShapes
 };
 constexpr int kBracketThreads = 512;
-constexpr int kRxTile = 4096;         // bucket-index entries per prefix-maximum tile
 __host__ __device__ inline int64_t blocks_of(Shape sh, const Workspace &w, int64_t cap) {
   const int64_t c = cap > 0 ? cap : 1;
   switch (sh) {
@@ -636,11 +652,11 @@ __host__ __device__ inline int64_t blocks_of(Shape sh, const Workspace &w, int64
       return b < w.bracket_blocks ? b : w.bracket_blocks;
     }
     case kShTrials: return cdiv(c, int64_t(w.trial_chunk) * (kBlock / 64));
-    case kShRxClear: {
-      const int64_t b = cdiv(w.rx_nb + 1, kBlock);
-      return b < 4096 ? b : 4096;
+    case kShRxFill: return w.star_blocks;
+    case kShRxLong: {
+      const int64_t b = cdiv(w.rx_nb + 1, kRxPiece);
+      return b < 1024 ? b : 1024;
     }
-    case kShRxTile: return cdiv(w.rx_nb + 1, kRxTile);
     case kShDiag: return w.star_blocks < kRedBlocks ? w.star_blocks : kRedBlocks;
     case kShBktTile: return w.bkt_bins ? w.bkt_tiles : 1;
     case kShBktGroup: return w.bkt_bins ? cdiv(w.bkt_bins, 64) : 1;

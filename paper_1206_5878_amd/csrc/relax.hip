@@ -146,7 +146,16 @@ __global__ __launch_bounds__(NT) void k_pair_tp(Ctx ctx, uint32_t step_arg) {
     const U4 w = pair_block<LF>(A, 2 * p, step, false);
     const PairGeo g = pair_geometry<MT, MIXED>(p, n, r, m, vr, vt, w, coulomb_log(gamma, n));
     if (g.wm > 0.0) {
-      tp_out[p] = g.tp;
+      // what the Newton evaluations need of t_p: beta = (pi/2) sqrt(dt) u
+      // with u = t_p^-1/2 (+inf for t_p = 0, 0 for t_p = inf); FP32 in the
+      // mixed form, whose t_p is an FP32 value
+      if (MIXED) {
+        const float tf = static_cast<float>(g.tp);
+        reinterpret_cast<float *>(tp_out)[p] =
+            tf == 0.0f ? kInfF : (isinf(tf) ? 0.0f : 1.0f / sqrtf(tf));
+      } else {
+        tp_out[p] = g.tp == 0.0 ? kInf : (isinf(g.tp) ? 0.0 : 1.0 / sqrt(g.tp));
+      }
       v[0] = 1.0;
       if (g.tp == 0.0)
         v[1] = 1.0;
@@ -154,8 +163,10 @@ __global__ __launch_bounds__(NT) void k_pair_tp(Ctx ctx, uint32_t step_arg) {
         v[2] = 1.0;
       else if (cold)
         v[3] = log(g.tp);
+    } else if (MIXED) {
+      reinterpret_cast<float *>(tp_out)[p] = -1.0f;  // no relative motion: not counted
     } else {
-      tp_out[p] = -1.0;  // no relative motion: not counted
+      tp_out[p] = -1.0;
     }
   }
   // the four block sums through one LDS exchange (wave order, then waves)
@@ -220,37 +231,55 @@ __global__ __launch_bounds__(IT) void k_dt_init(Ctx ctx, double target) {
   }
 }
 
-// One Newton evaluation: block partials of sum sin^2(beta/2) and of
-// d/dx sin^2(beta/2) = (1/4) beta sin(beta) (beta < pi) at dt = exp(x).
+// sin^2(beta/2) and its derivative d/dx = (1/4) beta sin(beta) (beta < pi) for
+// one pair, beta = min(pi, c u) with c = (pi/2) sqrt(dt) > 0 (u < 0: a pair
+// that is not counted).
+template <bool MIXED>
+__device__ __forceinline__ void dt_terms(double u, double c, double &h, double &d) {
+  if (!(u >= 0.0)) return;
+  const double bu = isinf(u) ? kPi : c * u;
+  const double b = bu < kPi ? bu : kPi;
+  if (MIXED) {  // per-pair terms in FP32, sums in FP64
+    const float bf = static_cast<float>(b);
+    float sf, cf;
+    sincosf(0.5f * bf, &sf, &cf);
+    h += static_cast<double>(sf * sf);
+    if (b < kPi) d += static_cast<double>(0.5f * bf * sf * cf);
+  } else {
+    double sn, cs;
+    sincos(0.5 * b, &sn, &cs);
+    h += sn * sn;
+    if (b < kPi) d += 0.5 * b * sn * cs;
+  }
+}
+
+// One Newton evaluation: block partials of sum sin^2(beta/2) and of its
+// derivative at dt = exp(x), from each pair's t_p^-1/2.  Each thread keeps
+// four loads in flight and adds its pairs in grid-stride order.
 template <class Ctx, bool MIXED>
 __global__ __launch_bounds__(NT) void k_dt_eval(Ctx ctx) {
   __shared__ double sh[NT / 64];
   const ClusterArgs &A = ctx.args();
-  const double *__restrict__ tp = A.w.pair_tp;
   const double *__restrict__ st = A.w.dt_state;
   double *__restrict__ part = A.w.red_part;
   if (st[kDone] != 0.0) return;
   const int64_t np = A.s.sc->n / 2;
-  const double dt = exp(st[kX]);
+  const double c = 0.5 * kPi * sqrt(exp(st[kX]));
   const int64_t blk = ctx.block();
+  const int64_t stride = ctx.nblocks() * NT;
   double h = 0.0, d = 0.0;
-  for (int64_t p = blk * NT + threadIdx.x; p < np; p += ctx.nblocks() * NT) {
-    const double t = tp[p];
-    if (t >= 0.0) {
-      const double b = beta_of(t, dt);
-      if (MIXED) {  // per-pair terms in FP32, sums in FP64
-        const float bf = static_cast<float>(b);
-        float sf, cf;
-        sincosf(0.5f * bf, &sf, &cf);
-        h += static_cast<double>(sf * sf);
-        if (b < kPi) d += static_cast<double>(0.5f * bf * sf * cf);
-      } else {
-        double s, c;
-        sincos(0.5 * b, &s, &c);
-        h += s * s;
-        if (b < kPi) d += 0.5 * b * s * c;  // (1/4) b sin b
-      }
+  for (int64_t p0 = blk * NT + threadIdx.x; p0 < np; p0 += 4 * stride) {
+    double t[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t p = p0 + q * stride;
+      t[q] = -1.0;
+      if (p < np)
+        t[q] = MIXED ? static_cast<double>(reinterpret_cast<const float *>(A.w.pair_tp)[p])
+                     : A.w.pair_tp[p];
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dt_terms<MIXED>(t[q], c, h, d);
   }
   h = block_sum<NT>(h, sh);
   d = block_sum<NT>(d, sh);

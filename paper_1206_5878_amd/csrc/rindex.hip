@@ -3,10 +3,13 @@
 // -(M_k / x + S_k) of Sec. 2.1 step 1 at a trial radius of step 5) costs one
 // bucket read and one short scan instead of a search over the whole table.
 //
-// Built in three streaming passes: clear start[]; the last star of every
-// non-empty bucket b writes its index + 1 into start[b + 1]; an inclusive
-// prefix maximum over start[] then fills every bucket with the number of
-// stars in the buckets before it (empty buckets included).
+// start[b] = the number of stars in buckets below b.  With b_k the bucket of
+// r_k, that is k for every bucket b_(k-1) < b <= b_k: star k's thread writes
+// its own range, so every entry is written once, in one pass over the radii
+// with no clear and no scan.  Ranges longer than kRxShort (sparse radii,
+// where a gap spans many buckets) go to a list, in pieces of at most
+// kRxPiece, which a second pass fills block by block; that pass also fills
+// the buckets above the last star's with n.
 #include <algorithm>
 
 #include "cmc_internal.hpp"
@@ -33,6 +36,7 @@ __global__ void k_rindex_prep(Ctx ctx) {
     c.shift = static_cast<uint32_t>(bits > lg_nb ? bits - lg_nb : 0);
   }
   *ctl = c;
+  *A.w.rx_nlong = 0u;
 }
 
 // Bucket of a table radius; clamped to [lo, hi] so that a table that is not
@@ -43,152 +47,62 @@ __device__ __forceinline__ int64_t bucket(double x, const RIndexCtl &c) {
   return static_cast<int64_t>((k - c.lo) >> c.shift);
 }
 
-constexpr int kScanTile = NT * 16;
-static_assert(kScanTile == kRxTile, "prefix-maximum tile");
-
-template <class Ctx>
-__global__ __launch_bounds__(NT) void k_rindex_clear(Ctx ctx) {
-  const ClusterArgs &A = ctx.args();
-  uint32_t *__restrict__ start = A.w.rx_start;
-  const int64_t len = A.w.rx_nb + 1;
-  for (int64_t b = ctx.block() * NT + threadIdx.x; b < len; b += ctx.nblocks() * NT)
-    start[b] = 0u;
+// Bucket of the last star (its radius's bits are hi); -1 for no star.
+__device__ __forceinline__ int64_t last_bucket(const RIndexCtl &c) {
+  return c.n > 0 ? static_cast<int64_t>((c.hi - c.lo) >> c.shift) : -1;
 }
 
 template <class Ctx>
-__global__ __launch_bounds__(NT) void k_rindex_ends(Ctx ctx) {
+__global__ __launch_bounds__(NT) void k_rindex_fill(Ctx ctx) {
   const ClusterArgs &A = ctx.args();
   const double *__restrict__ r = A.s.r;
   uint32_t *__restrict__ start = A.w.rx_start;
   const RIndexCtl c = *A.w.rx_ctl;
   const int64_t n = c.n;
-  for (int64_t k = ctx.block() * NT + threadIdx.x; k < n; k += ctx.nblocks() * NT) {
-    const int64_t bk = bucket(r[k], c);
-    if (k == n - 1 || bucket(r[k + 1], c) != bk) start[bk + 1] = static_cast<uint32_t>(k + 1);
+  const int64_t k = ctx.block() * NT + threadIdx.x;
+  // buckets [b0, b1) take k
+  int64_t b0 = 0, b1 = 0;
+  if (k < n) {
+    b0 = k > 0 ? bucket(r[k - 1], c) + 1 : 0;
+    b1 = bucket(r[k], c) + 1;
   }
-}
-
-__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) {
-  const int l = threadIdx.x & 63;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t u = __shfl_up(v, o, 64);
-    if (l >= o) v = u > v ? u : v;
-  }
-  return v;
-}
-
-// Exclusive prefix maximum over the block's threads (0 for thread 0).
-__device__ __forceinline__ uint32_t block_excl_max(uint32_t v, uint32_t *sh) {
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint32_t inc = wave_incl_max(v);
-  uint32_t exc = __shfl_up(inc, 1, 64);
-  if (l == 0) exc = 0u;
-  if (l == 63) sh[w] = inc;
-  __syncthreads();
+  const int64_t len = b1 - b0;
+  if (len > 0 && len <= kRxShort)
+    for (int64_t b = b0; b < b1; ++b) start[b] = static_cast<uint32_t>(k);
+  // the long ranges: one list slot per piece, one atomic per wavefront
+  const uint32_t pieces = len > kRxShort ? static_cast<uint32_t>(cdiv(len, kRxPiece)) : 0u;
+  if (__ballot(pieces != 0u) == 0ull) return;  // wave-uniform
+  const uint32_t incl = wave_incl_scan(pieces);
+  const uint32_t total = __shfl(incl, 63, 64);
   uint32_t base = 0u;
-#pragma unroll
-  for (int i = 0; i < NT / 64; ++i)
-    if (i < w) base = sh[i] > base ? sh[i] : base;
-  __syncthreads();
-  return base > exc ? base : exc;
-}
-
-template <class Ctx>
-__global__ __launch_bounds__(NT) void k_rindex_tilemax(Ctx ctx) {
-  __shared__ uint32_t sh[NT / 64];
-  const ClusterArgs &A = ctx.args();
-  const uint32_t *__restrict__ start = A.w.rx_start;
-  const int64_t len = A.w.rx_nb + 1;
-  uint32_t *__restrict__ tmax = A.w.rx_tile;
-  const int64_t blk = ctx.block();
-  const int64_t base = blk * kScanTile;
-  uint32_t v = 0u;
-  for (int j = 0; j < 16; ++j) {
-    const int64_t b = base + j * NT + threadIdx.x;
-    if (b < len) v = start[b] > v ? start[b] : v;
-  }
-  v = wave_incl_max(v);
-  if ((threadIdx.x & 63) == 63) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t m = 0u;
-    for (int i = 0; i < NT / 64; ++i) m = sh[i] > m ? sh[i] : m;
-    tmax[blk] = m;
+  if ((threadIdx.x & 63) == 63) base = atomicAdd(A.w.rx_nlong, total);
+  base = __shfl(base, 63, 64);
+  const int64_t e0 = static_cast<int64_t>(base) + (incl - pieces);
+  for (uint32_t q = 0; q < pieces && e0 + q < A.w.rx_long_cap; ++q) {
+    const int64_t a = b0 + static_cast<int64_t>(q) * kRxPiece;
+    const int64_t e = a + kRxPiece < b1 ? a + kRxPiece : b1;
+    A.w.rx_long[e0 + q] =
+        RxRange{static_cast<uint32_t>(a), static_cast<uint32_t>(e), static_cast<uint32_t>(k), 0u};
   }
 }
 
-// One block per cluster: exclusive prefix maximum over the tile maxima, in
-// place.
+// Block j fills the listed ranges j, j + grid, ...; then the grid fills the
+// buckets above the last star's with n.
 template <class Ctx>
-__global__ __launch_bounds__(NT) void k_rindex_tilescan(Ctx ctx) {
-  __shared__ uint32_t sh[NT / 64];
+__global__ __launch_bounds__(NT) void k_rindex_long(Ctx ctx) {
   const ClusterArgs &A = ctx.args();
-  uint32_t *__restrict__ tmax = A.w.rx_tile;
-  const int64_t tiles = cdiv(A.w.rx_nb + 1, kScanTile);
-  __shared__ uint32_t blk;
-  uint32_t carry = 0u;
-  for (int64_t t0 = 0; t0 < tiles; t0 += NT) {
-    const int64_t t = t0 + threadIdx.x;
-    const uint32_t v = t < tiles ? tmax[t] : 0u;
-    const uint32_t ex = block_excl_max(v, sh);
-    if (t < tiles) tmax[t] = carry > ex ? carry : ex;
-    if (threadIdx.x == NT - 1) blk = ex > v ? ex : v;
-    __syncthreads();
-    carry = blk > carry ? blk : carry;
-    __syncthreads();
-  }
-}
-
-template <class Ctx>
-__global__ __launch_bounds__(NT) void k_rindex_apply(Ctx ctx) {
-  __shared__ uint32_t sh[NT / 64];
-  const ClusterArgs &A = ctx.args();
+  const RIndexCtl c = *A.w.rx_ctl;
+  const int64_t cnt0 = *A.w.rx_nlong;
+  const int64_t cnt = cnt0 < A.w.rx_long_cap ? cnt0 : A.w.rx_long_cap;
   uint32_t *__restrict__ start = A.w.rx_start;
-  const int64_t len = A.w.rx_nb + 1;
-  const uint32_t *__restrict__ tcarry = A.w.rx_tile;
-  const int64_t blk = ctx.block();
-  const int64_t base = blk * kScanTile + threadIdx.x * 16;
-  // 16 consecutive entries per thread, moved as four 16-byte vectors where
-  // the whole vector is in range (start[] is 256-byte aligned)
-  uint32_t v[16];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t b = base + 4 * q;
-    if (b + 4 <= len) {
-      const uint4 x = *reinterpret_cast<const uint4 *>(start + b);
-      v[4 * q] = x.x;
-      v[4 * q + 1] = x.y;
-      v[4 * q + 2] = x.z;
-      v[4 * q + 3] = x.w;
-    } else {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) v[4 * q + j] = (b + j < len) ? start[b + j] : 0u;
-    }
+  for (int64_t e = ctx.block(); e < cnt; e += ctx.nblocks()) {
+    const RxRange g = A.w.rx_long[e];
+    for (int64_t b = g.b0 + threadIdx.x; b < g.b1; b += NT) start[b] = g.k;
   }
-  uint32_t run = 0u;
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    run = v[j] > run ? v[j] : run;
-    v[j] = run;
-  }
-  uint32_t ex = block_excl_max(run, sh);
-  const uint32_t c = tcarry[blk];
-  ex = c > ex ? c : ex;
-#pragma unroll
-  for (int j = 0; j < 16; ++j) v[j] = ex > v[j] ? ex : v[j];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t b = base + 4 * q;
-    if (b + 4 <= len) {
-      *reinterpret_cast<uint4 *>(start + b) =
-          make_uint4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
-    } else {
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (b + j < len) start[b + j] = v[4 * q + j];
-    }
-  }
+  const uint32_t nn = static_cast<uint32_t>(c.n);
+  for (int64_t b = last_bucket(c) + 1 + ctx.block() * NT + threadIdx.x; b <= A.w.rx_nb;
+       b += ctx.nblocks() * NT)
+    start[b] = nn;
 }
 
 }  // namespace
@@ -196,11 +110,8 @@ __global__ __launch_bounds__(NT) void k_rindex_apply(Ctx ctx) {
 hipError_t launch_rindex(const Target &t, hipStream_t st) {
   return dispatch(t, [&](const auto &l) {
     k_rindex_prep<<<l.grid(kShOne), 1, 0, st>>>(l.ctx(kShOne));
-    k_rindex_clear<<<l.grid(kShRxClear), NT, 0, st>>>(l.ctx(kShRxClear));
-    k_rindex_ends<<<l.grid(kShDiag), NT, 0, st>>>(l.ctx(kShDiag));
-    k_rindex_tilemax<<<l.grid(kShRxTile), NT, 0, st>>>(l.ctx(kShRxTile));
-    k_rindex_tilescan<<<l.grid(kShOne), NT, 0, st>>>(l.ctx(kShOne));
-    k_rindex_apply<<<l.grid(kShRxTile), NT, 0, st>>>(l.ctx(kShRxTile));
+    k_rindex_fill<<<l.grid(kShRxFill), NT, 0, st>>>(l.ctx(kShRxFill));
+    k_rindex_long<<<l.grid(kShRxLong), NT, 0, st>>>(l.ctx(kShRxLong));
     return hipGetLastError();
   });
 }
