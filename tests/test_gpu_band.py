@@ -1,15 +1,18 @@
-"""A free-running FP64 GPU trajectory inside the oracle's seed ensemble.
+"""Free-running FP64 GPU trajectories against the oracle's, as ensembles.
 
 N = 1e5 equal-mass Plummer, ln(0.11 N), 100 steps.  The oracle runs 8
-independent trajectories (initial model and step draws from seeds 2..9)
-and the GPU one more (seed 1).  Every step redraws every orbit, so
+independent trajectories (initial model and step draws from seeds 2..9) and
+the GPU 8 more (seeds 10..17).  Every step redraws every orbit, so
 trajectories decorrelate within a few steps and only their statistics can
-be compared: after steps 10, 20, ..., 100 the GPU's relative energy change
-(E - E0)/|E0|, virial ratio 2T/|W| and 10/50/90 % Lagrange radii must lie
-within the band of the 8 oracle runs, mean +- 5 sample standard deviations
-(times sqrt(1 + 1/8) for a new draw against an estimated mean; |t| > 5 at
-7 degrees of freedom has probability 0.0016).  The paper compares runs the
-same way, by their statistics (Sec. 4.1)."""
+be compared: after steps 10, 20, ..., 100, the relative energy change
+(E - E0)/|E0|, virial ratio 2T/|W| and 10/50/90 % Lagrange radii of the two
+ensembles must have the same mean, within 5 standard errors of the
+difference (Welch's t; |t| > 5 at about 14 degrees of freedom has
+probability 2e-4).  The paper compares runs the same way, by their
+statistics (Sec. 4.1).  The ensembles take their own initial models: one
+model's sampling offset persists through the 100 steps (seed 1's half-mass
+radius stays about 1.6 standard deviations above the mean), so a single
+trajectory against a band would test that draw rather than the step."""
 import threading
 
 import numpy as np
@@ -47,7 +50,21 @@ def oracle_track(ora, seed, out):
     out[seed] = np.array(rows)
 
 
-def test_gpu_trajectory_inside_oracle_seed_band(cmc, ora):
+def gpu_track(cmc, seed):
+    cl = cmc.Cluster(N)
+    cmc.cmc_init_plummer(cl, N, seed, 0)
+    cmc.cmc_potential(cl)
+    e0 = float(cmc.cmc_diagnostics(cl)["E"])
+    rows = []
+    for k in range(STEPS):
+        cmc.cmc_step(cl, cmc.Params(seed=seed, step=k, gamma=GAMMA))
+        if k % 10 == 9:
+            cmc.cmc_potential(cl)
+            rows.append(sample(cmc.cmc_diagnostics(cl), e0))
+    return np.array(rows)
+
+
+def test_gpu_ensemble_matches_oracle_ensemble(cmc, ora):
     seeds = list(range(2, 10))
     out = {}
     # the oracle is plain C behind ctypes, which releases the GIL: the 8
@@ -55,24 +72,16 @@ def test_gpu_trajectory_inside_oracle_seed_band(cmc, ora):
     th = [threading.Thread(target=oracle_track, args=(ora, s, out)) for s in seeds]
     for t in th:
         t.start()
-    cl = cmc.Cluster(N)
-    cmc.cmc_init_plummer(cl, N, 1, 0)
-    cmc.cmc_potential(cl)
-    e0 = float(cmc.cmc_diagnostics(cl)["E"])
-    gpu = []
-    for k in range(STEPS):
-        cmc.cmc_step(cl, cmc.Params(seed=1, step=k, gamma=GAMMA))
-        if k % 10 == 9:
-            cmc.cmc_potential(cl)
-            gpu.append(sample(cmc.cmc_diagnostics(cl), e0))
-    gpu = np.array(gpu)
+    gpu = np.stack([gpu_track(cmc, s) for s in range(10, 18)])   # (runs, samples, keys)
     for t in th:
         t.join()
-    band = np.stack([out[s] for s in seeds])          # (seeds, samples, keys)
-    mean, sd = band.mean(axis=0), band.std(axis=0, ddof=1)
-    z = (gpu - mean) / (sd * np.sqrt(1.0 + 1.0 / len(seeds)))
+    band = np.stack([out[s] for s in seeds])
+    mg, mo = gpu.mean(axis=0), band.mean(axis=0)
+    vg, vo = gpu.var(axis=0, ddof=1), band.var(axis=0, ddof=1)
+    tw = (mg - mo) / np.sqrt(vg / len(gpu) + vo / len(band))
     for j, key in enumerate(KEYS):
-        print(f"{key}: gpu {gpu[-1, j]:.5g}, oracle band {mean[-1, j]:.5g} +- "
-              f"{sd[-1, j]:.2g} (step 100); |z| max {np.abs(z[:, j]).max():.2f}")
-    assert np.all(sd > 0)
-    assert np.abs(z).max() < 5.0, z
+        print(f"{key} (step 100): gpu {mg[-1, j]:.5g} +- {np.sqrt(vg[-1, j]):.2g}, "
+              f"oracle {mo[-1, j]:.5g} +- {np.sqrt(vo[-1, j]):.2g}; |t| max "
+              f"{np.abs(tw[:, j]).max():.2f}")
+    assert np.all(vg > 0) and np.all(vo > 0)
+    assert np.abs(tw).max() < 5.0, tw
