@@ -5,10 +5,15 @@
 // tile sums (forward for M, backward for S), and a per-tile apply that adds
 // the carries to in-tile scans.  A tile is 4 rounds of 256 consecutive stars,
 // thread t holding star t of each round, so every load and store of a wave
-// is one contiguous run; the in-tile scans are block scans per round.  The
-// mixed form forms m / r in FP32; every sum is FP64.  HBM-bound: reads r and
-// m, writes the orbit table ((r, Phi) and (M, S) per star plus the sampled
-// search levels) and, for the standalone call, the state's phi, mcum, ssuf.
+// is one contiguous run; the in-tile scans are block scans per round.
+//
+// Sums: FP64 in the FP64 form.  The mixed form forms m / r in FP32 and sums
+// inside a tile in FP32 with a compensation term (each partial sum an
+// unevaluated pair hi + lo, two-sum on every addition, about 48 significant
+// bits); the tile sums and the carries across tiles are FP64.
+// HBM-bound: reads r and m, writes the orbit table ((r, Phi) and (M, S) per
+// star plus the sampled search levels) and, for the standalone call, the
+// state's phi, mcum, ssuf.
 #include <type_traits>
 
 #include "cmc_internal.hpp"
@@ -19,74 +24,124 @@ namespace {
 constexpr int PT = kBlock;
 constexpr int PJ = kPotTile / PT;  // rounds of PT consecutive stars per tile
 
-// m / r: FP64, or FP32 for the mixed form.
-template <bool MIXED>
-__device__ __forceinline__ double m_over_r(double m, double r) {
-  return MIXED ? static_cast<double>(static_cast<float>(m) / static_cast<float>(r)) : m / r;
+// ---------------------------------------------------------------- accumulators
+// FP64 sums.
+struct D1 {
+  double v;
+};
+__device__ __forceinline__ D1 acc_add(D1 a, D1 b) { return D1{a.v + b.v}; }
+__device__ __forceinline__ D1 acc_of(double x) { return D1{x}; }
+__device__ __forceinline__ double acc_val(D1 a) { return a.v; }
+__device__ __forceinline__ D1 acc_shfl_up(D1 a, int o) { return D1{__shfl_up(a.v, o, 64)}; }
+__device__ __forceinline__ D1 acc_shfl_down(D1 a, int o) { return D1{__shfl_down(a.v, o, 64)}; }
+
+// Compensated FP32 sums: hi + lo, renormalised after every addition
+// (Knuth's two-sum on the leading parts, the trailing parts added).
+struct F2 {
+  float hi, lo;
+};
+__device__ __forceinline__ F2 acc_add(F2 a, F2 b) {
+  const float s = a.hi + b.hi;
+  const float bb = s - a.hi;
+  const float err = (a.hi - (s - bb)) + (b.hi - bb);
+  const float t = err + (a.lo + b.lo);
+  const float h = s + t;
+  return F2{h, t - (h - s)};
+}
+__device__ __forceinline__ F2 acc_of(float x) { return F2{x, 0.0f}; }
+__device__ __forceinline__ double acc_val(F2 a) {
+  return static_cast<double>(a.hi) + static_cast<double>(a.lo);
+}
+__device__ __forceinline__ F2 acc_shfl_up(F2 a, int o) {
+  return F2{__shfl_up(a.hi, o, 64), __shfl_up(a.lo, o, 64)};
+}
+__device__ __forceinline__ F2 acc_shfl_down(F2 a, int o) {
+  return F2{__shfl_down(a.hi, o, 64), __shfl_down(a.lo, o, 64)};
 }
 
-// Over the block, in thread order: the exclusive prefix of a and the exclusive
-// suffix of b, with both block totals, through one LDS exchange.  The sums
-// run in the same order as block_excl_scan and block_excl_suffix.
-__device__ __forceinline__ void block_scan_pair(double a, double b, double *sh, double &pa,
-                                                double &sb, double &ta, double &tb) {
-  constexpr int NW = PT / 64;
+// The form's accumulator and the value type of m / r.
+template <bool MIXED>
+using Acc = std::conditional_t<MIXED, F2, D1>;
+template <bool MIXED>
+using Val = std::conditional_t<MIXED, float, double>;
+
+template <bool MIXED>
+__device__ __forceinline__ Val<MIXED> m_over_r(double m, double r) {
+  if constexpr (MIXED)
+    return static_cast<float>(m) / static_cast<float>(r);
+  else
+    return m / r;
+}
+
+// Over the block, in thread order: the exclusive prefix of a and the
+// exclusive suffix of b, with both block totals, through one LDS exchange.
+template <int NTB, class A>
+__device__ __forceinline__ void block_scan_pair(A a, A b, A *sh, A &pa, A &sb, A &ta, A &tb) {
+  constexpr int NW = NTB / 64;
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const double ia = wave_incl_scan(a);
-  const double ib = wave_incl_suffix(b);
-  double ea = __shfl_up(ia, 1, 64);
-  double eb = __shfl_down(ib, 1, 64);
-  if (l == 0) ea = 0.0;
-  if (l == 63) eb = 0.0;
+  A ia = a, ib = b;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const A ua = acc_shfl_up(ia, o);
+    const A ub = acc_shfl_down(ib, o);
+    if (l >= o) ia = acc_add(ua, ia);
+    if (l + o < 64) ib = acc_add(ib, ub);
+  }
+  A ea = acc_shfl_up(ia, 1);
+  A eb = acc_shfl_down(ib, 1);
+  const A zero = acc_of(Val<std::is_same_v<A, F2>>(0));
+  if (l == 0) ea = zero;
+  if (l == 63) eb = zero;
   if (l == 63) sh[w] = ia;
   if (l == 0) sh[NW + w] = ib;
   __syncthreads();
-  double ba = 0.0, bb = 0.0, sa = 0.0;
+  A ba = zero, bb = zero, sa = zero;
 #pragma unroll
   for (int i = 0; i < NW; ++i) {
-    const double x = sh[i];
-    if (i < w) ba += x;
-    sa += x;
+    const A x = sh[i];
+    if (i < w) ba = acc_add(ba, x);
+    sa = acc_add(sa, x);
   }
-  double sbt = 0.0;
+  A sbt = zero;
 #pragma unroll
   for (int i = NW - 1; i >= 0; --i) {
-    const double y = sh[NW + i];
-    if (i > w) bb += y;
-    sbt += y;
+    const A y = sh[NW + i];
+    if (i > w) bb = acc_add(bb, y);
+    sbt = acc_add(sbt, y);
   }
   __syncthreads();
-  pa = ba + ea;
-  sb = bb + eb;
+  pa = acc_add(ba, ea);
+  sb = acc_add(bb, eb);
   ta = sa;
   tb = sbt;
 }
 
 template <class Ctx, typename MT, bool MIXED>
 __global__ __launch_bounds__(PT) void k_pot_tile_sums(Ctx ctx) {
-  __shared__ double sh[PT / 64];
-  const ClusterArgs &A = ctx.args();
-  const double *__restrict__ r = A.s.r;
-  const MT *__restrict__ m = static_cast<const MT *>(A.s.m);
-  const int64_t n = A.s.sc->n;
-  const int64_t tiles = A.w.pot_tiles;
+  using A = Acc<MIXED>;
+  __shared__ A sh[2 * (PT / 64)];
+  const ClusterArgs &A_ = ctx.args();
+  const double *__restrict__ r = A_.s.r;
+  const MT *__restrict__ m = static_cast<const MT *>(A_.s.m);
+  const int64_t n = A_.s.sc->n;
+  const int64_t tiles = A_.w.pot_tiles;
   const int64_t t = ctx.block();
   const int64_t base = t * kPotTile + threadIdx.x;
-  double sm = 0.0, sq = 0.0;
+  A sm = acc_of(Val<MIXED>(0)), sq = sm;
 #pragma unroll
   for (int j = 0; j < PJ; ++j) {
     const int64_t k = base + j * PT;
     if (k < n) {
       const double mk = load_mass(m, k);
-      sm += mk;
-      sq += m_over_r<MIXED>(mk, r[k]);
+      sm = acc_add(sm, acc_of(static_cast<Val<MIXED>>(mk)));
+      sq = acc_add(sq, acc_of(m_over_r<MIXED>(mk, r[k])));
     }
   }
-  const double tm = block_sum<PT>(sm, sh);
-  const double tq = block_sum<PT>(sq, sh);
+  A pa, sb, tm, tq;
+  block_scan_pair<PT>(sm, sq, sh, pa, sb, tm, tq);
   if (threadIdx.x == 0) {
-    A.w.pot_tsum[t] = tm;
-    A.w.pot_tsum[tiles + t] = tq;
+    A_.w.pot_tsum[t] = acc_val(tm);
+    A_.w.pot_tsum[tiles + t] = acc_val(tq);
   }
 }
 
@@ -159,53 +214,58 @@ __global__ __launch_bounds__(ST) void k_pot_tile_scan(Ctx ctx) {
 // the workspace.
 template <class Ctx, typename MT, bool PUBLIC, bool MIXED, bool TABLE = true>
 __global__ __launch_bounds__(PT) void k_pot_apply(Ctx ctx) {
-  __shared__ double sh[2 * (PT / 64)];
-  const ClusterArgs &A = ctx.args();
-  const double *__restrict__ r = A.s.r;
-  const MT *__restrict__ m = static_cast<const MT *>(A.s.m);
-  const double *__restrict__ carry = A.w.pot_carry;
-  const int64_t n = A.s.sc->n;
-  const int64_t tiles = A.w.pot_tiles;
-  const Levels lv = levels_of(A.w);
+  using A = Acc<MIXED>;
+  __shared__ A sh[2 * (PT / 64)];
+  const ClusterArgs &A_ = ctx.args();
+  const double *__restrict__ r = A_.s.r;
+  const MT *__restrict__ m = static_cast<const MT *>(A_.s.m);
+  const double *__restrict__ carry = A_.w.pot_carry;
+  const int64_t n = A_.s.sc->n;
+  const int64_t tiles = A_.w.pot_tiles;
+  const Levels lv = levels_of(A_.w);
   const int64_t t = ctx.block();
   const int64_t base = t * kPotTile + threadIdx.x;
-  double rr[PJ], mk[PJ], q[PJ];
+  double rr[PJ], mk[PJ];
 #pragma unroll
   for (int j = 0; j < PJ; ++j) {
     const int64_t k = base + j * PT;
     const bool ok = k < n;
     rr[j] = ok ? r[k] : 1.0;
     mk[j] = ok ? load_mass(m, k) : 0.0;
-    q[j] = m_over_r<MIXED>(mk[j], rr[j]);
   }
   // M: inclusive prefix, round by round; S: exclusive suffix inside each
-  // round, then the later rounds' totals and the later tiles' carry
-  double M[PJ], S[PJ], tq[PJ];
-  double cm = carry[t];
+  // round, then the later rounds' totals (the later tiles' carry is added
+  // in FP64 below)
+  A pm[PJ], sq[PJ], tq[PJ];
+  A cm = acc_of(Val<MIXED>(0));
 #pragma unroll
   for (int j = 0; j < PJ; ++j) {
-    double ex, tm;
-    block_scan_pair(mk[j], q[j], sh, ex, S[j], tm, tq[j]);
-    M[j] = cm + (ex + mk[j]);
-    cm += tm;
+    const A mj = acc_of(static_cast<Val<MIXED>>(mk[j]));
+    A ex, tm;
+    block_scan_pair<PT>(mj, acc_of(m_over_r<MIXED>(mk[j], rr[j])), sh, ex, sq[j], tm, tq[j]);
+    pm[j] = acc_add(cm, acc_add(ex, mj));
+    cm = acc_add(cm, tm);
   }
-  double cq = carry[tiles + t];
+  A cs = acc_of(Val<MIXED>(0));
 #pragma unroll
   for (int j = PJ - 1; j >= 0; --j) {
-    S[j] += cq;
-    cq += tq[j];
+    sq[j] = acc_add(sq[j], cs);
+    cs = acc_add(cs, tq[j]);
   }
+  const double cmt = carry[t], cqt = carry[tiles + t];
 #pragma unroll
   for (int j = 0; j < PJ; ++j) {
     const int64_t k = base + j * PT;
     if (k < n) {
-      const double ph = -(M[j] / rr[j] + S[j]);
+      const double M = cmt + acc_val(pm[j]);
+      const double S = cqt + acc_val(sq[j]);
+      const double ph = -(M / rr[j] + S);
       if (PUBLIC) {
-        A.s.mcum[k] = M[j];
-        A.s.ssuf[k] = S[j];
-        A.s.phi[k] = ph;
+        A_.s.mcum[k] = M;
+        A_.s.ssuf[k] = S;
+        A_.s.phi[k] = ph;
       }
-      if (TABLE) put_table(lv, A.w.ms, k, rr[j], ph, M[j], S[j]);
+      if (TABLE) put_table(lv, A_.w.ms, k, rr[j], ph, M, S);
     }
   }
 }
