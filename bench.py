@@ -131,7 +131,7 @@ def main() -> int:
                     help="time plain cmc_step calls only (no per-phase events); for profilers")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB, --steps times "
-                         "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
+                         "(checks the byte formula of the L2 request counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding the "
@@ -627,9 +627,9 @@ def sources_sha256() -> str:
 
 
 def measured_traffic(workload: str, precision: str, phase: str):
-    """HBM bytes per launch of the phase's kernels from the FETCH_SIZE and
-    WRITE_SIZE counter runs recorded under profiles/ (scaled by the copy
-    calibration there), or None when they were taken on other sources."""
+    """HBM-side bytes per launch of the phase's kernels from the L2 request
+    counter runs recorded under profiles/ (request counts by size, checked
+    on a plain copy there), or None when they were taken on other sources."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.txt")
     if not os.path.exists(path):
         return None

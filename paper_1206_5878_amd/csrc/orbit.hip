@@ -1155,10 +1155,12 @@ __global__ __launch_bounds__(FT) void k_orbit_sum(Ctx ctx) {
   const int64_t nb = blocks_of(kShTrials, A.w, A.s.cap);
   cmc_scalars *__restrict__ sc = A.s.sc;
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
   for (int64_t b = threadIdx.x; b < na; b += FT) {
     v[0] += pa[2 * b];
     v[4] += pa[2 * b + 1];
   }
+#pragma unroll 8
   for (int64_t b = threadIdx.x; b < nb; b += FT)
 #pragma unroll
     for (int q = 0; q < 3; ++q) v[1 + q] += pb[3 * b + q];

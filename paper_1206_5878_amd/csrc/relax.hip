@@ -198,6 +198,7 @@ __global__ __launch_bounds__(IT) void k_dt_init(Ctx ctx, double target) {
   double *__restrict__ st = A.w.dt_state;
   cmc_scalars *__restrict__ sc = A.s.sc;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
   for (int64_t b = threadIdx.x; b < nblocks; b += IT)
     for (int q = 0; q < 4; ++q) v[q] += part[4 * b + q];
   for (int q = 0; q < 4; ++q) v[q] = block_sum<IT>(v[q], sh);
