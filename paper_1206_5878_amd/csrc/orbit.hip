@@ -699,6 +699,7 @@ __global__ __launch_bounds__(QT) void k_oq_start(Ctx ctx) {
   const uint32_t *__restrict__ tot = A.w.oq_tot;
   uint32_t *__restrict__ start = A.w.oq_start;
   uint32_t *__restrict__ chunk = A.w.oq_chunk;
+  uint32_t *__restrict__ bmap = A.w.oq_bmap;
   uint32_t carry = 0u, ccarry = 0u;
   for (int64_t b0 = 0; b0 < bins; b0 += QT) {
     const int64_t b = b0 + threadIdx.x;
@@ -710,6 +711,9 @@ __global__ __launch_bounds__(QT) void k_oq_start(Ctx ctx) {
     if (b < bins) {
       start[b] = carry + ex;
       chunk[b] = ccarry + cex;
+      // the search blocks' map: block c works on the group b with
+      // chunk[b] <= c < chunk[b + 1]
+      for (uint32_t c = 0; c < cv; ++c) bmap[ccarry + cex + c] = static_cast<uint32_t>(b);
     }
     carry += all;
     ccarry += call;
@@ -718,12 +722,6 @@ __global__ __launch_bounds__(QT) void k_oq_start(Ctx ctx) {
     start[bins] = carry;
     chunk[bins] = ccarry;
   }
-  __syncthreads();
-  // the search blocks' map: block c works on the group s with
-  // chunk[s] <= c < chunk[s + 1]
-  uint32_t *__restrict__ bmap = A.w.oq_bmap;
-  for (int64_t b = threadIdx.x; b < bins; b += QT)
-    for (uint32_t c = chunk[b]; c < chunk[b + 1]; ++c) bmap[c] = static_cast<uint32_t>(b);
 }
 
 // The star pass: what star_start does, then each search to its group at an
