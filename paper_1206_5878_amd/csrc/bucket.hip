@@ -73,45 +73,16 @@ __global__ __launch_bounds__(HT) void k_bkt_hist(Ctx ctx) {
   for (int b = threadIdx.x; b < bins; b += HT) row[b] = hist[b];
 }
 
-// Block g: bins 64 g .. 64 g + 63, one lane each; the 16 waves split the
-// tiles.  Counts become tile offsets inside the bin; tot gets the bin sums.
+// Block g: bins kBktColGroup g .. kBktColGroup (g + 1) - 1.  Counts become tile
+// offsets inside the bin; tot gets the bin sums.
 template <class Ctx>
 __global__ __launch_bounds__(HT) void k_bkt_colscan(Ctx ctx) {
-  __shared__ uint32_t part[HT / 64][64];
   const ClusterArgs &A = ctx.args();
   const int64_t n = A.s.sc->n;
   const int64_t bins = buckets_of(n) + 1;
-  const int64_t b = ctx.block() * 64 + (threadIdx.x & 63);
-  if (ctx.block() * 64 >= bins) return;
-  const int w = threadIdx.x >> 6;
-  const bool own = b < bins;
-  const int64_t tiles = cdiv(n, kBucketTile);
-  const int64_t per = cdiv(tiles, HT / 64);
-  const int64_t t0 = w * per;
-  const int64_t t1 = t0 + per < tiles ? t0 + per : tiles;
-  const int64_t stride = A.w.bkt_bins;
-  uint32_t *__restrict__ cnt = A.w.bkt_cnt;
-  uint32_t s = 0u;
-  if (own) {
-#pragma unroll 4
-    for (int64_t t = t0; t < t1; ++t) s += cnt[t * stride + b];
-  }
-  part[w][threadIdx.x & 63] = s;
-  __syncthreads();
-  uint32_t pre = 0u, tot = 0u;
-#pragma unroll
-  for (int q = 0; q < HT / 64; ++q) {
-    const uint32_t v = part[q][threadIdx.x & 63];
-    if (q < w) pre += v;
-    tot += v;
-  }
-  if (!own) return;
-  if (w == 0) A.w.bkt_tot[b] = tot;
-  for (int64_t t = t0; t < t1; ++t) {
-    const uint32_t v = cnt[t * stride + b];
-    cnt[t * stride + b] = pre;
-    pre += v;
-  }
+  const int64_t c0 = ctx.block() * kBktColGroup;
+  if (c0 >= bins) return;  // block-uniform
+  column_scan<HT, kBktColGroup>(A.w.bkt_cnt, A.w.bkt_bins, cdiv(n, kBucketTile), c0, bins, A.w.bkt_tot);
 }
 
 // One block per cluster: bucket starts; the escapers' bin comes last, so the

@@ -566,6 +566,51 @@ __device__ __forceinline__ void put_table(const Levels &lv, MS *ms, int64_t k, d
   }
 }
 
+// ---------------------------------------------------------------- column scan
+// The counting sorts' tile offsets.  cnt is a table of counts, row t for
+// tile t (rows stride apart); for the G columns c0 .. c0 + G - 1 below ncol,
+// every entry becomes the sum of its column above it (the tile's offset
+// inside the column) and tot[c] the column's total.  A block of NTB
+// threads: thread x takes column x mod G and one of NTB / G contiguous runs
+// of tiles, so a wave reads 64 / G runs of G adjacent counts and the grid has
+// one block per G columns.
+constexpr int kQColGroup = 16;    // the search sort: few tiles, few groups
+constexpr int kBktColGroup = 64;  // the step's sort
+template <int NTB, int G>
+__device__ __forceinline__ void column_scan(uint32_t *__restrict__ cnt, int64_t stride,
+                                            int64_t tiles, int64_t c0, int64_t ncol,
+                                            uint32_t *__restrict__ tot) {
+  constexpr int R = NTB / G;
+  __shared__ uint32_t part[R][G];
+  const int col = static_cast<int>(threadIdx.x) % G;
+  const int run = static_cast<int>(threadIdx.x) / G;
+  const int64_t c = c0 + col;
+  const bool own = c < ncol;
+  const int64_t per = cdiv(tiles, int64_t(R));
+  const int64_t t0 = run * per;
+  const int64_t t1 = t0 + per < tiles ? t0 + per : tiles;
+  uint32_t s = 0u;
+  if (own) {
+#pragma unroll 4
+    for (int64_t t = t0; t < t1; ++t) s += cnt[t * stride + c];
+  }
+  part[run][col] = s;
+  __syncthreads();
+  uint32_t pre = 0u, all = 0u;
+  for (int q = 0; q < R; ++q) {
+    const uint32_t v = part[q][col];
+    if (q < run) pre += v;
+    all += v;
+  }
+  if (!own) return;
+  if (run == 0) tot[c] = all;
+  for (int64_t t = t0; t < t1; ++t) {
+    const uint32_t v = cnt[t * stride + c];
+    cnt[t * stride + c] = pre;
+    pre += v;
+  }
+}
+
 // ---------------------------------------------------------------- launch context
 // What a kernel knows about the cluster it works on.  One cluster: the
 // arguments travel by value and block b of the launch is block b of the
@@ -628,10 +673,10 @@ enum Shape : int {
   kShRxLong,    // grid-stride over the bucket index's long ranges
   kShDiag,      // grid-stride diagnostics partials
   kShBktTile,   // histogram and scatter tiles of the step's sort
-  kShBktGroup,  // groups of 64 buckets
+  kShBktGroup,  // groups of kBktColGroup buckets
   kShBktSort,   // one block per bucket of kept stars
   kShQTile,     // tiles of the orbit pass's search sort
-  kShQGroup,    // groups of 64 top samples
+  kShQGroup,    // groups of kQColGroup top samples
   kShQSearch,   // blocks of sorted turning-point searches
   kShapes
 };
@@ -659,10 +704,10 @@ __host__ __device__ inline int64_t blocks_of(Shape sh, const Workspace &w, int64
     }
     case kShDiag: return w.star_blocks < kRedBlocks ? w.star_blocks : kRedBlocks;
     case kShBktTile: return w.bkt_bins ? w.bkt_tiles : 1;
-    case kShBktGroup: return w.bkt_bins ? cdiv(w.bkt_bins, 64) : 1;
+    case kShBktGroup: return w.bkt_bins ? cdiv(w.bkt_bins, int64_t(kBktColGroup)) : 1;
     case kShBktSort: return w.bkt_bins ? w.bkt_bins - 1 : 1;
     case kShQTile: return w.oq_tiles;
-    case kShQGroup: return cdiv(w.oq_bins, 64);
+    case kShQGroup: return cdiv(w.oq_bins, int64_t(kQColGroup));
     case kShQSearch: return w.oq_bins + cdiv(2 * c, kQuerySearchChunk);
     default: return 1;
   }

@@ -645,46 +645,16 @@ __global__ __launch_bounds__(QT) void k_oq_hist(Ctx ctx) {
   for (int b = threadIdx.x; b < bins; b += QT) row[b] = hist[b];
 }
 
-// Block g: samples 64 g .. 64 g + 63, one lane each; the 16 waves split the
-// tiles.  Counts become tile offsets inside the sample's group; oq_tot gets
-// the group sizes.
+// Block g: samples kQColGroup g .. kQColGroup (g + 1) - 1.  Counts become tile
+// offsets inside the sample's group; oq_tot gets the group sizes.
 template <class Ctx>
 __global__ __launch_bounds__(QT) void k_oq_colscan(Ctx ctx) {
-  __shared__ uint32_t part[QT / 64][64];
   const ClusterArgs &A = ctx.args();
   const int64_t n = A.w.rx_ctl->n;
   const int64_t bins = query_bins(A.top, n);
-  const int64_t b = ctx.block() * 64 + (threadIdx.x & 63);
-  if (ctx.block() * 64 >= bins) return;
-  const int w = threadIdx.x >> 6;
-  const bool own = b < bins;
-  const int64_t tiles = cdiv(n, kQueryTile);
-  const int64_t per = cdiv(tiles, QT / 64);
-  const int64_t t0 = w * per;
-  const int64_t t1 = t0 + per < tiles ? t0 + per : tiles;
-  const int64_t stride = A.w.oq_bins;
-  uint32_t *__restrict__ cnt = A.w.oq_cnt;
-  uint32_t s = 0u;
-  if (own) {
-#pragma unroll 4
-    for (int64_t t = t0; t < t1; ++t) s += cnt[t * stride + b];
-  }
-  part[w][threadIdx.x & 63] = s;
-  __syncthreads();
-  uint32_t pre = 0u, tot = 0u;
-#pragma unroll
-  for (int q = 0; q < QT / 64; ++q) {
-    const uint32_t v = part[q][threadIdx.x & 63];
-    if (q < w) pre += v;
-    tot += v;
-  }
-  if (!own) return;
-  if (w == 0) A.w.oq_tot[b] = tot;
-  for (int64_t t = t0; t < t1; ++t) {
-    const uint32_t v = cnt[t * stride + b];
-    cnt[t * stride + b] = pre;
-    pre += v;
-  }
+  const int64_t c0 = ctx.block() * kQColGroup;
+  if (c0 >= bins) return;  // block-uniform
+  column_scan<QT, kQColGroup>(A.w.oq_cnt, A.w.oq_bins, cdiv(n, kQueryTile), c0, bins, A.w.oq_tot);
 }
 
 // One block per cluster: the first search of each group (oq_start[bins] is
