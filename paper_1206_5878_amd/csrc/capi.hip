@@ -12,13 +12,13 @@ namespace cmc {
 
 // ---------------------------------------------------------------- launch table
 // Read-only while calls run (cmc_set_tuning is a setup call).  Built in: the
-// autotuner's choices on an MI355X (tune.py, 6 timed steps per candidate):
+// autotuner's choices on an MI355X (tune.py, 5 timed steps per candidate):
 // direct searches below 2^22 stars (the grouped form's sort costs more than
 // it saves there), grouped ones above; larger trial chunks for larger N.
 namespace {
 constexpr cmc_tuning kBuiltinTuning[] = {
-    {0, 0, 1024, 128, {0, 0, 0}},
-    {int64_t(1) << 17, 0, 512, 256, {0, 0, 0}},
+    {0, 0, 512, 128, {0, 0, 0}},
+    {int64_t(1) << 17, 0, 1024, 256, {0, 0, 0}},
     {int64_t(1) << 22, 1, 1024, 256, {0, 0, 0}},
 };
 cmc_tuning g_tuning[CMC_TUNING_MAX];
