@@ -261,6 +261,10 @@ struct alignas(64) OrbitRec {
   OrbitLo lo;
   OrbitHi hi;
 };
+// The grouped form writes each search's half where the search sits in the
+// grouped order (32-byte slots over the orbit records' memory), and each
+// star's two slots apart; a star that left has none.
+constexpr uint32_t kNoPos = 0xFFFFFFFFu;
 // One turning-point search left below the LDS-resident top levels: the
 // star's E, J and index, and the sample of the level ltop the search reached
 // (bit 31: the upper turning point).  Searches are grouped by that sample, so
@@ -411,8 +415,11 @@ struct Workspace {
   uint32_t *oq_chunk;       // [oq_bins + 1] first search block of each top sample
   uint32_t *oq_bmap;        // [search blocks] the top sample each search block works on
   uint32_t *oq_node;        // [cap] each star's two top samples
+  uint32_t *oq_pos;         // [2 cap] each star's two halves in the grouped form's
+                            // results (kNoPos: none, the star left)
   int64_t bkt_bins, bkt_tiles;  // bkt_bins = 0: capacity above kBucketCapMax
-  int64_t oq_bins, oq_tiles;    // samples of the level the LDS top ends at; tiles
+  int64_t oq_bins, oq_tiles;    // groups (samples of the level the LDS top ends at,
+                                // and one more); tiles
   // launch settings from the launch table (cluster_args; layout() leaves the
   // built-in defaults)
   int32_t sorted, bracket_blocks, trial_chunk;
@@ -521,7 +528,9 @@ inline Workspace layout(int64_t cap, void *base) {
   w.lfsr_jump = reinterpret_cast<uint32_t *>(take(4 * kLfsrJumpWords));
   {
     const OrbitTop tl = top_levels(w.nlev, c);
-    w.oq_bins = tl.ltop > 0 ? tl.len[tl.ltop] : 1;
+    // the groups: one per sample of level ltop, and one for the lower turning
+    // points the LDS levels already finish
+    w.oq_bins = tl.ltop > 0 ? tl.len[tl.ltop] + 1 : 1;
     w.oq_tiles = cdiv(c, kQueryTile);
     w.oq = reinterpret_cast<OrbQuery *>(take(sizeof(OrbQuery) * 2 * c));
     w.oq_cnt = reinterpret_cast<uint32_t *>(take(4 * w.oq_tiles * w.oq_bins));
@@ -530,6 +539,7 @@ inline Workspace layout(int64_t cap, void *base) {
     w.oq_chunk = reinterpret_cast<uint32_t *>(take(4 * (w.oq_bins + 1)));
     w.oq_bmap = reinterpret_cast<uint32_t *>(take(4 * (w.oq_bins + cdiv(2 * c, kQuerySearchChunk))));
     w.oq_node = reinterpret_cast<uint32_t *>(take(4 * c));
+    w.oq_pos = reinterpret_cast<uint32_t *>(take(8 * c));
   }
   w.bent = reinterpret_cast<BktEnt *>(w.orec);  // orec is dead once the orbit pass ends
   static_assert(sizeof(BktEnt) <= sizeof(OrbitRec), "bent fits in orec");

@@ -484,11 +484,13 @@ __device__ __forceinline__ void put_lfsr(const ClusterArgs &A, int64_t i, const 
 
 // Per-star work of the pass before the searches: the energy-correction
 // record, the staged RNG state, E and J, and the escapers (sent out here,
-// their masses and energies summed).  Returns whether the star is bound.
+// their masses and energies summed; mark: note the escaper in its orbit
+// record, where the records are in star order).  Returns whether the star
+// is bound.
 template <typename MT, bool TO_STAGE, bool LF>
 __device__ __forceinline__ bool star_start(const ClusterArgs &A, int64_t i, int corr, double &E,
                                            double &J, double &J2, double &c_esc, double &e_esc,
-                                           uint32_t &fl) {
+                                           uint32_t &fl, bool mark) {
   const RPhi me = A.w.lev[0][i];
   if (corr) A.w.cor[i] = me;  // r_old and Phi_old(r_old)
   // an LFSR113 state moves with its star; a Philox step stages it as it is
@@ -508,7 +510,7 @@ __device__ __forceinline__ bool star_start(const ClusterArgs &A, int64_t i, int 
   if (E != E) fl |= CMC_ST_NONFINITE;
   emit<TO_STAGE>(i, kInf, vri, vti, m[i], A.s.id[i], 0, A.s.r_new, A.s.vr, A.s.vt,
                  static_cast<StageRec<MT> *>(A.w.stage), A.w.keys[0], A.w.bkey);
-  A.w.orec[i].lo = escaper_lo(E);
+  if (mark) A.w.orec[i].lo = escaper_lo(E);
   return false;
 }
 
@@ -556,7 +558,7 @@ void k_orbit_bracket(Ctx ctx, int corr) {
     double c_esc = 0.0, e_esc = 0.0;
     double E = 0.0, J = 0.0, J2 = 0.0;
     const bool bound =
-        i < n && star_start<MT, TO_STAGE, LF>(A, i, corr, E, J, J2, c_esc, e_esc, fl);
+        i < n && star_start<MT, TO_STAGE, LF>(A, i, corr, E, J, J2, c_esc, e_esc, fl, true);
     const int32_t ii = static_cast<int32_t>(i);
     // brackets: the LDS levels per lane, the rest by groups of 8 lanes
     int32_t t0 = -1, t1 = -1;
@@ -583,9 +585,13 @@ void k_orbit_bracket(Ctx ctx, int corr) {
 // the L2.  k_oq_hist counts each tile's searches per sample, k_oq_colscan
 // and k_oq_start turn the counts into offsets, k_oq_scatter sends every
 // star's searches (E, J, index, sample) to their groups and finishes what
-// needs no search, and k_oq_search runs the grouped searches and writes
-// each star's half-records.  Brackets are unique, so the result is the one
-// of the direct form.
+// needs no search, and k_oq_search runs the grouped searches.  Each search
+// writes its half-record where it sits in the grouped order, coalesced; the
+// scatter records the two places of every star (oq_pos), where the trial
+// kernel reads them.  The lower turning points that the LDS levels already
+// finish (interval -1) take a group of their own, after the samples', which
+// no search block visits.  Brackets are unique, so the result is the one of
+// the direct form.
 constexpr int QT = 512;   // threads of the tile kernels
 constexpr int QS = kQuerySearchBlock;
 constexpr int kSubEntries = 704;  // LDS slots of a group's subtree in the search
@@ -619,7 +625,7 @@ __global__ __launch_bounds__(QT) void k_oq_hist(Ctx ctx) {
   const RPhi *__restrict__ tab = lv.lev[0];
   uint32_t *__restrict__ node = A.w.oq_node;
   load_top(top, lv, tl, QT);
-  for (int b = threadIdx.x; b < bins; b += QT) hist[b] = 0u;
+  for (int b = threadIdx.x; b <= bins; b += QT) hist[b] = 0u;
   __syncthreads();
   const int64_t k1 = k0 + kQueryTile < n ? k0 + kQueryTile : n;
   for (int64_t i = k0 + threadIdx.x; i < k1; i += QT) {
@@ -634,7 +640,7 @@ __global__ __launch_bounds__(QT) void k_oq_hist(Ctx ctx) {
       const int32_t ii = static_cast<int32_t>(i);
       const int32_t t0 = top_descend(top, tl, lv.nlev, n, QNeg{2.0 * E, J2, ii});
       const int32_t t1 = top_descend(top, tl, lv.nlev, n, QNonNeg{2.0 * E, J2, ii});
-      if (t0 >= 0) atomicAdd(&hist[t0], 1u);
+      atomicAdd(&hist[t0 >= 0 ? t0 : static_cast<int32_t>(bins)], 1u);
       atomicAdd(&hist[t1], 1u);
       code = static_cast<uint32_t>(t0 + 1) | (static_cast<uint32_t>(t1) << 16);
     }
@@ -642,7 +648,7 @@ __global__ __launch_bounds__(QT) void k_oq_hist(Ctx ctx) {
   }
   __syncthreads();
   uint32_t *__restrict__ row = A.w.oq_cnt + t * A.w.oq_bins;
-  for (int b = threadIdx.x; b < bins; b += QT) row[b] = hist[b];
+  for (int b = threadIdx.x; b <= bins; b += QT) row[b] = hist[b];
 }
 
 // Block g: samples kQColGroup g .. kQColGroup (g + 1) - 1.  Counts become tile
@@ -653,8 +659,9 @@ __global__ __launch_bounds__(QT) void k_oq_colscan(Ctx ctx) {
   const int64_t n = A.w.rx_ctl->n;
   const int64_t bins = query_bins(A.top, n);
   const int64_t c0 = ctx.block() * kQColGroup;
-  if (c0 >= bins) return;  // block-uniform
-  column_scan<QT, kQColGroup>(A.w.oq_cnt, A.w.oq_bins, cdiv(n, kQueryTile), c0, bins, A.w.oq_tot);
+  if (bins == 0 || c0 > bins) return;  // block-uniform
+  column_scan<QT, kQColGroup>(A.w.oq_cnt, A.w.oq_bins, cdiv(n, kQueryTile), c0, bins + 1,
+                              A.w.oq_tot);
 }
 
 // One block per cluster: the first search of each group (oq_start[bins] is
@@ -670,15 +677,18 @@ __global__ __launch_bounds__(QT) void k_oq_start(Ctx ctx) {
   uint32_t *__restrict__ start = A.w.oq_start;
   uint32_t *__restrict__ chunk = A.w.oq_chunk;
   uint32_t *__restrict__ bmap = A.w.oq_bmap;
+  // groups: the bins samples' and the finished lower turning points' (no
+  // search block)
+  const int64_t groups = bins > 0 ? bins + 1 : 0;
   uint32_t carry = 0u, ccarry = 0u;
-  for (int64_t b0 = 0; b0 < bins; b0 += QT) {
+  for (int64_t b0 = 0; b0 < groups; b0 += QT) {
     const int64_t b = b0 + threadIdx.x;
-    const uint32_t v = b < bins ? tot[b] : 0u;
-    const uint32_t cv = (v + kQuerySearchChunk - 1) / kQuerySearchChunk;
+    const uint32_t v = b < groups ? tot[b] : 0u;
+    const uint32_t cv = b < bins ? (v + kQuerySearchChunk - 1) / kQuerySearchChunk : 0u;
     uint32_t all, call;
     const uint32_t ex = block_excl_scan<QT>(v, sh, &all);
     const uint32_t cex = block_excl_scan<QT>(cv, sh, &call);
-    if (b < bins) {
+    if (b < groups) {
       start[b] = carry + ex;
       chunk[b] = ccarry + cex;
       // the search blocks' map: block c works on the group b with
@@ -689,17 +699,18 @@ __global__ __launch_bounds__(QT) void k_oq_start(Ctx ctx) {
     ccarry += call;
   }
   if (threadIdx.x == 0) {
-    start[bins] = carry;
-    chunk[bins] = ccarry;
+    start[groups] = carry;
+    chunk[groups] = ccarry;
   }
 }
 
 // The star pass: what star_start does, then each search to its group at an
-// LDS-atomic slot (the order inside a group does not matter: every search
-// writes its own star's half-record); a search the LDS levels already
-// finish (no index below) is finished here.  A table that fits the LDS
-// whole (no level below the top) has no groups: its stars are searched
-// here to the bottom.
+// LDS-atomic slot (the order inside a group does not matter: each half lands
+// where its search sits, and oq_pos says where); a lower turning point the
+// LDS levels already finish is finished here, in a slot of the extra group.
+// A table that fits the LDS whole (no level below the top) has no groups:
+// its stars are searched here to the bottom and their records written in
+// star order, the two slots of star i being 2i and 2i + 1.
 template <class Ctx, typename MT, bool TO_STAGE, bool LF>
 __global__ __launch_bounds__(QT) void k_oq_scatter(Ctx ctx, int corr) {
   extern __shared__ RPhi top[];
@@ -717,14 +728,16 @@ __global__ __launch_bounds__(QT) void k_oq_scatter(Ctx ctx, int corr) {
   const RPhi *__restrict__ tab = lv.lev[0];
   const MS *__restrict__ ms = A.w.ms;
   OrbitRec *__restrict__ orec = A.w.orec;
+  OrbitLo *__restrict__ res_lo = reinterpret_cast<OrbitLo *>(A.w.orec);
   OrbQuery *__restrict__ oq = A.w.oq;
+  uint2 *__restrict__ pos = reinterpret_cast<uint2 *>(A.w.oq_pos);
   uint32_t fl = 0;
   if (k0 < n) {  // block-uniform
     if (bins == 0) {
       load_top(top, lv, tl, QT);
     } else {
       const uint32_t *__restrict__ row = A.w.oq_cnt + t * A.w.oq_bins;
-      for (int b = threadIdx.x; b < bins; b += QT) cur[b] = A.w.oq_start[b] + row[b];
+      for (int b = threadIdx.x; b <= bins; b += QT) cur[b] = A.w.oq_start[b] + row[b];
     }
     __syncthreads();
     const int64_t k1 = k0 + kQueryTile < n ? k0 + kQueryTile : n;
@@ -733,7 +746,9 @@ __global__ __launch_bounds__(QT) void k_oq_scatter(Ctx ctx, int corr) {
       double c_esc = 0.0, e_esc = 0.0;
       double E = 0.0, J = 0.0, J2 = 0.0;
       const bool bound =
-          i < k1 && star_start<MT, TO_STAGE, LF>(A, i, corr, E, J, J2, c_esc, e_esc, fl);
+          i < k1 &&
+          star_start<MT, TO_STAGE, LF>(A, i, corr, E, J, J2, c_esc, e_esc, fl, bins == 0);
+      if (i < k1 && !bound) pos[i] = make_uint2(kNoPos, kNoPos);  // it left
       if (bins == 0) {
         if (bound) {  // the whole table in LDS: the samples are the brackets
           const int32_t ii = static_cast<int32_t>(i);
@@ -741,20 +756,25 @@ __global__ __launch_bounds__(QT) void k_oq_scatter(Ctx ctx, int corr) {
           const int32_t kmax = top_descend(top, tl, lv.nlev, n, QNonNeg{2.0 * E, J2, ii});
           orec[i].lo = finalize_lo(tab, ms, kmin, E, J, J2);
           orec[i].hi = finalize_hi(tab, ms, n, kmax, E, J, J2);
+          const uint32_t ui = static_cast<uint32_t>(i);
+          pos[i] = make_uint2(2u * ui, 2u * ui + 1u);
         }
       } else if (bound) {
         const uint32_t code = A.w.oq_node[i];
         const int32_t t0 = static_cast<int32_t>(code & 0xFFFFu) - 1;
         const uint32_t t1 = code >> 16;
         const uint32_t ui = static_cast<uint32_t>(i);
+        uint32_t plo;
         if (t0 < 0) {
-          orec[i].lo = finalize_lo(tab, ms, -1, E, J, J2);
+          plo = atomicAdd(&cur[bins], 1u);
+          res_lo[plo] = finalize_lo(tab, ms, -1, E, J, J2);
         } else {
-          const uint32_t pos = atomicAdd(&cur[t0], 1u);
-          oq[pos] = OrbQuery{E, J, ui, static_cast<uint32_t>(t0)};
+          plo = atomicAdd(&cur[t0], 1u);
+          oq[plo] = OrbQuery{E, J, ui, static_cast<uint32_t>(t0)};
         }
-        const uint32_t pos = atomicAdd(&cur[t1], 1u);
-        oq[pos] = OrbQuery{E, J, ui, t1 | kQueryHi};
+        const uint32_t phi_slot = atomicAdd(&cur[t1], 1u);
+        oq[phi_slot] = OrbQuery{E, J, ui, t1 | kQueryHi};
+        pos[i] = make_uint2(plo, phi_slot);
       }
       // escaper partials per 512 stars, as the direct form writes them
       esc_partials<QT>(c_esc, e_esc, shd, A.w.red_part, (k0 / QT) + j);
@@ -819,7 +839,8 @@ __global__ __launch_bounds__(QS) void k_oq_search(Ctx ctx) {
   __syncthreads();
   GParams *wprm = prm + (threadIdx.x & ~63);
   const RPhi *__restrict__ tab = lv.lev[0];
-  OrbitRec *__restrict__ orec = A.w.orec;
+  OrbitLo *__restrict__ res_lo = reinterpret_cast<OrbitLo *>(A.w.orec);
+  OrbitHi *__restrict__ res_hi = reinterpret_cast<OrbitHi *>(A.w.orec);
   for (int64_t qb = q0; qb < q1; qb += QS) {  // block-uniform
     const int64_t qi = qb + threadIdx.x;
     const bool act = qi < q1;
@@ -844,19 +865,34 @@ __global__ __launch_bounds__(QS) void k_oq_search(Ctx ctx) {
     }
     const GParams mine{twoE, J2, hi_b ? -ci - 1 : ci, act ? s : -1};
     const int32_t k = group_descend1<GQAny>(lv, lsub - 1, n, mine, wprm);
-    if (act) {
+    if (act) {  // the half where the search sits
       if (hi_b)
-        orec[qr.i].hi = finalize_hi(tab, A.w.ms, n, k, qr.E, qr.J, J2);
+        res_hi[qi] = finalize_hi(tab, A.w.ms, n, k, qr.E, qr.J, J2);
       else
-        orec[qr.i].lo = finalize_lo(tab, A.w.ms, k, qr.E, qr.J, J2);
+        res_lo[qi] = finalize_lo(tab, A.w.ms, k, qr.E, qr.J, J2);
     }
   }
+}
+
+// Star i's orbit record: in star order (the direct form), or its two halves
+// where the grouped form's searches left them.  False for a star that left.
+__device__ __forceinline__ bool load_orbit(const ClusterArgs &A, int grouped, int64_t i,
+                                           OrbitRec &o) {
+  if (grouped) {
+    const uint2 p = reinterpret_cast<const uint2 *>(A.w.oq_pos)[i];
+    if (p.x == kNoPos) return false;
+    o.lo = reinterpret_cast<const OrbitLo *>(A.w.orec)[p.x];
+    o.hi = reinterpret_cast<const OrbitHi *>(A.w.orec)[p.y];
+  } else {
+    o = A.w.orec[i];
+  }
+  return o.lo.E < 0.0;  // the direct form marks a star that left by E >= 0 (or NaN)
 }
 
 template <class Ctx, typename MT, bool TO_STAGE, bool MIXED, bool LF>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5)))
 void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap, int corr,
-                    double bound_factor) {
+                    double bound_factor, int grouped) {
   __shared__ double shd[NT / 64];
   // stars of each wavefront's chunk finished without trials (kept apart so
   // that their code does not hold registers in the trial loop)
@@ -875,7 +911,6 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap, int corr,
   StageRec<MT> *__restrict__ stage = static_cast<StageRec<MT> *>(A.w.stage);
   uint64_t *__restrict__ keys = A.w.keys[0];
   uint32_t *__restrict__ bkey = A.w.bkey;
-  const OrbitRec *__restrict__ orec = A.w.orec;
   double *__restrict__ pn = A.w.pn;
   cmc_scalars *__restrict__ sc = A.s.sc;
   double *__restrict__ part = A.w.red_part + 2 * A.w.star_blocks;
@@ -918,8 +953,8 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap, int corr,
       const int64_t mine = cursor + __popcll(need & lt);
       cursor += __popcll(need);
       if (!busy && mine < c_end) {
-        const OrbitRec o = orec[mine];
-        if (o.lo.E < 0.0) {  // else an escaper, already sent out
+        OrbitRec o;
+        if (load_orbit(A, grouped, mine, o)) {  // else an escaper, already sent out
           // the rejection bound: F = bound_factor * the larger endpoint
           // value of g(s), 2 r_a / |dQ/dr| under the square root
           const double oJ = o.hi.J, oJ2 = oJ * oJ;
@@ -1051,7 +1086,8 @@ void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap, int corr,
   const uint32_t nd = n_deferred[wv];
   for (uint32_t d = lane; d < nd; d += 64) {
     const int64_t mine = wave * chunk + deferred[wv][d];
-    const OrbitRec o = orec[mine];
+    OrbitRec o;
+    load_orbit(A, grouped, mine, o);
     const double oJ = o.hi.J, oJ2 = oJ * oJ;
     const double ora = 0.5 * (o.hi.rmax - o.lo.rmin);
     const double rdone = ora > 0.0 ? 0.5 * (o.hi.rmax + o.lo.rmin) : o.lo.rmin;
@@ -1173,12 +1209,13 @@ hipError_t run2(const L &l, const cmc_params &p, int corr, bool sorted, hipStrea
     k_orbit_bracket<Cb, MT, TO_STAGE, LF><<<l.grid(kShBracket), BT, top_bytes, st>>>(
         l.ctx(kShBracket), corr);
   }
+  const int grouped = sorted ? 1 : 0;
   if (p.precision == CMC_MIXED)
     k_orbit_trials<Ct, MT, TO_STAGE, true, LF><<<l.grid(kShTrials), NT, 0, st>>>(
-        l.ctx(kShTrials), p.step, cap, corr, bf);
+        l.ctx(kShTrials), p.step, cap, corr, bf, grouped);
   else
     k_orbit_trials<Ct, MT, TO_STAGE, false, LF><<<l.grid(kShTrials), NT, 0, st>>>(
-        l.ctx(kShTrials), p.step, cap, corr, bf);
+        l.ctx(kShTrials), p.step, cap, corr, bf, grouped);
   k_orbit_sum<<<l.grid(kShOne), FT, 0, st>>>(l.ctx(kShOne));
   return hipGetLastError();
 }
