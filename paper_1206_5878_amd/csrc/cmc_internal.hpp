@@ -364,7 +364,7 @@ constexpr int kTopEntries = kTopBytes / 16;  // LDS slots of 16 bytes, padding i
 __host__ __device__ inline int64_t top_padded(int64_t len) { return len + (len >> 3) + 1; }
 constexpr int kQueryTile = 8192;             // stars per tile of the search sort
 constexpr int kQuerySearchBlock = 256;       // threads of the sorted-search kernel
-constexpr int kQuerySearchChunk = 1024;      // searches of one group per block of it
+constexpr int kQuerySearchChunk = 512;       // searches of one group per block of it
 constexpr int kPhiBins = 16384;  // bins of the potential-bound table (orbit.hip)
 // LFSR113 stream seeding (rng.hip): for each component, the 32x32 bit matrix
 // of 2^(80+b) steps for every bit b of a stream index (a base below 2^33
