@@ -362,7 +362,7 @@ constexpr int kKingTab = 3 * kKingNodes + 8;
 constexpr int kTopBytes = 52 * 1024;
 constexpr int kTopEntries = kTopBytes / 16;  // LDS slots of 16 bytes, padding included
 __host__ __device__ inline int64_t top_padded(int64_t len) { return len + (len >> 3) + 1; }
-constexpr int kQueryTile = 8192;             // stars per tile of the search sort
+constexpr int kQueryTile = 4096;             // stars per tile of the search sort
 constexpr int kQuerySearchBlock = 256;       // threads of the sorted-search kernel
 constexpr int kQuerySearchChunk = 512;       // searches of one group per block of it
 constexpr int kPhiBins = 16384;  // bins of the potential-bound table (orbit.hip)

@@ -593,6 +593,7 @@ void k_orbit_bracket(Ctx ctx, int corr) {
 // no search block visits.  Brackets are unique, so the result is the one of
 // the direct form.
 constexpr int QT = 512;   // threads of the tile kernels
+constexpr int CT = 1024;  // threads of the column scan
 constexpr int QS = kQuerySearchBlock;
 constexpr int kSubEntries = 704;  // LDS slots of a group's subtree in the search
 
@@ -654,13 +655,13 @@ __global__ __launch_bounds__(QT) void k_oq_hist(Ctx ctx) {
 // Block g: samples kQColGroup g .. kQColGroup (g + 1) - 1.  Counts become tile
 // offsets inside the sample's group; oq_tot gets the group sizes.
 template <class Ctx>
-__global__ __launch_bounds__(QT) void k_oq_colscan(Ctx ctx) {
+__global__ __launch_bounds__(CT) void k_oq_colscan(Ctx ctx) {
   const ClusterArgs &A = ctx.args();
   const int64_t n = A.w.rx_ctl->n;
   const int64_t bins = query_bins(A.top, n);
   const int64_t c0 = ctx.block() * kQColGroup;
   if (bins == 0 || c0 > bins) return;  // block-uniform
-  column_scan<QT, kQColGroup>(A.w.oq_cnt, A.w.oq_bins, cdiv(n, kQueryTile), c0, bins + 1,
+  column_scan<CT, kQColGroup>(A.w.oq_cnt, A.w.oq_bins, cdiv(n, kQueryTile), c0, bins + 1,
                               A.w.oq_tot);
 }
 
@@ -1199,7 +1200,7 @@ hipError_t run2(const L &l, const cmc_params &p, int corr, bool sorted, hipStrea
   if (sorted) {
     using Cq = decltype(l.ctx(kShQTile));
     k_oq_hist<<<l.grid(kShQTile), QT, top_bytes, st>>>(l.ctx(kShQTile));
-    k_oq_colscan<<<l.grid(kShQGroup), QT, 0, st>>>(l.ctx(kShQGroup));
+    k_oq_colscan<<<l.grid(kShQGroup), CT, 0, st>>>(l.ctx(kShQGroup));
     k_oq_start<<<l.grid(kShOne), QT, 0, st>>>(l.ctx(kShOne));
     k_oq_scatter<Cq, MT, TO_STAGE, LF>
         <<<l.grid(kShQTile), QT, l.flat_top() ? top_bytes : 0, st>>>(l.ctx(kShQTile), corr);
