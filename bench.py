@@ -365,7 +365,7 @@ def ensemble_leg(P, wl, precision, K, warmup, drift_steps=50) -> dict:
         "clusters": len(specs),
         "n_min": min(sp["n"] for sp in specs), "n_max": max(sp["n"] for sp in specs),
         "precision": precision,
-        "launch_table": tune_entry(P, sum(cl.cap for cl in ens.clusters)),
+        "launch_table": tune_entry(P, max(cl.cap for cl in ens.clusters)),
         "per_cluster_fp64_calls": {"value": K * 0.5 * (m0 + m1) / el_loop,
                                    "ms_per_step": el_loop / K * 1e3},
         "drift": {"steps": drift_steps, "energy_corr": True,

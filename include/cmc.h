@@ -397,8 +397,8 @@ int cmc_batch_diagnostics(const cmc_batch *b, double *out_dev, void *stream);
 /* ---- launch table ------------------------------------------------------------
  * How the orbit pass (Sec. 2.1 item 5) is launched, by capacity: a read-only
  * table that the library consults when it sets up a call (each single-cluster
- * call, and cmc_batch_prepare for an ensemble, with the sum of its clusters'
- * capacities).  Every entry gives the same results bit for bit; only the
+ * call, and cmc_batch_prepare for an ensemble, with the capacity of its
+ * largest cluster).  Every entry gives the same results bit for bit; only the
  * speed differs.  The built-in table holds measured defaults; an autotuner
  * (the package's tune.py, after the paper's own launch-configuration study,
  * Appendix A) times candidates on the GPU and installs its table here.

@@ -74,18 +74,20 @@ int totals(const cmc_state *states, int32_t clusters, std::vector<ClusterArgs> *
            std::vector<int64_t> *blocks, int64_t *total) {
   if (!states || clusters < 1 || clusters > kMaxClusters) return CMC_EINVAL;
   args->clear();
-  int64_t cap_sum = 0;
+  int64_t cap_max = 0;
   for (int c = 0; c < clusters; ++c) {
     const int rc = check_state(states[c]);
     if (rc) return rc;
     if ((states[c].m_f32 != 0) != (states[0].m_f32 != 0)) return CMC_EINVAL;
     args->push_back(cluster_args(states[c], 0, 1.0));
-    cap_sum += states[c].cap;
+    cap_max = states[c].cap > cap_max ? states[c].cap : cap_max;
   }
-  // one launch table entry for the whole ensemble: that of its summed
-  // capacity (64 clusters of 1e4..1e6 stars, 1.4e7 in all: the grouped form,
-  // 6.4 ms per step, against 7.3 ms with the largest cluster's entry)
-  const cmc_tuning tun = tuning_for(cap_sum);
+  // one launch table entry for the whole ensemble: that of its largest
+  // cluster, since the searches run on each cluster's own table (64 clusters
+  // of 1e4..1e6 stars, 1.4e7 in all: the direct form, 6.02 ms per step,
+  // against 6.36 ms with the grouped form that the summed capacity's entry
+  // names)
+  const cmc_tuning tun = tuning_for(cap_max);
   for (auto &a : *args) apply_tuning(a.w, tun);
   shape_blocks(*args, blocks);
   for (int sh = 0; sh < kShapes; ++sh) {
