@@ -31,7 +31,8 @@
 //  - sorted (k_oq_*): the searches are first grouped by the LDS-level sample
 //    they reached (a counting sort of 2 N small records), so that the
 //    searches sharing a subtree run together and find it in the L2; each
-//    writes its half of the star's orbit record.
+//    writes its half of the star's orbit record where it sits in that
+//    order, and the trial kernel finds the two halves there.
 // Either way the roots inside the brackets and the rejection bound F follow.
 // k_orbit_trials then draws the radii: each wavefront owns a chunk of stars
 // and every lane draws trials for one star at a time, taking the chunk's
