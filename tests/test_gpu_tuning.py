@@ -4,7 +4,9 @@ Both forms of the turning-point searches (direct, and grouped by the LDS
 top's sample: "sorted"), with different resident blocks and trial chunks,
 must leave the same state.  The sorted form is also compared with the FP64
 oracle on the orbit cases of the parity tests, since the built-in table
-gives every capacity the direct form."""
+gives it only to capacities of 2^22 stars and more, above the sizes most
+parity cases use.  Those cases include J = 0 stars, whose lower turning
+point the LDS levels already finish (the grouped form's extra group)."""
 import numpy as np
 import pytest
 
