@@ -246,7 +246,7 @@ int cmc_step_timed(cmc_state *s, const cmc_params *p, void *const *events, void 
  *    its device address is looked up once per GPU, on the first call made
  *    while that GPU is current.  `stream` must belong to the current device.
  *  - Capacity limit: cmc_workspace_bytes(s->cap) <= CMC_SCRATCH_BYTES, about
- *    250,000 stars (about 270 bytes per star); a larger cap returns
+ *    238,000 stars (about 282 bytes per star); a larger cap returns
  *    CMC_ESCRATCH and enqueues nothing.
  *  - p->energy_corr must be 0 (CMC_EINVAL otherwise): a pending correction's
  *    data would have to outlive the call in scratch that the next call on the
