@@ -9,10 +9,10 @@ resident blocks of the direct search kernel, and the stars per wavefront
 chunk of the rejection-trial kernel.  Every entry gives the same results bit
 for bit, so only the speed is at stake.  This module times the candidates on
 the GPU on each band's workload, with HIP events on the stream the kernels
-run on, and writes the winning table to tuning.json beside it; lib() installs
-that file at load.
+run on (the median of a few interleaved rounds), and writes the winning
+table to tuning.json beside it; lib() installs that file at load.
 
-python -m paper_1206_5878_amd.tune [--steps K] [--out PATH]
+python -m paper_1206_5878_amd.tune [--steps K] [--rounds R] [--out PATH]
 """
 from __future__ import annotations
 
@@ -75,44 +75,71 @@ def load(path: str = TABLE_PATH) -> list:
         return json.load(f)["table"]
 
 
-def time_band(P, band: dict, steps: int, warmup: int) -> list:
-    """ms per step of every candidate on the band's workload."""
+def time_band(P, band: dict, steps: int, warmup: int, rounds: int) -> list:
+    """ms per step of every candidate on the band's workload: the median over
+    `rounds` rounds of every candidate in turn, each timing taken from a fresh
+    initial model (warm-up steps, then `steps` timed ones), as the benchmark
+    times the step."""
+    import statistics
+
     import torch
     cl = P.Cluster(band["n"], m_f32=band["m_f32"])
-    P.cmc_init_plummer(cl, band["n"], 1, band["mass_spectrum"])
-    k = 0
+    cands = list(candidates())
+    times = [[] for _ in cands]
+    for _ in range(rounds):
+        for c, cand in enumerate(cands):
+            set_table([dict(min_cap=0, **cand)])
+            P.cmc_init_plummer(cl, band["n"], 1, band["mass_spectrum"])
+            k = 0
+            for _ in range(warmup):
+                P.cmc_step(cl, P.Params(seed=1, step=k, gamma=band["gamma"],
+                                        precision=band["precision"]))
+                k += 1
+            # the calls enqueue on torch's current stream, where these events go
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(steps):
+                P.cmc_step(cl, P.Params(seed=1, step=k, gamma=band["gamma"],
+                                        precision=band["precision"]))
+                k += 1
+            e1.record()
+            torch.cuda.synchronize()
+            times[c].append(e0.elapsed_time(e1) / steps)
     rows = []
-    for cand in candidates():
-        set_table([dict(min_cap=0, **cand)])
-        for _ in range(warmup):
-            P.cmc_step(cl, P.Params(seed=1, step=k, gamma=band["gamma"],
-                                    precision=band["precision"]))
-            k += 1
-        # the calls enqueue on torch's current stream, where these events go
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(steps):
-            P.cmc_step(cl, P.Params(seed=1, step=k, gamma=band["gamma"],
-                                    precision=band["precision"]))
-            k += 1
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
-        rows.append(dict(cand, ms_per_step=ms))
-        print(f"# n={band['n']} {cand}: {ms:.3f} ms/step", flush=True)
+    for cand, t in zip(cands, times):
+        ms = statistics.median(t)
+        rows.append(dict(cand, ms_per_step=ms, rounds_ms=t))
+        print(f"# n={band['n']} {cand}: {ms:.3f} ms/step (median of {len(t)})", flush=True)
     return rows
 
 
-def tune(steps: int = 5, warmup: int = 1) -> dict:
+# A candidate within this fraction of the fastest median counts as tied with
+# it; the library's built-in entry for the band is kept when it ties, so that
+# repeated sweeps do not change the table on timing noise.
+TIE = 0.02
+
+
+def pick(rows: list, incumbent: dict) -> dict:
+    best = min(rows, key=lambda r: r["ms_per_step"])
+    for r in rows:
+        if all(r[f] == incumbent[f] for f in FIELDS if f != "min_cap") and \
+                r["ms_per_step"] <= best["ms_per_step"] * (1.0 + TIE):
+            return r
+    return best
+
+
+def tune(steps: int = 5, warmup: int = 1, rounds: int = 3) -> dict:
     import paper_1206_5878_amd as P
     import torch
     table, measured = [], []
+    set_table([])
+    builtin = {band["min_cap"]: get(band["min_cap"]) for band in BANDS}
     try:
         for band in BANDS:
-            rows = time_band(P, band, steps, warmup)
-            best = min(rows, key=lambda r: r["ms_per_step"])
+            rows = time_band(P, band, steps, warmup, rounds)
+            best = pick(rows, builtin[band["min_cap"]])
             table.append({"min_cap": band["min_cap"],
                           **{f: best[f] for f in FIELDS if f != "min_cap"}})
             measured.append({"workload": {k: band[k] for k in
@@ -123,16 +150,17 @@ def tune(steps: int = 5, warmup: int = 1) -> dict:
     return {"table": table, "measured": measured,
             "device": torch.cuda.get_device_name(0),
             "date": time.strftime("%Y-%m-%d %H:%M:%S"),
-            "steps": steps, "warmup": warmup}
+            "steps": steps, "warmup": warmup, "rounds": rounds, "tie": TIE}
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--rounds", type=int, default=3)
     ap.add_argument("--out", default=TABLE_PATH)
     args = ap.parse_args()
-    res = tune(args.steps, args.warmup)
+    res = tune(args.steps, args.warmup, args.rounds)
     with open(args.out, "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res["table"]), flush=True)
