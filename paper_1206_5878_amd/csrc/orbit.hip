@@ -891,8 +891,12 @@ __device__ __forceinline__ bool load_orbit(const ClusterArgs &A, int grouped, in
   return o.lo.E < 0.0;  // the direct form marks a star that left by E >= 0 (or NaN)
 }
 
+// Waves per SIMD: the FP64 form needs ~120 VGPRs and runs spill-free at 4
+// (1.18 ms at N = 1e7, against 1.32 ms at 5 with 56-80 bytes of spill per
+// lane); the mixed form fits 96 at 5 (a 12-byte spill, and 1.15 against
+// 1.17 ms at 4).
 template <class Ctx, typename MT, bool TO_STAGE, bool MIXED, bool LF>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MIXED ? 5 : 4)))
 void k_orbit_trials(Ctx ctx, uint32_t step_arg, int32_t trial_cap, int corr,
                     double bound_factor, int grouped) {
   __shared__ double shd[NT / 64];
