@@ -91,7 +91,8 @@ __device__ __forceinline__ PairGeo pair_geometry(int64_t p, int64_t n,
   const double u1 = u01(w.y, w.x);
   g.u2 = u01(w.w, w.z);
   const double psi = 2.0 * kPi * u1;
-  const double cp = cos(psi), sp = sin(psi);
+  double sp, cp;
+  sincos(psi, &sp, &cp);
   g.v2y = vt[b] * cp;
   g.v2z = vt[b] * sp;
   g.wx = g.v1x - g.v2x;
@@ -440,7 +441,9 @@ __global__ __launch_bounds__(NT) void k_relax(Ctx ctx, uint32_t step_arg) {
   const double e3y = e1z * e2x - e1x * e2z;
   const double e3z = e1x * e2y - e1y * e2x;
   const double psi2 = 2.0 * kPi * g.u2;
-  const double cb = cos(beta), sb = sin(beta), c2 = cos(psi2), s2 = sin(psi2);
+  double sb, cb, s2, c2;
+  sincos(beta, &sb, &cb);
+  sincos(psi2, &s2, &c2);
   const double wnx = g.wm * (cb * e1x + sb * (c2 * e2x + s2 * e3x));
   const double wny = g.wm * (cb * e1y + sb * (c2 * e2y + s2 * e3y));
   const double wnz = g.wm * (cb * e1z + sb * (c2 * e2z + s2 * e3z));
