@@ -405,21 +405,22 @@ __global__ __launch_bounds__(NT) void k_relax(Ctx ctx, uint32_t step_arg) {
     const float wnx = wm * (cb * e1x + sb * (c2 * e2x + s2 * e3x));
     const float wny = wm * (cb * e1y + sb * (c2 * e2y + s2 * e3y));
     const float wnz = wm * (cb * e1z + sb * (c2 * e2z + s2 * e3z));
-    const double ms = g.ma + g.mb;
-    const double fa = g.ma / ms, fb = g.mb / ms;
+    const double ims = 1.0 / (g.ma + g.mb);
+    const double fa = g.ma * ims, fb = g.mb * ims;
     const double cmx = fa * g.v1x + fb * g.v2x;
     const double cmy = fa * g.v1y + fb * g.v2y;
     const double cmz = fb * g.v2z;
     const double n1x = cmx + fb * wnx, n1y = cmy + fb * wny, n1z = cmz + fb * wnz;
     const double n2x = cmx - fa * wnx, n2y = cmy - fa * wny, n2z = cmz - fa * wnz;
     vr[a] = n1x;
-    vt[a] = hypot(n1y, n1z);
+    vt[a] = sqrt(n1y * n1y + n1z * n1z);
     vr[b] = n2x;
-    vt[b] = hypot(n2y, n2z);
+    vt[b] = sqrt(n2y * n2y + n2z * n2z);
     return;
   }
 
-  const double e1x = g.wx / g.wm, e1y = g.wy / g.wm, e1z = g.wz / g.wm;
+  const double iwm = 1.0 / g.wm;
+  const double e1x = g.wx * iwm, e1y = g.wy * iwm, e1z = g.wz * iwm;
   const double ax = fabs(g.wx), ay = fabs(g.wy), az = fabs(g.wz);
   double cx, cy, cz;  // e1 x (axis of the smallest |w| component)
   if (ax <= ay && ax <= az) {
@@ -435,8 +436,8 @@ __global__ __launch_bounds__(NT) void k_relax(Ctx ctx, uint32_t step_arg) {
     cy = -e1x;
     cz = 0.0;
   }
-  const double cn = sqrt(cx * cx + cy * cy + cz * cz);
-  const double e2x = cx / cn, e2y = cy / cn, e2z = cz / cn;
+  const double icn = 1.0 / sqrt(cx * cx + cy * cy + cz * cz);
+  const double e2x = cx * icn, e2y = cy * icn, e2z = cz * icn;
   const double e3x = e1y * e2z - e1z * e2y;
   const double e3y = e1z * e2x - e1x * e2z;
   const double e3z = e1x * e2y - e1y * e2x;
@@ -447,17 +448,18 @@ __global__ __launch_bounds__(NT) void k_relax(Ctx ctx, uint32_t step_arg) {
   const double wnx = g.wm * (cb * e1x + sb * (c2 * e2x + s2 * e3x));
   const double wny = g.wm * (cb * e1y + sb * (c2 * e2y + s2 * e3y));
   const double wnz = g.wm * (cb * e1z + sb * (c2 * e2z + s2 * e3z));
-  const double ms = g.ma + g.mb;
-  const double fa = g.ma / ms, fb = g.mb / ms;
+  const double ims = 1.0 / (g.ma + g.mb);
+  const double fa = g.ma * ims, fb = g.mb * ims;
   const double cmx = fa * g.v1x + fb * g.v2x;
   const double cmy = fa * g.v1y + fb * g.v2y;
   const double cmz = fa * 0.0 + fb * g.v2z;
   const double n1x = cmx + fb * wnx, n1y = cmy + fb * wny, n1z = cmz + fb * wnz;
   const double n2x = cmx - fa * wnx, n2y = cmy - fa * wny, n2z = cmz - fa * wnz;
+  // |v_t| from its two components (O(1) speeds: no overflow to guard against)
   vr[a] = n1x;
-  vt[a] = hypot(n1y, n1z);
+  vt[a] = sqrt(n1y * n1y + n1z * n1z);
   vr[b] = n2x;
-  vt[b] = hypot(n2y, n2z);
+  vt[b] = sqrt(n2y * n2y + n2z * n2z);
 }
 
 template <class L, typename MT, bool MIXED>
