@@ -365,6 +365,13 @@ __host__ __device__ inline int64_t top_padded(int64_t len) { return len + (len >
 constexpr int kQueryTile = 4096;             // stars per tile of the search sort
 constexpr int kQuerySearchBlock = 256;       // threads of the sorted-search kernel
 constexpr int kQuerySearchChunk = 512;       // searches of one group per block of it
+// Where a group's subtree spans at most kStagedLevels levels (8^4 = 4096
+// stars), its search block holds the whole subtree in LDS, level 0 and the
+// (M, S) of its stars included, and runs kStagedChunk searches of the group.
+constexpr int kStagedLevels = 4;
+constexpr int kStagedSpan = 1 << (3 * kStagedLevels);
+constexpr int kStagedChunk = 16384;
+constexpr int kStagedThreads = 1024;
 constexpr int kPhiBins = 16384;  // bins of the potential-bound table (orbit.hip)
 // LFSR113 stream seeding (rng.hip): for each component, the 32x32 bit matrix
 // of 2^(80+b) steps for every bit b of a stream index (a base below 2^33
@@ -420,6 +427,7 @@ struct Workspace {
   int64_t bkt_bins, bkt_tiles;  // bkt_bins = 0: capacity above kBucketCapMax
   int64_t oq_bins, oq_tiles;    // groups (samples of the level the LDS top ends at,
                                 // and one more); tiles
+  int32_t oq_staged;            // the groups' searches run with the subtree in LDS
   // launch settings from the launch table (cluster_args; layout() leaves the
   // built-in defaults)
   int32_t sorted, bracket_blocks, trial_chunk;
@@ -531,6 +539,7 @@ inline Workspace layout(int64_t cap, void *base) {
     // the groups: one per sample of level ltop, and one for the lower turning
     // points the LDS levels already finish
     w.oq_bins = tl.ltop > 0 ? tl.len[tl.ltop] + 1 : 1;
+    w.oq_staged = (tl.ltop > 0 && tl.ltop <= kStagedLevels) ? 1 : 0;
     w.oq_tiles = cdiv(c, kQueryTile);
     w.oq = reinterpret_cast<OrbQuery *>(take(sizeof(OrbQuery) * 2 * c));
     w.oq_cnt = reinterpret_cast<uint32_t *>(take(4 * w.oq_tiles * w.oq_bins));
@@ -687,7 +696,8 @@ enum Shape : int {
   kShBktSort,   // one block per bucket of kept stars
   kShQTile,     // tiles of the orbit pass's search sort
   kShQGroup,    // groups of kQColGroup top samples
-  kShQSearch,   // blocks of sorted turning-point searches
+  kShQSearch,   // blocks of sorted turning-point searches (subtree below the LDS)
+  kShQStaged,   // blocks of sorted turning-point searches (subtree in LDS)
   kShapes
 };
 constexpr int kBracketThreads = 512;
@@ -718,7 +728,9 @@ __host__ __device__ inline int64_t blocks_of(Shape sh, const Workspace &w, int64
     case kShBktSort: return w.bkt_bins ? w.bkt_bins - 1 : 1;
     case kShQTile: return w.oq_tiles;
     case kShQGroup: return cdiv(w.oq_bins, int64_t(kQColGroup));
-    case kShQSearch: return w.oq_bins + cdiv(2 * c, kQuerySearchChunk);
+    // one form or the other, by the subtree's depth
+    case kShQSearch: return w.oq_staged ? 0 : w.oq_bins + cdiv(2 * c, kQuerySearchChunk);
+    case kShQStaged: return w.oq_staged ? w.oq_bins + cdiv(2 * c, kStagedChunk) : 0;
     default: return 1;
   }
 }

@@ -30,9 +30,12 @@
 //    of a table far larger than the L2.
 //  - sorted (k_oq_*): the searches are first grouped by the LDS-level sample
 //    they reached (a counting sort of 2 N small records), so that the
-//    searches sharing a subtree run together and find it in the L2; each
-//    writes its half of the star's orbit record where it sits in that
-//    order, and the trial kernel finds the two halves there.
+//    searches sharing a subtree run together: where the subtree is small
+//    enough (4096 stars at most), a block holds it whole in LDS, level 0
+//    and the (M, S) included, and its searches read no table line at all;
+//    a deeper subtree is found in the L2.  Each search writes its half of
+//    the star's orbit record where it sits in that order, and the trial
+//    kernel finds the two halves there.
 // Either way the roots inside the brackets and the rejection bound F follow.
 // k_orbit_trials then draws the radii: each wavefront owns a chunk of stars
 // and every lane draws trials for one star at a time, taking the chunk's
@@ -78,10 +81,14 @@ __device__ __forceinline__ double phi_in(const Levels &lv, const MS *__restrict_
   return -(t.M / x + t.S);
 }
 
+// dQ/dr at x in interval k (M = M_k; no mass inside the innermost star)
+__device__ __forceinline__ double dq_of(double M, int64_t k, double x, double J2) {
+  const double grav = (k >= 0) ? -2.0 * M / (x * x) : 0.0;
+  return grav + 2.0 * J2 / (x * x * x);
+}
 __device__ __forceinline__ double dq_in(const MS *__restrict__ ms, int64_t k, double x,
                                         double J2) {
-  const double grav = (k >= 0) ? -2.0 * ms[k].M / (x * x) : 0.0;
-  return grav + 2.0 * J2 / (x * x * x);
+  return dq_of(k >= 0 ? ms[k].M : 0.0, k, x, J2);
 }
 
 // Interval of x for the potential: the last k with r_k <= x, kept inside the
@@ -368,52 +375,61 @@ __device__ __forceinline__ int32_t group_descend1(const Levels &lv, int lhi, int
 // ---------------------------------------------------------------- turning points
 // The lower turning point in interval kmin (-1: inside the innermost star,
 // where the potential is flat), from r^2 Q = 2(E + S_k) r^2 + 2 M_k r - J^2
-// in the cancellation-free form, kept inside the interval; with dQ/dr there.
-__device__ __forceinline__ OrbitLo finalize_lo(const RPhi *__restrict__ tab,
-                                               const MS *__restrict__ ms, int64_t kmin, double E,
-                                               double J, double J2) {
+// in the cancellation-free form, kept inside the interval [rl, rh]; with
+// dQ/dr there.  t = (M, S) of the interval, phi0 = Phi_0 (used for kmin < 0).
+__device__ __forceinline__ OrbitLo lower_point(int64_t kmin, MS t, double rl, double rh,
+                                               double phi0, double E, double J, double J2) {
   double rmin;
   if (J2 == 0.0) {
     rmin = 0.0;
   } else if (kmin < 0) {
-    rmin = J / sqrt(2.0 * (E - tab[0].phi));
+    rmin = J / sqrt(2.0 * (E - phi0));
   } else {
-    const MS t = ms[kmin];
     const double a = 2.0 * (E + t.S);
     const double b = 2.0 * t.M;
     const double disc = b * b + 4.0 * a * J2;
     const double den = b + sqrt(disc > 0.0 ? disc : 0.0);
-    rmin = den > 0.0 ? 2.0 * J2 / den : tab[kmin].r;
+    rmin = den > 0.0 ? 2.0 * J2 / den : rl;
   }
-  const double rl = kmin >= 0 ? tab[kmin].r : 0.0, rh = tab[kmin + 1].r;
   rmin = rmin < rl ? rl : (rmin > rh ? rh : rmin);
   OrbitLo o{};
   o.E = E;
   o.rmin = rmin;
-  o.dq = (J2 != 0.0) ? dq_in(ms, kmin, rmin, J2) : 0.0;
+  o.dq = (J2 != 0.0) ? dq_of(t.M, kmin, rmin, J2) : 0.0;
   o.kmin = static_cast<int32_t>(kmin);
   return o;
 }
+__device__ __forceinline__ OrbitLo finalize_lo(const RPhi *__restrict__ tab,
+                                               const MS *__restrict__ ms, int64_t kmin, double E,
+                                               double J, double J2) {
+  const MS t = kmin >= 0 ? ms[kmin] : MS{0.0, 0.0};
+  const double rl = kmin >= 0 ? tab[kmin].r : 0.0;
+  const double phi0 = kmin < 0 ? tab[0].phi : 0.0;
+  return lower_point(kmin, t, rl, tab[kmin + 1].r, phi0, E, J, J2);
+}
 
-// The upper turning point in interval kmax (n - 1: beyond the last star).
-__device__ __forceinline__ OrbitHi finalize_hi(const RPhi *__restrict__ tab,
-                                               const MS *__restrict__ ms, int64_t n, int64_t kmax,
+// The upper turning point in interval kmax (n - 1: beyond the last star,
+// rh = +inf), kept inside [rl, rh].
+__device__ __forceinline__ OrbitHi upper_point(int64_t kmax, MS t, double rl, double rh,
                                                double E, double J, double J2) {
-  const MS t = ms[kmax];
   const double a = 2.0 * (E + t.S);
   const double b = 2.0 * t.M;
   const double disc = b * b + 4.0 * a * J2;
   const double sq = sqrt(disc > 0.0 ? disc : 0.0);
-  const double rl = tab[kmax].r;
-  const double rh = (kmax + 1 < n) ? tab[kmax + 1].r : kInf;
   double rmax = a < 0.0 ? (b + sq) / (-2.0 * a) : rh;
   rmax = rmax < rl ? rl : (rmax > rh ? rh : rmax);
   OrbitHi o{};
   o.J = J;
   o.rmax = rmax;
-  o.dq = dq_in(ms, kmax, rmax, J2);
+  o.dq = dq_of(t.M, kmax, rmax, J2);
   o.kmax = static_cast<int32_t>(kmax);
   return o;
+}
+__device__ __forceinline__ OrbitHi finalize_hi(const RPhi *__restrict__ tab,
+                                               const MS *__restrict__ ms, int64_t n, int64_t kmax,
+                                               double E, double J, double J2) {
+  const double rh = (kmax + 1 < n) ? tab[kmax + 1].r : kInf;
+  return upper_point(kmax, ms[kmax], tab[kmax].r, rh, E, J, J2);
 }
 
 // The record of a star that leaves the cluster (E >= 0 or NaN): the trial
@@ -668,8 +684,9 @@ __global__ __launch_bounds__(CT) void k_oq_colscan(Ctx ctx) {
 
 // One block per cluster: the first search of each group (oq_start[bins] is
 // the number of searches), and the first block of the search kernel that
-// works on each group, kQuerySearchChunk searches per block (oq_chunk[bins]
-// is the number of blocks with work).
+// works on each group, kQuerySearchChunk searches per block, or kStagedChunk
+// where the subtree is staged whole (oq_chunk[bins] is the number of blocks
+// with work).
 template <class Ctx>
 __global__ __launch_bounds__(QT) void k_oq_start(Ctx ctx) {
   __shared__ uint32_t sh[QT / 64];
@@ -682,11 +699,12 @@ __global__ __launch_bounds__(QT) void k_oq_start(Ctx ctx) {
   // groups: the bins samples' and the finished lower turning points' (no
   // search block)
   const int64_t groups = bins > 0 ? bins + 1 : 0;
+  const uint32_t per = A.w.oq_staged ? kStagedChunk : kQuerySearchChunk;
   uint32_t carry = 0u, ccarry = 0u;
   for (int64_t b0 = 0; b0 < groups; b0 += QT) {
     const int64_t b = b0 + threadIdx.x;
     const uint32_t v = b < groups ? tot[b] : 0u;
-    const uint32_t cv = b < bins ? (v + kQuerySearchChunk - 1) / kQuerySearchChunk : 0u;
+    const uint32_t cv = b < bins ? (v + per - 1) / per : 0u;
     uint32_t all, call;
     const uint32_t ex = block_excl_scan<QT>(v, sh, &all);
     const uint32_t cex = block_excl_scan<QT>(cv, sh, &call);
@@ -873,6 +891,113 @@ __global__ __launch_bounds__(QS) void k_oq_search(Ctx ctx) {
       else
         res_lo[qi] = finalize_lo(tab, A.w.ms, k, qr.E, qr.J, J2);
     }
+  }
+}
+
+// The grouped searches where a group's subtree spans at most kStagedLevels
+// levels: block b stages the whole subtree of its group in LDS -- the levels
+// below the top (padded as the top levels), level 0 itself and the (M, S) of
+// its stars, each read once, coalesced -- and runs up to kStagedChunk of the
+// group's searches, each lane alone from the group's sample down to its
+// interval and on to the turning point.  No table line is read per search;
+// the one global read is the search itself, fetched a round ahead.
+constexpr int SS = kStagedThreads;
+constexpr int kStagedSub = (8 + 1 + 1) + (64 + 8 + 1) + (512 + 64 + 1);  // levels 3..1, padded
+constexpr int kStagedL0 = kStagedSpan + kStagedSpan / 8 + 1;            // level 0, padded
+static_assert(kStagedLevels == 4, "kStagedSub holds the padded levels 3..1");
+static_assert(16 * (kStagedSub + kStagedL0 + kStagedSpan) + 64 <= 160 * 1024,
+              "the staged subtree fits a workgroup's LDS");
+
+template <class Ctx>
+__global__ __launch_bounds__(SS) void k_oq_search_staged(Ctx ctx) {
+  __shared__ RPhi sub[kStagedSub];
+  __shared__ RPhi lv0[kStagedL0];
+  __shared__ MS ms0[kStagedSpan];
+  __shared__ double r_next;  // radius of the first star after the group (+inf: none)
+  const ClusterArgs &A = ctx.args();
+  const OrbitTop &tl = A.top;
+  const int64_t n = A.w.rx_ctl->n;
+  const int64_t bins = query_bins(tl, n);
+  if (bins == 0) return;
+  const uint32_t *__restrict__ chunk = A.w.oq_chunk;
+  const int64_t b = ctx.block();
+  if (b >= static_cast<int64_t>(chunk[bins])) return;  // block-uniform
+  const int64_t node = A.w.oq_bmap[b];  // the group of block b
+  const int64_t q0 = A.w.oq_start[node] + (b - chunk[node]) * int64_t(kStagedChunk);
+  const int64_t qe = A.w.oq_start[node + 1];
+  const int64_t q1 = q0 + kStagedChunk < qe ? q0 + kStagedChunk : qe;
+  const Levels lv = levels_of(A.w);
+  const int ltop = tl.ltop;  // 1 .. kStagedLevels
+  {
+    int64_t off = 0;
+    for (int L = ltop - 1; L >= 1; --L) {
+      const int64_t span = int64_t(1) << (3 * (ltop - L));
+      const int64_t stride = int64_t(1) << (3 * L);
+      const int64_t cnt = (n + stride - 1) / stride;
+      const int64_t base = node * span;
+      const RPhi *__restrict__ src = lv.lev[L];
+      for (int64_t e = threadIdx.x; e < span; e += SS)
+        if (base + e < cnt) sub[pad_slot(off, e)] = src[base + e];
+      off += top_padded(span);
+    }
+  }
+  const int64_t span0 = int64_t(1) << (3 * ltop);
+  const int64_t k0 = node * span0;
+  const int64_t avail0 = n - k0 < span0 ? n - k0 : span0;
+  {
+    const RPhi *__restrict__ tab = lv.lev[0];
+    const MS *__restrict__ ms = A.w.ms;
+#pragma unroll 4
+    for (int64_t e = threadIdx.x; e < avail0; e += SS) {
+      lv0[pad_slot(0, e)] = tab[k0 + e];
+      ms0[e] = ms[k0 + e];
+    }
+    if (threadIdx.x == 0) r_next = k0 + span0 < n ? tab[k0 + span0].r : kInf;
+  }
+  __syncthreads();
+  OrbitLo *__restrict__ res_lo = reinterpret_cast<OrbitLo *>(A.w.orec);
+  OrbitHi *__restrict__ res_hi = reinterpret_cast<OrbitHi *>(A.w.orec);
+  const OrbQuery *__restrict__ oq = A.w.oq;
+  int64_t qi = q0 + threadIdx.x;
+  OrbQuery qr{0.0, 0.0, 0u, 0u};
+  if (qi < q1) qr = oq[qi];
+  for (int64_t qb = q0; qb < q1; qb += SS) {  // block-uniform
+    const int64_t qn = qi + SS;
+    OrbQuery nx{0.0, 0.0, 0u, 0u};
+    if (qn < q1) nx = oq[qn];
+    if (qi < q1) {
+      const bool hi_b = (qr.node & kQueryHi) != 0u;
+      const double J2 = qr.J * qr.J;
+      const int32_t ci = static_cast<int32_t>(qr.i);
+      const QAny pred{2.0 * qr.E, J2, hi_b ? -ci - 1 : ci};
+      int32_t s = static_cast<int32_t>(node);
+      int64_t off = 0;
+      for (int L = ltop - 1; L >= 1; --L) {
+        const int64_t span = int64_t(1) << (3 * (ltop - L));
+        const int32_t stride = int32_t(1) << (3 * L);
+        const int32_t cnt = static_cast<int32_t>((n + stride - 1) / stride);
+        const int32_t base = s * 8;
+        const int32_t local = base - static_cast<int32_t>(node * span);
+        s = base + node_last(sub + pad_slot(off, local), cnt - base, base * stride, stride, pred);
+        off += top_padded(span);
+      }
+      // level 0: the interval itself, then its end radii and (M, S)
+      const int32_t base = s * 8;
+      const int32_t lb = base - static_cast<int32_t>(k0);
+      const int32_t k =
+          base + node_last(lv0 + pad_slot(0, lb), static_cast<int32_t>(n) - base, base, 1, pred);
+      const int32_t lk = k - static_cast<int32_t>(k0);
+      const double rl = lv0[pad_slot(0, lk)].r;
+      const double rh =
+          k + 1 >= n ? kInf : (lk + 1 < span0 ? lv0[pad_slot(0, lk + 1)].r : r_next);
+      const MS t = ms0[lk];
+      if (hi_b)
+        res_hi[qi] = upper_point(k, t, rl, rh, qr.E, qr.J, J2);
+      else
+        res_lo[qi] = lower_point(k, t, rl, rh, 0.0, qr.E, qr.J, J2);
+    }
+    qr = nx;
+    qi = qn;
   }
 }
 
@@ -1209,7 +1334,11 @@ hipError_t run2(const L &l, const cmc_params &p, int corr, bool sorted, hipStrea
     k_oq_start<<<l.grid(kShOne), QT, 0, st>>>(l.ctx(kShOne));
     k_oq_scatter<Cq, MT, TO_STAGE, LF>
         <<<l.grid(kShQTile), QT, l.flat_top() ? top_bytes : 0, st>>>(l.ctx(kShQTile), corr);
-    k_oq_search<<<l.grid(kShQSearch), QS, 0, st>>>(l.ctx(kShQSearch));
+    // by the subtree's depth (an ensemble may hold both kinds)
+    if (l.grid(kShQSearch) > 0)
+      k_oq_search<<<l.grid(kShQSearch), QS, 0, st>>>(l.ctx(kShQSearch));
+    if (l.grid(kShQStaged) > 0)
+      k_oq_search_staged<<<l.grid(kShQStaged), SS, 0, st>>>(l.ctx(kShQStaged));
   } else {
     using Cb = decltype(l.ctx(kShBracket));
     k_orbit_bracket<Cb, MT, TO_STAGE, LF><<<l.grid(kShBracket), BT, top_bytes, st>>>(

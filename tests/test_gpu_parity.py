@@ -196,9 +196,9 @@ def test_relax(cmc, ora, n, seed, kw):
 
 
 # ---------------------------------------------------------------- orbit
-def _orbit_case(cmc, ora, st, seed=5, step=1):
+def _orbit_case(cmc, ora, st, seed=5, step=1, cap=None):
     tab = ora.potential(st.r, st.m)
-    cl = upload(cmc, st)
+    cl = upload(cmc, st, cap)
     import torch
     n = st.n
     for k, v in zip(("phi", "mcum", "ssuf"), tab):

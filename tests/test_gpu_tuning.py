@@ -53,6 +53,46 @@ SORTED_ORBIT_CASES = [("plummer", 100_000), ("plummer", 2_500), ("generic", 20_0
                       ("wide_range", 6000), ("centre_star", 3001), ("kepler", 30_000)]
 
 
+def _one_orbit_state(ora, n, seed):
+    """Seven in ten stars on one orbit (the same E and J, turning points at
+    r = 0.8 and 1.5), the rest on random bound orbits from r = 0.3 to 3: the
+    lower and the upper searches crowd into the two groups that hold the
+    turning points, each group taking several search blocks."""
+    rng = np.random.default_rng(seed)
+    k = (7 * n) // 10
+    r = np.sort(np.concatenate([np.exp(rng.uniform(np.log(0.8), np.log(1.5), k)),
+                                np.exp(rng.uniform(np.log(0.3), np.log(3.0), n - k))]))
+    m = np.full(n, 1.0 / n)
+    tab = ora.potential(r, m)
+    rp, ra = 0.8, 1.5
+    pp, pa = ora.phi_at(r, tab, rp), ora.phi_at(r, tab, ra)
+    # Q = 2 (E - Phi) - J^2 / r^2 vanishes at r_p and r_a
+    J2 = 2.0 * (pa - pp) / (1.0 / rp ** 2 - 1.0 / ra ** 2)
+    E = pp + 0.5 * J2 / rp ** 2
+    q = 2.0 * (E - tab[0]) - J2 / r ** 2
+    on = (r > rp) & (r < ra) & (q > 0.0)
+    vr = 0.3 * rng.standard_normal(n)
+    vt = np.abs(0.3 * rng.standard_normal(n))
+    sign = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    vr[on] = sign[on] * np.sqrt(q[on])
+    vt[on] = np.sqrt(J2) / r[on]
+    assert on.sum() > n // 2
+    return ora.State(r, vr, vt, m, np.arange(n, dtype=np.uint32) * 5 + 1)
+
+
+def _sorted_orbit_check(cmc, ora, st, cap=None):
+    h, s, (rn, vrn, vtn, so, d), tab = _orbit_case(cmc, ora, st, seed=3, step=2, cap=cap)
+    fin = np.isfinite(rn)
+    assert np.array_equal(np.isfinite(h["r_new"]), fin)
+    assert rel(h["r_new"][fin], rn[fin]) < TOL
+    E, J = d["E"][fin], d["J"][fin]
+    qscale = 2 * np.abs(E) + 2 * np.abs(tab[0][fin]) + (J / np.maximum(rn[fin], 1e-300)) ** 2
+    assert np.max(np.abs(h["vr"][fin] ** 2 - vrn[fin] ** 2) / qscale, initial=0.0) < TOL
+    assert s["n_esc"] == so["n_esc"] and s["trials"] == so["trials"]
+    assert s["violations"] == so["violations"] and s["capped"] == so["capped"]
+    assert rel(s["e_esc"], so["e_esc"], 1e-300) < 1e-10
+
+
 @pytest.mark.parametrize("case,n", SORTED_ORBIT_CASES)
 def test_sorted_orbit_against_oracle(cmc, ora, table, case, n):
     """cmc_orbit with grouped searches against the oracle (a 2500-star table
@@ -70,16 +110,26 @@ def test_sorted_orbit_against_oracle(cmc, ora, table, case, n):
         st = _radii_state(ora, np.sort(np.concatenate([[0.0], rng.lognormal(0, 1, n - 1)])), 12)
     else:
         st = ora.State(*inputs.kepler_probes(n, -0.2, 0.3, 3))
-    h, s, (rn, vrn, vtn, so, d), tab = _orbit_case(cmc, ora, st, seed=3, step=2)
-    fin = np.isfinite(rn)
-    assert np.array_equal(np.isfinite(h["r_new"]), fin)
-    assert rel(h["r_new"][fin], rn[fin]) < TOL
-    E, J = d["E"][fin], d["J"][fin]
-    qscale = 2 * np.abs(E) + 2 * np.abs(tab[0][fin]) + (J / np.maximum(rn[fin], 1e-300)) ** 2
-    assert np.max(np.abs(h["vr"][fin] ** 2 - vrn[fin] ** 2) / qscale, initial=0.0) < TOL
-    assert s["n_esc"] == so["n_esc"] and s["trials"] == so["trials"]
-    assert s["violations"] == so["violations"] and s["capped"] == so["capped"]
-    assert rel(s["e_esc"], so["e_esc"], 1e-300) < 1e-10
+    _sorted_orbit_check(cmc, ora, st)
+
+
+@pytest.mark.parametrize("cap", [2_000_000, 12_000_000])
+@pytest.mark.parametrize("case", ["plummer", "one_orbit"])
+def test_sorted_orbit_group_depths(cmc, ora, table, case, cap):
+    """The capacity sets the depth of the groups' subtrees below the LDS top:
+    4 levels (4096 stars) at 2e6, where a search block stages its group's
+    whole subtree in LDS, and 5 at 1.2e7, where the searches read the levels
+    below the LDS from the table.  100k stars, grouped searches, against the
+    oracle; in the one-orbit state a group holds more searches than one block
+    runs."""
+    table("sorted_64")
+    n = 100_000
+    if case == "plummer":
+        st = ora.plummer(n, 9)
+        st.vr[::4999] = 3.0  # escapers
+    else:
+        st = _one_orbit_state(ora, n, 4)
+    _sorted_orbit_check(cmc, ora, st, cap=cap)
 
 
 def run_steps(cmc, name, table, n, precision, m_f32, ms, steps=2, **kw):
