@@ -179,6 +179,23 @@ struct QAny {
   }
 };
 
+// The same predicates for the staged search, evaluated without branches:
+// lower (hi false) Q_k < 0 and k < lim, upper Q_k >= 0 or k <= lim (lim =
+// the star's index).  The sign tests are q_neg's and q_nonneg's.
+struct QSel {
+  double twoE, J2;
+  int32_t lim;
+  bool hi;
+};
+__device__ __forceinline__ bool qsel(const QSel &p, int32_t k, const RPhi &e) {
+  const double d = p.twoE - 2.0 * e.phi;
+  const double w = d * (e.r * e.r);
+  const bool r0 = e.r == 0.0;
+  const bool neg = r0 ? ((p.J2 > 0.0) | (d < 0.0)) : (w < p.J2);
+  const bool nonneg = r0 ? ((p.J2 == 0.0) & (d >= 0.0)) : (w >= p.J2);
+  return p.hi ? ((k <= p.lim) | nonneg) : ((k < p.lim) & neg);
+}
+
 // LDS slot of entry e of a padded level that starts at slot off.
 __device__ __forceinline__ int64_t pad_slot(int64_t off, int64_t e) { return off + e + (e >> 3); }
 
@@ -210,6 +227,20 @@ __device__ __forceinline__ int node_last(const RPhi *blk, int avail, int32_t k0,
   return c;
 }
 
+// node_last for qsel, reading all probed children (the caller's node lies
+// wholly inside its LDS array) and choosing by select.
+__device__ __forceinline__ int node_last_sel(const RPhi *blk, int avail, int32_t k0,
+                                             int32_t stride, const QSel &p) {
+  int c = 0;
+#pragma unroll
+  for (int h = 4; h >= 1; h >>= 1) {
+    const int q = c + h;
+    const RPhi e = blk[q];
+    c = ((q < avail) & qsel(p, k0 + q * stride, e)) ? q : c;
+  }
+  return c;
+}
+
 template <class Pred>
 __device__ __forceinline__ int32_t top_descend(const RPhi *top, const OrbitTop &tl, int nlev,
                                                int64_t n, const Pred &pred) {
@@ -219,7 +250,7 @@ __device__ __forceinline__ int32_t top_descend(const RPhi *top, const OrbitTop &
   for (int L = kMaxLevels - 1; L >= 0; --L) {
     if (L < nlev && L >= tl.ltop) {
       const int32_t stride = int32_t(1) << (3 * L);
-      const int32_t cnt = static_cast<int32_t>((n + stride - 1) / stride);
+      const int32_t cnt = static_cast<int32_t>((n + stride - 1) >> (3 * L));
       const int32_t base = s * 8;
       const RPhi *blk = top + pad_slot(tl.off[L], base);
       s = base + node_last(blk, cnt - base, base * stride, stride, pred);
@@ -286,7 +317,7 @@ __device__ __forceinline__ void group_descend2(const Levels &lv, int lhi, int64_
       // 16 sets of them live in registers
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
       const int64_t stride = int64_t(1) << (3 * L);
-      const int64_t cnt = (n + stride - 1) / stride;
+      const int64_t cnt = (n + stride - 1) >> (3 * L);
       const RPhi *lev = lv.lev[L];
 #pragma unroll
       for (int h = 0; h < 16; h += kGroupBatch) {
@@ -344,7 +375,7 @@ __device__ __forceinline__ int32_t group_descend1(const Levels &lv, int lhi, int
     if (L <= lhi) {
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
       const int64_t stride = int64_t(1) << (3 * L);
-      const int64_t cnt = (n + stride - 1) / stride;
+      const int64_t cnt = (n + stride - 1) >> (3 * L);
       const RPhi *lev = lv.lev[L];
       RPhi e[8];
 #pragma unroll
@@ -377,6 +408,23 @@ __device__ __forceinline__ int32_t group_descend1(const Levels &lv, int lhi, int
 // where the potential is flat), from r^2 Q = 2(E + S_k) r^2 + 2 M_k r - J^2
 // in the cancellation-free form, kept inside the interval [rl, rh]; with
 // dQ/dr there.  t = (M, S) of the interval, phi0 = Phi_0 (used for kmin < 0).
+// The root of r^2 Q in an interval [rl, rh] with (M, S) = t: with
+// a = 2(E + S), b = 2M and s = b + sqrt(b^2 + 4 a J^2), the lower one is
+// 2 J^2 / s (no cancellation), the upper one s / (-2a); where the root does
+// not exist (s <= 0, a >= 0) the interval's inner or outer end.  hi selects
+// the upper root; both forms of the search share this arithmetic.
+__device__ __forceinline__ double interval_root(bool hi, MS t, double rl, double rh, double E,
+                                                double J2) {
+  const double a = 2.0 * (E + t.S);
+  const double b = 2.0 * t.M;
+  const double disc = b * b + 4.0 * a * J2;
+  const double bs = b + sqrt(disc > 0.0 ? disc : 0.0);
+  const double num = hi ? bs : 2.0 * J2;
+  const double den = hi ? -2.0 * a : bs;
+  const bool ok = hi ? (a < 0.0) : (den > 0.0);
+  const double x = num / den;
+  return ok ? x : (hi ? rh : rl);
+}
 __device__ __forceinline__ OrbitLo lower_point(int64_t kmin, MS t, double rl, double rh,
                                                double phi0, double E, double J, double J2) {
   double rmin;
@@ -385,11 +433,7 @@ __device__ __forceinline__ OrbitLo lower_point(int64_t kmin, MS t, double rl, do
   } else if (kmin < 0) {
     rmin = J / sqrt(2.0 * (E - phi0));
   } else {
-    const double a = 2.0 * (E + t.S);
-    const double b = 2.0 * t.M;
-    const double disc = b * b + 4.0 * a * J2;
-    const double den = b + sqrt(disc > 0.0 ? disc : 0.0);
-    rmin = den > 0.0 ? 2.0 * J2 / den : rl;
+    rmin = interval_root(false, t, rl, rh, E, J2);
   }
   rmin = rmin < rl ? rl : (rmin > rh ? rh : rmin);
   OrbitLo o{};
@@ -412,11 +456,7 @@ __device__ __forceinline__ OrbitLo finalize_lo(const RPhi *__restrict__ tab,
 // rh = +inf), kept inside [rl, rh].
 __device__ __forceinline__ OrbitHi upper_point(int64_t kmax, MS t, double rl, double rh,
                                                double E, double J, double J2) {
-  const double a = 2.0 * (E + t.S);
-  const double b = 2.0 * t.M;
-  const double disc = b * b + 4.0 * a * J2;
-  const double sq = sqrt(disc > 0.0 ? disc : 0.0);
-  double rmax = a < 0.0 ? (b + sq) / (-2.0 * a) : rh;
+  double rmax = interval_root(true, t, rl, rh, E, J2);
   rmax = rmax < rl ? rl : (rmax > rh ? rh : rmax);
   OrbitHi o{};
   o.J = J;
@@ -851,7 +891,7 @@ __global__ __launch_bounds__(QS) void k_oq_search(Ctx ctx) {
   for (int L = ltop - 1; L >= lsub; --L) {
     const int64_t span = int64_t(1) << (3 * (ltop - L));
     const int64_t stride = int64_t(1) << (3 * L);
-    const int64_t cnt = (n + stride - 1) / stride;
+    const int64_t cnt = (n + stride - 1) >> (3 * L);
     const int64_t base = node * span;
     for (int64_t e = threadIdx.x; e < span; e += QS)
       if (base + e < cnt) sub[pad_slot(soff[L], e)] = lv.lev[L][base + e];
@@ -876,7 +916,7 @@ __global__ __launch_bounds__(QS) void k_oq_search(Ctx ctx) {
     if (act) {
       for (int L = ltop - 1; L >= lsub; --L) {
         const int32_t stride = int32_t(1) << (3 * L);
-        const int32_t cnt = static_cast<int32_t>((n + stride - 1) / stride);
+        const int32_t cnt = static_cast<int32_t>((n + stride - 1) >> (3 * L));
         const int32_t base = s * 8;
         const int32_t local = base - static_cast<int32_t>(node) * (int32_t(1) << (3 * (ltop - L)));
         s = base + node_last(sub + pad_slot(soff[L], local), cnt - base, base * stride, stride,
@@ -933,7 +973,7 @@ __global__ __launch_bounds__(SS) void k_oq_search_staged(Ctx ctx) {
     for (int L = ltop - 1; L >= 1; --L) {
       const int64_t span = int64_t(1) << (3 * (ltop - L));
       const int64_t stride = int64_t(1) << (3 * L);
-      const int64_t cnt = (n + stride - 1) / stride;
+      const int64_t cnt = (n + stride - 1) >> (3 * L);
       const int64_t base = node * span;
       const RPhi *__restrict__ src = lv.lev[L];
       for (int64_t e = threadIdx.x; e < span; e += SS)
@@ -955,9 +995,12 @@ __global__ __launch_bounds__(SS) void k_oq_search_staged(Ctx ctx) {
     if (threadIdx.x == 0) r_next = k0 + span0 < n ? tab[k0 + span0].r : kInf;
   }
   __syncthreads();
-  OrbitLo *__restrict__ res_lo = reinterpret_cast<OrbitLo *>(A.w.orec);
-  OrbitHi *__restrict__ res_hi = reinterpret_cast<OrbitHi *>(A.w.orec);
+  // Lanes of a wavefront mix lower and upper searches, so the search runs
+  // as one path for both: levels unrolled, every child read (inside the
+  // staged arrays) and tested with selects, one root.
+  OrbitLo *__restrict__ res = reinterpret_cast<OrbitLo *>(A.w.orec);
   const OrbQuery *__restrict__ oq = A.w.oq;
+  const int32_t n32 = static_cast<int32_t>(n);
   int64_t qi = q0 + threadIdx.x;
   OrbQuery qr{0.0, 0.0, 0u, 0u};
   if (qi < q1) qr = oq[qi];
@@ -965,37 +1008,43 @@ __global__ __launch_bounds__(SS) void k_oq_search_staged(Ctx ctx) {
     const int64_t qn = qi + SS;
     OrbQuery nx{0.0, 0.0, 0u, 0u};
     if (qn < q1) nx = oq[qn];
-    if (qi < q1) {
-      const bool hi_b = (qr.node & kQueryHi) != 0u;
-      const double J2 = qr.J * qr.J;
-      const int32_t ci = static_cast<int32_t>(qr.i);
-      const QAny pred{2.0 * qr.E, J2, hi_b ? -ci - 1 : ci};
-      int32_t s = static_cast<int32_t>(node);
-      int64_t off = 0;
-      for (int L = ltop - 1; L >= 1; --L) {
-        const int64_t span = int64_t(1) << (3 * (ltop - L));
+    const bool hi = (qr.node & kQueryHi) != 0u;
+    const double J2 = qr.J * qr.J;
+    const QSel pred{2.0 * qr.E, J2, static_cast<int32_t>(qr.i), hi};
+    int32_t s = static_cast<int32_t>(node);
+    int32_t off = 0;
+#pragma unroll
+    for (int L = kStagedLevels - 1; L >= 1; --L) {
+      if (L < ltop) {  // uniform
         const int32_t stride = int32_t(1) << (3 * L);
-        const int32_t cnt = static_cast<int32_t>((n + stride - 1) / stride);
+        const int32_t cnt = static_cast<int32_t>((n + stride - 1) >> (3 * L));
+        const int32_t span = int32_t(1) << (3 * (ltop - L));
         const int32_t base = s * 8;
-        const int32_t local = base - static_cast<int32_t>(node * span);
-        s = base + node_last(sub + pad_slot(off, local), cnt - base, base * stride, stride, pred);
-        off += top_padded(span);
+        const int32_t local = base - static_cast<int32_t>(node) * span;
+        s = base + node_last_sel(sub + pad_slot(off, local), cnt - base, base * stride, stride,
+                                 pred);
+        off += span + (span >> 3) + 1;
       }
-      // level 0: the interval itself, then its end radii and (M, S)
-      const int32_t base = s * 8;
-      const int32_t lb = base - static_cast<int32_t>(k0);
-      const int32_t k =
-          base + node_last(lv0 + pad_slot(0, lb), static_cast<int32_t>(n) - base, base, 1, pred);
-      const int32_t lk = k - static_cast<int32_t>(k0);
-      const double rl = lv0[pad_slot(0, lk)].r;
-      const double rh =
-          k + 1 >= n ? kInf : (lk + 1 < span0 ? lv0[pad_slot(0, lk + 1)].r : r_next);
-      const MS t = ms0[lk];
-      if (hi_b)
-        res_hi[qi] = upper_point(k, t, rl, rh, qr.E, qr.J, J2);
-      else
-        res_lo[qi] = lower_point(k, t, rl, rh, 0.0, qr.E, qr.J, J2);
     }
+    // level 0: the interval itself, then its end radii and (M, S)
+    const int32_t base = s * 8;
+    const int32_t lb = base - static_cast<int32_t>(k0);
+    const int32_t k = base + node_last_sel(lv0 + pad_slot(0, lb), n32 - base, base, 1, pred);
+    const int32_t lk = k - static_cast<int32_t>(k0);
+    const double rl = lv0[pad_slot(0, lk)].r;
+    const double rh1 = lv0[pad_slot(0, lk + 1 < kStagedSpan ? lk + 1 : lk)].r;
+    const double rh = k + 1 >= n32 ? kInf : (lk + 1 < span0 ? rh1 : r_next);
+    const MS t = ms0[lk];
+    double x = interval_root(hi, t, rl, rh, qr.E, J2);
+    x = (!hi && J2 == 0.0) ? 0.0 : x;
+    x = x < rl ? rl : (x > rh ? rh : x);
+    // the 32-byte half: (E, rmin, dq, kmin) or (J, rmax, dq, kmax)
+    OrbitLo o{};
+    o.E = hi ? qr.J : qr.E;
+    o.rmin = x;
+    o.dq = (hi || J2 != 0.0) ? dq_of(t.M, k, x, J2) : 0.0;
+    o.kmin = k;
+    if (qi < q1) res[qi] = o;
     qr = nx;
     qi = qn;
   }
