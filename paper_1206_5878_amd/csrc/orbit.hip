@@ -64,13 +64,19 @@ static_assert(16 % kGroupBatch == 0, "batches split the 16 searches of a group")
 // (2E - 2Phi_k) r_k^2 against J^2.  A star at r_k = 0 takes the limit r -> 0:
 // Q = -inf when J != 0 (the J^2/r^2 term wins, even against Phi_k = -inf),
 // else 2E - 2Phi_k.
+// (Both sides are evaluated and combined by select: lanes of a wavefront
+// take them alike, with no branch.)
 __device__ __forceinline__ bool q_neg(double twoE, double J2, const RPhi &e) {
-  if (e.r == 0.0) return J2 > 0.0 || twoE - 2.0 * e.phi < 0.0;
-  return (twoE - 2.0 * e.phi) * (e.r * e.r) < J2;
+  const double d = twoE - 2.0 * e.phi;
+  const bool at0 = (J2 > 0.0) | (d < 0.0);
+  const bool off0 = d * (e.r * e.r) < J2;
+  return e.r == 0.0 ? at0 : off0;
 }
 __device__ __forceinline__ bool q_nonneg(double twoE, double J2, const RPhi &e) {
-  if (e.r == 0.0) return J2 == 0.0 && twoE - 2.0 * e.phi >= 0.0;
-  return (twoE - 2.0 * e.phi) * (e.r * e.r) >= J2;
+  const double d = twoE - 2.0 * e.phi;
+  const bool at0 = (J2 == 0.0) & (d >= 0.0);
+  const bool off0 = d * (e.r * e.r) >= J2;
+  return e.r == 0.0 ? at0 : off0;
 }
 // Potential inside interval k from the defining sum: -(M_k / x + S_k); flat
 // at Phi_0 inside the innermost star.
@@ -159,14 +165,18 @@ struct QNeg {
   double twoE, J2;
   int32_t below;
   __device__ bool operator()(int32_t k, const RPhi &e) const {
-    return k < below && q_neg(twoE, J2, e);
+    const bool in = k < below;
+    const bool q = q_neg(twoE, J2, e);
+    return in & q;
   }
 };
 struct QNonNeg {
   double twoE, J2;
   int32_t upto;
   __device__ bool operator()(int32_t k, const RPhi &e) const {
-    return k <= upto || q_nonneg(twoE, J2, e);
+    const bool in = k <= upto;
+    const bool q = q_nonneg(twoE, J2, e);
+    return in | q;
   }
 };
 // Either bracket for the search kernel: c >= 0 the lower bracket below star
@@ -175,7 +185,9 @@ struct QAny {
   double twoE, J2;
   int32_t c;
   __device__ bool operator()(int32_t k, const RPhi &e) const {
-    return c >= 0 ? (k < c && q_neg(twoE, J2, e)) : (k <= -c - 1 || q_nonneg(twoE, J2, e));
+    const bool low = (k < c) & q_neg(twoE, J2, e);
+    const bool up = (k <= -c - 1) | q_nonneg(twoE, J2, e);
+    return c >= 0 ? low : up;
   }
 };
 
@@ -191,9 +203,13 @@ __device__ __forceinline__ bool qsel(const QSel &p, int32_t k, const RPhi &e) {
   const double d = p.twoE - 2.0 * e.phi;
   const double w = d * (e.r * e.r);
   const bool r0 = e.r == 0.0;
-  const bool neg = r0 ? ((p.J2 > 0.0) | (d < 0.0)) : (w < p.J2);
-  const bool nonneg = r0 ? ((p.J2 == 0.0) & (d >= 0.0)) : (w >= p.J2);
-  return p.hi ? ((k <= p.lim) | nonneg) : ((k < p.lim) & neg);
+  const bool neg0 = (p.J2 > 0.0) | (d < 0.0), negw = w < p.J2;
+  const bool non0 = (p.J2 == 0.0) & (d >= 0.0), nonw = w >= p.J2;
+  const bool neg = r0 ? neg0 : negw;
+  const bool nonneg = r0 ? non0 : nonw;
+  const bool up = (k <= p.lim) | nonneg;
+  const bool low = (k < p.lim) & neg;
+  return p.hi ? up : low;
 }
 
 // LDS slot of entry e of a padded level that starts at slot off.
@@ -222,7 +238,9 @@ __device__ __forceinline__ int node_last(const RPhi *blk, int avail, int32_t k0,
 #pragma unroll
   for (int h = 4; h >= 1; h >>= 1) {
     const int q = c + h;
-    if (q < avail && pred(k0 + q * stride, blk[q])) c = q;
+    const RPhi e = blk[q < avail ? q : avail - 1];  // a child that exists
+    const bool ok = (q < avail) & pred(k0 + q * stride, e);
+    c = ok ? q : c;
   }
   return c;
 }
@@ -236,7 +254,8 @@ __device__ __forceinline__ int node_last_sel(const RPhi *blk, int avail, int32_t
   for (int h = 4; h >= 1; h >>= 1) {
     const int q = c + h;
     const RPhi e = blk[q];
-    c = ((q < avail) & qsel(p, k0 + q * stride, e)) ? q : c;
+    const bool ok = (q < avail) & qsel(p, k0 + q * stride, e);
+    c = ok ? q : c;
   }
   return c;
 }
@@ -273,20 +292,23 @@ struct GParams {
 };
 struct GQNeg {
   __device__ static bool eval(const GParams &p, int64_t k, const RPhi &e) {
-    return k < p.c && q_neg(p.a, p.b, e);
+    const bool in = k < p.c;
+    return in & q_neg(p.a, p.b, e);
   }
 };
 struct GQNonNeg {
   __device__ static bool eval(const GParams &p, int64_t k, const RPhi &e) {
-    return k <= p.c || q_nonneg(p.a, p.b, e);
+    const bool in = k <= p.c;
+    return in | q_nonneg(p.a, p.b, e);
   }
 };
 // Either bracket: c >= 0 is the lower bracket below star c, c < 0 the upper
 // bracket of star -c - 1.
 struct GQAny {
   __device__ static bool eval(const GParams &p, int64_t k, const RPhi &e) {
-    return p.c >= 0 ? (k < p.c && q_neg(p.a, p.b, e))
-                    : (k <= -static_cast<int64_t>(p.c) - 1 || q_nonneg(p.a, p.b, e));
+    const bool low = (k < p.c) & q_neg(p.a, p.b, e);
+    const bool up = (k <= -static_cast<int64_t>(p.c) - 1) | q_nonneg(p.a, p.b, e);
+    return p.c >= 0 ? low : up;
   }
 };
 
