@@ -404,7 +404,9 @@ int cmc_batch_diagnostics(const cmc_batch *b, double *out_dev, void *stream);
  * Appendix A) times candidates on the GPU and installs its table here.
  *  sorted         : 1: the turning-point searches are grouped by the sample
  *                   of the LDS-resident top levels they reach, so that the
- *                   searches sharing a subtree run together; 0: each star's
+ *                   searches sharing a subtree run together (where a group
+ *                   spans at most 4096 stars, capacities up to about 1.06e7,
+ *                   its block holds the whole subtree in LDS); 0: each star's
  *                   wavefront searches its own brackets to the bottom.
  *  bracket_blocks : resident blocks of the direct search kernel for a single
  *                   cluster (an ensemble shares them out by capacity), 8..65535.

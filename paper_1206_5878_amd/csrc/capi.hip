@@ -17,7 +17,7 @@ namespace cmc {
 // it saves there), grouped ones above; larger trial chunks for larger N.
 namespace {
 constexpr cmc_tuning kBuiltinTuning[] = {
-    {0, 0, 512, 128, {0, 0, 0}},
+    {0, 0, 2048, 64, {0, 0, 0}},
     {int64_t(1) << 17, 0, 1024, 256, {0, 0, 0}},
     {int64_t(1) << 22, 1, 1024, 256, {0, 0, 0}},
 };

@@ -166,8 +166,12 @@ def test_tables_give_identical_steps(cmc, table, n, precision, m_f32, ms, kw):
 
 
 def test_tables_give_identical_ensembles(cmc, table):
+    """Ensembles under each form; the last cluster's capacity (1.2e7) puts its
+    groups below the LDS, the others' groups fit it whole, so the grouped
+    form runs both search kernels in one step."""
     from test_gpu_batch import SPECS
-    specs = SPECS + [dict(n=80_000, seed=21, gamma=0.11, model=0)]
+    specs = SPECS + [dict(n=80_000, seed=21, gamma=0.11, model=0),
+                     dict(n=50_000, seed=22, gamma=0.11, model=1, w0=6.0, cap=12_000_000)]
     out = {}
     for name in ("direct", "sorted_128", "direct_512_64"):
         table(name)
