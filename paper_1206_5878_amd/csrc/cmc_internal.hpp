@@ -372,6 +372,7 @@ constexpr int kStagedLevels = 4;
 constexpr int kStagedSpan = 1 << (3 * kStagedLevels);
 constexpr int kStagedChunk = 16384;
 constexpr int kStagedThreads = 1024;
+constexpr int kStagedBlocks = 256;  // resident blocks of the staged search (one per CU)
 constexpr int kPhiBins = 16384;  // bins of the potential-bound table (orbit.hip)
 // LFSR113 stream seeding (rng.hip): for each component, the 32x32 bit matrix
 // of 2^(80+b) steps for every bit b of a stream index (a base below 2^33
@@ -419,7 +420,8 @@ struct Workspace {
   uint32_t *oq_cnt;         // [oq_tiles * oq_bins] per-tile counts, then tile offsets
   uint32_t *oq_tot;         // [oq_bins] searches per top sample
   uint32_t *oq_start;       // [oq_bins + 1] first search of each top sample
-  uint32_t *oq_chunk;       // [oq_bins + 1] first search block of each top sample
+  uint32_t *oq_chunk;       // [oq_bins + 1] first search block of each top sample,
+                            // then the staged search's work counter
   uint32_t *oq_bmap;        // [search blocks] the top sample each search block works on
   uint32_t *oq_node;        // [cap] each star's two top samples
   uint32_t *oq_pos;         // [2 cap] each star's two halves in the grouped form's
@@ -545,7 +547,8 @@ inline Workspace layout(int64_t cap, void *base) {
     w.oq_cnt = reinterpret_cast<uint32_t *>(take(4 * w.oq_tiles * w.oq_bins));
     w.oq_tot = reinterpret_cast<uint32_t *>(take(4 * w.oq_bins));
     w.oq_start = reinterpret_cast<uint32_t *>(take(4 * (w.oq_bins + 1)));
-    w.oq_chunk = reinterpret_cast<uint32_t *>(take(4 * (w.oq_bins + 1)));
+    // (+ the staged search's work counter at oq_bins + 1)
+    w.oq_chunk = reinterpret_cast<uint32_t *>(take(4 * (w.oq_bins + 2)));
     w.oq_bmap = reinterpret_cast<uint32_t *>(take(4 * (w.oq_bins + cdiv(2 * c, kQuerySearchChunk))));
     w.oq_node = reinterpret_cast<uint32_t *>(take(4 * c));
     w.oq_pos = reinterpret_cast<uint32_t *>(take(8 * c));
@@ -730,7 +733,10 @@ __host__ __device__ inline int64_t blocks_of(Shape sh, const Workspace &w, int64
     case kShQGroup: return cdiv(w.oq_bins, int64_t(kQColGroup));
     // one form or the other, by the subtree's depth
     case kShQSearch: return w.oq_staged ? 0 : w.oq_bins + cdiv(2 * c, kQuerySearchChunk);
-    case kShQStaged: return w.oq_staged ? w.oq_bins + cdiv(2 * c, kStagedChunk) : 0;
+    case kShQStaged: {
+      const int64_t b = w.oq_bins + cdiv(2 * c, kStagedChunk);
+      return w.oq_staged ? (b < kStagedBlocks ? b : kStagedBlocks) : 0;
+    }
     default: return 1;
   }
 }

@@ -783,6 +783,7 @@ __global__ __launch_bounds__(QT) void k_oq_start(Ctx ctx) {
   if (threadIdx.x == 0) {
     start[groups] = carry;
     chunk[groups] = ccarry;
+    A.w.oq_chunk[A.w.oq_bins + 1] = 0u;  // the staged search's work counter
   }
 }
 
@@ -957,118 +958,181 @@ __global__ __launch_bounds__(QS) void k_oq_search(Ctx ctx) {
 }
 
 // The grouped searches where a group's subtree spans at most kStagedLevels
-// levels: block b stages the whole subtree of its group in LDS -- the levels
-// below the top (padded as the top levels), level 0 itself and the (M, S) of
-// its stars, each read once, coalesced -- and runs up to kStagedChunk of the
-// group's searches, each lane alone from the group's sample down to its
-// interval and on to the turning point.  No table line is read per search;
-// the one global read is the search itself, fetched a round ahead.
+// levels.  A work item is up to kStagedChunk searches of one group (the
+// search blocks' map of k_oq_start).  Each resident block holds an item's
+// whole subtree in LDS -- the levels below the top (padded as the top
+// levels), level 0 itself and the (M, S) of its stars, each read once,
+// coalesced -- and runs its searches, each lane alone from the group's
+// sample down to its interval and on to the turning point: no table line
+// is read per search.  A block takes its first item by its index and the
+// next ones from a counter, and loads the next item's subtree into
+// registers while the current item's searches run.
 constexpr int SS = kStagedThreads;
 constexpr int kStagedSub = (8 + 1 + 1) + (64 + 8 + 1) + (512 + 64 + 1);  // levels 3..1, padded
 constexpr int kStagedL0 = kStagedSpan + kStagedSpan / 8 + 1;            // level 0, padded
+constexpr int kStagedPer = kStagedSpan / SS;                            // level-0 entries a thread stages
 static_assert(kStagedLevels == 4, "kStagedSub holds the padded levels 3..1");
+static_assert(8 + 64 + 512 <= SS, "one subtree entry per thread");
 static_assert(16 * (kStagedSub + kStagedL0 + kStagedSpan) + 64 <= 160 * 1024,
               "the staged subtree fits a workgroup's LDS");
+
+// One item's subtree, held by the block's threads in registers on its way
+// to LDS.
+// (Plain doubles: the compiler keeps them in registers.)
+struct StagedFetch {
+  double sr, sphi;  // this thread's entry of the levels above level 0
+  int32_t s_slot;   // its LDS slot (-1: none)
+  double er[kStagedPer], ephi[kStagedPer], mM[kStagedPer], mS[kStagedPer];
+  double r_next;    // thread 0: radius of the first star after the group (+inf: none)
+};
+
+__device__ __forceinline__ void staged_fetch(const ClusterArgs &A, const Levels &lv, int ltop,
+                                             int64_t n, int64_t node, StagedFetch &f) {
+  // thread x takes entry x of the levels ltop - 1 .. 1 laid end to end
+  f.s_slot = -1;
+  int64_t x = threadIdx.x, off = 0;
+  for (int L = ltop - 1; L >= 1; --L) {
+    const int64_t span = int64_t(1) << (3 * (ltop - L));
+    const int64_t cnt = (n + (int64_t(1) << (3 * L)) - 1) >> (3 * L);
+    if (x >= 0 && x < span && node * span + x < cnt) {
+      const RPhi v = lv.lev[L][node * span + x];
+      f.sr = v.r;
+      f.sphi = v.phi;
+      f.s_slot = static_cast<int32_t>(pad_slot(off, x));
+    }
+    x -= span;
+    off += top_padded(span);
+  }
+  const int64_t span0 = int64_t(1) << (3 * ltop);
+  const int64_t k0 = node * span0;
+  const int64_t avail0 = n - k0 < span0 ? n - k0 : span0;
+  const RPhi *__restrict__ tab = lv.lev[0];
+  const MS *__restrict__ ms = A.w.ms;
+#pragma unroll
+  for (int u = 0; u < kStagedPer; ++u) {
+    const int64_t e = threadIdx.x + u * SS;
+    if (e < avail0) {
+      const RPhi v = tab[k0 + e];
+      const MS w = ms[k0 + e];
+      f.er[u] = v.r;
+      f.ephi[u] = v.phi;
+      f.mM[u] = w.M;
+      f.mS[u] = w.S;
+    }
+  }
+  if (threadIdx.x == 0) f.r_next = k0 + span0 < n ? tab[k0 + span0].r : kInf;
+}
 
 template <class Ctx>
 __global__ __launch_bounds__(SS) void k_oq_search_staged(Ctx ctx) {
   __shared__ RPhi sub[kStagedSub];
   __shared__ RPhi lv0[kStagedL0];
   __shared__ MS ms0[kStagedSpan];
-  __shared__ double r_next;  // radius of the first star after the group (+inf: none)
+  __shared__ double r_next;
+  __shared__ int64_t claim;
   const ClusterArgs &A = ctx.args();
   const OrbitTop &tl = A.top;
   const int64_t n = A.w.rx_ctl->n;
   const int64_t bins = query_bins(tl, n);
   if (bins == 0) return;
   const uint32_t *__restrict__ chunk = A.w.oq_chunk;
-  const int64_t b = ctx.block();
-  if (b >= static_cast<int64_t>(chunk[bins])) return;  // block-uniform
-  const int64_t node = A.w.oq_bmap[b];  // the group of block b
-  const int64_t q0 = A.w.oq_start[node] + (b - chunk[node]) * int64_t(kStagedChunk);
-  const int64_t qe = A.w.oq_start[node + 1];
-  const int64_t q1 = q0 + kStagedChunk < qe ? q0 + kStagedChunk : qe;
+  const uint32_t *__restrict__ qstart = A.w.oq_start;
+  const uint32_t *__restrict__ bmap = A.w.oq_bmap;
+  uint32_t *counter = A.w.oq_chunk + A.w.oq_bins + 1;
+  const int64_t items = chunk[bins];
+  const int64_t nb = ctx.nblocks();
+  int64_t item = ctx.block();
+  if (item >= items) return;  // block-uniform
   const Levels lv = levels_of(A.w);
   const int ltop = tl.ltop;  // 1 .. kStagedLevels
-  {
-    int64_t off = 0;
-    for (int L = ltop - 1; L >= 1; --L) {
-      const int64_t span = int64_t(1) << (3 * (ltop - L));
-      const int64_t stride = int64_t(1) << (3 * L);
-      const int64_t cnt = (n + stride - 1) >> (3 * L);
-      const int64_t base = node * span;
-      const RPhi *__restrict__ src = lv.lev[L];
-      for (int64_t e = threadIdx.x; e < span; e += SS)
-        if (base + e < cnt) sub[pad_slot(off, e)] = src[base + e];
-      off += top_padded(span);
-    }
-  }
   const int64_t span0 = int64_t(1) << (3 * ltop);
-  const int64_t k0 = node * span0;
-  const int64_t avail0 = n - k0 < span0 ? n - k0 : span0;
-  {
-    const RPhi *__restrict__ tab = lv.lev[0];
-    const MS *__restrict__ ms = A.w.ms;
-#pragma unroll 4
-    for (int64_t e = threadIdx.x; e < avail0; e += SS) {
-      lv0[pad_slot(0, e)] = tab[k0 + e];
-      ms0[e] = ms[k0 + e];
-    }
-    if (threadIdx.x == 0) r_next = k0 + span0 < n ? tab[k0 + span0].r : kInf;
-  }
-  __syncthreads();
-  // Lanes of a wavefront mix lower and upper searches, so the search runs
-  // as one path for both: levels unrolled, every child read (inside the
-  // staged arrays) and tested with selects, one root.
+  const int32_t n32 = static_cast<int32_t>(n);
   OrbitLo *__restrict__ res = reinterpret_cast<OrbitLo *>(A.w.orec);
   const OrbQuery *__restrict__ oq = A.w.oq;
-  const int32_t n32 = static_cast<int32_t>(n);
-  int64_t qi = q0 + threadIdx.x;
-  OrbQuery qr{0.0, 0.0, 0u, 0u};
-  if (qi < q1) qr = oq[qi];
-  for (int64_t qb = q0; qb < q1; qb += SS) {  // block-uniform
-    const int64_t qn = qi + SS;
-    OrbQuery nx{0.0, 0.0, 0u, 0u};
-    if (qn < q1) nx = oq[qn];
-    const bool hi = (qr.node & kQueryHi) != 0u;
-    const double J2 = qr.J * qr.J;
-    const QSel pred{2.0 * qr.E, J2, static_cast<int32_t>(qr.i), hi};
-    int32_t s = static_cast<int32_t>(node);
-    int32_t off = 0;
+  int64_t node = bmap[item];
+  StagedFetch f;
+  staged_fetch(A, lv, ltop, n, node, f);
+  bool fresh = true;  // f holds the current item's subtree
+  for (;;) {          // block-uniform
+    const int64_t k0 = node * span0;
+    if (fresh) {
+      const int64_t avail0 = n - k0 < span0 ? n - k0 : span0;
+      if (f.s_slot >= 0) sub[f.s_slot] = RPhi{f.sr, f.sphi};
 #pragma unroll
-    for (int L = kStagedLevels - 1; L >= 1; --L) {
-      if (L < ltop) {  // uniform
-        const int32_t stride = int32_t(1) << (3 * L);
-        const int32_t cnt = static_cast<int32_t>((n + stride - 1) >> (3 * L));
-        const int32_t span = int32_t(1) << (3 * (ltop - L));
-        const int32_t base = s * 8;
-        const int32_t local = base - static_cast<int32_t>(node) * span;
-        s = base + node_last_sel(sub + pad_slot(off, local), cnt - base, base * stride, stride,
-                                 pred);
-        off += span + (span >> 3) + 1;
+      for (int u = 0; u < kStagedPer; ++u) {
+        const int64_t e = threadIdx.x + u * SS;
+        if (e < avail0) {
+          lv0[pad_slot(0, e)] = RPhi{f.er[u], f.ephi[u]};
+          ms0[e] = MS{f.mM[u], f.mS[u]};
+        }
       }
+      if (threadIdx.x == 0) r_next = f.r_next;
     }
-    // level 0: the interval itself, then its end radii and (M, S)
-    const int32_t base = s * 8;
-    const int32_t lb = base - static_cast<int32_t>(k0);
-    const int32_t k = base + node_last_sel(lv0 + pad_slot(0, lb), n32 - base, base, 1, pred);
-    const int32_t lk = k - static_cast<int32_t>(k0);
-    const double rl = lv0[pad_slot(0, lk)].r;
-    const double rh1 = lv0[pad_slot(0, lk + 1 < kStagedSpan ? lk + 1 : lk)].r;
-    const double rh = k + 1 >= n32 ? kInf : (lk + 1 < span0 ? rh1 : r_next);
-    const MS t = ms0[lk];
-    double x = interval_root(hi, t, rl, rh, qr.E, J2);
-    x = (!hi && J2 == 0.0) ? 0.0 : x;
-    x = x < rl ? rl : (x > rh ? rh : x);
-    // the 32-byte half: (E, rmin, dq, kmin) or (J, rmax, dq, kmax)
-    OrbitLo o{};
-    o.E = hi ? qr.J : qr.E;
-    o.rmin = x;
-    o.dq = (hi || J2 != 0.0) ? dq_of(t.M, k, x, J2) : 0.0;
-    o.kmin = k;
-    if (qi < q1) res[qi] = o;
-    qr = nx;
-    qi = qn;
+    if (threadIdx.x == 0) claim = nb + static_cast<int64_t>(atomicAdd(counter, 1u));
+    __syncthreads();
+    // the next item: its subtree is read while this item's searches run
+    const int64_t next = claim;
+    const bool more = next < items;
+    const int64_t next_node = more ? static_cast<int64_t>(bmap[next]) : -1;
+    fresh = more && next_node != node;
+    if (fresh) staged_fetch(A, lv, ltop, n, next_node, f);
+    const int64_t q0 = qstart[node] + (item - chunk[node]) * int64_t(kStagedChunk);
+    const int64_t qe = qstart[node + 1];
+    const int64_t q1 = q0 + kStagedChunk < qe ? q0 + kStagedChunk : qe;
+    // Lanes of a wavefront mix lower and upper searches, so the search runs
+    // as one path for both: levels unrolled, every child read (inside the
+    // staged arrays) and tested with selects, one root.
+    int64_t qi = q0 + threadIdx.x;
+    OrbQuery qr{0.0, 0.0, 0u, 0u};
+    if (qi < q1) qr = oq[qi];
+    for (int64_t qb = q0; qb < q1; qb += SS) {  // block-uniform
+      const int64_t qn = qi + SS;
+      OrbQuery nx{0.0, 0.0, 0u, 0u};
+      if (qn < q1) nx = oq[qn];
+      const bool hi = (qr.node & kQueryHi) != 0u;
+      const double J2 = qr.J * qr.J;
+      const QSel pred{2.0 * qr.E, J2, static_cast<int32_t>(qr.i), hi};
+      int32_t s = static_cast<int32_t>(node);
+      int32_t off = 0;
+#pragma unroll
+      for (int L = kStagedLevels - 1; L >= 1; --L) {
+        if (L < ltop) {  // uniform
+          const int32_t stride = int32_t(1) << (3 * L);
+          const int32_t cnt = static_cast<int32_t>((n + stride - 1) >> (3 * L));
+          const int32_t span = int32_t(1) << (3 * (ltop - L));
+          const int32_t base = s * 8;
+          const int32_t local = base - static_cast<int32_t>(node) * span;
+          s = base + node_last_sel(sub + pad_slot(off, local), cnt - base, base * stride, stride,
+                                   pred);
+          off += span + (span >> 3) + 1;
+        }
+      }
+      // level 0: the interval itself, then its end radii and (M, S)
+      const int32_t base = s * 8;
+      const int32_t lb = base - static_cast<int32_t>(k0);
+      const int32_t k = base + node_last_sel(lv0 + pad_slot(0, lb), n32 - base, base, 1, pred);
+      const int32_t lk = k - static_cast<int32_t>(k0);
+      const double rl = lv0[pad_slot(0, lk)].r;
+      const double rh1 = lv0[pad_slot(0, lk + 1 < kStagedSpan ? lk + 1 : lk)].r;
+      const double rh = k + 1 >= n32 ? kInf : (lk + 1 < span0 ? rh1 : r_next);
+      const MS t = ms0[lk];
+      double x = interval_root(hi, t, rl, rh, qr.E, J2);
+      x = (!hi && J2 == 0.0) ? 0.0 : x;
+      x = x < rl ? rl : (x > rh ? rh : x);
+      // the 32-byte half: (E, rmin, dq, kmin) or (J, rmax, dq, kmax)
+      OrbitLo o{};
+      o.E = hi ? qr.J : qr.E;
+      o.rmin = x;
+      o.dq = (hi || J2 != 0.0) ? dq_of(t.M, k, x, J2) : 0.0;
+      o.kmin = k;
+      if (qi < q1) res[qi] = o;
+      qr = nx;
+      qi = qn;
+    }
+    if (!more) break;
+    __syncthreads();  // every search done before the LDS takes the next subtree
+    item = next;
+    node = next_node;
   }
 }
 
