@@ -708,23 +708,40 @@ __global__ __launch_bounds__(QT) void k_oq_hist(Ctx ctx) {
   for (int b = threadIdx.x; b <= bins; b += QT) hist[b] = 0u;
   __syncthreads();
   const int64_t k1 = k0 + kQueryTile < n ? k0 + kQueryTile : n;
-  for (int64_t i = k0 + threadIdx.x; i < k1; i += QT) {
-    const RPhi me = tab[i];
-    const double vri = A.s.vr[i], vti = A.s.vt[i];
-    const double E = me.phi + 0.5 * (vri * vri + vti * vti);
-    const double J = me.r * vti;
-    const double J2 = J * J;
-    // the two samples for the scatter: (t0 + 1) | t1 << 16, or none
-    uint32_t code = 0xFFFFFFFFu;
-    if (E < 0.0) {
-      const int32_t ii = static_cast<int32_t>(i);
-      const int32_t t0 = top_descend(top, tl, lv.nlev, n, QNeg{2.0 * E, J2, ii});
-      const int32_t t1 = top_descend(top, tl, lv.nlev, n, QNonNeg{2.0 * E, J2, ii});
-      atomicAdd(&hist[t0 >= 0 ? t0 : static_cast<int32_t>(bins)], 1u);
-      atomicAdd(&hist[t1], 1u);
-      code = static_cast<uint32_t>(t0 + 1) | (static_cast<uint32_t>(t1) << 16);
+  // two stars per thread and pass: four independent descents in flight
+  for (int64_t i0 = k0 + threadIdx.x; i0 < k1; i0 += 2 * QT) {
+    double E[2], J2[2];
+    bool in[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t i = i0 + u * QT;
+      in[u] = i < k1;
+      const int64_t ic = in[u] ? i : i0;
+      const RPhi me = tab[ic];
+      const double vri = A.s.vr[ic], vti = A.s.vt[ic];
+      E[u] = me.phi + 0.5 * (vri * vri + vti * vti);
+      const double J = me.r * vti;
+      J2[u] = J * J;
     }
-    node[i] = code;
+    int32_t t0[2], t1[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int32_t ii = static_cast<int32_t>(i0 + u * QT);
+      t0[u] = top_descend(top, tl, lv.nlev, n, QNeg{2.0 * E[u], J2[u], ii});
+      t1[u] = top_descend(top, tl, lv.nlev, n, QNonNeg{2.0 * E[u], J2[u], ii});
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (!in[u]) continue;
+      // the two samples for the scatter: (t0 + 1) | t1 << 16, or none
+      uint32_t code = 0xFFFFFFFFu;
+      if (E[u] < 0.0) {
+        atomicAdd(&hist[t0[u] >= 0 ? t0[u] : static_cast<int32_t>(bins)], 1u);
+        atomicAdd(&hist[t1[u]], 1u);
+        code = static_cast<uint32_t>(t0[u] + 1) | (static_cast<uint32_t>(t1[u]) << 16);
+      }
+      node[i0 + u * QT] = code;
+    }
   }
   __syncthreads();
   uint32_t *__restrict__ row = A.w.oq_cnt + t * A.w.oq_bins;
