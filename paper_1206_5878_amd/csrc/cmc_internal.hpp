@@ -611,10 +611,18 @@ __device__ __forceinline__ void column_scan(uint32_t *__restrict__ cnt, int64_t 
   const int64_t per = cdiv(tiles, int64_t(R));
   const int64_t t0 = run * per;
   const int64_t t1 = t0 + per < tiles ? t0 + per : tiles;
+  // (each thread's run is read kScanBatch entries at a time, all in flight:
+  // the run is a chain of dependent steps otherwise)
+  constexpr int kScanBatch = 8;
   uint32_t s = 0u;
   if (own) {
-#pragma unroll 4
-    for (int64_t t = t0; t < t1; ++t) s += cnt[t * stride + c];
+    for (int64_t t = t0; t < t1; t += kScanBatch) {
+      uint32_t v[kScanBatch];
+#pragma unroll
+      for (int u = 0; u < kScanBatch; ++u) v[u] = t + u < t1 ? cnt[(t + u) * stride + c] : 0u;
+#pragma unroll
+      for (int u = 0; u < kScanBatch; ++u) s += v[u];
+    }
   }
   part[run][col] = s;
   __syncthreads();
@@ -626,10 +634,15 @@ __device__ __forceinline__ void column_scan(uint32_t *__restrict__ cnt, int64_t 
   }
   if (!own) return;
   if (run == 0) tot[c] = all;
-  for (int64_t t = t0; t < t1; ++t) {
-    const uint32_t v = cnt[t * stride + c];
-    cnt[t * stride + c] = pre;
-    pre += v;
+  for (int64_t t = t0; t < t1; t += kScanBatch) {
+    uint32_t v[kScanBatch];
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u) v[u] = t + u < t1 ? cnt[(t + u) * stride + c] : 0u;
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u) {
+      if (t + u < t1) cnt[(t + u) * stride + c] = pre;
+      pre += v[u];
+    }
   }
 }
 

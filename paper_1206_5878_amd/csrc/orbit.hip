@@ -755,7 +755,8 @@ __global__ __launch_bounds__(CT) void k_oq_colscan(Ctx ctx) {
   const ClusterArgs &A = ctx.args();
   const int64_t n = A.w.rx_ctl->n;
   const int64_t bins = query_bins(A.top, n);
-  const int64_t c0 = ctx.block() * kQColGroup;
+  // neighbouring column groups on one XCD: they share the count rows' lines
+  const int64_t c0 = xcd_order(ctx.block(), ctx.nblocks()) * kQColGroup;
   if (bins == 0 || c0 > bins) return;  // block-uniform
   column_scan<CT, kQColGroup>(A.w.oq_cnt, A.w.oq_bins, cdiv(n, kQueryTile), c0, bins + 1,
                               A.w.oq_tot);
