@@ -1107,6 +1107,13 @@ __global__ __launch_bounds__(SS) void k_oq_search_staged(Ctx ctx) {
       const int64_t qn = qi + SS;
       OrbQuery nx{0.0, 0.0, 0u, 0u};
       if (qn < q1) nx = oq[qn];
+      // a wavefront past the item's last search skips the round (the body
+      // runs every lane unmasked, and the LDS is the bound)
+      if (qb + static_cast<int64_t>(threadIdx.x & ~63u) >= q1) {
+        qr = nx;
+        qi = qn;
+        continue;
+      }
       const bool hi = (qr.node & kQueryHi) != 0u;
       const double J2 = qr.J * qr.J;
       const QSel pred{2.0 * qr.E, J2, static_cast<int32_t>(qr.i), hi};
