@@ -38,12 +38,16 @@ BatchLayout batch_layout(int32_t clusters, const int64_t *total) {
 }
 
 // Blocks of each cluster in each launch shape.  The bracket kernel's
-// resident blocks (the launch table's, for the summed capacity) are shared
-// out in proportion to the clusters' capacities.
+// resident blocks (the launch table's entry for the largest capacity) go to
+// the largest cluster, and to each other cluster in proportion to its
+// capacity: every cluster gets the density of resident blocks the entry
+// gives the largest one (at 64 clusters from 1e4 to 9.4e5 stars, 5.47 ms a
+// step against 5.83 ms for the same blocks shared out over the summed
+// capacity).
 void shape_blocks(const std::vector<ClusterArgs> &a, std::vector<int64_t> *blocks) {
   const int C = static_cast<int>(a.size());
-  double cap_sum = 0.0;
-  for (const auto &x : a) cap_sum += static_cast<double>(x.s.cap);
+  double cap_max = 1.0;
+  for (const auto &x : a) cap_max = std::max(cap_max, static_cast<double>(x.s.cap));
   const int64_t resident = a.empty() ? 1 : a[0].w.bracket_blocks;
   for (int sh = 0; sh < kShapes; ++sh) {
     blocks[sh].assign(C, 0);
@@ -52,7 +56,7 @@ void shape_blocks(const std::vector<ClusterArgs> &a, std::vector<int64_t> *block
       int64_t b = blocks_of(static_cast<Shape>(sh), w, a[c].s.cap);
       if (sh == kShBracket) {
         const int64_t share = static_cast<int64_t>(
-            std::llround(resident * static_cast<double>(a[c].s.cap) / cap_sum));
+            std::llround(resident * static_cast<double>(a[c].s.cap) / cap_max));
         b = std::max<int64_t>(1, std::min<int64_t>(share, b));
       }
       blocks[sh][c] = b;
