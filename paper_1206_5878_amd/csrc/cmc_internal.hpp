@@ -713,7 +713,7 @@ enum Shape : int {
   kShQTile,     // tiles of the orbit pass's search sort
   kShQGroup,    // groups of kQColGroup top samples
   kShQSearch,   // blocks of sorted turning-point searches (subtree below the LDS)
-  kShQStaged,   // blocks of sorted turning-point searches (subtree in LDS)
+  kShQStaged,   // resident blocks of sorted turning-point searches (subtree in LDS)
   kShapes
 };
 constexpr int kBracketThreads = 512;

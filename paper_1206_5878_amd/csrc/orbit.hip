@@ -995,8 +995,7 @@ static_assert(16 * (kStagedSub + kStagedL0 + kStagedSpan) + 64 <= 160 * 1024,
               "the staged subtree fits a workgroup's LDS");
 
 // One item's subtree, held by the block's threads in registers on its way
-// to LDS.
-// (Plain doubles: the compiler keeps them in registers.)
+// to LDS (as plain doubles, which the compiler keeps in registers).
 struct StagedFetch {
   double sr, sphi;  // this thread's entry of the levels above level 0
   int32_t s_slot;   // its LDS slot (-1: none)
